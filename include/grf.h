@@ -1,0 +1,160 @@
+/*
+ * grf.h -- C ABI of the MI355X (gfx950) Gaussian random field sampler.
+ *
+ * Implements the FFT-based sampling of centred stationary Gaussian random
+ * fields on a periodic rectangular grid of Lang & Potthoff, "Fast simulation
+ * of Gaussian random fields" (arXiv 1105.2737), Section 3:
+ *   - the two-FFT algorithm (white noise, forward FFT, multiplication by
+ *     gamma^{1/2} |D|^{-1}, inverse FFT), from eq. (1);
+ *   - the one-FFT algorithm (Hermitian-symmetric complex noise drawn directly
+ *     in Fourier space through the paper's data arrangement, rules a-e of
+ *     Section 2 and eq. (3), then one inverse FFT), from eq. (2) and Lemma 1;
+ * plus the adjoint of the one-FFT sampler (gradients of a loss with respect to
+ * the covariance parameters and the noise).
+ *
+ * Problem statement (the algorithms' Input/Output lists): a region D with edge
+ * lengths l_i, grid sizes N_i (all even), the square root of a symmetric
+ * positive spectral density gamma, and a generator of independent normals;
+ * output a real field B on the grid whose covariance is the Fourier transform
+ * of gamma.
+ *
+ * Conventions fixed by this library (the paper leaves them open):
+ *   - spectral density S in cycles: C(x) = int S(p) exp(-2 pi i p.x) dp
+ *     (Section 2); frequency of index k along axis i: p = kappa(k)/l_i with
+ *     kappa(k) = k for k < N_i/2 and k - N_i otherwise;
+ *   - output phi_j = sum_k A_k exp(+2 pi i k.j/N) with A_k = h_k xi_k,
+ *     h_k = sqrt(S(p_k)/|D|), so Cov(phi_0, phi_j) = (1/|D|) sum_k S(p_k)
+ *     exp(2 pi i k.j/N), the Riemann sum of the covariance integral;
+ *   - noise: Philox-4x32-10 (Salmon et al., SC'11), key = seed + b for field b,
+ *     counter (s div 4, row, tag, 0) for slot s of a row, Box-Muller normals;
+ *     tag 0 = two-FFT white noise, tag 1 = one-FFT Fourier noise.  The noise
+ *     z of a field is a real array with the field's shape; the one-FFT
+ *     algorithm maps it bijectively onto the independent real and imaginary
+ *     parts of the Hermitian half-spectrum.
+ *
+ * Memory: all data pointers are DEVICE pointers unless stated otherwise; the
+ * caller owns them.  Fields are stored row-major [batch][N_1]...[N_d].  A plan
+ * owns only small device tables (twiddles, default per-field constants).
+ * Streams are hipStream_t passed as void* (NULL = default stream).  All work
+ * is asynchronous on that stream; a device error surfaces as GRF_EDEVICE at
+ * the launch or at a later call.  Every call validates its arguments on the
+ * host before launching anything: on GRF_EINVAL nothing has been written.
+ * Results are deterministic: the same plan, parameters and seed give the same
+ * bits whatever the batch size or the field's position in the batch.
+ * A plan may be used by one stream at a time.
+ */
+#ifndef GRF_H
+#define GRF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct grf_plan_s* grf_plan;
+
+typedef enum {
+  GRF_OK = 0,
+  GRF_EINVAL = -1,       /* invalid argument (nothing written) */
+  GRF_ENOMEM = -2,       /* device or host allocation failed */
+  GRF_EDEVICE = -3,      /* HIP runtime error */
+  GRF_EUNSUPPORTED = -4  /* valid request outside what this build implements */
+} grf_status;
+
+enum { GRF_ALG_TWO_FFT = 1, GRF_ALG_ONE_FFT = 2 };
+enum { GRF_F32 = 0, GRF_F64 = 1 };
+enum { GRF_COV_GAUSSIAN = 0, GRF_COV_MATERN = 1, GRF_COV_EXPONENTIAL = 2 };
+enum { GRF_OP_SAMPLE = 0, GRF_OP_BACKWARD = 1 };
+
+/*
+ * Plan description.
+ *   ndim      2 or 3 (the grid's dimension d).
+ *   dims      N_1..N_d: each even (Section 2 requires even N_i).  Leading
+ *             lengths N_1 (and N_2 for d = 3) from {4, 8, 12, 16, 24, 32, 48,
+ *             64, 96, 128, 180, 256, 360, 500, 512, 1000, 1024}; the last
+ *             length N_d with N_d/2 from {4, ..., 512} of the same list.
+ *   lengths   l_1..l_d > 0 (edge lengths of D; the unit torus is all 1).
+ *   alg       GRF_ALG_TWO_FFT (d = 2 only in this build) or GRF_ALG_ONE_FFT.
+ *   dtype     GRF_F32 (complex64 arithmetic, twiddles from float64) or GRF_F64.
+ *   cov_kind  covariance family:
+ *               GAUSSIAN    C(r) = sigma^2 exp(-r^2 / (2 ell^2))
+ *               MATERN      C(r) = sigma^2 2^{1-nu}/Gamma(nu) (sqrt(2nu) r/ell)^nu K_nu(sqrt(2nu) r/ell)
+ *               EXPONENTIAL C(r) = sigma^2 exp(-r/ell)   (nu ignored)
+ *   sigma, length_scale, nu   default parameters (> 0).
+ */
+typedef struct {
+  int32_t ndim;
+  int32_t alg;
+  int32_t dtype;
+  int32_t cov_kind;
+  int64_t dims[3];
+  double lengths[3];
+  double sigma;
+  double length_scale;
+  double nu;
+} grf_plan_desc;
+
+/* Create a plan: validates the description, builds float64 twiddle tables
+ * (rounded once to the working precision) and the default per-field
+ * constants.  *out receives a library-owned handle.  Errors: GRF_EINVAL (bad
+ * description, null pointer), GRF_EUNSUPPORTED (length not in the lists,
+ * two-FFT with d = 3), GRF_ENOMEM, GRF_EDEVICE. */
+grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out);
+
+/* Release a plan and its device tables (NULL is accepted). */
+grf_status grf_plan_destroy(grf_plan plan);
+
+/* Bytes of device workspace that grf_sample / grf_sample_from_noise
+ * (op = GRF_OP_SAMPLE) or grf_backward (op = GRF_OP_BACKWARD) need for
+ * `batch` fields (host pointer `bytes`).  The sampler runs in place in the
+ * output buffer; its workspace only holds per-field constants. */
+grf_status grf_workspace_size(grf_plan plan, int64_t batch, int32_t op, size_t* bytes);
+
+/* Sample fields seed, seed+1, ..., seed+batch-1 (Section 3: the plan's
+ * algorithm).  out: device, batch * N_1 * ... * N_d elements of the plan's
+ * dtype.  theta: NULL (use the plan's parameters) or a device array
+ * [batch][3] of float64 (sigma, length_scale, nu) per field.  workspace: device,
+ * at least grf_workspace_size(..., GRF_OP_SAMPLE) bytes (may be NULL if that
+ * size is 0).  batch = 0 is a no-op. */
+grf_status grf_sample(grf_plan plan, uint64_t seed, int64_t batch, const double* theta, void* out,
+                      void* workspace, size_t workspace_bytes, void* stream);
+
+/* As grf_sample, but the normals z are read from `noise` (device, same
+ * shape and dtype as the output) instead of being generated. */
+grf_status grf_sample_from_noise(grf_plan plan, const void* noise, int64_t batch, const double* theta,
+                                 void* out, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Write the noise z of the contract for fields seed..seed+batch-1 (device,
+ * same shape and dtype as the output). */
+grf_status grf_noise(grf_plan plan, uint64_t seed, int64_t batch, void* noise_out, void* stream);
+
+/* Adjoint of the one-FFT sampler.  Given the upstream gradient
+ * grad_out = dL/dphi (device, field-shaped, plan dtype), computes
+ *   grad_theta[b] = dL/d(sigma, length_scale, nu) of field b (device float64
+ *                   [batch][3]; the derivative for a parameter the family does
+ *                   not have is 0), and
+ *   grad_noise    = dL/dz (device, field-shaped; NULL to skip).
+ * The noise is regenerated from `seed` (noise == NULL) or read from `noise`.
+ * The Fourier transform of grad_out is recomputed; no spectrum is stored by
+ * the forward call.  Requires alg = GRF_ALG_ONE_FFT, ndim = 2. */
+grf_status grf_backward(grf_plan plan, uint64_t seed, const void* noise, int64_t batch, const double* theta,
+                        const void* grad_out, double* grad_theta, void* grad_noise, void* workspace,
+                        size_t workspace_bytes, void* stream);
+
+/* Raw Philox-4x32-10 blocks: counters (device, n x 4 uint32) -> out (device,
+ * n x 4 uint32) under key = seed.  For bit-exact checks of the generator. */
+grf_status grf_debug_philox(uint64_t seed, const uint32_t* counters, int64_t n, uint32_t* out, void* stream);
+
+/* Human-readable message of the last error on the calling thread. */
+const char* grf_last_error(void);
+
+/* Library version string. */
+const char* grf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRF_H */

@@ -1,0 +1,17 @@
+"""MI355X (gfx950) sampler of stationary Gaussian random fields by FFT.
+
+Lang & Potthoff, "Fast simulation of Gaussian random fields" (arXiv
+1105.2737), Section 3: the two-FFT algorithm and the one-FFT algorithm with
+the Hermitian data arrangement, on periodic 2D and 3D grids, plus the adjoint
+of the one-FFT sampler for training.  All arithmetic runs in the HIP library
+libgrf.so (include/grf.h); this package marshals torch tensors (device memory
+and streams) into its C ABI.
+
+    plan = Plan((512, 512), cov="matern", sigma=1.0, length_scale=0.1, nu=1.5)
+    phi = plan.sample(seed=0, batch=1024)              # [1024, 512, 512] float32 on cuda
+    phi = GRFSample.apply(theta, plan, seed, noise)    # differentiable in theta (and noise)
+"""
+from .api import Plan, GRFSample, COV_KINDS  # noqa: F401
+from ._lib import (GRFError, grf_plan_create, grf_plan_destroy, grf_workspace_size,  # noqa: F401
+                   grf_sample, grf_sample_from_noise, grf_noise, grf_backward, grf_debug_philox,
+                   grf_last_error, grf_version)

@@ -1,0 +1,115 @@
+"""ctypes binding of libgrf.so: the C ABI of include/grf.h under the same
+names.  Argument marshalling only; every step of the sampler runs in the HIP
+library.  Importing this module fails loudly if the library is not built."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgrf.so")
+
+GRF_OK, GRF_EINVAL, GRF_ENOMEM, GRF_EDEVICE, GRF_EUNSUPPORTED = 0, -1, -2, -3, -4
+GRF_ALG_TWO_FFT, GRF_ALG_ONE_FFT = 1, 2
+GRF_F32, GRF_F64 = 0, 1
+GRF_COV_GAUSSIAN, GRF_COV_MATERN, GRF_COV_EXPONENTIAL = 0, 1, 2
+GRF_OP_SAMPLE, GRF_OP_BACKWARD = 0, 1
+
+STATUS_NAMES = {0: "GRF_OK", -1: "GRF_EINVAL", -2: "GRF_ENOMEM", -3: "GRF_EDEVICE", -4: "GRF_EUNSUPPORTED"}
+
+# every symbol include/grf.h declares
+EXPORTS = ["grf_plan_create", "grf_plan_destroy", "grf_workspace_size", "grf_sample",
+           "grf_sample_from_noise", "grf_noise", "grf_backward", "grf_debug_philox",
+           "grf_last_error", "grf_version"]
+
+
+class grf_plan_desc(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("alg", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("cov_kind", ctypes.c_int32), ("dims", ctypes.c_int64 * 3), ("lengths", ctypes.c_double * 3),
+                ("sigma", ctypes.c_double), ("length_scale", ctypes.c_double), ("nu", ctypes.c_double)]
+
+
+class GRFError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_1105_2737_amd/build.py "
+                          "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, c64, u64, sz, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_int32
+    sig = {
+        "grf_plan_create": (ctypes.c_int, [ctypes.POINTER(grf_plan_desc), ctypes.POINTER(vp)]),
+        "grf_plan_destroy": (ctypes.c_int, [vp]),
+        "grf_workspace_size": (ctypes.c_int, [vp, c64, i32, ctypes.POINTER(sz)]),
+        "grf_sample": (ctypes.c_int, [vp, u64, c64, vp, vp, vp, sz, vp]),
+        "grf_sample_from_noise": (ctypes.c_int, [vp, vp, c64, vp, vp, vp, sz, vp]),
+        "grf_noise": (ctypes.c_int, [vp, u64, c64, vp, vp]),
+        "grf_backward": (ctypes.c_int, [vp, u64, vp, c64, vp, vp, vp, vp, vp, sz, vp]),
+        "grf_debug_philox": (ctypes.c_int, [u64, vp, c64, vp, vp]),
+        "grf_last_error": (ctypes.c_char_p, []),
+        "grf_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def check(status):
+    if status != GRF_OK:
+        raise GRFError(status, lib.grf_last_error().decode())
+    return status
+
+
+# ---- same-name wrappers (raise GRFError on a non-OK status) ----------------
+
+def grf_plan_create(desc):
+    h = ctypes.c_void_p()
+    check(lib.grf_plan_create(ctypes.byref(desc), ctypes.byref(h)))
+    return h
+
+
+def grf_plan_destroy(plan):
+    return check(lib.grf_plan_destroy(plan))
+
+
+def grf_workspace_size(plan, batch, op):
+    n = ctypes.c_size_t()
+    check(lib.grf_workspace_size(plan, batch, op, ctypes.byref(n)))
+    return n.value
+
+
+def grf_sample(plan, seed, batch, theta, out, workspace, workspace_bytes, stream):
+    return check(lib.grf_sample(plan, seed, batch, theta, out, workspace, workspace_bytes, stream))
+
+
+def grf_sample_from_noise(plan, noise, batch, theta, out, workspace, workspace_bytes, stream):
+    return check(lib.grf_sample_from_noise(plan, noise, batch, theta, out, workspace, workspace_bytes, stream))
+
+
+def grf_noise(plan, seed, batch, out, stream):
+    return check(lib.grf_noise(plan, seed, batch, out, stream))
+
+
+def grf_backward(plan, seed, noise, batch, theta, grad_out, grad_theta, grad_noise, workspace,
+                 workspace_bytes, stream):
+    return check(lib.grf_backward(plan, seed, noise, batch, theta, grad_out, grad_theta, grad_noise,
+                                  workspace, workspace_bytes, stream))
+
+
+def grf_debug_philox(seed, counters, n, out, stream):
+    return check(lib.grf_debug_philox(seed, counters, n, out, stream))
+
+
+def grf_last_error():
+    return lib.grf_last_error().decode()
+
+
+def grf_version():
+    return lib.grf_version().decode()

@@ -1,0 +1,156 @@
+"""torch-facing wrapper of the C ABI: plans, sampling and the autograd Function.
+
+torch provides device memory (the caching allocator) and the current stream;
+the library does all the work on that stream."""
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+COV_KINDS = {"gaussian": L.GRF_COV_GAUSSIAN, "matern": L.GRF_COV_MATERN, "exponential": L.GRF_COV_EXPONENTIAL}
+ALGS = {1: L.GRF_ALG_TWO_FFT, 2: L.GRF_ALG_ONE_FFT, "two_fft": L.GRF_ALG_TWO_FFT, "one_fft": L.GRF_ALG_ONE_FFT}
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """A sampling plan: grid, domain, algorithm, precision and covariance family.
+
+    dims: (N_1, ..., N_d), d in {2, 3}, all even; lengths: edge lengths
+    (default the unit torus); alg: 2 = one-FFT (Hermitian), 1 = two-FFT;
+    dtype: torch.float32 or torch.float64; cov: 'gaussian' | 'matern' |
+    'exponential' with default parameters sigma, length_scale, nu.
+    """
+
+    def __init__(self, dims, lengths=None, alg=2, dtype=torch.float32, cov="matern", sigma=1.0,
+                 length_scale=0.1, nu=1.5, device=None):
+        dims = tuple(int(n) for n in dims)
+        lengths = tuple(float(v) for v in (lengths or (1.0,) * len(dims)))
+        if len(lengths) != len(dims):
+            raise ValueError("lengths must match dims")
+        self.dims, self.lengths = dims, lengths
+        self.alg = ALGS[alg]
+        self.dtype = dtype
+        self.cov = cov
+        self.params = (float(sigma), float(length_scale), float(nu))
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        d = L.grf_plan_desc()
+        d.ndim = len(dims)
+        d.alg = self.alg
+        d.dtype = L.GRF_F32 if dtype == torch.float32 else L.GRF_F64
+        if dtype not in (torch.float32, torch.float64):
+            raise ValueError("dtype must be float32 or float64")
+        d.cov_kind = COV_KINDS[cov]
+        for i, (n, l) in enumerate(zip(dims, lengths)):
+            d.dims[i] = n
+            d.lengths[i] = l
+        d.sigma, d.length_scale, d.nu = self.params
+        with torch.cuda.device(self.device):
+            self.handle = L.grf_plan_create(d)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                L.lib.grf_plan_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    # -- helpers -------------------------------------------------------------
+    def _empty(self, batch):
+        return torch.empty((batch,) + self.dims, dtype=self.dtype, device=self.device)
+
+    def _workspace(self, batch, op):
+        n = L.grf_workspace_size(self.handle, batch, op)
+        ws = torch.empty(max(n, 1), dtype=torch.uint8, device=self.device)
+        return ws, n
+
+    def _theta(self, theta, batch):
+        if theta is None:
+            return None
+        theta = torch.as_tensor(theta, dtype=torch.float64, device=self.device)
+        if theta.dim() == 1:
+            theta = theta.expand(batch, 3)
+        if theta.shape != (batch, 3):
+            raise ValueError(f"theta must be [batch, 3] or [3], got {tuple(theta.shape)}")
+        return theta.contiguous()
+
+    # -- sampling ------------------------------------------------------------
+    def sample(self, seed=0, batch=1, theta=None, out=None):
+        """Fields seed .. seed+batch-1, shape [batch, *dims]."""
+        th = self._theta(theta, batch)
+        out = self._empty(batch) if out is None else out
+        ws, n = self._workspace(batch, L.GRF_OP_SAMPLE)
+        L.grf_sample(self.handle, int(seed) & (2 ** 64 - 1), batch, _ptr(th), _ptr(out), _ptr(ws), n, _stream())
+        return out
+
+    def sample_from_noise(self, noise, theta=None, out=None):
+        noise = noise.to(device=self.device, dtype=self.dtype).contiguous()
+        batch = noise.shape[0]
+        th = self._theta(theta, batch)
+        out = self._empty(batch) if out is None else out
+        ws, n = self._workspace(batch, L.GRF_OP_SAMPLE)
+        L.grf_sample_from_noise(self.handle, _ptr(noise), batch, _ptr(th), _ptr(out), _ptr(ws), n, _stream())
+        return out
+
+    def noise(self, seed=0, batch=1):
+        out = self._empty(batch)
+        L.grf_noise(self.handle, int(seed) & (2 ** 64 - 1), batch, _ptr(out), _stream())
+        return out
+
+    def backward(self, grad_out, seed=0, theta=None, noise=None, need_noise_grad=False):
+        """(dL/dtheta [batch, 3] float64, dL/dz or None) for the one-FFT sampler."""
+        grad_out = grad_out.to(device=self.device, dtype=self.dtype).contiguous()
+        batch = grad_out.shape[0]
+        th = self._theta(theta, batch)
+        if noise is not None:
+            noise = noise.to(device=self.device, dtype=self.dtype).contiguous()
+        gt = torch.empty((batch, 3), dtype=torch.float64, device=self.device)
+        gz = self._empty(batch) if need_noise_grad else None
+        ws, n = self._workspace(batch, L.GRF_OP_BACKWARD)
+        L.grf_backward(self.handle, int(seed) & (2 ** 64 - 1), _ptr(noise), batch, _ptr(th), _ptr(grad_out),
+                       _ptr(gt), _ptr(gz), _ptr(ws), n, _stream())
+        return gt, gz
+
+
+class GRFSample(torch.autograd.Function):
+    """phi = sampler(theta, z): differentiable in theta = [batch, 3]
+    (sigma, length_scale, nu; float64) and, when given, in the noise z.
+
+    The forward keeps only theta, the seed and the noise (if given); the
+    backward recomputes the Fourier transform of the upstream gradient and
+    regenerates the noise in the library (no spectrum is stored)."""
+
+    @staticmethod
+    def forward(ctx, theta, plan, seed=0, noise=None):
+        batch = theta.shape[0] if noise is None else noise.shape[0]
+        theta_c = theta.detach().to(device=plan.device, dtype=torch.float64)
+        if theta_c.dim() == 1:
+            theta_c = theta_c.expand(batch, 3)
+        theta_c = theta_c.contiguous()
+        if noise is None:
+            out = plan.sample(seed=seed, batch=batch, theta=theta_c)
+        else:
+            out = plan.sample_from_noise(noise.detach(), theta=theta_c)
+        ctx.plan, ctx.seed = plan, seed
+        ctx.theta_dim = theta.dim()
+        ctx.save_for_backward(theta_c, noise.detach() if noise is not None else None)
+        ctx.has_noise = noise is not None
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        theta_c, noise = ctx.saved_tensors
+        need_z = ctx.has_noise and ctx.needs_input_grad[3]
+        gt, gz = ctx.plan.backward(g, seed=ctx.seed, theta=theta_c, noise=noise, need_noise_grad=need_z)
+        if ctx.theta_dim == 1:
+            gt = gt.sum(0)
+        return gt, None, None, gz

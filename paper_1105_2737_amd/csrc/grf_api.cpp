@@ -1,0 +1,468 @@
+// Host side of the C ABI declared in include/grf.h: argument validation, plan
+// tables and the sequence of passes for each entry point.
+//
+// Pass sequences (packed half-spectrum layout, in place in the output buffer):
+//   one-FFT algorithm (Section 3), d = 2:
+//       column noise generation + inverse transform along axis 1
+//       -> last-axis complex-to-real
+//   one-FFT algorithm, d = 3: as above with an inverse transform along axis 2
+//       between the two
+//   two-FFT algorithm (Section 3), d = 2:
+//       last-axis white noise + real-to-complex
+//       -> axis 1 forward, multiply by h / sqrt(P), axis 1 inverse
+//       -> last-axis complex-to-real
+//   adjoint of the one-FFT algorithm, d = 2:
+//       last-axis real-to-complex of dL/dphi -> axis 1 forward + reduction
+//       -> per-field sum of the partials
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/grf.h"
+#include "grf_dispatch.hpp"
+#include "grf_kernels.hpp"
+
+using grf::Args;
+using grf::FieldRec;
+
+struct grf_plan_s {
+  grf_plan_desc desc;
+  int d;
+  int n1, no, nd, M;        // N_1, middle (N_2 if d = 3 else 1), last, last/2
+  long long P;              // points per field
+  double vol;
+  double il2[3];
+  int dtype;
+  size_t esz;               // bytes per real element
+  void* tw_col1 = nullptr;  // W_{N_1}
+  void* tw_col2 = nullptr;  // W_{N_2} (d = 3)
+  void* tw_row = nullptr;   // W_{N_d}
+  FieldRec* rec_dev = nullptr;
+  int device = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+grf_status fail(grf_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+grf_status hip_fail(hipError_t e, const char* what) {
+  return fail(GRF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool smooth235(long long n) {
+  if (n <= 0) return false;
+  for (int p : {2, 3, 5})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+// W_L[i] = exp(2 pi i i / L) in float64, stored in the working precision.
+grf_status make_table(int L, int dtype, void** out) {
+  std::vector<double> w(2 * (size_t)L);
+  for (int i = 0; i < L; ++i) {
+    // reduce i/L to an angle in [-pi, pi] before cos/sin for accuracy
+    long long ii = i;
+    if (2 * ii > L) ii -= L;
+    const double ang = 2.0 * M_PI * (double)ii / (double)L;
+    w[2 * i] = std::cos(ang);
+    w[2 * i + 1] = std::sin(ang);
+  }
+  const size_t bytes = (size_t)L * 2 * (dtype == GRF_F32 ? 4 : 8);
+  hipError_t e = hipMalloc(out, bytes);
+  if (e != hipSuccess) return fail(GRF_ENOMEM, "hipMalloc of twiddle table failed");
+  if (dtype == GRF_F32) {
+    std::vector<float> f(w.begin(), w.end());
+    e = hipMemcpy(*out, f.data(), bytes, hipMemcpyHostToDevice);
+  } else {
+    e = hipMemcpy(*out, w.data(), bytes, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return hip_fail(e, "twiddle upload");
+  return GRF_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Workspace layout: [records][partials][spectrum]
+struct WsLayout {
+  size_t recs, partial, spec, total;
+};
+
+WsLayout ws_layout(const grf_plan_s* p, long long batch, int op) {
+  WsLayout w{};
+  w.recs = 0;
+  size_t off = align256((size_t)batch * sizeof(FieldRec));
+  w.partial = off;
+  if (op == GRF_OP_BACKWARD) {
+    const grf::Geom g = grf::pass_geom(grf::PASS_COL_GRAD, p->dtype, p->n1);
+    const long long ntile = (p->M + 2 * g.per_wg - 1) / (2 * g.per_wg);
+    off += align256((size_t)batch * ntile * 3 * sizeof(double));
+    w.spec = off;
+    off += align256((size_t)batch * p->P * p->esz);
+  } else {
+    w.spec = off;
+  }
+  w.total = off;
+  return w;
+}
+
+grf_status check_stream_device(const grf_plan_s* p) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != p->device) return fail(GRF_EINVAL, "plan was created on another device");
+  return GRF_OK;
+}
+
+// Per-field constants: from device theta (prep kernel) or the plan default.
+grf_status field_records(const grf_plan_s* p, const double* theta, long long batch, void* workspace,
+                         size_t ws_bytes, hipStream_t s, const FieldRec** recs, int* stride) {
+  if (theta == nullptr) {
+    *recs = p->rec_dev;
+    *stride = 0;
+    return GRF_OK;
+  }
+  if (workspace == nullptr || ws_bytes < (size_t)batch * sizeof(FieldRec))
+    return fail(GRF_EINVAL, "workspace too small for per-field parameters");
+  FieldRec* out = (FieldRec*)workspace;
+  hipError_t e = grf::launch_prep_recs(theta, (int)batch, p->desc.cov_kind, p->d, p->vol, out, nullptr, s);
+  if (e != hipSuccess) return hip_fail(e, "per-field constants");
+  *recs = out;
+  *stride = 1;
+  return GRF_OK;
+}
+
+Args base_args(const grf_plan_s* p, long long batch) {
+  Args a;
+  std::memset(&a, 0, sizeof(a));
+  a.field_stride = p->P / 2;
+  a.batch = (int)batch;
+  a.n1 = p->n1;
+  a.no = p->no;
+  a.nd = p->nd;
+  a.M = p->M;
+  a.il2[0] = p->il2[0];
+  a.il2[1] = p->il2[1];
+  a.il2[2] = p->il2[2];
+  a.scale = 1.0;
+  a.nfixed = 1;
+  a.rows_per_field = (int)(p->P / p->nd);
+  return a;
+}
+
+grf_status run_pass(const grf_plan_s* p, int pass, int L, Args a, long long nfixed_blocks_per_field,
+                    long long batch, hipStream_t s) {
+  (void)nfixed_blocks_per_field;
+  const grf::Geom g = grf::pass_geom(pass, p->dtype, L);
+  if (g.threads <= 0) return fail(GRF_EUNSUPPORTED, "no kernel for this length");
+  long long nblocks;
+  if (pass >= grf::PASS_ROW_C2R) {
+    nblocks = (a.rows + g.per_wg - 1) / g.per_wg;
+  } else {
+    a.ntile = (a.M + 2 * g.per_wg - 1) / (2 * g.per_wg);
+    nblocks = (long long)a.ntile * a.nfixed * batch;
+  }
+  if (nblocks <= 0) return GRF_OK;
+  if (nblocks > 0x7fffffffLL) return fail(GRF_EINVAL, "batch too large for one launch");
+  hipError_t e = grf::launch_pass(pass, p->dtype, L, a, nblocks, s);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return GRF_OK;
+}
+
+// The sampler proper; zsrc == nullptr generates the noise from the seed.
+grf_status sample_impl(grf_plan p, uint64_t seed, const void* zsrc, int64_t batch, const double* theta, void* out,
+                       void* workspace, size_t ws_bytes, void* stream) {
+  if (p == nullptr) return fail(GRF_EINVAL, "null plan");
+  if (batch < 0) return fail(GRF_EINVAL, "negative batch");
+  if (batch == 0) return GRF_OK;
+  if (out == nullptr) return fail(GRF_EINVAL, "null output");
+  if (batch > 0x7fffffff) return fail(GRF_EINVAL, "batch too large");
+  grf_status st = check_stream_device(p);
+  if (st != GRF_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const FieldRec* recs;
+  int rstride;
+  st = field_records(p, theta, batch, workspace, ws_bytes, s, &recs, &rstride);
+  if (st != GRF_OK) return st;
+  Args a = base_args(p, batch);
+  a.data = out;
+  a.src = zsrc;
+  a.recs = recs;
+  a.rec_stride = rstride;
+  a.seed = seed;
+  if (p->desc.alg == GRF_ALG_ONE_FFT) {
+    a.tag = 1;
+    a.tw = p->tw_col1;
+    if (p->d == 2) {
+      a.stride_ax = p->M;
+      a.stride_fixed = p->M;
+      a.nfixed = 1;
+    } else {
+      a.stride_ax = (long long)p->no * p->M;
+      a.stride_fixed = p->M;
+      a.nfixed = p->no;
+    }
+    st = run_pass(p, grf::PASS_COL_GEN_INV, p->n1, a, 0, batch, s);
+    if (st != GRF_OK) return st;
+    if (p->d == 3) {
+      Args m = a;
+      m.src = nullptr;
+      m.tw = p->tw_col2;
+      m.stride_ax = p->M;
+      m.stride_fixed = (long long)p->no * p->M;
+      m.nfixed = p->n1;
+      st = run_pass(p, grf::PASS_COL_LOAD_INV, p->no, m, 0, batch, s);
+      if (st != GRF_OK) return st;
+    }
+  } else {
+    // two-FFT algorithm, d = 2
+    Args r = a;
+    r.tag = 0;
+    r.tw2 = p->tw_row;
+    r.rows = batch * (long long)p->n1;
+    const int rpass = zsrc ? grf::PASS_ROW_R2C_LOAD : grf::PASS_ROW_R2C_GEN;
+    st = run_pass(p, rpass, p->M, r, 0, batch, s);
+    if (st != GRF_OK) return st;
+    Args c = a;
+    c.src = nullptr;
+    c.tw = p->tw_col1;
+    c.stride_ax = p->M;
+    c.stride_fixed = p->M;
+    c.nfixed = 1;
+    c.scale = 1.0 / std::sqrt((double)p->P);
+    st = run_pass(p, grf::PASS_COL_FILTER, p->n1, c, 0, batch, s);
+    if (st != GRF_OK) return st;
+  }
+  Args b = a;
+  b.src = nullptr;
+  b.tw2 = p->tw_row;
+  b.rows = batch * (p->P / p->nd);
+  return run_pass(p, grf::PASS_ROW_C2R, p->M, b, 0, batch, s);
+}
+
+}  // namespace
+
+namespace grf {
+
+bool col_length_supported(int L) {
+  switch (L) {
+#define GRF_X(L_) case L_:
+    GRF_COL_LENGTHS(GRF_X)
+#undef GRF_X
+    return true;
+    default:
+      return false;
+  }
+}
+
+bool row_length_supported(int M) {
+  switch (M) {
+#define GRF_X(M_) case M_:
+    GRF_ROW_LENGTHS(GRF_X)
+#undef GRF_X
+    return true;
+    default:
+      return false;
+  }
+}
+
+Geom pass_geom(int pass, int dtype, int L) {
+  if (pass >= PASS_ROW_C2R) return dtype == 0 ? geom_row_f32(L) : geom_row_f64(L);
+  return dtype == 0 ? geom_col_f32(L) : geom_col_f64(L);
+}
+
+hipError_t launch_pass(int pass, int dtype, int L, const Args& a, long long nblocks, hipStream_t s) {
+  if (pass >= PASS_ROW_C2R)
+    return dtype == 0 ? launch_row_f32(pass, L, a, nblocks, s) : launch_row_f64(pass, L, a, nblocks, s);
+  return dtype == 0 ? launch_col_f32(pass, L, a, nblocks, s) : launch_col_f64(pass, L, a, nblocks, s);
+}
+
+}  // namespace grf
+
+extern "C" {
+
+const char* grf_last_error(void) { return g_err.c_str(); }
+
+const char* grf_version(void) { return "grf-mi355x 0.1 (gfx950)"; }
+
+grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out) {
+  if (desc == nullptr || out == nullptr) return fail(GRF_EINVAL, "null argument");
+  *out = nullptr;
+  const grf_plan_desc& d = *desc;
+  if (d.ndim < 2 || d.ndim > 3) return fail(GRF_EUNSUPPORTED, "ndim must be 2 or 3");
+  if (d.alg != GRF_ALG_TWO_FFT && d.alg != GRF_ALG_ONE_FFT) return fail(GRF_EINVAL, "unknown algorithm");
+  if (d.dtype != GRF_F32 && d.dtype != GRF_F64) return fail(GRF_EINVAL, "unknown dtype");
+  if (d.cov_kind < GRF_COV_GAUSSIAN || d.cov_kind > GRF_COV_EXPONENTIAL)
+    return fail(GRF_EINVAL, "unknown covariance kind");
+  for (int i = 0; i < d.ndim; ++i) {
+    if (d.dims[i] <= 0 || (d.dims[i] % 2) != 0) return fail(GRF_EINVAL, "grid sizes must be positive and even");
+    if (!smooth235(d.dims[i])) return fail(GRF_EINVAL, "grid sizes must factor into 2, 3 and 5");
+    if (!(d.lengths[i] > 0) || !std::isfinite(d.lengths[i])) return fail(GRF_EINVAL, "edge lengths must be > 0");
+  }
+  if (!(d.sigma > 0) || !(d.length_scale > 0) || !std::isfinite(d.sigma) || !std::isfinite(d.length_scale))
+    return fail(GRF_EINVAL, "sigma and length_scale must be > 0");
+  if (d.cov_kind == GRF_COV_MATERN && (!(d.nu > 0) || !std::isfinite(d.nu)))
+    return fail(GRF_EINVAL, "nu must be > 0");
+  if (d.alg == GRF_ALG_TWO_FFT && d.ndim != 2)
+    return fail(GRF_EUNSUPPORTED, "two-FFT algorithm implemented for d = 2");
+  const int last = d.ndim - 1;
+  if (!grf::col_length_supported((int)d.dims[0]) || (d.ndim == 3 && !grf::col_length_supported((int)d.dims[1])) ||
+      d.dims[last] > 2 * 512 || !grf::row_length_supported((int)(d.dims[last] / 2)))
+    return fail(GRF_EUNSUPPORTED, "grid length not in the supported list");
+
+  grf_plan_s* p = new (std::nothrow) grf_plan_s();
+  if (p == nullptr) return fail(GRF_ENOMEM, "host allocation failed");
+  p->desc = d;
+  p->d = d.ndim;
+  p->n1 = (int)d.dims[0];
+  p->no = d.ndim == 3 ? (int)d.dims[1] : 1;
+  p->nd = (int)d.dims[last];
+  p->M = p->nd / 2;
+  p->P = (long long)p->n1 * p->no * p->nd;
+  p->vol = 1.0;
+  for (int i = 0; i < d.ndim; ++i) p->vol *= d.lengths[i];
+  p->il2[0] = 1.0 / (d.lengths[0] * d.lengths[0]);
+  p->il2[1] = d.ndim == 3 ? 1.0 / (d.lengths[1] * d.lengths[1]) : 0.0;
+  p->il2[2] = 1.0 / (d.lengths[last] * d.lengths[last]);
+  p->dtype = d.dtype;
+  p->esz = d.dtype == GRF_F32 ? 4 : 8;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipGetDevice");
+  }
+  FieldRec rec;
+  if (grf::make_field_rec(d.cov_kind, d.ndim, p->vol, d.sigma, d.length_scale, d.nu, &rec) != 0) {
+    delete p;
+    return fail(GRF_EINVAL, "invalid covariance parameters");
+  }
+  grf_status st = make_table(p->n1, p->dtype, &p->tw_col1);
+  if (st == GRF_OK && d.ndim == 3) st = make_table(p->no, p->dtype, &p->tw_col2);
+  if (st == GRF_OK) st = make_table(p->nd, p->dtype, &p->tw_row);
+  if (st == GRF_OK) {
+    e = hipMalloc((void**)&p->rec_dev, sizeof(FieldRec));
+    if (e != hipSuccess) st = fail(GRF_ENOMEM, "hipMalloc of field record failed");
+    else {
+      e = hipMemcpy(p->rec_dev, &rec, sizeof(FieldRec), hipMemcpyHostToDevice);
+      if (e != hipSuccess) st = hip_fail(e, "record upload");
+    }
+  }
+  if (st != GRF_OK) {
+    grf_plan_destroy(p);
+    return st;
+  }
+  *out = p;
+  return GRF_OK;
+}
+
+grf_status grf_plan_destroy(grf_plan p) {
+  if (p == nullptr) return GRF_OK;
+  if (p->tw_col1) (void)hipFree(p->tw_col1);
+  if (p->tw_col2) (void)hipFree(p->tw_col2);
+  if (p->tw_row) (void)hipFree(p->tw_row);
+  if (p->rec_dev) (void)hipFree(p->rec_dev);
+  delete p;
+  return GRF_OK;
+}
+
+grf_status grf_workspace_size(grf_plan p, int64_t batch, int32_t op, size_t* bytes) {
+  if (p == nullptr || bytes == nullptr) return fail(GRF_EINVAL, "null argument");
+  if (batch < 0) return fail(GRF_EINVAL, "negative batch");
+  if (op != GRF_OP_SAMPLE && op != GRF_OP_BACKWARD) return fail(GRF_EINVAL, "unknown op");
+  *bytes = ws_layout(p, batch, op).total;
+  return GRF_OK;
+}
+
+grf_status grf_sample(grf_plan p, uint64_t seed, int64_t batch, const double* theta, void* out, void* workspace,
+                      size_t workspace_bytes, void* stream) {
+  return sample_impl(p, seed, nullptr, batch, theta, out, workspace, workspace_bytes, stream);
+}
+
+grf_status grf_sample_from_noise(grf_plan p, const void* noise, int64_t batch, const double* theta, void* out,
+                                 void* workspace, size_t workspace_bytes, void* stream) {
+  if (noise == nullptr && batch > 0) return fail(GRF_EINVAL, "null noise");
+  if (noise != nullptr && noise == out) return fail(GRF_EINVAL, "noise and output must not alias");
+  return sample_impl(p, 0, noise, batch, theta, out, workspace, workspace_bytes, stream);
+}
+
+grf_status grf_noise(grf_plan p, uint64_t seed, int64_t batch, void* noise_out, void* stream) {
+  if (p == nullptr) return fail(GRF_EINVAL, "null plan");
+  if (batch < 0) return fail(GRF_EINVAL, "negative batch");
+  if (batch == 0) return GRF_OK;
+  if (noise_out == nullptr) return fail(GRF_EINVAL, "null output");
+  const int tag = p->desc.alg == GRF_ALG_ONE_FFT ? 1 : 0;
+  hipError_t e = grf::launch_noise(p->dtype, seed, tag, (int)(p->P / p->nd), p->nd, (int)batch, noise_out,
+                                   (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "noise kernel");
+  return GRF_OK;
+}
+
+grf_status grf_backward(grf_plan p, uint64_t seed, const void* noise, int64_t batch, const double* theta,
+                        const void* grad_out, double* grad_theta, void* grad_noise, void* workspace,
+                        size_t workspace_bytes, void* stream) {
+  if (p == nullptr) return fail(GRF_EINVAL, "null plan");
+  if (p->desc.alg != GRF_ALG_ONE_FFT || p->d != 2)
+    return fail(GRF_EUNSUPPORTED, "adjoint implemented for the one-FFT algorithm with d = 2");
+  if (batch < 0) return fail(GRF_EINVAL, "negative batch");
+  if (batch == 0) return GRF_OK;
+  if (grad_out == nullptr || grad_theta == nullptr) return fail(GRF_EINVAL, "null gradient pointer");
+  if (batch > 0x7fffffff) return fail(GRF_EINVAL, "batch too large");
+  const WsLayout w = ws_layout(p, batch, GRF_OP_BACKWARD);
+  if (workspace == nullptr || workspace_bytes < w.total) return fail(GRF_EINVAL, "workspace too small");
+  grf_status st = check_stream_device(p);
+  if (st != GRF_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const FieldRec* recs;
+  int rstride;
+  st = field_records(p, theta, batch, ws + w.recs, w.partial, s, &recs, &rstride);
+  if (st != GRF_OK) return st;
+  Args a = base_args(p, batch);
+  a.recs = recs;
+  a.rec_stride = rstride;
+  a.seed = seed;
+  a.tag = 1;
+  // G = F[g]: last axis real-to-complex, then axis 1 forward inside the reduction pass
+  Args r = a;
+  r.data = ws + w.spec;
+  r.src = grad_out;
+  r.tw2 = p->tw_row;
+  r.rows = batch * (long long)p->n1;
+  st = run_pass(p, grf::PASS_ROW_R2C_LOAD, p->M, r, 0, batch, s);
+  if (st != GRF_OK) return st;
+  Args c = a;
+  c.data = ws + w.spec;
+  c.src = noise;
+  c.aux = grad_noise;
+  c.partial = (double*)(ws + w.partial);
+  c.tw = p->tw_col1;
+  c.stride_ax = p->M;
+  c.stride_fixed = p->M;
+  c.nfixed = 1;
+  st = run_pass(p, grf::PASS_COL_GRAD, p->n1, c, 0, batch, s);
+  if (st != GRF_OK) return st;
+  const grf::Geom g = grf::pass_geom(grf::PASS_COL_GRAD, p->dtype, p->n1);
+  const int ntile = (p->M + 2 * g.per_wg - 1) / (2 * g.per_wg);
+  hipError_t e = grf::launch_reduce_partials((const double*)(ws + w.partial), (int)batch, ntile, grad_theta, s);
+  if (e != hipSuccess) return hip_fail(e, "reduction");
+  return GRF_OK;
+}
+
+grf_status grf_debug_philox(uint64_t seed, const uint32_t* counters, int64_t n, uint32_t* out, void* stream) {
+  if (n < 0) return fail(GRF_EINVAL, "negative count");
+  if (n == 0) return GRF_OK;
+  if (counters == nullptr || out == nullptr) return fail(GRF_EINVAL, "null pointer");
+  hipError_t e = grf::launch_philox_raw(seed, counters, n, out, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "philox kernel");
+  return GRF_OK;
+}
+
+}  // extern "C"

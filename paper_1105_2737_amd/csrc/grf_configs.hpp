@@ -1,0 +1,58 @@
+// Compile-time schedule per transform length.  The radix order, threads per
+// transform and tile shapes here are the defaults the plan uses.
+#pragma once
+#include "grf_fft.hpp"
+
+namespace grf {
+
+// Column (leading-axis) transforms.
+template <int L> struct ColCfg;
+#define GRF_COLCFG(L_, CP32_, CP64_, PAD_, ...)            \
+  template <> struct ColCfg<L_> {                          \
+    using Rad = Radices<__VA_ARGS__>;                      \
+    static constexpr int CP32 = CP32_, CP64 = CP64_, PAD = PAD_; \
+  };
+GRF_COLCFG(4, 16, 16, 1, 4)
+GRF_COLCFG(8, 16, 16, 1, 8)
+GRF_COLCFG(12, 16, 16, 1, 3, 4)
+GRF_COLCFG(16, 16, 16, 1, 4, 4)
+GRF_COLCFG(24, 16, 16, 1, 4, 6)
+GRF_COLCFG(32, 16, 16, 1, 8, 4)
+GRF_COLCFG(48, 16, 8, 1, 6, 8)
+GRF_COLCFG(64, 16, 8, 1, 8, 8)
+GRF_COLCFG(96, 16, 8, 1, 8, 12)
+GRF_COLCFG(128, 16, 8, 1, 16, 8)
+GRF_COLCFG(180, 8, 4, 1, 5, 6, 6)
+GRF_COLCFG(256, 8, 4, 1, 16, 16)
+GRF_COLCFG(360, 8, 4, 1, 8, 5, 9)
+GRF_COLCFG(500, 4, 2, 1, 10, 10, 5)
+GRF_COLCFG(512, 8, 4, 1, 8, 8, 8)
+GRF_COLCFG(1000, 4, 2, 0, 10, 10, 10)
+GRF_COLCFG(1024, 4, 2, 0, 16, 8, 8)
+#undef GRF_COLCFG
+
+// Row (last-axis) transforms of half-length M.
+template <int M> struct RowCfg;
+#define GRF_ROWCFG(M_, RB32_, RB64_, ...)                  \
+  template <> struct RowCfg<M_> {                          \
+    using Rad = Radices<__VA_ARGS__>;                      \
+    static constexpr int RB32 = RB32_, RB64 = RB64_, PADR = 0; \
+  };
+GRF_ROWCFG(4, 64, 64, 4)
+GRF_ROWCFG(8, 64, 64, 8)
+GRF_ROWCFG(12, 32, 32, 3, 4)
+GRF_ROWCFG(16, 32, 32, 4, 4)
+GRF_ROWCFG(24, 32, 32, 4, 6)
+GRF_ROWCFG(32, 32, 32, 8, 4)
+GRF_ROWCFG(48, 16, 16, 6, 8)
+GRF_ROWCFG(64, 16, 16, 8, 8)
+GRF_ROWCFG(96, 16, 8, 8, 12)
+GRF_ROWCFG(128, 16, 8, 16, 8)
+GRF_ROWCFG(180, 4, 4, 5, 6, 6)
+GRF_ROWCFG(256, 16, 8, 16, 16)
+GRF_ROWCFG(360, 4, 4, 8, 5, 9)
+GRF_ROWCFG(500, 4, 2, 10, 10, 5)
+GRF_ROWCFG(512, 4, 4, 8, 8, 8)
+#undef GRF_ROWCFG
+
+}  // namespace grf

@@ -1,0 +1,104 @@
+// Noise generation and spectral filter, device side.
+//
+// * Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): the counter-based
+//   generator that plays the role of the paper's R() (Section 3, Input 4 of
+//   each algorithm).  Field b uses key seed+b; the block with counter
+//   (q, row, tag, 0) supplies the four normals of slots 4q..4q+3 of that row.
+// * Box & Muller (1958) turns the four uniforms (x + 1/2) 2^-32 into four
+//   independent N(0,1) values.
+// * The filter h_k = sqrt(S(p_k)/|D|) with the spectral densities of the
+//   supported covariance families (Section 2: C is the Fourier transform of
+//   gamma = S); its parameters arrive as a per-field record computed in
+//   float64 (FieldRec, grf_common.hpp).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "grf_common.hpp"
+#include "grf_fft.hpp"
+
+namespace grf {
+
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Box-Muller on one pair of 32-bit outputs, float32 arithmetic.
+// -ln u is taken from the hardware log2 except in the top 2^-7 of the
+// interval, where u = 1 - d cannot be held in float32; there the series
+// -ln(1-d) = d + d^2/2 + d^3/3 + d^4/4 (+ O(d^5) < 2^-37 relative) is used
+// with d computed from the complement ~x, which is exact.
+__device__ __forceinline__ void box_muller(uint32_t xa, uint32_t xb, float& n0, float& n1) {
+  const float u = fmaf((float)xa, 0x1p-32f, 0x1p-33f);
+  const float d = fmaf((float)(~xa), 0x1p-32f, 0x1p-33f);
+  const float lg = -__builtin_amdgcn_logf(u) * 0.693147180559945309f;
+  const float ser = d * fmaf(d, fmaf(d, fmaf(d, 0.25f, 0.333333343f), 0.5f), 1.0f);
+  const float nl = (xa >= 0xFE000000u) ? ser : lg;
+  const float r = __builtin_amdgcn_sqrtf(2.0f * nl);
+  const float t = fmaf((float)xb, 0x1p-32f, 0x1p-33f);   // revolutions
+  n0 = r * __builtin_amdgcn_cosf(t);
+  n1 = r * __builtin_amdgcn_sinf(t);
+}
+
+// float64 version: the uniforms are exact in float64.
+__device__ __forceinline__ void box_muller(uint32_t xa, uint32_t xb, double& n0, double& n1) {
+  const double u = ((double)xa + 0.5) * 0x1p-32;
+  const double t = ((double)xb + 0.5) * 0x1p-32;
+  const double r = sqrt(-2.0 * log(u));
+  double s, c;
+  sincospi(2.0 * t, &s, &c);
+  n0 = r * c;
+  n1 = r * s;
+}
+
+template <typename T>
+__device__ __forceinline__ void normals4(uint32_t q, uint32_t row, uint32_t tag, uint32_t k0, uint32_t k1, T* z) {
+  const uint4 x = philox4x32_10(make_uint4(q, row, tag, 0u), k0, k1);
+  box_muller(x.x, x.y, z[0], z[1]);
+  box_muller(x.z, x.w, z[2], z[3]);
+}
+
+// Per-field filter constants converted once to the working precision.
+template <typename T> struct Filt {
+  int kind;
+  T c0, a, b, e;
+};
+
+template <typename T>
+__device__ __forceinline__ Filt<T> load_filt(const FieldRec& r, double extra_scale) {
+  Filt<T> f;
+  f.kind = r.kind;
+  f.c0 = (T)(r.c0 * extra_scale);
+  f.a = (T)r.a;
+  f.b = (T)r.b;
+  f.e = (T)r.e;
+  if (r.kind == COV_GAUSSIAN && sizeof(T) == 4) f.e = (T)(r.e * 1.4426950408889634);  // exp -> exp2
+  return f;
+}
+
+// h at squared frequency p2 (cycles^2).
+__device__ __forceinline__ float filt_h(const Filt<float>& f, float p2) {
+  if (f.kind == COV_GAUSSIAN) return f.c0 * __builtin_amdgcn_exp2f(f.e * p2);
+  const float u = fmaf(f.b, p2, f.a);
+  return f.c0 * __builtin_amdgcn_exp2f(f.e * __builtin_amdgcn_logf(u));
+}
+__device__ __forceinline__ double filt_h(const Filt<double>& f, double p2) {
+  if (f.kind == COV_GAUSSIAN) return f.c0 * exp(f.e * p2);
+  const double u = fma(f.b, p2, f.a);
+  return f.c0 * exp(f.e * log(u));
+}
+
+// wrapped frequency index kappa(k) = k (k < n/2), k - n (k >= n/2)
+__device__ __forceinline__ int wrapk(int k, int n) { return (2 * k < n) ? k : k - n; }
+
+}  // namespace grf

@@ -1,0 +1,64 @@
+// Per-length launch configurations and the dispatch interface between the
+// host library and the kernel translation units.
+//
+// Column passes: Rad = radix order (first radix R_0 sets NT = L / R_0 threads
+// per column), CP = column pairs per workgroup (float32 / float64), PAD = LDS
+// row padding in column pairs.  Row passes: RB rows per workgroup.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "grf_common.hpp"
+
+namespace grf {
+
+struct Args;
+
+// Supported transform lengths (2^a 3^b 5^c):
+//   column (leading-axis) lengths: GRF_COL_LENGTHS
+//   row half-lengths M = N_d / 2:  GRF_ROW_LENGTHS
+#define GRF_COL_LENGTHS(X) X(4) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(180) X(256) X(360) X(500) X(512) X(1000) X(1024)
+#define GRF_ROW_LENGTHS(X) X(4) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(180) X(256) X(360) X(500) X(512)
+
+enum PassKind {
+  PASS_COL_GEN_INV = 0,   // noise generation + inverse transform (one-FFT algorithm, axis 1)
+  PASS_COL_LOAD_INV = 1,  // inverse transform of a stored spectrum (middle axis)
+  PASS_COL_LOAD_FWD = 2,  // forward transform (adjoint, middle axis)
+  PASS_COL_FILTER = 3,    // forward, filter, inverse (two-FFT algorithm, axis 1)
+  PASS_COL_GRAD = 4,      // forward transform + adjoint reduction (axis 1)
+  PASS_ROW_C2R = 5,       // last axis, complex-to-real inverse
+  PASS_ROW_R2C_GEN = 6,   // last axis, white noise + real-to-complex forward
+  PASS_ROW_R2C_LOAD = 7,  // last axis, stored real rows + real-to-complex forward
+};
+
+// Workgroup geometry of a pass at a given length (for grid sizing).
+struct Geom {
+  int threads;   // threads per workgroup
+  int per_wg;    // column pairs (column passes) or rows (row passes) per workgroup
+};
+
+bool col_length_supported(int L);
+bool row_length_supported(int M);
+Geom pass_geom(int pass, int dtype, int L);
+
+// Launch one pass over `nblocks` workgroups.  dtype: 0 = float32, 1 = float64.
+hipError_t launch_pass(int pass, int dtype, int L, const Args& a, long long nblocks, hipStream_t s);
+
+// Per-dtype implementations (defined in the kernel translation units).
+hipError_t launch_col_f32(int pass, int L, const Args& a, long long nblocks, hipStream_t s);
+hipError_t launch_col_f64(int pass, int L, const Args& a, long long nblocks, hipStream_t s);
+hipError_t launch_row_f32(int pass, int M, const Args& a, long long nblocks, hipStream_t s);
+hipError_t launch_row_f64(int pass, int M, const Args& a, long long nblocks, hipStream_t s);
+Geom geom_col_f32(int L);
+Geom geom_col_f64(int L);
+Geom geom_row_f32(int M);
+Geom geom_row_f64(int M);
+
+// helper kernels (grf_util.hip)
+hipError_t launch_prep_recs(const double* theta, int batch, int kind, int d, double vol, FieldRec* out, int* err,
+                            hipStream_t s);
+hipError_t launch_reduce_partials(const double* partial, int batch, int nper, double* grad, hipStream_t s);
+hipError_t launch_philox_raw(unsigned long long seed, const uint32_t* ctr, long long n, uint32_t* out, hipStream_t s);
+hipError_t launch_noise(int dtype, unsigned long long seed, int tag, int rows, int nd, int batch, void* out,
+                        hipStream_t s);
+
+}  // namespace grf

@@ -1,0 +1,642 @@
+// Kernel templates of the sampling path.
+//
+// Data layout in HBM (per field, complex elements of the working precision):
+// the "packed half-spectrum" [N_1][O][M], M = N_d/2, O = N_2 for d = 3 and 1
+// for d = 2.  Entry (k, m) for 1 <= m < M is A(k, m); slot m = 0 holds the two
+// self-mirrored planes k_d = 0 and k_d = N_d/2 as A(k, 0) + i A(k, N_d/2).
+// Because the inverse transforms along the leading axes turn each of those
+// planes into a real array, the packing survives them, and the last-axis
+// complex-to-real pass unpacks it.  The packed spectrum occupies exactly the
+// bytes of the real output field, so the whole pipeline runs in place in the
+// output buffer.
+//
+// Passes (one kernel each):
+//   col  : transform along a leading axis over column tiles (CP column pairs
+//          per workgroup, NT threads per column); source = Hermitian noise
+//          generation (the one-FFT algorithm's data arrangement, Section 3) or
+//          a global load; direction +1 / -1.
+//   colf : forward transform, spectral filter, inverse transform along axis 1
+//          (two-FFT algorithm, Section 3).
+//   colg : forward transform along axis 1 and the adjoint reduction.
+//   row  : last-axis complex-to-real (inverse) or real-to-complex (forward,
+//          with noise generation or a global load), one row per NT threads.
+#pragma once
+#include "grf_device.hpp"
+
+namespace grf {
+
+template <typename T, int NC> struct alignas(sizeof(C<T>) * NC) Vec { C<T> v[NC]; };
+
+struct Args {
+  void* data;                 // packed spectrum / output (in place)
+  const void* src;            // optional input: noise z or upstream gradient g
+  void* aux;                  // optional output: dL/dz
+  double* partial;            // adjoint partial sums [batch][no][ntile][3]
+  const FieldRec* recs;       // per-field constants
+  const void* tw;             // twiddle table W_L of the transform length (complex)
+  const void* tw2;            // row passes: table W_{N_d} (complex)
+  unsigned long long seed;
+  long long field_stride;     // complex elements per field
+  long long stride_ax;        // complex stride along the transformed axis
+  long long stride_fixed;     // complex stride of the fixed (tile) index
+  long long rows;             // row passes: total number of rows
+  double il2[3];              // 1/l^2 of axis 1, middle axis, last axis
+  double scale;               // extra factor folded into h (1/sqrt(P) for the two-FFT algorithm)
+  int rec_stride;             // 0: one record for all fields, 1: one per field
+  int batch;
+  int n1, no, nd, M;          // N_1, O (middle length, 1 if d = 2), N_d, N_d/2
+  int ntile;                  // column tiles per fixed index
+  int nfixed;                 // number of fixed indices
+  int rows_per_field;
+  int tag;
+};
+
+// ---------------------------------------------------------------------------
+// Block FFT engine: NC interleaved length-L transforms per thread group.
+// x[c][b*R + m] holds the inputs of butterfly b (j = t + b NT) of the current
+// stage.  Stage 0 inputs must be in registers (NB(0) == 1, NT = L / R_0).
+template <typename T, int L, class Rad, int NT, int NC, int TWS>
+struct Eng {
+  using V = C<T>;
+  using E = Vec<T, NC>;
+  static constexpr int S = Rad::count;
+  static constexpr int NB(int s) { return (L / Rad::get(s) + NT - 1) / NT; }
+  static constexpr int reg() {
+    int r = 0;
+    for (int s = 0; s < S; ++s) r = (NB(s) * Rad::get(s) > r) ? NB(s) * Rad::get(s) : r;
+    return r;
+  }
+  static constexpr int REG = reg();
+  static_assert(Rad::prod() == L, "radices must multiply to L");
+  static_assert(L / Rad::get(0) == NT, "stage 0 must give one butterfly per thread");
+
+  template <int s, int DIR, class Lds, class Out>
+  __device__ __forceinline__ static void stage(V (&x)[NC][REG], int t, bool act, Lds lds, const V* tw, Out out) {
+    constexpr int Rs = Rad::get(s), Ns = Rad::ns(s), nb = NB(s), LR = L / Rs;
+    constexpr bool last = (s == S - 1);
+    constexpr int TSTEP = L / (Ns * Rs);
+    if (act) {
+#pragma unroll
+      for (int b = 0; b < nb; ++b) {
+        const int j = t + b * NT;
+        if (nb * NT == LR || j < LR) {
+          const int k = j % Ns;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            V y[Rs];
+#pragma unroll
+            for (int m = 0; m < Rs; ++m) y[m] = x[c][b * Rs + m];
+            if constexpr (Ns > 1) {
+#pragma unroll
+              for (int m = 1; m < Rs; ++m) y[m] = ctw<DIR>(y[m], tw[TWS * (m * k * TSTEP)]);
+            }
+            Dft<Rs, DIR, V>::run(y);
+#pragma unroll
+            for (int m = 0; m < Rs; ++m) x[c][b * Rs + m] = y[m];
+          }
+          if constexpr (last) {
+#pragma unroll
+            for (int m = 0; m < Rs; ++m) {
+              E e;
+#pragma unroll
+              for (int c = 0; c < NC; ++c) e.v[c] = x[c][b * Rs + m];
+              out(j + m * LR, e);
+            }
+          } else {
+            const int base = (j / Ns) * Ns * Rs + k;
+#pragma unroll
+            for (int m = 0; m < Rs; ++m) {
+              E e;
+#pragma unroll
+              for (int c = 0; c < NC; ++c) e.v[c] = x[c][b * Rs + m];
+              lds(base + m * Ns) = e;
+            }
+          }
+        }
+      }
+    }
+    if constexpr (!last) {
+      __syncthreads();
+      constexpr int R2 = Rad::get(s + 1), nb2 = NB(s + 1), LR2 = L / R2;
+      if (act) {
+#pragma unroll
+        for (int b = 0; b < nb2; ++b) {
+          const int j = t + b * NT;
+          if (nb2 * NT == LR2 || j < LR2) {
+#pragma unroll
+            for (int m = 0; m < R2; ++m) {
+              const E e = lds(j + m * LR2);
+#pragma unroll
+              for (int c = 0; c < NC; ++c) x[c][b * R2 + m] = e.v[c];
+            }
+          }
+        }
+      }
+      __syncthreads();
+      stage<s + 1, DIR>(x, t, act, lds, tw, out);
+    }
+  }
+
+  template <int DIR, class Lds, class Out>
+  __device__ __forceinline__ static void run(V (&x)[NC][REG], int t, bool act, Lds lds, const V* tw, Out out) {
+    stage<0, DIR>(x, t, act, lds, tw, out);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Hermitian noise + filter for the column pair (m0, m0 + 1) of row k1 (fixed
+// middle index o).  See the layout note at the top: m0 = 0 yields the packed
+// plane slot.  z comes from Philox (zsrc == nullptr) or from a noise array
+// laid out like the field.
+template <typename T>
+__device__ __forceinline__ void load_z4(const Args& a, const T* zsrc, int b, int row, int m0, uint32_t k0,
+                                        uint32_t k1, T* z) {
+  if (zsrc == nullptr) {
+    normals4<T>((uint32_t)(m0 >> 1), (uint32_t)row, (uint32_t)a.tag, k0, k1, z);
+  } else {
+    const T* p = zsrc + (long long)b * a.field_stride * 2 + (long long)row * a.nd + 2 * m0;
+    z[0] = p[0];
+    z[1] = p[1];
+    const bool two = (m0 + 1) < a.M;
+    z[2] = two ? p[2] : (T)0;
+    z[3] = two ? p[3] : (T)0;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void gen_pair(const Args& a, const Filt<T>& f, const T* zsrc, int b, uint32_t k0,
+                                         uint32_t k1, int kk1, int o, int m0, C<T>& A0, C<T>& A1) {
+  const int row = kk1 * a.no + o;
+  T z[4];
+  load_z4<T>(a, zsrc, b, row, m0, k0, k1, z);
+  const int q1 = wrapk(kk1, a.n1), qo = wrapk(o, a.no);
+  const T p2b = (T)(q1 * q1) * (T)a.il2[0] + (T)(qo * qo) * (T)a.il2[1];
+  const T il2d = (T)a.il2[2];
+  const T s = (T)0.70710678118654752440;
+  const T h1 = filt_h(f, p2b + (T)((m0 + 1) * (m0 + 1)) * il2d);
+  A1 = mk<T>(h1 * s * z[2], h1 * s * z[3]);
+  if (m0 > 0) {
+    const T h0 = filt_h(f, p2b + (T)(m0 * m0) * il2d);
+    A0 = mk<T>(h0 * s * z[0], h0 * s * z[1]);
+  } else {
+    const int nrow = ((a.n1 - kk1) % a.n1) * a.no + (a.no - o) % a.no;
+    const T hz = filt_h(f, p2b);
+    const T hn = filt_h(f, p2b + (T)a.M * (T)a.M * il2d);
+    C<T> x0, xn;
+    if (nrow == row) {
+      x0 = mk<T>(z[0], (T)0);
+      xn = mk<T>(z[1], (T)0);
+    } else {
+      T zz[4];
+      load_z4<T>(a, zsrc, b, nrow, 0, k0, k1, zz);
+      if (row < nrow) {
+        x0 = mk<T>(s * z[0], s * z[1]);
+        xn = mk<T>(s * zz[0], s * zz[1]);
+      } else {
+        x0 = mk<T>(s * zz[0], -s * zz[1]);
+        xn = mk<T>(s * z[0], -s * z[1]);
+      }
+    }
+    // A(k, 0) + i A(k, N_d/2)
+    A0 = mk<T>(hz * x0.x - hn * xn.y, hz * x0.y + hn * xn.x);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column pass over a leading axis.
+enum { SRC_GEN = 0, SRC_LOAD = 1 };
+
+template <typename T, int L, class Rad, int CP, int PAD, int SRC, int DIR>
+__global__ void __launch_bounds__(((L / Rad::get(0)) * CP + 63) / 64 * 64)
+k_col(Args a) {
+  using V = C<T>;
+  using E = Vec<T, 2>;
+  constexpr int NT = L / Rad::get(0);
+  constexpr int RS = CP + PAD;
+  constexpr int R0 = Rad::get(0);
+  using EN = Eng<T, L, Rad, NT, 2, 1>;
+  __shared__ E sm[L * RS];
+  __shared__ V tw[L];
+  const int tid = threadIdx.x;
+  const int cp = tid % CP;
+  const int t = tid / CP;
+  int bid = blockIdx.x;
+  const int tile = bid % a.ntile;
+  bid /= a.ntile;
+  const int fx = bid % a.nfixed;
+  const int b = bid / a.nfixed;
+  for (int i = tid; i < L; i += blockDim.x) tw[i] = ((const V*)a.tw)[i];
+  const int m0 = (tile * CP + cp) * 2;
+  const bool act = (t < NT) && (m0 < a.M);
+  const bool two = (m0 + 1) < a.M;
+  V* base = (V*)a.data + (long long)b * a.field_stride + (long long)fx * a.stride_fixed + m0;
+  V x[2][EN::REG];
+  if (act) {
+    if constexpr (SRC == SRC_GEN) {
+      const FieldRec& rec = a.recs[b * a.rec_stride];
+      const Filt<T> f = load_filt<T>(rec, a.scale);
+      const unsigned long long key = a.seed + (unsigned long long)b;
+      const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
+      const T* zsrc = (const T*)a.src;
+#pragma unroll
+      for (int m = 0; m < R0; ++m) gen_pair<T>(a, f, zsrc, b, k0, k1, t + m * NT, fx, m0, x[0][m], x[1][m]);
+    } else {
+#pragma unroll
+      for (int m = 0; m < R0; ++m) {
+        const V* p = base + (long long)(t + m * NT) * a.stride_ax;
+        x[0][m] = p[0];
+        x[1][m] = two ? p[1] : mk<T>((T)0, (T)0);
+      }
+    }
+  }
+  auto lds = [&](int i) -> E& { return sm[i * RS + cp]; };
+  auto out = [&](int i, const E& e) {
+    V* p = base + (long long)i * a.stride_ax;
+    p[0] = e.v[0];
+    if (two) p[1] = e.v[1];
+  };
+  EN::template run<DIR>(x, t, act, lds, tw, out);
+}
+
+// ---------------------------------------------------------------------------
+// Two-FFT algorithm, column stage: forward transform along axis 1, multiply by
+// h / sqrt(P) (separating the packed planes first), inverse transform.
+template <typename T, int L, class Rad, int CP, int PAD>
+__global__ void __launch_bounds__(((L / Rad::get(0)) * CP + 63) / 64 * 64)
+k_colf(Args a) {
+  using V = C<T>;
+  using E = Vec<T, 2>;
+  constexpr int NT = L / Rad::get(0);
+  constexpr int RS = CP + PAD;
+  constexpr int R0 = Rad::get(0);
+  using EN = Eng<T, L, Rad, NT, 2, 1>;
+  __shared__ E sm[L * RS];
+  __shared__ V tw[L];
+  const int tid = threadIdx.x;
+  const int cp = tid % CP;
+  const int t = tid / CP;
+  int bid = blockIdx.x;
+  const int tile = bid % a.ntile;
+  const int b = bid / a.ntile;
+  for (int i = tid; i < L; i += blockDim.x) tw[i] = ((const V*)a.tw)[i];
+  const int m0 = (tile * CP + cp) * 2;
+  const bool act = (t < NT) && (m0 < a.M);
+  const bool two = (m0 + 1) < a.M;
+  V* base = (V*)a.data + (long long)b * a.field_stride + m0;
+  V x[2][EN::REG];
+  if (act) {
+#pragma unroll
+    for (int m = 0; m < R0; ++m) {
+      const V* p = base + (long long)(t + m * NT) * a.stride_ax;
+      x[0][m] = p[0];
+      x[1][m] = two ? p[1] : mk<T>((T)0, (T)0);
+    }
+  }
+  auto lds = [&](int i) -> E& { return sm[i * RS + cp]; };
+  auto to_lds = [&](int i, const E& e) { sm[i * RS + cp] = e; };
+  EN::template run<-1>(x, t, act, lds, tw, to_lds);
+  __syncthreads();
+  if (act) {
+    const Filt<T> f = load_filt<T>(a.recs[b * a.rec_stride], a.scale);
+    const T il2d = (T)a.il2[2];
+#pragma unroll
+    for (int m = 0; m < R0; ++m) {
+      const int k1 = t + m * NT;
+      const int q1 = wrapk(k1, L);
+      const T p2b = (T)(q1 * q1) * (T)a.il2[0];
+      const E e = sm[k1 * RS + cp];
+      const T h1 = filt_h(f, p2b + (T)((m0 + 1) * (m0 + 1)) * il2d);
+      x[1][m] = cscale(e.v[1], h1);
+      if (m0 > 0) {
+        const T h0 = filt_h(f, p2b + (T)(m0 * m0) * il2d);
+        x[0][m] = cscale(e.v[0], h0);
+      } else {
+        const V w = e.v[0];
+        const V wm = sm[((L - k1) % L) * RS + cp].v[0];
+        // F[X0] = (w + conj wm)/2, F[XN] = (w - conj wm)/(2i)
+        const V f0 = mk<T>((T)0.5 * (w.x + wm.x), (T)0.5 * (w.y - wm.y));
+        const V fn = mk<T>((T)0.5 * (w.y + wm.y), (T)-0.5 * (w.x - wm.x));
+        const T hz = filt_h(f, p2b);
+        const T hn = filt_h(f, p2b + (T)a.M * (T)a.M * il2d);
+        const V a0 = cscale(f0, hz), an = cscale(fn, hn);
+        x[0][m] = mk<T>(a0.x - an.y, a0.y + an.x);
+      }
+    }
+  }
+  __syncthreads();
+  auto out = [&](int i, const E& e) {
+    V* p = base + (long long)i * a.stride_ax;
+    p[0] = e.v[0];
+    if (two) p[1] = e.v[1];
+  };
+  EN::template run<+1>(x, t, act, lds, tw, out);
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the one-FFT algorithm, column stage (d = 2): forward transform of
+// the row-transformed upstream gradient along axis 1 gives G = F[g]; each
+// entry then regenerates its noise xi and adds
+//   w_k (h_k / 2) dlogS/dtheta Re(xi_k conj G_k)
+// (w = 2 for interior columns, 1 in the two planes) to per-workgroup float64
+// partial sums; dL/dz is written through the Hermitian arrangement if asked.
+template <typename T, int L, class Rad, int CP, int PAD>
+__global__ void __launch_bounds__(((L / Rad::get(0)) * CP + 63) / 64 * 64)
+k_colg(Args a) {
+  using V = C<T>;
+  using E = Vec<T, 2>;
+  constexpr int NT = L / Rad::get(0);
+  constexpr int RS = CP + PAD;
+  constexpr int R0 = Rad::get(0);
+  constexpr int NW = (NT * CP + 63) / 64;
+  using EN = Eng<T, L, Rad, NT, 2, 1>;
+  __shared__ E sm[L * RS];
+  __shared__ V tw[L];
+  __shared__ double red[3][NW];
+  const int tid = threadIdx.x;
+  const int cp = tid % CP;
+  const int t = tid / CP;
+  int bid = blockIdx.x;
+  const int tile = bid % a.ntile;
+  const int b = bid / a.ntile;
+  for (int i = tid; i < L; i += blockDim.x) tw[i] = ((const V*)a.tw)[i];
+  const int m0 = (tile * CP + cp) * 2;
+  const bool act = (t < NT) && (m0 < a.M);
+  const bool two = (m0 + 1) < a.M;
+  V* base = (V*)a.data + (long long)b * a.field_stride + m0;
+  V x[2][EN::REG];
+  if (act) {
+#pragma unroll
+    for (int m = 0; m < R0; ++m) {
+      const V* p = base + (long long)(t + m * NT) * a.stride_ax;
+      x[0][m] = p[0];
+      x[1][m] = two ? p[1] : mk<T>((T)0, (T)0);
+    }
+  }
+  auto lds = [&](int i) -> E& { return sm[i * RS + cp]; };
+  auto to_lds = [&](int i, const E& e) { sm[i * RS + cp] = e; };
+  EN::template run<-1>(x, t, act, lds, tw, to_lds);
+  __syncthreads();
+  double acc0 = 0, acc1 = 0, acc2 = 0;
+  if (act) {
+    const FieldRec& rec = a.recs[b * a.rec_stride];
+    const Filt<T> f = load_filt<T>(rec, 1.0);
+    const unsigned long long key = a.seed + (unsigned long long)b;
+    const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
+    const T* zsrc = (const T*)a.src;
+    T* gz = (T*)a.aux;
+    const double il2d = a.il2[2];
+    const double s2 = 1.4142135623730950488;
+    // d log S / d theta at squared frequency p2 (float64)
+    auto dlog = [&](double p2, double& dl, double& dn) {
+      if (rec.kind == COV_GAUSSIAN) {
+        dl = rec.gl0 + rec.gl1 * p2;
+        dn = 0.0;
+      } else {
+        const double u = rec.a + rec.b * p2;
+        const double iu = 1.0 / u;
+        dl = rec.gl0 + rec.gl1 * iu;
+        dn = rec.has_nu ? (rec.gn0 - log(u) - rec.gn1 * iu) : 0.0;
+      }
+    };
+    auto add = [&](double w, double h, double p2, V xi, V G) {
+      double dl, dn;
+      dlog(p2, dl, dn);
+      const double c = w * 0.5 * h * ((double)xi.x * (double)G.x + (double)xi.y * (double)G.y);
+      acc0 += c * rec.gs;
+      acc1 += c * dl;
+      acc2 += c * dn;
+    };
+    const T s = (T)0.70710678118654752440;
+#pragma unroll
+    for (int m = 0; m < R0; ++m) {
+      const int kk1 = t + m * NT;
+      const int row = kk1;
+      T z[4];
+      load_z4<T>(a, zsrc, b, row, m0, k0, k1, z);
+      const int q1 = wrapk(kk1, L);
+      const double p2b = (double)(q1 * q1) * a.il2[0];
+      const E e = sm[kk1 * RS + cp];
+      T* gzr = gz ? gz + (long long)b * a.field_stride * 2 + (long long)row * a.nd + 2 * m0 : nullptr;
+      if (two) {
+        const double p2 = p2b + (double)((m0 + 1) * (m0 + 1)) * il2d;
+        const T h = filt_h(f, (T)p2);
+        add(2.0, (double)h, p2, mk<T>(s * z[2], s * z[3]), e.v[1]);
+        if (gzr) {
+          gzr[2] = (T)(s2 * (double)h * (double)e.v[1].x);
+          gzr[3] = (T)(s2 * (double)h * (double)e.v[1].y);
+        }
+      }
+      if (m0 > 0) {
+        const double p2 = p2b + (double)(m0 * m0) * il2d;
+        const T h = filt_h(f, (T)p2);
+        add(2.0, (double)h, p2, mk<T>(s * z[0], s * z[1]), e.v[0]);
+        if (gzr) {
+          gzr[0] = (T)(s2 * (double)h * (double)e.v[0].x);
+          gzr[1] = (T)(s2 * (double)h * (double)e.v[0].y);
+        }
+      } else {
+        const V w = e.v[0];
+        const V wm = sm[((L - kk1) % L) * RS + cp].v[0];
+        const V g0 = mk<T>((T)0.5 * (w.x + wm.x), (T)0.5 * (w.y - wm.y));
+        const V gn = mk<T>((T)0.5 * (w.y + wm.y), (T)-0.5 * (w.x - wm.x));
+        const int nrow = (L - kk1) % L;
+        const double p2n = p2b + (double)a.M * (double)a.M * il2d;
+        const T hz = filt_h(f, (T)p2b);
+        const T hn = filt_h(f, (T)p2n);
+        V x0, xn;
+        if (nrow == row) {
+          x0 = mk<T>(z[0], (T)0);
+          xn = mk<T>(z[1], (T)0);
+          if (gzr) {
+            gzr[0] = (T)((double)hz * (double)g0.x);
+            gzr[1] = (T)((double)hn * (double)gn.x);
+          }
+        } else {
+          T zz[4];
+          load_z4<T>(a, zsrc, b, nrow, 0, k0, k1, zz);
+          if (row < nrow) {
+            x0 = mk<T>(s * z[0], s * z[1]);
+            xn = mk<T>(s * zz[0], s * zz[1]);
+            if (gzr) {
+              gzr[0] = (T)(s2 * (double)hz * (double)g0.x);
+              gzr[1] = (T)(s2 * (double)hz * (double)g0.y);
+            }
+          } else {
+            x0 = mk<T>(s * zz[0], -s * zz[1]);
+            xn = mk<T>(s * z[0], -s * z[1]);
+            if (gzr) {   // slots of a mirrored row carry the Nyquist plane of its partner
+              gzr[0] = (T)(s2 * (double)hn * (double)gn.x);
+              gzr[1] = (T)(-s2 * (double)hn * (double)gn.y);
+            }
+          }
+        }
+        add(1.0, (double)hz, p2b, x0, g0);
+        add(1.0, (double)hn, p2n, xn, gn);
+      }
+    }
+  }
+  // workgroup reduction in a fixed order (deterministic)
+  for (int off = 32; off > 0; off >>= 1) {
+    acc0 += __shfl_xor(acc0, off);
+    acc1 += __shfl_xor(acc1, off);
+    acc2 += __shfl_xor(acc2, off);
+  }
+  const int lane = tid & 63, wv = tid >> 6;
+  if (lane == 0) {
+    red[0][wv] = acc0;
+    red[1][wv] = acc1;
+    red[2][wv] = acc2;
+  }
+  __syncthreads();
+  if (tid < 3) {
+    double sacc = 0;
+    for (int w = 0; w < NW; ++w) sacc += red[tid][w];
+    a.partial[((long long)b * a.ntile + tile) * 3 + tid] = sacc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Last-axis pass: complex-to-real inverse transform of packed rows.
+// Row data X_k (k = 0..M-1, X_0 slot = (X_0, X_M)) become
+//   Z_k = E_k + i O_k,  E_k = X_k + conj X_{M-k},  O_k = (X_k - conj X_{M-k}) w^k,
+// w = exp(2 pi i / N_d); z = inverse length-M transform of Z; and
+// x[2n] = Re z_n, x[2n+1] = Im z_n.
+template <typename T, int M, class Rad, int RB, int PADR>
+__global__ void __launch_bounds__(((M / Rad::get(0)) * RB + 63) / 64 * 64)
+k_row_c2r(Args a) {
+  using V = C<T>;
+  using E = Vec<T, 1>;
+  constexpr int NT = M / Rad::get(0);
+  constexpr int RSR = M + PADR;
+  using EN = Eng<T, M, Rad, NT, 1, 2>;
+  __shared__ E sm[RB * RSR];
+  __shared__ V tw[2 * M];
+  const int tid = threadIdx.x;
+  const int r = tid / NT;
+  const int t = tid % NT;
+  const long long row0 = (long long)blockIdx.x * RB;
+  const long long left = a.rows - row0;
+  const int nrows = left < RB ? (int)left : RB;
+  V* g = (V*)a.data + row0 * M;
+  for (int i = tid; i < nrows * M; i += blockDim.x) sm[(i / M) * RSR + (i % M)].v[0] = g[i];
+  for (int i = tid; i < 2 * M; i += blockDim.x) tw[i] = ((const V*)a.tw2)[i];
+  __syncthreads();
+  const bool act = (r < nrows) && (t < NT);
+  if (act) {
+    E* rowp = sm + r * RSR;
+    for (int k = t; 2 * k <= M; k += NT) {
+      if (k == 0) {
+        const V x0 = rowp[0].v[0];
+        rowp[0].v[0] = mk<T>(x0.x + x0.y, x0.x - x0.y);
+      } else {
+        const int km = M - k;
+        const V xk = rowp[k].v[0], xm = rowp[km].v[0];
+        const V wk = tw[k], wm = tw[km];
+        const V ek = cadd(xk, cconj(xm));
+        const V ok = cmul(csub(xk, cconj(xm)), wk);
+        const V zk = mk<T>(ek.x - ok.y, ek.y + ok.x);
+        rowp[k].v[0] = zk;
+        if (km != k) {
+          const V em = cadd(xm, cconj(xk));
+          const V om = cmul(csub(xm, cconj(xk)), wm);
+          rowp[km].v[0] = mk<T>(em.x - om.y, em.y + om.x);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  constexpr int R0 = Rad::get(0);
+  V x[1][EN::REG];
+  if (act) {
+#pragma unroll
+    for (int m = 0; m < R0; ++m) x[0][m] = sm[r * RSR + t + m * NT].v[0];
+  }
+  __syncthreads();
+  auto lds = [&](int i) -> E& { return sm[r * RSR + i]; };
+  V* o = g + (long long)r * M;
+  auto out = [&](int i, const E& e) { o[i] = e.v[0]; };
+  EN::template run<+1>(x, t, act, lds, tw, out);
+}
+
+// ---------------------------------------------------------------------------
+// Last-axis pass: real-to-complex forward transform into packed rows.  Real
+// row x (length N_d, from Philox with the two-FFT algorithm's tag, or loaded)
+// is read as y_n = x[2n] + i x[2n+1]; Y = forward length-M transform;
+//   X_k = E_k + w^{-k} D_k,  E_k = (Y_k + conj Y_{M-k})/2,  D_k = (Y_k - conj Y_{M-k})/(2i),
+// and the slot 0 holds (X_0, X_M) = (Re Y_0 + Im Y_0, Re Y_0 - Im Y_0).
+template <typename T, int M, class Rad, int RB, int PADR, int SRC>
+__global__ void __launch_bounds__(((M / Rad::get(0)) * RB + 63) / 64 * 64)
+k_row_r2c(Args a) {
+  using V = C<T>;
+  using E = Vec<T, 1>;
+  constexpr int NT = M / Rad::get(0);
+  constexpr int RSR = M + PADR;
+  using EN = Eng<T, M, Rad, NT, 1, 2>;
+  __shared__ E sm[RB * RSR];
+  __shared__ V tw[2 * M];
+  const int tid = threadIdx.x;
+  const int r = tid / NT;
+  const int t = tid % NT;
+  const long long row0 = (long long)blockIdx.x * RB;
+  const long long left = a.rows - row0;
+  const int nrows = left < RB ? (int)left : RB;
+  V* g = (V*)a.data + row0 * M;
+  if constexpr (SRC == SRC_LOAD) {
+    const V* s = (const V*)a.src + row0 * M;
+    for (int i = tid; i < nrows * M; i += blockDim.x) sm[(i / M) * RSR + (i % M)].v[0] = s[i];
+  } else {
+    // Philox blocks: 4 reals = 2 complex per block, NQ blocks per row
+    constexpr int NQ = (M + 1) / 2;
+    for (int i = tid; i < nrows * NQ; i += blockDim.x) {
+      const int rr = i / NQ, q = i % NQ;
+      const long long grow = row0 + rr;
+      const int b = (int)(grow / a.rows_per_field);
+      const int frow = (int)(grow % a.rows_per_field);
+      const unsigned long long key = a.seed + (unsigned long long)b;
+      T z[4];
+      normals4<T>((uint32_t)q, (uint32_t)frow, (uint32_t)a.tag, (uint32_t)key, (uint32_t)(key >> 32), z);
+      sm[rr * RSR + 2 * q].v[0] = mk<T>(z[0], z[1]);
+      if (2 * q + 1 < M) sm[rr * RSR + 2 * q + 1].v[0] = mk<T>(z[2], z[3]);
+    }
+  }
+  for (int i = tid; i < 2 * M; i += blockDim.x) tw[i] = ((const V*)a.tw2)[i];
+  __syncthreads();
+  const bool act = (r < nrows) && (t < NT);
+  constexpr int R0 = Rad::get(0);
+  V x[1][EN::REG];
+  if (act) {
+#pragma unroll
+    for (int m = 0; m < R0; ++m) x[0][m] = sm[r * RSR + t + m * NT].v[0];
+  }
+  __syncthreads();
+  auto lds = [&](int i) -> E& { return sm[r * RSR + i]; };
+  auto to_lds = [&](int i, const E& e) { sm[r * RSR + i] = e; };
+  EN::template run<-1>(x, t, act, lds, tw, to_lds);
+  __syncthreads();
+  if (act) {
+    const E* rowp = sm + r * RSR;
+    V* o = g + (long long)r * M;
+    for (int k = t; 2 * k <= M; k += NT) {
+      if (k == 0) {
+        const V y0 = rowp[0].v[0];
+        o[0] = mk<T>(y0.x + y0.y, y0.x - y0.y);
+      } else {
+        const int km = M - k;
+        const V yk = rowp[k].v[0], ym = rowp[km].v[0];
+        // X_k = (Y_k + conj Y_m)/2 + conj(w^k) (Y_k - conj Y_m)/(2i)
+        const V ek = cscale(cadd(yk, cconj(ym)), (T)0.5);
+        const V dk = cscale(csub(yk, cconj(ym)), (T)0.5);        // times 1/i below
+        const V dki = mk<T>(dk.y, -dk.x);
+        o[k] = cadd(ek, cmul(dki, cconj(tw[k])));
+        if (km != k) {
+          const V em = cscale(cadd(ym, cconj(yk)), (T)0.5);
+          const V dm = cscale(csub(ym, cconj(yk)), (T)0.5);
+          const V dmi = mk<T>(dm.y, -dm.x);
+          o[km] = cadd(em, cmul(dmi, cconj(tw[km])));
+        }
+      }
+    }
+  }
+}
+
+}  // namespace grf

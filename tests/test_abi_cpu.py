@@ -1,0 +1,91 @@
+"""The C ABI library loads and exports every declared symbol; host-side
+validation rejects bad descriptors before any device work.  CPU only: nothing
+here initialises a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "grf.h")
+LIB = os.path.join(ROOT, "paper_1105_2737_amd", "libgrf.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libgrf.so not built")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(grf_\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_header_declares_the_binding_exports():
+    from paper_1105_2737_amd import _lib
+    assert declared_functions() == sorted(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    for name in declared_functions():
+        assert re.search(rf"\bT {name}\b", out), name
+
+
+def _desc(**kw):
+    from paper_1105_2737_amd import _lib as L
+    d = L.grf_plan_desc()
+    d.ndim, d.alg, d.dtype, d.cov_kind = 2, L.GRF_ALG_ONE_FFT, L.GRF_F32, L.GRF_COV_MATERN
+    d.dims[0], d.dims[1] = 64, 64
+    d.lengths[0] = d.lengths[1] = d.lengths[2] = 1.0
+    d.sigma, d.length_scale, d.nu = 1.0, 0.1, 1.5
+    for k, v in kw.items():
+        if k == "dims":
+            for i, n in enumerate(v):
+                d.dims[i] = n
+        elif k == "lengths":
+            for i, n in enumerate(v):
+                d.lengths[i] = n
+        else:
+            setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(dims=(63, 64)), -1),            # odd N (the paper requires even N_i)
+    (dict(dims=(64, 14)), -1),            # prime factor 7
+    (dict(dims=(0, 64)), -1),
+    (dict(sigma=0.0), -1),
+    (dict(length_scale=-1.0), -1),
+    (dict(nu=0.0), -1),
+    (dict(lengths=(1.0, 0.0)), -1),
+    (dict(alg=3), -1),
+    (dict(dtype=7), -1),
+    (dict(cov_kind=9), -1),
+    (dict(ndim=4), -4),
+    (dict(dims=(2048, 64)), -4),          # length not in the list
+    (dict(dims=(64, 4096)), -4),
+    (dict(ndim=3, alg=1, dims=(16, 16, 16)), -4),
+])
+def test_invalid_descriptors_are_rejected_on_the_host(kw, status):
+    from paper_1105_2737_amd import _lib as L
+    h = ctypes.c_void_p()
+    st = L.lib.grf_plan_create(ctypes.byref(_desc(**kw)), ctypes.byref(h))
+    assert st == status, L.grf_last_error()
+    assert not h.value
+    assert L.grf_last_error()
+
+
+def test_null_arguments():
+    from paper_1105_2737_amd import _lib as L
+    assert L.lib.grf_plan_create(None, None) == L.GRF_EINVAL
+    assert L.lib.grf_plan_destroy(None) == L.GRF_OK
+    n = ctypes.c_size_t()
+    assert L.lib.grf_workspace_size(None, 1, 0, ctypes.byref(n)) == L.GRF_EINVAL
+    assert L.lib.grf_sample(None, 0, 1, None, None, None, 0, None) == L.GRF_EINVAL
+    assert L.lib.grf_backward(None, 0, None, 1, None, None, None, None, None, 0, None) == L.GRF_EINVAL
+    assert L.lib.grf_debug_philox(0, None, -1, None, None) == L.GRF_EINVAL
+    assert L.lib.grf_debug_philox(0, None, 0, None, None) == L.GRF_OK
+    assert L.grf_version().startswith("grf-mi355x")
