@@ -1,0 +1,293 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the MI355X Gaussian random field sampler.
+
+One step = one batch of the headline workload through the whole sampling path:
+512 x 512 periodic grid on the unit torus, Matern covariance (sigma 1, length
+scale 0.1, nu 1.5), float32, one-FFT (Hermitian) algorithm, 1024 independent
+fields with seeds 0..1023, output resident in HBM.  value = grid points per
+second (2^28 points per step / seconds per step).
+
+Printed alongside on the same JSON line:
+  roofline      the dominant kernel of the step: algorithmic bytes per launch /
+                its mean duration (HIP events on the launch stream) vs 8 TB/s
+  cpu_baseline  the float64 oracle on a bounded sample of the same workload
+  extra         two-FFT algorithm on the same workload, the 256^3 x 16
+                exponential workload, forward+adjoint vs forward at 1024^2 x 64,
+                and the float32-vs-float64 error of sampled fields
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# HBM bytes per launch of the headline step's kernels, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch) scaled by the same counters on a 1 GiB device copy
+# (FETCH x2, WRITE x1); profiles/grf_sample_512x512x1024_f32.md.  Set an entry to
+# None when its kernel changes.
+MEASURED_TRAFFIC = {
+    "column noise+inverse FFT (axis 1)": int((200.25 * 2 + 1048576) * 1024),
+    "last-axis C2R": int((524390.3 * 2 + 1048576) * 1024),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-extra", action="store_true", help="headline workload only")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--profile-stage", type=int, default=None,
+                    help="profiling mode: launch only this stage of the headline step, --steps times")
+    ap.add_argument("--profile-alg", type=int, default=2, help="algorithm for --profile-stage")
+    ap.add_argument("--profile-dims", type=str, default="512,512", help="grid for --profile-stage")
+    ap.add_argument("--profile-batch", type=int, default=1024)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="profiling mode: device copy of 1 GiB, --steps times (counter calibration)")
+    return ap.parse_args()
+
+
+def profile_mode(args):
+    """Kernel launches only, for rocprofv3 counter runs (prints one line)."""
+    import ctypes
+
+    import torch
+
+    import paper_1105_2737_amd as grf
+    if args.copy_calib:
+        a = torch.empty(2 ** 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(args.warmup + args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"copy calibration: {args.steps} x {a.numel() * 4} bytes", flush=True)
+        return
+    dims = tuple(int(x) for x in args.profile_dims.split(","))
+    cov = "exponential" if len(dims) == 3 else "matern"
+    plan = grf.Plan(dims, alg=args.profile_alg, dtype=torch.float32, cov=cov, sigma=1.0,
+                    length_scale=0.05 if len(dims) == 3 else 0.1, nu=1.5)
+    batch = args.profile_batch
+    out = torch.empty((batch,) + dims, dtype=torch.float32, device="cuda")
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for _ in range(args.warmup + args.steps):
+        grf.grf_sample_stage(plan.handle, args.profile_stage, 0, batch, None, ctypes.c_void_p(out.data_ptr()),
+                             None, 0, stream)
+    torch.cuda.synchronize()
+    print(f"profiled stage {args.profile_stage} of alg {args.profile_alg} on {dims} x {batch}", flush=True)
+
+
+def timed(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def event_ms(fn, reps, torch):
+    """Mean duration of fn's launches on the current stream (HIP events)."""
+    s = torch.cuda.current_stream()
+    fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def stage_table(plan, batch, torch, grf, reps):
+    """Per-stage mean kernel time (ms) of plan.sample, each stage launched alone."""
+    import ctypes
+    n = grf.grf_sample_stage_count(plan.handle, batch)
+    out = torch.empty((batch,) + plan.dims, dtype=plan.dtype, device="cuda")
+    times = []
+    for st in range(n):
+        def f(st=st):
+            grf.grf_sample_stage(plan.handle, st, 0, batch, None, ctypes.c_void_p(out.data_ptr()), None, 0,
+                                 ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        times.append(event_ms(f, reps, torch))
+    del out
+    return times
+
+
+def algorithmic_bytes(plan, batch):
+    """Bytes each stage must move per launch (packed spectrum = output size)."""
+    P = 1
+    for n in plan.dims:
+        P *= n
+    esz = 4 if plan.dtype.itemsize == 4 else 8
+    field = P * esz
+    if plan.alg == 2:
+        per = [field] + [2 * field] * (len(plan.dims) - 2) + [2 * field]
+        names = ["column noise+inverse FFT (axis 1)"] + ["inverse FFT (axis 2)"] * (len(plan.dims) - 2) + \
+                ["last-axis C2R"]
+    else:
+        per = [field, 2 * field, 2 * field]
+        names = ["last-axis noise+R2C", "column fwd FFT x h x inv FFT", "last-axis C2R"]
+    return [b * batch for b in per], names
+
+
+def main():
+    args = parse()
+    if args.profile_stage is not None or args.copy_calib:
+        if args.gpus != 1:
+            sys.exit(2)
+        profile_mode(args)
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
+              "(fields are independent; a multi-GPU run would shard the batch without communication).",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1105_2737_amd as grf
+
+    torch.cuda.init()
+    dev = torch.cuda.current_device()
+    dims, batch = (512, 512), 1024
+    P = dims[0] * dims[1]
+    plan = grf.Plan(dims, alg=2, dtype=torch.float32, cov="matern", sigma=1.0, length_scale=0.1, nu=1.5)
+    out = torch.empty((batch,) + dims, dtype=torch.float32, device="cuda")
+    sec = timed(lambda: plan.sample(seed=0, batch=batch, out=out), args.steps, args.warmup, torch)
+    value = P * batch / sec
+
+    # per-kernel times and roofline of the dominant kernel
+    st_ms = stage_table(plan, batch, torch, grf, max(args.steps, 10))
+    total_bytes = 12 * P * batch                       # packed spectrum write + read, output write
+    sep_ms = st_ms
+    abytes, names = algorithmic_bytes(plan, batch)
+    separate = [{"kernel": nm, "ms": round(t, 4), "algorithmic_GB": round(b / 1e9, 4),
+                 "GBps": round(b / (t * 1e-3) / 1e9, 1)} for nm, t, b in zip(names, sep_ms, abytes)]
+    if len(st_ms) > len(sep_ms):
+        # chunked schedule: every launch is the fused kernel (column generation of chunk k,
+        # last-axis C2R of chunk k-1); per launch it moves total_bytes / launches on average
+        kname = "fused column noise+inverse FFT | last-axis C2R"
+        kms = sum(st_ms) / len(st_ms)
+        kbytes = total_bytes / len(st_ms)
+    else:
+        dom = int(np.argmax(st_ms))
+        kname, kms, kbytes = names[dom], st_ms[dom], abytes[dom]
+    achieved = kbytes / (kms * 1e-3) / 1e9
+    traffic = MEASURED_TRAFFIC.get(kname)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic / 1e9, 4), "traffic_unit": "GB/launch",
+                "kernel": kname, "kernel_ms": round(kms, 4), "launches_per_step": len(st_ms),
+                "algorithmic_bytes_per_launch": int(kbytes),
+                "whole_step_model_GBps": round(total_bytes / sec / 1e9, 1),
+                "whole_step_model_frac": round(total_bytes / sec / 1e9 / HBM_PEAK_GBS, 4),
+                "separate_passes": separate}
+
+    result = {
+        "metric": "GRF points/s + HBM-roofline % (512^2, 256^3 FP32); batched & fwd+adjoint vs plain",
+        "value": round(value, 1), "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "512x512 unit torus, Matern(sigma=1, ell=0.1, nu=1.5), one-FFT algorithm, "
+                               "1024 fields (seeds 0..1023)", "global_batch": batch, "grid": list(dims),
+                   "algorithm": "one-FFT (Hermitian)", "parallelism": "single GPU"},
+        "fields_per_s": round(batch / sec, 1),
+        "roofline": roofline,
+    }
+    del out
+    torch.cuda.empty_cache()
+
+    extra = {}
+    if not args.no_extra:
+        # two-FFT algorithm on the same workload
+        p1 = grf.Plan(dims, alg=1, dtype=torch.float32, cov="matern", sigma=1.0, length_scale=0.1, nu=1.5)
+        o1 = torch.empty((batch,) + dims, dtype=torch.float32, device="cuda")
+        s1 = timed(lambda: p1.sample(seed=0, batch=batch, out=o1), args.steps, args.warmup, torch)
+        extra["two_fft_512"] = {"points_per_s": round(P * batch / s1, 1), "ms_per_step": round(s1 * 1e3, 4),
+                                "model_frac": round(20 * P * batch / s1 / 1e9 / HBM_PEAK_GBS, 4),
+                                "time_ratio_vs_one_fft": round(s1 / sec, 3),
+                                "stages_ms": [round(t, 4) for t in stage_table(p1, batch, torch, grf, 10)]}
+        del o1
+        # error vs float64 of sampled fields (both algorithms)
+        errs = {}
+        for alg, pl in ((2, plan), (1, p1)):
+            p64 = grf.Plan(dims, alg=alg, dtype=torch.float64, cov="matern", sigma=1.0, length_scale=0.1, nu=1.5)
+            e = []
+            for b in (0, 1, batch // 2, batch - 1):
+                f32 = pl.sample(seed=b, batch=1).double()
+                f64 = p64.sample(seed=b, batch=1)
+                e.append(float((f32 - f64).abs().max() / f64.abs().max()))
+            errs[f"alg{alg}"] = max(e)
+        extra["max_rel_err_vs_fp64_512"] = errs
+        torch.cuda.empty_cache()
+
+        # 256^3 x 16, exponential l = 0.05, one-FFT
+        d3, b3 = (256, 256, 256), 16
+        p3 = grf.Plan(d3, alg=2, dtype=torch.float32, cov="exponential", sigma=1.0, length_scale=0.05)
+        o3 = torch.empty((b3,) + d3, dtype=torch.float32, device="cuda")
+        s3 = timed(lambda: p3.sample(seed=0, batch=b3, out=o3), max(args.steps // 2, 5), 2, torch)
+        ab3, nm3 = algorithmic_bytes(p3, b3)
+        st3 = stage_table(p3, b3, torch, grf, 5)
+        extra["one_fft_256cubed_x16"] = {
+            "points_per_s": round(2 ** 24 * b3 / s3, 1), "ms_per_step": round(s3 * 1e3, 4),
+            "model_GBps": round(sum(ab3) / s3 / 1e9, 1), "model_frac": round(sum(ab3) / s3 / 1e9 / HBM_PEAK_GBS, 4),
+            "stages": [{"kernel": n, "ms": round(t, 4), "GBps": round(b / (t * 1e-3) / 1e9, 1)}
+                       for n, t, b in zip(nm3, st3, ab3)]}
+        p3_64 = grf.Plan(d3, alg=2, dtype=torch.float64, cov="exponential", sigma=1.0, length_scale=0.05)
+        f64 = p3_64.sample(seed=0, batch=1)
+        extra["one_fft_256cubed_x16"]["max_rel_err_vs_fp64"] = float(
+            (o3[0].double() - f64[0]).abs().max() / f64.abs().max())
+        del o3, f64
+        torch.cuda.empty_cache()
+
+        # forward + adjoint vs forward, 1024^2 x 64
+        d5, b5 = (1024, 1024), 64
+        p5 = grf.Plan(d5, alg=2, dtype=torch.float32, cov="matern", sigma=1.0, length_scale=0.1, nu=1.5)
+        w = torch.rand((b5,) + d5, device="cuda", generator=torch.Generator(device="cuda").manual_seed(1))
+        o5 = torch.empty((b5,) + d5, dtype=torch.float32, device="cuda")
+        sf = timed(lambda: p5.sample(seed=0, batch=b5, out=o5), args.steps, args.warmup, torch)
+        g = 2 * w * o5
+
+        def fwd_bwd():
+            p5.sample(seed=0, batch=b5, out=o5)
+            torch.mul(o5, w, out=g)
+            g.mul_(2.0)
+            p5.backward(g, seed=0)
+        sfb = timed(fwd_bwd, args.steps, args.warmup, torch)
+        sb = timed(lambda: p5.backward(g, seed=0), args.steps, args.warmup, torch)
+        extra["adjoint_1024_x64"] = {"fwd_ms": round(sf * 1e3, 4), "fwd_plus_adjoint_ms": round(sfb * 1e3, 4),
+                                     "adjoint_ms": round(sb * 1e3, 4), "ratio_fwd_bwd_vs_fwd": round(sfb / sf, 3),
+                                     "fwd_points_per_s": round(2 ** 20 * b5 / sf, 1)}
+        del w, o5, g
+        torch.cuda.empty_cache()
+    result["extra"] = extra
+
+    if not args.no_cpu:
+        from oracle import grf as ogrf, spectra
+        nthreads = 1
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < args.cpu_seconds and n < batch:
+            ogrf.sample(dims, (1.0, 1.0), spectra.MATERN, 1.0, 0.1, 1.5, seed=n, batch=1, alg=2)
+            n += 1
+        el = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": round(P * n / el, 1), "unit": "points/s", "cores": nthreads,
+                                  "kind": "oracle",
+                                  "sample": f"{n} of the 1024 fields (seeds 0..{n - 1}), 512x512 one-FFT float64 "
+                                            "oracle (numpy Philox + Box-Muller, Hermitian arrangement, "
+                                            "numpy irfftn), single thread"}
+    result["device"] = torch.cuda.get_device_name(dev)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

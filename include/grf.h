@@ -126,6 +126,22 @@ grf_status grf_sample(grf_plan plan, uint64_t seed, int64_t batch, const double*
 grf_status grf_sample_from_noise(grf_plan plan, const void* noise, int64_t batch, const double* theta,
                                  void* out, void* workspace, size_t workspace_bytes, void* stream);
 
+/* Measurement support: grf_sample runs a fixed sequence of kernel launches
+ * (one-FFT d = 2: column generation + inverse transform, then last-axis
+ * complex-to-real; d = 3 adds the middle-axis inverse transform; two-FFT:
+ * last-axis noise + real-to-complex, column forward/filter/inverse, last-axis
+ * complex-to-real; with the environment variable GRF_FUSE=1 a one-FFT d = 2
+ * batch of a square grid instead runs chunk by chunk, each launch pairing the
+ * column pass of one chunk with the last-axis pass of the previous chunk).
+ * grf_sample_stage_count returns the number of launches for a batch of
+ * `batch` fields (host pointer); grf_sample_stage runs only launch `stage`
+ * (0-based) with the arguments of grf_sample, so that each kernel can be
+ * timed on its own.  Run alone, a later stage transforms whatever `out`
+ * holds. */
+grf_status grf_sample_stage_count(grf_plan plan, int64_t batch, int32_t* count);
+grf_status grf_sample_stage(grf_plan plan, int32_t stage, uint64_t seed, int64_t batch, const double* theta,
+                            void* out, void* workspace, size_t workspace_bytes, void* stream);
+
 /* Write the noise z of the contract for fields seed..seed+batch-1 (device,
  * same shape and dtype as the output). */
 grf_status grf_noise(grf_plan plan, uint64_t seed, int64_t batch, void* noise_out, void* stream);

@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "GRF_OK", -1: "GRF_EINVAL", -2: "GRF_ENOMEM", -3: "GRF_EDEVIC
 
 # every symbol include/grf.h declares
 EXPORTS = ["grf_plan_create", "grf_plan_destroy", "grf_workspace_size", "grf_sample",
-           "grf_sample_from_noise", "grf_noise", "grf_backward", "grf_debug_philox",
+           "grf_sample_stage_count", "grf_sample_stage", "grf_sample_from_noise", "grf_noise", "grf_backward", "grf_debug_philox",
            "grf_last_error", "grf_version"]
 
 
@@ -44,6 +44,8 @@ def _load():
         "grf_plan_destroy": (ctypes.c_int, [vp]),
         "grf_workspace_size": (ctypes.c_int, [vp, c64, i32, ctypes.POINTER(sz)]),
         "grf_sample": (ctypes.c_int, [vp, u64, c64, vp, vp, vp, sz, vp]),
+        "grf_sample_stage_count": (ctypes.c_int, [vp, c64, ctypes.POINTER(i32)]),
+        "grf_sample_stage": (ctypes.c_int, [vp, i32, u64, c64, vp, vp, vp, sz, vp]),
         "grf_sample_from_noise": (ctypes.c_int, [vp, vp, c64, vp, vp, vp, sz, vp]),
         "grf_noise": (ctypes.c_int, [vp, u64, c64, vp, vp]),
         "grf_backward": (ctypes.c_int, [vp, u64, vp, c64, vp, vp, vp, vp, vp, sz, vp]),
@@ -87,6 +89,16 @@ def grf_workspace_size(plan, batch, op):
 
 def grf_sample(plan, seed, batch, theta, out, workspace, workspace_bytes, stream):
     return check(lib.grf_sample(plan, seed, batch, theta, out, workspace, workspace_bytes, stream))
+
+
+def grf_sample_stage_count(plan, batch):
+    n = ctypes.c_int32()
+    check(lib.grf_sample_stage_count(plan, batch, ctypes.byref(n)))
+    return n.value
+
+
+def grf_sample_stage(plan, stage, seed, batch, theta, out, workspace, workspace_bytes, stream):
+    return check(lib.grf_sample_stage(plan, stage, seed, batch, theta, out, workspace, workspace_bytes, stream))
 
 
 def grf_sample_from_noise(plan, noise, batch, theta, out, workspace, workspace_bytes, stream):

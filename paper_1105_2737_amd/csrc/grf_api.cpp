@@ -16,8 +16,10 @@
 //       -> per-field sum of the partials
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -177,27 +179,108 @@ grf_status run_pass(const grf_plan_s* p, int pass, int L, Args a, long long nfix
   return GRF_OK;
 }
 
-// The sampler proper; zsrc == nullptr generates the noise from the seed.
-grf_status sample_impl(grf_plan p, uint64_t seed, const void* zsrc, int64_t batch, const double* theta, void* out,
-                       void* workspace, size_t ws_bytes, void* stream) {
-  if (p == nullptr) return fail(GRF_EINVAL, "null plan");
-  if (batch < 0) return fail(GRF_EINVAL, "negative batch");
-  if (batch == 0) return GRF_OK;
-  if (out == nullptr) return fail(GRF_EINVAL, "null output");
-  if (batch > 0x7fffffff) return fail(GRF_EINVAL, "batch too large");
-  grf_status st = check_stream_device(p);
-  if (st != GRF_OK) return st;
-  hipStream_t s = (hipStream_t)stream;
-  const FieldRec* recs;
-  int rstride;
-  st = field_records(p, theta, batch, workspace, ws_bytes, s, &recs, &rstride);
-  if (st != GRF_OK) return st;
+// One launch of the sampler: a single pass (pass >= 0), or (pass == -1) a
+// fused launch of a column generation pass (args a, length L) and a last-axis
+// complex-to-real pass over another chunk of fields (args b, half-length M2).
+struct PassLaunch {
+  int pass;
+  int L;
+  Args a;
+  int M2 = 0;
+  Args b{};
+  bool hasA = true, hasB = true;
+};
+
+// Fields per chunk of the fused schedule: the packed spectra of a chunk
+// (written by one launch, read by the next) are sized to stay in the
+// 256 MB last-level cache.  GRF_CHUNK_BYTES overrides.
+long long chunk_fields(const grf_plan_s* p, long long batch) {
+  long long bytes = 64ll << 20;
+  if (const char* e = std::getenv("GRF_CHUNK_BYTES")) {
+    const long long v = std::atoll(e);
+    if (v > 0) bytes = v;
+  }
+  long long c = bytes / (p->P * (long long)p->esz);
+  if (c < 1) c = 1;
+  if (c > batch) c = batch;
+  return c;
+}
+
+// The fused schedule is opt-in (GRF_FUSE=1): measured on MI355X it is slower
+// than the two separate passes for the supported shapes.
+bool fuse_enabled() {
+  const char* e = std::getenv("GRF_FUSE");
+  return e && e[0] == '1';
+}
+
+grf_status run_launch(const grf_plan_s* p, const PassLaunch& pl, long long batch, hipStream_t s) {
+  if (pl.pass >= 0) return run_pass(p, pl.pass, pl.L, pl.a, 0, batch, s);
+  const grf::FusedGeom g = grf::fused_geom(p->dtype, pl.L, pl.M2);
+  if (g.threads <= 0) return fail(GRF_EUNSUPPORTED, "no fused kernel for this shape");
+  Args a = pl.a;
+  a.ntile = (a.M + 2 * g.cp - 1) / (2 * g.cp);
+  const long long nA = pl.hasA ? (long long)a.ntile * a.nfixed * a.batch : 0;
+  const long long nB = pl.hasB ? (pl.b.rows + g.rb - 1) / g.rb : 0;
+  if (nA + nB <= 0) return GRF_OK;
+  if (nA + nB > 0x7fffffffLL) return fail(GRF_EINVAL, "batch too large for one launch");
+  hipError_t e = grf::launch_fused(p->dtype, pl.L, pl.M2, a, pl.b, (int)nA, (int)nB, s);
+  if (e != hipSuccess) return hip_fail(e, "fused kernel launch");
+  return GRF_OK;
+}
+
+// The pass sequence of the sampler (zsrc == nullptr generates the noise).
+std::vector<PassLaunch> sample_passes(const grf_plan_s* p, uint64_t seed, const void* zsrc, long long batch,
+                                      const FieldRec* recs, int rstride, void* out) {
+  std::vector<PassLaunch> v;
   Args a = base_args(p, batch);
   a.data = out;
   a.src = zsrc;
   a.recs = recs;
   a.rec_stride = rstride;
   a.seed = seed;
+  if (p->desc.alg == GRF_ALG_ONE_FFT && p->d == 2 && fuse_enabled() && batch >= 2 &&
+      grf::fused_geom(p->dtype, p->n1, p->M).threads > 0) {
+    // Chunked schedule: launch k runs the column generation pass of chunk k
+    // and the last-axis pass of chunk k-1, so that the VALU-heavy and the
+    // memory-heavy passes share the CUs.
+    a.tag = 1;
+    a.tw = p->tw_col1;
+    a.stride_ax = p->M;
+    a.stride_fixed = p->M;
+    a.nfixed = 1;
+    Args rb = a;
+    rb.src = nullptr;
+    rb.tw2 = p->tw_row;
+    const long long C = chunk_fields(p, batch);
+    const long long nch = (batch + C - 1) / C;
+    const size_t fbytes = (size_t)p->P * p->esz;
+    auto chunk = [&](long long k, Args x, bool gen) {
+      const long long c0 = k * C;
+      const long long nb = std::min(C, batch - c0);
+      x.data = (char*)out + c0 * fbytes;
+      if (gen) {
+        x.seed = seed + (uint64_t)c0;
+        x.batch = (int)nb;
+        if (rstride) x.recs = recs + c0;
+        if (zsrc) x.src = (const char*)zsrc + c0 * fbytes;
+      } else {
+        x.rows = nb * (long long)p->n1;
+      }
+      return x;
+    };
+    for (long long k = 0; k <= nch; ++k) {
+      PassLaunch pl;
+      pl.pass = -1;
+      pl.L = p->n1;
+      pl.M2 = p->M;
+      pl.hasA = k < nch;
+      pl.hasB = k >= 1;
+      pl.a = pl.hasA ? chunk(k, a, true) : a;
+      pl.b = pl.hasB ? chunk(k - 1, rb, false) : rb;
+      v.push_back(pl);
+    }
+    return v;
+  }
   if (p->desc.alg == GRF_ALG_ONE_FFT) {
     a.tag = 1;
     a.tw = p->tw_col1;
@@ -210,8 +293,7 @@ grf_status sample_impl(grf_plan p, uint64_t seed, const void* zsrc, int64_t batc
       a.stride_fixed = p->M;
       a.nfixed = p->no;
     }
-    st = run_pass(p, grf::PASS_COL_GEN_INV, p->n1, a, 0, batch, s);
-    if (st != GRF_OK) return st;
+    v.push_back({grf::PASS_COL_GEN_INV, p->n1, a});
     if (p->d == 3) {
       Args m = a;
       m.src = nullptr;
@@ -219,18 +301,14 @@ grf_status sample_impl(grf_plan p, uint64_t seed, const void* zsrc, int64_t batc
       m.stride_ax = p->M;
       m.stride_fixed = (long long)p->no * p->M;
       m.nfixed = p->n1;
-      st = run_pass(p, grf::PASS_COL_LOAD_INV, p->no, m, 0, batch, s);
-      if (st != GRF_OK) return st;
+      v.push_back({grf::PASS_COL_LOAD_INV, p->no, m});
     }
   } else {
-    // two-FFT algorithm, d = 2
     Args r = a;
     r.tag = 0;
     r.tw2 = p->tw_row;
     r.rows = batch * (long long)p->n1;
-    const int rpass = zsrc ? grf::PASS_ROW_R2C_LOAD : grf::PASS_ROW_R2C_GEN;
-    st = run_pass(p, rpass, p->M, r, 0, batch, s);
-    if (st != GRF_OK) return st;
+    v.push_back({zsrc ? grf::PASS_ROW_R2C_LOAD : grf::PASS_ROW_R2C_GEN, p->M, r});
     Args c = a;
     c.src = nullptr;
     c.tw = p->tw_col1;
@@ -238,14 +316,39 @@ grf_status sample_impl(grf_plan p, uint64_t seed, const void* zsrc, int64_t batc
     c.stride_fixed = p->M;
     c.nfixed = 1;
     c.scale = 1.0 / std::sqrt((double)p->P);
-    st = run_pass(p, grf::PASS_COL_FILTER, p->n1, c, 0, batch, s);
-    if (st != GRF_OK) return st;
+    v.push_back({grf::PASS_COL_FILTER, p->n1, c});
   }
   Args b = a;
   b.src = nullptr;
   b.tw2 = p->tw_row;
   b.rows = batch * (p->P / p->nd);
-  return run_pass(p, grf::PASS_ROW_C2R, p->M, b, 0, batch, s);
+  v.push_back({grf::PASS_ROW_C2R, p->M, b});
+  return v;
+}
+
+// stage < 0: run every pass; otherwise only that one.
+grf_status sample_impl(grf_plan p, uint64_t seed, const void* zsrc, int64_t batch, const double* theta, void* out,
+                       void* workspace, size_t ws_bytes, void* stream, int stage = -1) {
+  if (p == nullptr) return fail(GRF_EINVAL, "null plan");
+  if (batch < 0) return fail(GRF_EINVAL, "negative batch");
+  if (batch == 0) return GRF_OK;
+  if (out == nullptr) return fail(GRF_EINVAL, "null output");
+  if (batch > 0x7fffffff) return fail(GRF_EINVAL, "batch too large");
+  grf_status st = check_stream_device(p);
+  if (st != GRF_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const FieldRec* recs;
+  int rstride;
+  st = field_records(p, theta, batch, workspace, ws_bytes, s, &recs, &rstride);
+  if (st != GRF_OK) return st;
+  const std::vector<PassLaunch> v = sample_passes(p, seed, zsrc, batch, recs, rstride, out);
+  if (stage >= (int)v.size()) return fail(GRF_EINVAL, "stage out of range");
+  for (int i = 0; i < (int)v.size(); ++i) {
+    if (stage >= 0 && i != stage) continue;
+    st = run_launch(p, v[i], batch, s);
+    if (st != GRF_OK) return st;
+  }
+  return GRF_OK;
 }
 
 }  // namespace
@@ -277,6 +380,12 @@ bool row_length_supported(int M) {
 Geom pass_geom(int pass, int dtype, int L) {
   if (pass >= PASS_ROW_C2R) return dtype == 0 ? geom_row_f32(L) : geom_row_f64(L);
   return dtype == 0 ? geom_col_f32(L) : geom_col_f64(L);
+}
+
+FusedGeom fused_geom(int dtype, int L, int M) { return dtype == 0 ? fused_geom_f32(L, M) : fused_geom_f64(L, M); }
+
+hipError_t launch_fused(int dtype, int L, int M, const Args& aA, const Args& aB, int nA, int nB, hipStream_t s) {
+  return dtype == 0 ? launch_fused_f32(L, M, aA, aB, nA, nB, s) : launch_fused_f64(L, M, aA, aB, nA, nB, s);
 }
 
 hipError_t launch_pass(int pass, int dtype, int L, const Args& a, long long nblocks, hipStream_t s) {
@@ -391,6 +500,19 @@ grf_status grf_sample_from_noise(grf_plan p, const void* noise, int64_t batch, c
   if (noise == nullptr && batch > 0) return fail(GRF_EINVAL, "null noise");
   if (noise != nullptr && noise == out) return fail(GRF_EINVAL, "noise and output must not alias");
   return sample_impl(p, 0, noise, batch, theta, out, workspace, workspace_bytes, stream);
+}
+
+grf_status grf_sample_stage_count(grf_plan p, int64_t batch, int32_t* count) {
+  if (p == nullptr || count == nullptr) return fail(GRF_EINVAL, "null argument");
+  if (batch < 1) return fail(GRF_EINVAL, "batch must be positive");
+  *count = (int32_t)sample_passes(p, 0, nullptr, batch, p->rec_dev, 0, nullptr).size();
+  return GRF_OK;
+}
+
+grf_status grf_sample_stage(grf_plan p, int32_t stage, uint64_t seed, int64_t batch, const double* theta, void* out,
+                            void* workspace, size_t workspace_bytes, void* stream) {
+  if (stage < 0) return fail(GRF_EINVAL, "negative stage");
+  return sample_impl(p, seed, nullptr, batch, theta, out, workspace, workspace_bytes, stream, stage);
 }
 
 grf_status grf_noise(grf_plan p, uint64_t seed, int64_t batch, void* noise_out, void* stream) {

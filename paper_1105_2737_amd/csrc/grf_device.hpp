@@ -19,14 +19,33 @@
 
 namespace grf {
 
+// One round's "hi ^ c ^ k" with the key in a scalar register: a single
+// three-input VALU op (gfx950 bitop3 with the xor truth table; the compiler
+// splits it into two xors otherwise).  Pure ALU.
+__device__ __forceinline__ uint32_t xor3_sk(uint32_t a, uint32_t b, uint32_t k) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "s"(k), "v"(a), "v"(b));   // 0x96 = a ^ b ^ c
+  return r;
+}
+
+// UNIFORM_KEY: the key (k0, k1) is the same for every lane of the wave (one
+// field per workgroup); then it lives in scalar registers.
+template <bool UNIFORM_KEY = false>
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+  if constexpr (UNIFORM_KEY) {
+    k0 = __builtin_amdgcn_readfirstlane(k0);
+    k1 = __builtin_amdgcn_readfirstlane(k1);
+  }
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
     const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
     const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    if constexpr (UNIFORM_KEY)
+      c = make_uint4(xor3_sk(hi1, c.y, k0), lo1, xor3_sk(hi0, c.w, k1), lo0);
+    else
+      c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -61,9 +80,9 @@ __device__ __forceinline__ void box_muller(uint32_t xa, uint32_t xb, double& n0,
   n1 = r * s;
 }
 
-template <typename T>
+template <typename T, bool UNIFORM_KEY = false>
 __device__ __forceinline__ void normals4(uint32_t q, uint32_t row, uint32_t tag, uint32_t k0, uint32_t k1, T* z) {
-  const uint4 x = philox4x32_10(make_uint4(q, row, tag, 0u), k0, k1);
+  const uint4 x = philox4x32_10<UNIFORM_KEY>(make_uint4(q, row, tag, 0u), k0, k1);
   box_muller(x.x, x.y, z[0], z[1]);
   box_muller(x.z, x.w, z[2], z[3]);
 }

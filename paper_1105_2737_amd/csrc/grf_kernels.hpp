@@ -152,7 +152,8 @@ template <typename T>
 __device__ __forceinline__ void load_z4(const Args& a, const T* zsrc, int b, int row, int m0, uint32_t k0,
                                         uint32_t k1, T* z) {
   if (zsrc == nullptr) {
-    normals4<T>((uint32_t)(m0 >> 1), (uint32_t)row, (uint32_t)a.tag, k0, k1, z);
+    // one field per workgroup in every caller: the key is wave-uniform
+    normals4<T, true>((uint32_t)(m0 >> 1), (uint32_t)row, (uint32_t)a.tag, k0, k1, z);
   } else {
     const T* p = zsrc + (long long)b * a.field_stride * 2 + (long long)row * a.nd + 2 * m0;
     z[0] = p[0];
@@ -202,60 +203,89 @@ __device__ __forceinline__ void gen_pair(const Args& a, const Filt<T>& f, const 
   }
 }
 
+// Column-pair global access: one 16-byte (float32) / 32-byte (float64) access
+// when both columns exist and the pair is aligned (even M), else per column.
+template <typename T>
+__device__ __forceinline__ void ld_pair(const C<T>* p, bool two, bool al, C<T>& x0, C<T>& x1) {
+  if (two && al) {
+    const Vec<T, 2> e = *reinterpret_cast<const Vec<T, 2>*>(p);
+    x0 = e.v[0];
+    x1 = e.v[1];
+  } else {
+    x0 = p[0];
+    x1 = two ? p[1] : mk<T>((T)0, (T)0);
+  }
+}
+template <typename T>
+__device__ __forceinline__ void st_pair(C<T>* p, bool two, bool al, const Vec<T, 2>& e) {
+  if (two && al) {
+    *reinterpret_cast<Vec<T, 2>*>(p) = e;
+  } else {
+    p[0] = e.v[0];
+    if (two) p[1] = e.v[1];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Column pass over a leading axis.
 enum { SRC_GEN = 0, SRC_LOAD = 1 };
 
 template <typename T, int L, class Rad, int CP, int PAD, int SRC, int DIR>
-__global__ void __launch_bounds__(((L / Rad::get(0)) * CP + 63) / 64 * 64)
-k_col(Args a) {
+struct ColPass {
   using V = C<T>;
   using E = Vec<T, 2>;
-  constexpr int NT = L / Rad::get(0);
-  constexpr int RS = CP + PAD;
-  constexpr int R0 = Rad::get(0);
+  static constexpr int NT = L / Rad::get(0);
+  static constexpr int THREADS = (NT * CP + 63) / 64 * 64;
+  static constexpr int RS = CP + PAD;
+  static constexpr int R0 = Rad::get(0);
+  static constexpr int LDS_BYTES = L * RS * (int)sizeof(E) + L * (int)sizeof(V);
   using EN = Eng<T, L, Rad, NT, 2, 1>;
-  __shared__ E sm[L * RS];
-  __shared__ V tw[L];
-  const int tid = threadIdx.x;
-  const int cp = tid % CP;
-  const int t = tid / CP;
-  int bid = blockIdx.x;
-  const int tile = bid % a.ntile;
-  bid /= a.ntile;
-  const int fx = bid % a.nfixed;
-  const int b = bid / a.nfixed;
-  for (int i = tid; i < L; i += blockDim.x) tw[i] = ((const V*)a.tw)[i];
-  const int m0 = (tile * CP + cp) * 2;
-  const bool act = (t < NT) && (m0 < a.M);
-  const bool two = (m0 + 1) < a.M;
-  V* base = (V*)a.data + (long long)b * a.field_stride + (long long)fx * a.stride_fixed + m0;
-  V x[2][EN::REG];
-  if (act) {
-    if constexpr (SRC == SRC_GEN) {
-      const FieldRec& rec = a.recs[b * a.rec_stride];
-      const Filt<T> f = load_filt<T>(rec, a.scale);
-      const unsigned long long key = a.seed + (unsigned long long)b;
-      const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
-      const T* zsrc = (const T*)a.src;
+
+  // Workgroup `bid` of the pass; smem holds LDS_BYTES (16-byte aligned).
+  __device__ __forceinline__ static void run(const Args& a, int bid, char* smem) {
+    E* sm = reinterpret_cast<E*>(smem);
+    V* tw = reinterpret_cast<V*>(smem + L * RS * sizeof(E));
+    const int tid = threadIdx.x;
+    const int cp = tid % CP;
+    const int t = tid / CP;
+    const int tile = bid % a.ntile;
+    bid /= a.ntile;
+    const int fx = bid % a.nfixed;
+    const int b = bid / a.nfixed;
+    for (int i = tid; i < L; i += blockDim.x) tw[i] = ((const V*)a.tw)[i];
+    const int m0 = (tile * CP + cp) * 2;
+    const bool act = (t < NT) && (m0 < a.M);
+    const bool two = (m0 + 1) < a.M;
+    const bool al = (a.M & 1) == 0;
+    V* base = (V*)a.data + (long long)b * a.field_stride + (long long)fx * a.stride_fixed + m0;
+    V x[2][EN::REG];
+    if (act) {
+      if constexpr (SRC == SRC_GEN) {
+        const FieldRec& rec = a.recs[b * a.rec_stride];
+        const Filt<T> f = load_filt<T>(rec, a.scale);
+        const unsigned long long key = a.seed + (unsigned long long)b;
+        const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
+        const T* zsrc = (const T*)a.src;
 #pragma unroll
-      for (int m = 0; m < R0; ++m) gen_pair<T>(a, f, zsrc, b, k0, k1, t + m * NT, fx, m0, x[0][m], x[1][m]);
-    } else {
+        for (int m = 0; m < R0; ++m) gen_pair<T>(a, f, zsrc, b, k0, k1, t + m * NT, fx, m0, x[0][m], x[1][m]);
+      } else {
 #pragma unroll
-      for (int m = 0; m < R0; ++m) {
-        const V* p = base + (long long)(t + m * NT) * a.stride_ax;
-        x[0][m] = p[0];
-        x[1][m] = two ? p[1] : mk<T>((T)0, (T)0);
+        for (int m = 0; m < R0; ++m)
+          ld_pair<T>(base + (long long)(t + m * NT) * a.stride_ax, two, al, x[0][m], x[1][m]);
       }
     }
+    auto lds = [&](int i) -> E& { return sm[i * RS + cp]; };
+    auto out = [&](int i, const E& e) { st_pair<T>(base + (long long)i * a.stride_ax, two, al, e); };
+    EN::template run<DIR>(x, t, act, lds, tw, out);
   }
-  auto lds = [&](int i) -> E& { return sm[i * RS + cp]; };
-  auto out = [&](int i, const E& e) {
-    V* p = base + (long long)i * a.stride_ax;
-    p[0] = e.v[0];
-    if (two) p[1] = e.v[1];
-  };
-  EN::template run<DIR>(x, t, act, lds, tw, out);
+};
+
+template <typename T, int L, class Rad, int CP, int PAD, int SRC, int DIR>
+__global__ void __launch_bounds__((ColPass<T, L, Rad, CP, PAD, SRC, DIR>::THREADS))
+k_col(Args a) {
+  using PS = ColPass<T, L, Rad, CP, PAD, SRC, DIR>;
+  __shared__ __align__(16) char smem[PS::LDS_BYTES];
+  PS::run(a, blockIdx.x, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -282,15 +312,13 @@ k_colf(Args a) {
   const int m0 = (tile * CP + cp) * 2;
   const bool act = (t < NT) && (m0 < a.M);
   const bool two = (m0 + 1) < a.M;
+  const bool al = (a.M & 1) == 0;
   V* base = (V*)a.data + (long long)b * a.field_stride + m0;
   V x[2][EN::REG];
   if (act) {
 #pragma unroll
-    for (int m = 0; m < R0; ++m) {
-      const V* p = base + (long long)(t + m * NT) * a.stride_ax;
-      x[0][m] = p[0];
-      x[1][m] = two ? p[1] : mk<T>((T)0, (T)0);
-    }
+    for (int m = 0; m < R0; ++m)
+      ld_pair<T>(base + (long long)(t + m * NT) * a.stride_ax, two, al, x[0][m], x[1][m]);
   }
   auto lds = [&](int i) -> E& { return sm[i * RS + cp]; };
   auto to_lds = [&](int i, const E& e) { sm[i * RS + cp] = e; };
@@ -324,11 +352,7 @@ k_colf(Args a) {
     }
   }
   __syncthreads();
-  auto out = [&](int i, const E& e) {
-    V* p = base + (long long)i * a.stride_ax;
-    p[0] = e.v[0];
-    if (two) p[1] = e.v[1];
-  };
+  auto out = [&](int i, const E& e) { st_pair<T>(base + (long long)i * a.stride_ax, two, al, e); };
   EN::template run<+1>(x, t, act, lds, tw, out);
 }
 
@@ -362,15 +386,13 @@ k_colg(Args a) {
   const int m0 = (tile * CP + cp) * 2;
   const bool act = (t < NT) && (m0 < a.M);
   const bool two = (m0 + 1) < a.M;
+  const bool al = (a.M & 1) == 0;
   V* base = (V*)a.data + (long long)b * a.field_stride + m0;
   V x[2][EN::REG];
   if (act) {
 #pragma unroll
-    for (int m = 0; m < R0; ++m) {
-      const V* p = base + (long long)(t + m * NT) * a.stride_ax;
-      x[0][m] = p[0];
-      x[1][m] = two ? p[1] : mk<T>((T)0, (T)0);
-    }
+    for (int m = 0; m < R0; ++m)
+      ld_pair<T>(base + (long long)(t + m * NT) * a.stride_ax, two, al, x[0][m], x[1][m]);
   }
   auto lds = [&](int i) -> E& { return sm[i * RS + cp]; };
   auto to_lds = [&](int i, const E& e) { sm[i * RS + cp] = e; };
@@ -496,66 +518,132 @@ k_colg(Args a) {
 }
 
 // ---------------------------------------------------------------------------
+// Row-pass LDS layout: one padding slot after every 16 complex elements, so
+// that the radix-R stores to j R + m (a stride of R elements across lanes) and
+// the unit-stride loads both spread over the LDS banks.
+template <int M> struct RowLds {
+  static constexpr int PADDED = M >= 16;
+  static constexpr int STRIDE = M + (PADDED ? M / 16 : 0);
+  __device__ __forceinline__ static int idx(int i) { return PADDED ? i + (i >> 4) : i; }
+};
+
+// ---------------------------------------------------------------------------
+// Flat copy of `count` complex elements global -> LDS (contiguous on both
+// sides) in 16-byte vectors; every load of the thread is issued before the
+// first LDS store so that the loads overlap.
+template <typename T, int M, int MAXC, int NTHR, typename E>
+__device__ __forceinline__ void copy_in(const C<T>* __restrict__ g, E* sm, int count, int tid) {
+  constexpr int VW = 16 / sizeof(C<T>);            // complex per 16-byte vector
+  static_assert(M % VW == 0, "rows must hold whole vectors");
+  using W = Vec<T, VW>;
+  using RL = RowLds<M>;
+  constexpr int NV = (MAXC / VW + NTHR - 1) / NTHR;
+  const int nvec = count / VW;
+  const W* gv = reinterpret_cast<const W*>(g);
+  W buf[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int idx = tid + i * NTHR;
+    if (idx < nvec) buf[i] = gv[idx];
+  }
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int idx = tid + i * NTHR;
+    if (idx < nvec) {
+      const int e = idx * VW;
+      const int r = e / M, c = e % M;
+#pragma unroll
+      for (int v = 0; v < VW; ++v) sm[r * RL::STRIDE + RL::idx(c + v)].v[0] = buf[i].v[v];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Last-axis pass: complex-to-real inverse transform of packed rows.
 // Row data X_k (k = 0..M-1, X_0 slot = (X_0, X_M)) become
 //   Z_k = E_k + i O_k,  E_k = X_k + conj X_{M-k},  O_k = (X_k - conj X_{M-k}) w^k,
 // w = exp(2 pi i / N_d); z = inverse length-M transform of Z; and
-// x[2n] = Re z_n, x[2n+1] = Im z_n.
+// x[2n] = Re z_n, x[2n+1] = Im z_n.  Z is formed while loading the first
+// stage's inputs.
 template <typename T, int M, class Rad, int RB, int PADR>
-__global__ void __launch_bounds__(((M / Rad::get(0)) * RB + 63) / 64 * 64)
-k_row_c2r(Args a) {
+struct RowC2R {
   using V = C<T>;
   using E = Vec<T, 1>;
-  constexpr int NT = M / Rad::get(0);
-  constexpr int RSR = M + PADR;
+  using RL = RowLds<M>;
+  static constexpr int NT = M / Rad::get(0);
+  static constexpr int THREADS = (NT * RB + 63) / 64 * 64;
+  static constexpr int R0 = Rad::get(0);
+  static constexpr int LDS_BYTES = RB * RL::STRIDE * (int)sizeof(E) + 2 * M * (int)sizeof(V);
+  static_assert(PADR == 0, "row passes use the RowLds layout");
   using EN = Eng<T, M, Rad, NT, 1, 2>;
-  __shared__ E sm[RB * RSR];
-  __shared__ V tw[2 * M];
-  const int tid = threadIdx.x;
-  const int r = tid / NT;
-  const int t = tid % NT;
-  const long long row0 = (long long)blockIdx.x * RB;
-  const long long left = a.rows - row0;
-  const int nrows = left < RB ? (int)left : RB;
-  V* g = (V*)a.data + row0 * M;
-  for (int i = tid; i < nrows * M; i += blockDim.x) sm[(i / M) * RSR + (i % M)].v[0] = g[i];
-  for (int i = tid; i < 2 * M; i += blockDim.x) tw[i] = ((const V*)a.tw2)[i];
-  __syncthreads();
-  const bool act = (r < nrows) && (t < NT);
-  if (act) {
-    E* rowp = sm + r * RSR;
-    for (int k = t; 2 * k <= M; k += NT) {
-      if (k == 0) {
-        const V x0 = rowp[0].v[0];
-        rowp[0].v[0] = mk<T>(x0.x + x0.y, x0.x - x0.y);
-      } else {
-        const int km = M - k;
-        const V xk = rowp[k].v[0], xm = rowp[km].v[0];
-        const V wk = tw[k], wm = tw[km];
-        const V ek = cadd(xk, cconj(xm));
-        const V ok = cmul(csub(xk, cconj(xm)), wk);
-        const V zk = mk<T>(ek.x - ok.y, ek.y + ok.x);
-        rowp[k].v[0] = zk;
-        if (km != k) {
-          const V em = cadd(xm, cconj(xk));
-          const V om = cmul(csub(xm, cconj(xk)), wm);
-          rowp[km].v[0] = mk<T>(em.x - om.y, em.y + om.x);
+
+  __device__ __forceinline__ static void run(const Args& a, int bid, char* smem) {
+    E* sm = reinterpret_cast<E*>(smem);
+    V* tw = reinterpret_cast<V*>(smem + RB * RL::STRIDE * sizeof(E));
+    const int tid = threadIdx.x;
+    const int r = tid / NT;
+    const int t = tid % NT;
+    const long long row0 = (long long)bid * RB;
+    const long long left = a.rows - row0;
+    const int nrows = left < RB ? (int)left : RB;
+    V* g = (V*)a.data + row0 * M;
+    if (tid < THREADS) {
+      copy_in<T, M, RB * M, THREADS>(g, sm, nrows * M, tid);
+      for (int i = tid; i < 2 * M; i += THREADS) tw[i] = ((const V*)a.tw2)[i];
+    }
+    __syncthreads();
+    const bool act = (r < nrows) && (t < NT);
+    V x[1][EN::REG];
+    if (act) {
+      const E* rowp = sm + r * RL::STRIDE;
+#pragma unroll
+      for (int m = 0; m < R0; ++m) {
+        const int k = t + m * NT;
+        const V xk = rowp[RL::idx(k)].v[0];
+        if (k == 0) {
+          x[0][m] = mk<T>(xk.x + xk.y, xk.x - xk.y);
+        } else {
+          const V xm = cconj(rowp[RL::idx(M - k)].v[0]);
+          const V ek = cadd(xk, xm);
+          const V ok = cmul(csub(xk, xm), tw[k]);
+          x[0][m] = mk<T>(ek.x - ok.y, ek.y + ok.x);
         }
       }
     }
+    __syncthreads();
+    auto lds = [&](int i) -> E& { return sm[r * RL::STRIDE + RL::idx(i)]; };
+    V* o = g + (long long)r * M;
+    auto out = [&](int i, const E& e) { o[i] = e.v[0]; };
+    EN::template run<+1>(x, t, act, lds, tw, out);
   }
-  __syncthreads();
-  constexpr int R0 = Rad::get(0);
-  V x[1][EN::REG];
-  if (act) {
-#pragma unroll
-    for (int m = 0; m < R0; ++m) x[0][m] = sm[r * RSR + t + m * NT].v[0];
-  }
-  __syncthreads();
-  auto lds = [&](int i) -> E& { return sm[r * RSR + i]; };
-  V* o = g + (long long)r * M;
-  auto out = [&](int i, const E& e) { o[i] = e.v[0]; };
-  EN::template run<+1>(x, t, act, lds, tw, out);
+};
+
+// Kernel wrapper of RowC2R.
+template <typename T, int M, class Rad, int RB, int PADR>
+__global__ void __launch_bounds__((RowC2R<T, M, Rad, RB, PADR>::THREADS))
+k_row_c2r(Args a) {
+  using PS = RowC2R<T, M, Rad, RB, PADR>;
+  __shared__ __align__(16) char smem[PS::LDS_BYTES];
+  PS::run(a, blockIdx.x, smem);
+}
+
+// ---------------------------------------------------------------------------
+// One launch that interleaves the workgroups of two independent passes: nA
+// workgroups of PA (arguments aa) and nB of PB (arguments ab), spread evenly
+// over the grid, so that a memory-bound and a VALU-bound pass share the CUs.
+template <class PA, class PB>
+__global__ void __launch_bounds__(PA::THREADS > PB::THREADS ? PA::THREADS : PB::THREADS)
+k_fused(Args aa, Args ab, int nA, int nB) {
+  constexpr int LDS = PA::LDS_BYTES > PB::LDS_BYTES ? PA::LDS_BYTES : PB::LDS_BYTES;
+  __shared__ __align__(16) char smem[LDS];
+  const long long n = (long long)nA + nB;
+  const long long b = blockIdx.x;
+  const int ia = (int)(b * nA / n);
+  const int ia1 = (int)((b + 1) * nA / n);
+  if (ia1 > ia)
+    PA::run(aa, ia, smem);
+  else
+    PB::run(ab, (int)(b - ia), smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -570,7 +658,9 @@ k_row_r2c(Args a) {
   using V = C<T>;
   using E = Vec<T, 1>;
   constexpr int NT = M / Rad::get(0);
-  constexpr int RSR = M + PADR;
+  static_assert(PADR == 0, "row passes use the RowLds layout");
+  using RL = RowLds<M>;
+  constexpr int RSR = RL::STRIDE;
   using EN = Eng<T, M, Rad, NT, 1, 2>;
   __shared__ E sm[RB * RSR];
   __shared__ V tw[2 * M];
@@ -582,8 +672,8 @@ k_row_r2c(Args a) {
   const int nrows = left < RB ? (int)left : RB;
   V* g = (V*)a.data + row0 * M;
   if constexpr (SRC == SRC_LOAD) {
-    const V* s = (const V*)a.src + row0 * M;
-    for (int i = tid; i < nrows * M; i += blockDim.x) sm[(i / M) * RSR + (i % M)].v[0] = s[i];
+    constexpr int NTHR = (NT * RB + 63) / 64 * 64;
+    copy_in<T, M, RB * M, NTHR>((const V*)a.src + row0 * M, sm, nrows * M, tid);
   } else {
     // Philox blocks: 4 reals = 2 complex per block, NQ blocks per row
     constexpr int NQ = (M + 1) / 2;
@@ -595,8 +685,8 @@ k_row_r2c(Args a) {
       const unsigned long long key = a.seed + (unsigned long long)b;
       T z[4];
       normals4<T>((uint32_t)q, (uint32_t)frow, (uint32_t)a.tag, (uint32_t)key, (uint32_t)(key >> 32), z);
-      sm[rr * RSR + 2 * q].v[0] = mk<T>(z[0], z[1]);
-      if (2 * q + 1 < M) sm[rr * RSR + 2 * q + 1].v[0] = mk<T>(z[2], z[3]);
+      sm[rr * RSR + RL::idx(2 * q)].v[0] = mk<T>(z[0], z[1]);
+      if (2 * q + 1 < M) sm[rr * RSR + RL::idx(2 * q + 1)].v[0] = mk<T>(z[2], z[3]);
     }
   }
   for (int i = tid; i < 2 * M; i += blockDim.x) tw[i] = ((const V*)a.tw2)[i];
@@ -606,11 +696,11 @@ k_row_r2c(Args a) {
   V x[1][EN::REG];
   if (act) {
 #pragma unroll
-    for (int m = 0; m < R0; ++m) x[0][m] = sm[r * RSR + t + m * NT].v[0];
+    for (int m = 0; m < R0; ++m) x[0][m] = sm[r * RSR + RL::idx(t + m * NT)].v[0];
   }
   __syncthreads();
-  auto lds = [&](int i) -> E& { return sm[r * RSR + i]; };
-  auto to_lds = [&](int i, const E& e) { sm[r * RSR + i] = e; };
+  auto lds = [&](int i) -> E& { return sm[r * RSR + RL::idx(i)]; };
+  auto to_lds = [&](int i, const E& e) { sm[r * RSR + RL::idx(i)] = e; };
   EN::template run<-1>(x, t, act, lds, tw, to_lds);
   __syncthreads();
   if (act) {
@@ -622,7 +712,7 @@ k_row_r2c(Args a) {
         o[0] = mk<T>(y0.x + y0.y, y0.x - y0.y);
       } else {
         const int km = M - k;
-        const V yk = rowp[k].v[0], ym = rowp[km].v[0];
+        const V yk = rowp[RL::idx(k)].v[0], ym = rowp[RL::idx(km)].v[0];
         // X_k = (Y_k + conj Y_m)/2 + conj(w^k) (Y_k - conj Y_m)/(2i)
         const V ek = cscale(cadd(yk, cconj(ym)), (T)0.5);
         const V dk = cscale(csub(yk, cconj(ym)), (T)0.5);        // times 1/i below

@@ -207,3 +207,22 @@ def test_autograd_function(grf):
     Lb = (w * phi.double() ** 2).sum(dim=(1, 2))
     np.testing.assert_allclose(theta.grad[:, 0].cpu().numpy(), (2 * Lb / theta[:, 0]).detach().cpu().numpy(),
                                rtol=1e-5)
+
+
+@pytest.mark.parametrize("dims", [(512, 512), (96, 96)])
+def test_fused_schedule_matches_separate_passes(grf, dims):
+    """The opt-in chunked schedule (GRF_FUSE=1) gives the same bits."""
+    import os
+    plan = grf.Plan(dims, alg=2)
+    ref = plan.sample(seed=5, batch=9)
+    old = dict(os.environ)
+    try:
+        os.environ["GRF_FUSE"] = "1"
+        os.environ["GRF_CHUNK_BYTES"] = str(3 * dims[0] * dims[1] * 4)   # 3 fields per chunk, ragged tail
+        got = plan.sample(seed=5, batch=9)
+        n = grf.grf_sample_stage_count(plan.handle, 9)
+    finally:
+        os.environ.clear()
+        os.environ.update(old)
+    assert n == 4
+    assert torch.equal(got, ref)
