@@ -159,6 +159,45 @@ grf_status grf_backward(grf_plan plan, uint64_t seed, const void* noise, int64_t
                         const void* grad_out, double* grad_theta, void* grad_noise, void* workspace,
                         size_t workspace_bytes, void* stream);
 
+/* ---- Batches of fields with different sizes and parameters --------------
+ * d = 2, one-FFT algorithm, float32.  Every field has its own grid, edge
+ * lengths, covariance parameters and seed.  grf_batch_sample runs the whole
+ * batch as two persistent launches (column generation of every field, then
+ * the last-axis pass of every field), each workgroup taking work items from an
+ * atomic queue in decreasing order of cost; the launches are captured once in
+ * a hipGraph and replayed.  Results are bit-identical to sampling each field
+ * with its own plan.  N_1 must be one of {64, 96, 128, 180, 256, 360, 500, 512,
+ * 1000, 1024} and N_2/2 one of {32, 48, 64, 96, 128, 180, 256, 360, 500, 512}. */
+typedef struct grf_batch_s* grf_batch;
+
+typedef struct {
+  int64_t dims[2];      /* N_1, N_2 (even) */
+  double lengths[2];    /* l_1, l_2 > 0 */
+  int32_t cov_kind;     /* GRF_COV_* */
+  int32_t reserved;
+  double sigma, length_scale, nu;
+  uint64_t seed;        /* Philox key of this field */
+} grf_field_desc;
+
+/* fields: host array of nfields descriptors (copied).  Allocates the device
+ * tables of the batch (field records, work queues, twiddles).  Tile shapes come
+ * from the autotune cache file named by GRF_TUNE_CACHE when it exists. */
+grf_status grf_batch_create(const grf_field_desc* fields, int64_t nfields, grf_batch* out);
+/* Output layout: field f occupies elements [offsets[f], offsets[f+1]) of the
+ * output, row-major N_1 x N_2; offsets is a host array of nfields + 1. */
+grf_status grf_batch_offsets(grf_batch b, int64_t* offsets);
+/* Sample every field into out (device, offsets[nfields] float32 elements). */
+grf_status grf_batch_sample(grf_batch b, void* out, void* stream);
+/* The same fields, one plan-style launch pair per field (the baseline the
+ * persistent launch is compared with). */
+grf_status grf_batch_sample_plain(grf_batch b, void* out, void* stream);
+/* Autotuner: times both tile shapes of each length present in the batch on
+ * the batch's own work items (writing into out, which must hold the batch),
+ * keeps the faster, and appends the choice to the GRF_TUNE_CACHE file if set.
+ * Synchronises the stream. */
+grf_status grf_batch_tune(grf_batch b, void* out, void* stream);
+grf_status grf_batch_destroy(grf_batch b);
+
 /* Raw Philox-4x32-10 blocks: counters (device, n x 4 uint32) -> out (device,
  * n x 4 uint32) under key = seed.  For bit-exact checks of the generator. */
 grf_status grf_debug_philox(uint64_t seed, const uint32_t* counters, int64_t n, uint32_t* out, void* stream);

@@ -11,7 +11,7 @@ and streams) into its C ABI.
     phi = plan.sample(seed=0, batch=1024)              # [1024, 512, 512] float32 on cuda
     phi = GRFSample.apply(theta, plan, seed, noise)    # differentiable in theta (and noise)
 """
-from .api import Plan, GRFSample, COV_KINDS  # noqa: F401
+from .api import Plan, Batch, GRFSample, COV_KINDS  # noqa: F401
 from ._lib import (GRFError, grf_plan_create, grf_plan_destroy, grf_workspace_size,  # noqa: F401
                    grf_sample, grf_sample_stage_count, grf_sample_stage,
                    grf_sample_from_noise, grf_noise, grf_backward, grf_debug_philox,

@@ -18,13 +18,20 @@ STATUS_NAMES = {0: "GRF_OK", -1: "GRF_EINVAL", -2: "GRF_ENOMEM", -3: "GRF_EDEVIC
 # every symbol include/grf.h declares
 EXPORTS = ["grf_plan_create", "grf_plan_destroy", "grf_workspace_size", "grf_sample",
            "grf_sample_stage_count", "grf_sample_stage", "grf_sample_from_noise", "grf_noise", "grf_backward", "grf_debug_philox",
-           "grf_last_error", "grf_version"]
+           "grf_batch_create", "grf_batch_offsets", "grf_batch_sample", "grf_batch_sample_plain",
+           "grf_batch_tune", "grf_batch_destroy", "grf_last_error", "grf_version"]
 
 
 class grf_plan_desc(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("alg", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("cov_kind", ctypes.c_int32), ("dims", ctypes.c_int64 * 3), ("lengths", ctypes.c_double * 3),
                 ("sigma", ctypes.c_double), ("length_scale", ctypes.c_double), ("nu", ctypes.c_double)]
+
+
+class grf_field_desc(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int64 * 2), ("lengths", ctypes.c_double * 2), ("cov_kind", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("sigma", ctypes.c_double), ("length_scale", ctypes.c_double),
+                ("nu", ctypes.c_double), ("seed", ctypes.c_uint64)]
 
 
 class GRFError(RuntimeError):
@@ -50,6 +57,12 @@ def _load():
         "grf_noise": (ctypes.c_int, [vp, u64, c64, vp, vp]),
         "grf_backward": (ctypes.c_int, [vp, u64, vp, c64, vp, vp, vp, vp, vp, sz, vp]),
         "grf_debug_philox": (ctypes.c_int, [u64, vp, c64, vp, vp]),
+        "grf_batch_create": (ctypes.c_int, [ctypes.POINTER(grf_field_desc), c64, ctypes.POINTER(vp)]),
+        "grf_batch_offsets": (ctypes.c_int, [vp, ctypes.POINTER(c64)]),
+        "grf_batch_sample": (ctypes.c_int, [vp, vp, vp]),
+        "grf_batch_sample_plain": (ctypes.c_int, [vp, vp, vp]),
+        "grf_batch_tune": (ctypes.c_int, [vp, vp, vp]),
+        "grf_batch_destroy": (ctypes.c_int, [vp]),
         "grf_last_error": (ctypes.c_char_p, []),
         "grf_version": (ctypes.c_char_p, []),
     }
@@ -117,6 +130,36 @@ def grf_backward(plan, seed, noise, batch, theta, grad_out, grad_theta, grad_noi
 
 def grf_debug_philox(seed, counters, n, out, stream):
     return check(lib.grf_debug_philox(seed, counters, n, out, stream))
+
+
+def grf_batch_create(fields):
+    n = len(fields)
+    arr = (grf_field_desc * n)(*fields)
+    h = ctypes.c_void_p()
+    check(lib.grf_batch_create(arr, n, ctypes.byref(h)))
+    return h
+
+
+def grf_batch_offsets(batch, nfields):
+    arr = (ctypes.c_int64 * (nfields + 1))()
+    check(lib.grf_batch_offsets(batch, arr))
+    return list(arr)
+
+
+def grf_batch_sample(batch, out, stream):
+    return check(lib.grf_batch_sample(batch, out, stream))
+
+
+def grf_batch_sample_plain(batch, out, stream):
+    return check(lib.grf_batch_sample_plain(batch, out, stream))
+
+
+def grf_batch_tune(batch, out, stream):
+    return check(lib.grf_batch_tune(batch, out, stream))
+
+
+def grf_batch_destroy(batch):
+    return check(lib.grf_batch_destroy(batch))
 
 
 def grf_last_error():

@@ -154,3 +154,58 @@ class GRFSample(torch.autograd.Function):
         if ctx.theta_dim == 1:
             gt = gt.sum(0)
         return gt, None, None, gz
+
+
+class Batch:
+    """Fields of different sizes and parameters (d = 2, one-FFT, float32)
+    sampled together by two persistent launches replayed from a hipGraph.
+
+    fields: iterable of dicts with keys dims=(N_1, N_2), seed, and optionally
+    lengths, cov ('gaussian' | 'matern' | 'exponential'), sigma, length_scale, nu.
+    """
+
+    def __init__(self, fields, device=None):
+        descs = []
+        for f in fields:
+            d = L.grf_field_desc()
+            d.dims[0], d.dims[1] = (int(v) for v in f["dims"])
+            ls = f.get("lengths", (1.0, 1.0))
+            d.lengths[0], d.lengths[1] = float(ls[0]), float(ls[1])
+            d.cov_kind = COV_KINDS[f.get("cov", "matern")]
+            d.sigma = float(f.get("sigma", 1.0))
+            d.length_scale = float(f.get("length_scale", 0.1))
+            d.nu = float(f.get("nu", 1.5))
+            d.seed = int(f["seed"]) & (2 ** 64 - 1)
+            descs.append(d)
+        self.n = len(descs)
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        with torch.cuda.device(self.device):
+            self.handle = L.grf_batch_create(descs)
+        self.offsets = L.grf_batch_offsets(self.handle, self.n)
+        self.dims = [tuple(int(v) for v in f["dims"]) for f in fields]
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                L.lib.grf_batch_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    def empty(self):
+        return torch.empty(self.offsets[-1], dtype=torch.float32, device=self.device)
+
+    def sample(self, out=None, plain=False):
+        """Flat float32 output; field f is out[offsets[f]:offsets[f+1]] viewed as dims[f]."""
+        out = self.empty() if out is None else out
+        f = L.grf_batch_sample_plain if plain else L.grf_batch_sample
+        f(self.handle, _ptr(out), _stream())
+        return out
+
+    def tune(self, out=None):
+        out = self.empty() if out is None else out
+        L.grf_batch_tune(self.handle, _ptr(out), _stream())
+
+    def field(self, out, f):
+        return out[self.offsets[f]:self.offsets[f + 1]].view(self.dims[f])

@@ -26,6 +26,7 @@
 
 #include "../../include/grf.h"
 #include "grf_dispatch.hpp"
+#include "grf_host.hpp"
 #include "grf_kernels.hpp"
 
 using grf::Args;
@@ -47,7 +48,8 @@ struct grf_plan_s {
   int device = 0;
 };
 
-namespace {
+namespace grf {
+namespace host {
 
 thread_local std::string g_err;
 
@@ -67,9 +69,8 @@ bool smooth235(long long n) {
   return n == 1;
 }
 
-// W_L[i] = exp(2 pi i i / L) in float64, stored in the working precision.
-grf_status make_table(int L, int dtype, void** out) {
-  std::vector<double> w(2 * (size_t)L);
+void table_values(int L, std::vector<double>& w) {
+  w.resize(2 * (size_t)L);
   for (int i = 0; i < L; ++i) {
     // reduce i/L to an angle in [-pi, pi] before cos/sin for accuracy
     long long ii = i;
@@ -78,6 +79,12 @@ grf_status make_table(int L, int dtype, void** out) {
     w[2 * i] = std::cos(ang);
     w[2 * i + 1] = std::sin(ang);
   }
+}
+
+// W_L[i] = exp(2 pi i i / L) in float64, stored in the working precision.
+grf_status make_table(int L, int dtype, void** out) {
+  std::vector<double> w;
+  table_values(L, w);
   const size_t bytes = (size_t)L * 2 * (dtype == GRF_F32 ? 4 : 8);
   hipError_t e = hipMalloc(out, bytes);
   if (e != hipSuccess) return fail(GRF_ENOMEM, "hipMalloc of twiddle table failed");
@@ -90,6 +97,17 @@ grf_status make_table(int L, int dtype, void** out) {
   if (e != hipSuccess) return hip_fail(e, "twiddle upload");
   return GRF_OK;
 }
+
+}  // namespace host
+}  // namespace grf
+
+namespace {
+
+using grf::host::fail;
+using grf::host::g_err;
+using grf::host::hip_fail;
+using grf::host::make_table;
+using grf::host::smooth235;
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 

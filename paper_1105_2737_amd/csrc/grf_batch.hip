@@ -1,0 +1,195 @@
+// Persistent launches for batches of fields of different sizes (d = 2,
+// one-FFT algorithm, float32).  See grf_batch.hpp.
+//
+// Both passes reuse the kernel bodies of the single-plan sampler
+// (ColPass / RowC2R), so a field sampled in a batch has the same bits as the
+// same field sampled by a plan.  Column workgroups have 256 threads and at most
+// ~48 KB of LDS (three per CU at the column bodies' register use); row
+// workgroups 512 threads and at most ~70 KB (two per CU).  Each length has two
+// tile shapes (the second with half the columns / rows per workgroup) between
+// which the autotuner chooses.
+#include "grf_batch.hpp"
+#include "grf_configs.hpp"
+#include "grf_kernels.hpp"
+
+namespace grf {
+
+// (length, column pairs variant 0, variant 1)
+#define GRF_BATCH_COL(X) X(64, 32, 16) X(96, 16, 8) X(128, 16, 8) X(180, 7, 4) X(256, 8, 4) \
+  X(360, 5, 3) X(500, 4, 2) X(512, 4, 2) X(1000, 2, 1) X(1024, 2, 1)
+// (half-length, rows variant 0, variant 1)
+#define GRF_BATCH_ROW(X) X(32, 128, 64) X(48, 64, 32) X(64, 64, 32) X(96, 42, 21) X(128, 64, 32) \
+  X(180, 14, 7) X(256, 32, 16) X(360, 11, 5) X(500, 10, 5) X(512, 8, 4)
+
+template <int L, int CP>
+using BColPass = ColPass<float, L, typename ColCfg<L>::Rad, CP, ColCfg<L>::PAD, SRC_GEN, +1>;
+template <int M, int RB>
+using BRowPass = RowC2R<float, M, typename RowCfg<M>::Rad, RB, 0>;
+
+// LDS of the largest body
+#define GRF_COL_LDS(L_, A_, B_) (BColPass<L_, A_>::LDS_BYTES > BColPass<L_, B_>::LDS_BYTES ? BColPass<L_, A_>::LDS_BYTES : BColPass<L_, B_>::LDS_BYTES),
+#define GRF_ROW_LDS(M_, A_, B_) (BRowPass<M_, A_>::LDS_BYTES > BRowPass<M_, B_>::LDS_BYTES ? BRowPass<M_, A_>::LDS_BYTES : BRowPass<M_, B_>::LDS_BYTES),
+constexpr int col_lds_list[] = {GRF_BATCH_COL(GRF_COL_LDS) 0};
+constexpr int row_lds_list[] = {GRF_BATCH_ROW(GRF_ROW_LDS) 0};
+constexpr int max_of(const int* a, int n) {
+  int m = 0;
+  for (int i = 0; i < n; ++i) m = a[i] > m ? a[i] : m;
+  return m;
+}
+constexpr int COL_LDS = max_of(col_lds_list, sizeof(col_lds_list) / sizeof(int));
+constexpr int ROW_LDS = max_of(row_lds_list, sizeof(row_lds_list) / sizeof(int));
+static_assert(COL_LDS <= 52 * 1024, "three column workgroups per CU");
+static_assert(ROW_LDS <= 80 * 1024, "two row workgroups per CU");
+
+#define GRF_CHECK_THREADS(L_, A_, B_) static_assert(BColPass<L_, A_>::THREADS <= BATCH_COL_THREADS, "too many threads");
+GRF_BATCH_COL(GRF_CHECK_THREADS)
+#undef GRF_CHECK_THREADS
+#define GRF_CHECK_THREADS(M_, A_, B_) static_assert(BRowPass<M_, A_>::THREADS <= BATCH_ROW_THREADS, "too many threads");
+GRF_BATCH_ROW(GRF_CHECK_THREADS)
+#undef GRF_CHECK_THREADS
+
+__device__ __forceinline__ Args batch_args(const BatchField& f, const BatchField* F, int field, float* out,
+                                           const float2* tw) {
+  Args a;
+  a.data = (void*)(out + f.out_off);
+  a.src = nullptr;
+  a.aux = nullptr;
+  a.partial = nullptr;
+  a.recs = &F[field].rec;
+  a.tw = tw + f.tw1;
+  a.tw2 = tw + f.twd;
+  a.seed = f.seed;
+  a.field_stride = (long long)f.n1 * f.M;
+  a.stride_ax = f.M;
+  a.stride_fixed = f.M;
+  a.rows = f.n1;
+  a.il2[0] = f.il2[0];
+  a.il2[1] = f.il2[1];
+  a.il2[2] = f.il2[2];
+  a.scale = 1.0;
+  a.rec_stride = 0;
+  a.batch = 1;
+  a.n1 = f.n1;
+  a.no = 1;
+  a.nd = f.nd;
+  a.M = f.M;
+  a.ntile = f.ntile;
+  a.nfixed = 1;
+  a.rows_per_field = f.n1;
+  a.tag = 1;
+  return a;
+}
+
+// One body per (length, tile shape), compiled as a separate function so that
+// each gets its own register allocation (inlined into one switch, the
+// allocator handles all bodies together and spills).
+template <int L, int CP>
+__device__ __attribute__((noinline)) void bcol_body(const BatchField* F, int field, int sub, float* out,
+                                                    const float2* tw, char* smem) {
+  const Args a = batch_args(F[field], F, field, out, tw);
+  BColPass<L, CP>::run(a, sub, smem);
+}
+template <int M, int RB>
+__device__ __attribute__((noinline)) void brow_body(const BatchField* F, int field, int sub, float* out,
+                                                    const float2* tw, char* smem) {
+  const Args a = batch_args(F[field], F, field, out, tw);
+  BRowPass<M, RB>::run(a, sub, smem);
+}
+
+// Next work item of the workgroup (uniform); -1 when the queue is drained.
+__device__ __forceinline__ int next_item(int* counter, int n, int* s_item) {
+  if (threadIdx.x == 0) *s_item = atomicAdd(counter, 1);
+  __syncthreads();
+  const int i = *s_item;
+  __syncthreads();
+  return i < n ? i : -1;
+}
+
+__global__ void __launch_bounds__(BATCH_COL_THREADS)
+k_batch_col(const BatchField* __restrict__ F, const BatchItem* __restrict__ items, int n, const float2* tw,
+            float* out, int* counter) {
+  __shared__ __align__(16) char smem[COL_LDS];
+  __shared__ int s_item;
+  for (int i = next_item(counter, n, &s_item); i >= 0; i = next_item(counter, n, &s_item)) {
+    const BatchItem w = items[i];
+    const BatchField& f = F[w.field];
+    const int key = f.n1 * 4 + f.cvar;
+    switch (key) {
+#define GRF_CASE(L_, A_, B_)                                                  \
+  case L_ * 4 + 0: bcol_body<L_, A_>(F, w.field, w.sub, out, tw, smem); break; \
+  case L_ * 4 + 1: bcol_body<L_, B_>(F, w.field, w.sub, out, tw, smem); break;
+      GRF_BATCH_COL(GRF_CASE)
+#undef GRF_CASE
+      default: break;
+    }
+    __syncthreads();  // the next item reuses the LDS
+  }
+}
+
+__global__ void __launch_bounds__(BATCH_ROW_THREADS)
+k_batch_row(const BatchField* __restrict__ F, const BatchItem* __restrict__ items, int n, const float2* tw,
+            float* out, int* counter) {
+  __shared__ __align__(16) char smem[ROW_LDS];
+  __shared__ int s_item;
+  for (int i = next_item(counter, n, &s_item); i >= 0; i = next_item(counter, n, &s_item)) {
+    const BatchItem w = items[i];
+    const BatchField& f = F[w.field];
+    const int key = f.M * 4 + f.rvar;
+    switch (key) {
+#define GRF_CASE(M_, A_, B_)                                                  \
+  case M_ * 4 + 0: brow_body<M_, A_>(F, w.field, w.sub, out, tw, smem); break; \
+  case M_ * 4 + 1: brow_body<M_, B_>(F, w.field, w.sub, out, tw, smem); break;
+      GRF_BATCH_ROW(GRF_CASE)
+#undef GRF_CASE
+      default: break;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_reset_counters(int* c, int n) {
+  if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
+}
+
+int batch_col_cp(int L, int var) {
+  switch (L) {
+#define GRF_X(L_, A_, B_) \
+  case L_: return var == 0 ? A_ : B_;
+    GRF_BATCH_COL(GRF_X)
+#undef GRF_X
+    default: return 0;
+  }
+}
+int batch_row_rb(int M, int var) {
+  switch (M) {
+#define GRF_X(M_, A_, B_) \
+  case M_: return var == 0 ? A_ : B_;
+    GRF_BATCH_ROW(GRF_X)
+#undef GRF_X
+    default: return 0;
+  }
+}
+bool batch_col_supported(int L) { return batch_col_cp(L, 0) > 0; }
+bool batch_row_supported(int M) { return batch_row_rb(M, 0) > 0; }
+
+hipError_t launch_batch_col(const BatchField* fields, const BatchItem* items, int nitems, const void* twpool,
+                            float* out, int* counter, int nwg, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_col, dim3(nwg), dim3(BATCH_COL_THREADS), 0, s, fields, items, nitems,
+                     (const float2*)twpool, out, counter);
+  return hipGetLastError();
+}
+hipError_t launch_batch_row(const BatchField* fields, const BatchItem* items, int nitems, const void* twpool,
+                            float* out, int* counter, int nwg, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_row, dim3(nwg), dim3(BATCH_ROW_THREADS), 0, s, fields, items, nitems,
+                     (const float2*)twpool, out, counter);
+  return hipGetLastError();
+}
+const void* k_batch_col_ptr() { return reinterpret_cast<const void*>(&k_batch_col); }
+const void* k_batch_row_ptr() { return reinterpret_cast<const void*>(&k_batch_row); }
+
+hipError_t launch_reset_counters(int* counters, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, counters, n);
+  return hipGetLastError();
+}
+
+}  // namespace grf

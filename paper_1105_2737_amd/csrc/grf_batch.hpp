@@ -1,0 +1,52 @@
+// Batches of fields with different grid sizes and parameters (d = 2, one-FFT
+// algorithm, float32), sampled by two persistent launches: every workgroup
+// takes work items -- (field, column tile) for the column generation pass,
+// (field, row block) for the last-axis pass -- from an atomic queue in
+// decreasing order of cost and runs the kernel body of the field's length.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "grf_common.hpp"
+
+namespace grf {
+
+// Device record of one field of a batch.
+struct BatchField {
+  long long out_off;          // offset of the field in the output (real elements)
+  unsigned long long seed;    // Philox key of the field
+  int n1, nd, M;              // N_1, N_2, N_2 / 2
+  int cvar, rvar;             // tile-shape variants of the two passes
+  int ntile;                  // column tiles of the field (for its variant)
+  int tw1, twd;               // offsets of W_{N_1} and W_{N_2} in the twiddle pool (complex)
+  int pad;
+  double il2[3];
+  FieldRec rec;
+};
+
+struct BatchItem {
+  int field;
+  int sub;                    // column tile or row block
+};
+
+constexpr int BATCH_COL_THREADS = 256;
+constexpr int BATCH_ROW_THREADS = 512;
+constexpr int BATCH_VARIANTS = 2;
+
+// Geometry of a variant: column pairs per column workgroup / rows per row workgroup.
+int batch_col_cp(int L, int var);
+int batch_row_rb(int M, int var);
+bool batch_col_supported(int L);
+bool batch_row_supported(int M);
+
+// One persistent launch over `nitems` items (grid = nwg workgroups).
+hipError_t launch_batch_col(const BatchField* fields, const BatchItem* items, int nitems, const void* twpool,
+                            float* out, int* counter, int nwg, hipStream_t s);
+hipError_t launch_batch_row(const BatchField* fields, const BatchItem* items, int nitems, const void* twpool,
+                            float* out, int* counter, int nwg, hipStream_t s);
+hipError_t launch_reset_counters(int* counters, int n, hipStream_t s);
+// The two persistent kernels (for occupancy queries).
+const void* k_batch_col_ptr();
+const void* k_batch_row_ptr();
+
+}  // namespace grf

@@ -1,0 +1,410 @@
+// Host side of the batch entry points of include/grf.h: field records, work
+// queues, the hipGraph of the two persistent launches, the one-field-per-launch
+// baseline and the tile-shape autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/grf.h"
+#include "grf_batch.hpp"
+#include "grf_dispatch.hpp"
+#include "grf_host.hpp"
+#include "grf_kernels.hpp"
+
+using grf::BatchField;
+using grf::BatchItem;
+using grf::host::fail;
+using grf::host::hip_fail;
+
+struct grf_batch_s {
+  std::vector<grf_field_desc> desc;
+  std::vector<long long> offsets;      // element offsets, nfields + 1
+  std::vector<BatchField> fields;      // host copy of the device records
+  std::map<int, int> cvar, rvar;       // tile-shape variant per column length / half-length
+  std::map<int, int> twoff;            // twiddle pool offset per length
+  BatchField* d_fields = nullptr;
+  BatchItem* d_col = nullptr;
+  BatchItem* d_row = nullptr;
+  int ncol = 0, nrow = 0;
+  void* d_tw = nullptr;
+  int* d_counters = nullptr;
+  int nwg_col = 0, nwg_row = 0;
+  hipStream_t cap = nullptr;           // capture stream
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* graph_out = nullptr;           // output pointer baked into the graph
+  int device = 0;
+};
+
+namespace {
+
+void free_graph(grf_batch_s* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->graph_out = nullptr;
+}
+
+// Cost weights for largest-first ordering of the work queues.
+struct WItem {
+  BatchItem it;
+  long long cost;
+};
+
+// (Re)build field records and work queues for the current variants; upload.
+grf_status build_queues(grf_batch_s* b) {
+  const int n = (int)b->desc.size();
+  std::vector<WItem> col, row;
+  for (int f = 0; f < n; ++f) {
+    BatchField& r = b->fields[f];
+    r.cvar = b->cvar[r.n1];
+    r.rvar = b->rvar[r.M];
+    const int cp = grf::batch_col_cp(r.n1, r.cvar);
+    const int rb = grf::batch_row_rb(r.M, r.rvar);
+    r.ntile = (r.M + 2 * cp - 1) / (2 * cp);
+    for (int t = 0; t < r.ntile; ++t) col.push_back({{f, t}, (long long)r.n1 * 2 * cp});
+    const int nrb = (r.n1 + rb - 1) / rb;
+    for (int k = 0; k < nrb; ++k) row.push_back({{f, k}, (long long)r.M * 2 * rb});
+  }
+  auto by_cost = [](const WItem& x, const WItem& y) {
+    if (x.cost != y.cost) return x.cost > y.cost;
+    if (x.it.field != y.it.field) return x.it.field < y.it.field;
+    return x.it.sub < y.it.sub;
+  };
+  std::stable_sort(col.begin(), col.end(), by_cost);
+  std::stable_sort(row.begin(), row.end(), by_cost);
+  std::vector<BatchItem> hc(col.size()), hr(row.size());
+  for (size_t i = 0; i < col.size(); ++i) hc[i] = col[i].it;
+  for (size_t i = 0; i < row.size(); ++i) hr[i] = row[i].it;
+  if (b->d_col) (void)hipFree(b->d_col);
+  if (b->d_row) (void)hipFree(b->d_row);
+  b->d_col = nullptr;
+  b->d_row = nullptr;
+  b->ncol = (int)hc.size();
+  b->nrow = (int)hr.size();
+  hipError_t e = hipMalloc((void**)&b->d_col, std::max<size_t>(1, hc.size()) * sizeof(BatchItem));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_row, std::max<size_t>(1, hr.size()) * sizeof(BatchItem));
+  if (e != hipSuccess) return fail(GRF_ENOMEM, "hipMalloc of work queues failed");
+  e = hipMemcpy(b->d_col, hc.data(), hc.size() * sizeof(BatchItem), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_row, hr.data(), hr.size() * sizeof(BatchItem), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_fields, b->fields.data(), b->fields.size() * sizeof(BatchField), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "batch upload");
+  free_graph(b);
+  return GRF_OK;
+}
+
+grf_status enqueue(grf_batch_s* b, void* out, hipStream_t s) {
+  hipError_t e = grf::launch_reset_counters(b->d_counters, 2, s);
+  if (e == hipSuccess)
+    e = grf::launch_batch_col(b->d_fields, b->d_col, b->ncol, b->d_tw, (float*)out, b->d_counters, b->nwg_col, s);
+  if (e == hipSuccess)
+    e = grf::launch_batch_row(b->d_fields, b->d_row, b->nrow, b->d_tw, (float*)out, b->d_counters + 1, b->nwg_row,
+                              s);
+  if (e != hipSuccess) return hip_fail(e, "batch launch");
+  return GRF_OK;
+}
+
+// Tune cache: text lines "<arch> col|row <length> <variant>".
+std::string cache_path() {
+  const char* e = std::getenv("GRF_TUNE_CACHE");
+  return e ? std::string(e) : std::string();
+}
+
+std::string arch_name(int dev) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+void load_cache(grf_batch_s* b) {
+  const std::string path = cache_path();
+  if (path.empty()) return;
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return;
+  const std::string arch = arch_name(b->device);
+  char a[64], kind[8];
+  int len, var;
+  while (std::fscanf(f, "%63s %7s %d %d", a, kind, &len, &var) == 4) {
+    if (arch != a || var < 0 || var >= grf::BATCH_VARIANTS) continue;   // foreign or corrupt entries are ignored
+    if (!std::strcmp(kind, "col") && b->cvar.count(len)) b->cvar[len] = var;
+    if (!std::strcmp(kind, "row") && b->rvar.count(len)) b->rvar[len] = var;
+  }
+  std::fclose(f);
+}
+
+}  // namespace
+
+extern "C" {
+
+grf_status grf_batch_create(const grf_field_desc* fields, int64_t nfields, grf_batch* out) {
+  if (fields == nullptr || out == nullptr) return fail(GRF_EINVAL, "null argument");
+  *out = nullptr;
+  if (nfields <= 0 || nfields > (1 << 24)) return fail(GRF_EINVAL, "nfields out of range");
+  for (int64_t f = 0; f < nfields; ++f) {
+    const grf_field_desc& d = fields[f];
+    for (int i = 0; i < 2; ++i) {
+      if (d.dims[i] <= 0 || d.dims[i] % 2) return fail(GRF_EINVAL, "grid sizes must be positive and even");
+      if (!grf::host::smooth235(d.dims[i])) return fail(GRF_EINVAL, "grid sizes must factor into 2, 3 and 5");
+      if (!(d.lengths[i] > 0) || !std::isfinite(d.lengths[i])) return fail(GRF_EINVAL, "edge lengths must be > 0");
+    }
+    if (d.cov_kind < GRF_COV_GAUSSIAN || d.cov_kind > GRF_COV_EXPONENTIAL)
+      return fail(GRF_EINVAL, "unknown covariance kind");
+    grf::FieldRec rec;
+    if (grf::make_field_rec(d.cov_kind, 2, d.lengths[0] * d.lengths[1], d.sigma, d.length_scale, d.nu, &rec) != 0)
+      return fail(GRF_EINVAL, "invalid covariance parameters");
+    if (!grf::batch_col_supported((int)d.dims[0]) || d.dims[1] > 1024 ||
+        !grf::batch_row_supported((int)(d.dims[1] / 2)))
+      return fail(GRF_EUNSUPPORTED, "grid length not in the batch lists");
+  }
+  grf_batch_s* b = new (std::nothrow) grf_batch_s();
+  if (b == nullptr) return fail(GRF_ENOMEM, "host allocation failed");
+  b->desc.assign(fields, fields + nfields);
+  hipError_t e = hipGetDevice(&b->device);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e, "hipGetDevice");
+  }
+  // twiddle pool: every distinct length once
+  std::vector<int> lens;
+  for (const auto& d : b->desc) {
+    lens.push_back((int)d.dims[0]);
+    lens.push_back((int)d.dims[1]);
+    b->cvar[(int)d.dims[0]] = 0;
+    b->rvar[(int)(d.dims[1] / 2)] = 0;
+  }
+  std::sort(lens.begin(), lens.end());
+  lens.erase(std::unique(lens.begin(), lens.end()), lens.end());
+  std::vector<float> pool;
+  for (int L : lens) {
+    b->twoff[L] = (int)(pool.size() / 2);
+    std::vector<double> w;
+    grf::host::table_values(L, w);
+    pool.insert(pool.end(), w.begin(), w.end());
+  }
+  b->offsets.resize(nfields + 1);
+  b->offsets[0] = 0;
+  b->fields.resize(nfields);
+  for (int64_t f = 0; f < nfields; ++f) {
+    const grf_field_desc& d = b->desc[f];
+    BatchField& r = b->fields[f];
+    std::memset(&r, 0, sizeof(r));
+    r.out_off = b->offsets[f];
+    r.seed = d.seed;
+    r.n1 = (int)d.dims[0];
+    r.nd = (int)d.dims[1];
+    r.M = r.nd / 2;
+    r.tw1 = b->twoff[r.n1];
+    r.twd = b->twoff[r.nd];
+    r.il2[0] = 1.0 / (d.lengths[0] * d.lengths[0]);
+    r.il2[1] = 0.0;
+    r.il2[2] = 1.0 / (d.lengths[1] * d.lengths[1]);
+    grf::make_field_rec(d.cov_kind, 2, d.lengths[0] * d.lengths[1], d.sigma, d.length_scale, d.nu, &r.rec);
+    b->offsets[f + 1] = b->offsets[f] + d.dims[0] * d.dims[1];
+  }
+  load_cache(b);
+  grf_status st = GRF_OK;
+  e = hipMalloc(&b->d_tw, pool.size() * sizeof(float));
+  if (e == hipSuccess) e = hipMemcpy(b->d_tw, pool.data(), pool.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_fields, b->fields.size() * sizeof(BatchField));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_counters, 2 * sizeof(int));
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) st = hip_fail(e, "batch allocation");
+  if (st == GRF_OK) st = build_queues(b);
+  if (st == GRF_OK) {
+    // persistent grids: every workgroup slot of the device once
+    int ncu = 0, occ_c = 0, occ_r = 0;
+    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_c, grf::k_batch_col_ptr(),
+                                                       grf::BATCH_COL_THREADS, 0);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_r, grf::k_batch_row_ptr(),
+                                                       grf::BATCH_ROW_THREADS, 0);
+    if (e != hipSuccess) st = hip_fail(e, "occupancy query");
+    b->nwg_col = std::max(1, ncu * std::max(1, occ_c));
+    b->nwg_row = std::max(1, ncu * std::max(1, occ_r));
+  }
+  if (st != GRF_OK) {
+    grf_batch_destroy(b);
+    return st;
+  }
+  *out = b;
+  return GRF_OK;
+}
+
+grf_status grf_batch_offsets(grf_batch b, int64_t* offsets) {
+  if (b == nullptr || offsets == nullptr) return fail(GRF_EINVAL, "null argument");
+  for (size_t i = 0; i < b->offsets.size(); ++i) offsets[i] = b->offsets[i];
+  return GRF_OK;
+}
+
+grf_status grf_batch_sample(grf_batch b, void* out, void* stream) {
+  if (b == nullptr || out == nullptr) return fail(GRF_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  if (b->exec == nullptr || b->graph_out != out) {
+    free_graph(b);
+    hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "graph capture");
+    grf_status st = enqueue(b, out, b->cap);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->cap, &g);
+    if (st != GRF_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "graph capture");
+    b->graph = g;
+    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      free_graph(b);
+      return hip_fail(e, "graph instantiation");
+    }
+    b->graph_out = out;
+  }
+  hipError_t e = hipGraphLaunch(b->exec, s);
+  if (e != hipSuccess) return hip_fail(e, "graph launch");
+  return GRF_OK;
+}
+
+grf_status grf_batch_sample_plain(grf_batch b, void* out, void* stream) {
+  if (b == nullptr || out == nullptr) return fail(GRF_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  for (size_t f = 0; f < b->fields.size(); ++f) {
+    const BatchField& r = b->fields[f];
+    grf::Args a;
+    std::memset(&a, 0, sizeof(a));
+    a.data = (float*)out + r.out_off;
+    a.recs = &b->d_fields[f].rec;
+    a.tw = (const float*)b->d_tw + 2 * (size_t)r.tw1;
+    a.tw2 = (const float*)b->d_tw + 2 * (size_t)r.twd;
+    a.seed = r.seed;
+    a.field_stride = (long long)r.n1 * r.M;
+    a.stride_ax = r.M;
+    a.stride_fixed = r.M;
+    a.rows = r.n1;
+    a.il2[0] = r.il2[0];
+    a.il2[2] = r.il2[2];
+    a.scale = 1.0;
+    a.batch = 1;
+    a.n1 = r.n1;
+    a.no = 1;
+    a.nd = r.nd;
+    a.M = r.M;
+    a.nfixed = 1;
+    a.rows_per_field = r.n1;
+    a.tag = 1;
+    const grf::Geom gc = grf::pass_geom(grf::PASS_COL_GEN_INV, 0, r.n1);
+    const grf::Geom gr = grf::pass_geom(grf::PASS_ROW_C2R, 0, r.M);
+    a.ntile = (r.M + 2 * gc.per_wg - 1) / (2 * gc.per_wg);
+    hipError_t e = grf::launch_pass(grf::PASS_COL_GEN_INV, 0, r.n1, a, a.ntile, s);
+    if (e == hipSuccess) e = grf::launch_pass(grf::PASS_ROW_C2R, 0, r.M, a, (r.n1 + gr.per_wg - 1) / gr.per_wg, s);
+    if (e != hipSuccess) return hip_fail(e, "plain batch launch");
+  }
+  return GRF_OK;
+}
+
+grf_status grf_batch_tune(grf_batch b, void* out, void* stream) {
+  if (b == nullptr || out == nullptr) return fail(GRF_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(GRF_EDEVICE, "event creation");
+  // time one pass of the batch restricted to the fields of one length, per variant
+  auto time_pass = [&](bool colpass, int len, int var, float* ms) -> grf_status {
+    auto& vm = colpass ? b->cvar : b->rvar;
+    const std::map<int, int> saved = vm;
+    vm[len] = var;
+    grf_status st = build_queues(b);
+    if (st != GRF_OK) return st;
+    // work items of this length only: a prefix-free filter on the host copies
+    std::vector<BatchItem> items;
+    for (size_t f = 0; f < b->fields.size(); ++f) {
+      const BatchField& r = b->fields[f];
+      if ((colpass ? r.n1 : r.M) != len) continue;
+      const int per = colpass ? grf::batch_col_cp(len, var) : grf::batch_row_rb(len, var);
+      const int nsub = colpass ? (r.M + 2 * per - 1) / (2 * per) : (r.n1 + per - 1) / per;
+      for (int k = 0; k < nsub; ++k) items.push_back({(int)f, k});
+    }
+    BatchItem* d_items = nullptr;
+    hipError_t e = hipMalloc((void**)&d_items, items.size() * sizeof(BatchItem));
+    if (e == hipSuccess) e = hipMemcpy(d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice);
+    float best = 1e30f;
+    for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+      e = grf::launch_reset_counters(b->d_counters, 2, s);
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      if (e == hipSuccess)
+        e = colpass ? grf::launch_batch_col(b->d_fields, d_items, (int)items.size(), b->d_tw, (float*)out,
+                                            b->d_counters, b->nwg_col, s)
+                    : grf::launch_batch_row(b->d_fields, d_items, (int)items.size(), b->d_tw, (float*)out,
+                                            b->d_counters + 1, b->nwg_row, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float t = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+      if (rep > 0) best = std::min(best, t);   // first run warms up
+    }
+    if (d_items) (void)hipFree(d_items);
+    vm = saved;
+    if (e != hipSuccess) return hip_fail(e, "tuning run");
+    *ms = best;
+    return GRF_OK;
+  };
+  grf_status st = GRF_OK;
+  std::string lines;
+  const std::string arch = arch_name(b->device);
+  for (int pass = 0; pass < 2 && st == GRF_OK; ++pass) {
+    auto& vm = pass == 0 ? b->cvar : b->rvar;
+    for (auto& kv : std::map<int, int>(vm)) {
+      float tv[grf::BATCH_VARIANTS];
+      for (int v = 0; v < grf::BATCH_VARIANTS && st == GRF_OK; ++v) st = time_pass(pass == 0, kv.first, v, &tv[v]);
+      if (st != GRF_OK) break;
+      int bv = 0;
+      for (int v = 1; v < grf::BATCH_VARIANTS; ++v)
+        if (tv[v] < tv[bv]) bv = v;
+      vm[kv.first] = bv;
+      char buf[96];
+      std::snprintf(buf, sizeof(buf), "%s %s %d %d\n", arch.c_str(), pass == 0 ? "col" : "row", kv.first, bv);
+      lines += buf;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != GRF_OK) return st;
+  st = build_queues(b);
+  if (st != GRF_OK) return st;
+  const std::string path = cache_path();
+  if (!path.empty()) {
+    FILE* f = std::fopen(path.c_str(), "a");
+    if (f) {
+      std::fputs(lines.c_str(), f);
+      std::fclose(f);
+    }
+  }
+  return GRF_OK;
+}
+
+grf_status grf_batch_destroy(grf_batch b) {
+  if (b == nullptr) return GRF_OK;
+  free_graph(b);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->d_fields) (void)hipFree(b->d_fields);
+  if (b->d_col) (void)hipFree(b->d_col);
+  if (b->d_row) (void)hipFree(b->d_row);
+  if (b->d_tw) (void)hipFree(b->d_tw);
+  if (b->d_counters) (void)hipFree(b->d_counters);
+  delete b;
+  return GRF_OK;
+}
+
+}  // extern "C"

@@ -5,7 +5,9 @@
 
 namespace grf {
 
-// Column (leading-axis) transforms.
+// Column (leading-axis) transforms.  Radices stay <= 10 here: a thread holds
+// a column pair, and a radix-16 butterfly on pairs keeps 32 complex values
+// live, which costs occupancy.
 template <int L> struct ColCfg;
 #define GRF_COLCFG(L_, CP32_, CP64_, PAD_, ...)            \
   template <> struct ColCfg<L_> {                          \
@@ -20,15 +22,15 @@ GRF_COLCFG(24, 16, 16, 1, 4, 6)
 GRF_COLCFG(32, 16, 16, 1, 8, 4)
 GRF_COLCFG(48, 16, 8, 1, 6, 8)
 GRF_COLCFG(64, 16, 8, 1, 8, 8)
-GRF_COLCFG(96, 16, 8, 1, 8, 12)
-GRF_COLCFG(128, 16, 8, 1, 16, 8)
+GRF_COLCFG(96, 16, 8, 1, 8, 4, 3)
+GRF_COLCFG(128, 16, 8, 1, 8, 4, 4)
 GRF_COLCFG(180, 8, 4, 1, 5, 6, 6)
-GRF_COLCFG(256, 8, 4, 1, 16, 16)
+GRF_COLCFG(256, 8, 4, 1, 8, 8, 4)
 GRF_COLCFG(360, 8, 4, 1, 8, 5, 9)
 GRF_COLCFG(500, 4, 2, 1, 10, 10, 5)
 GRF_COLCFG(512, 8, 4, 1, 8, 8, 8)
 GRF_COLCFG(1000, 4, 2, 0, 10, 10, 10)
-GRF_COLCFG(1024, 4, 2, 0, 16, 8, 8)
+GRF_COLCFG(1024, 4, 2, 0, 8, 8, 4, 4)
 #undef GRF_COLCFG
 
 // Row (last-axis) transforms of half-length M.

@@ -89,3 +89,19 @@ def test_null_arguments():
     assert L.lib.grf_debug_philox(0, None, -1, None, None) == L.GRF_EINVAL
     assert L.lib.grf_debug_philox(0, None, 0, None, None) == L.GRF_OK
     assert L.grf_version().startswith("grf-mi355x")
+
+
+@pytest.mark.parametrize("dims,status", [((64, 63), -1), ((64, 14), -1), ((2048, 64), -4), ((64, 2048), -4),
+                                         ((4, 64), -4)])
+def test_batch_descriptors_rejected_on_the_host(dims, status):
+    from paper_1105_2737_amd import _lib as L
+    d = L.grf_field_desc()
+    d.dims[0], d.dims[1] = dims
+    d.lengths[0] = d.lengths[1] = 1.0
+    d.cov_kind, d.sigma, d.length_scale, d.nu, d.seed = 1, 1.0, 0.1, 1.5, 0
+    arr = (L.grf_field_desc * 1)(d)
+    h = ctypes.c_void_p()
+    assert L.lib.grf_batch_create(arr, 1, ctypes.byref(h)) == status
+    assert not h.value
+    assert L.lib.grf_batch_create(arr, 0, ctypes.byref(h)) == L.GRF_EINVAL
+    assert L.lib.grf_batch_destroy(None) == L.GRF_OK

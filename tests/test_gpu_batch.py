@@ -1,0 +1,86 @@
+"""GPU tests of the batched uneven-size launch: each field equals the same
+field sampled by its own plan (bitwise), the float64 oracle (float32
+tolerance), the one-field-per-launch baseline (bitwise); graph replays agree
+with each other; the autotuner keeps results unchanged."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import grf as ogrf  # noqa: E402
+from oracle import spectra  # noqa: E402
+from synth import uneven_fields  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def grf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1105_2737_amd as m
+    return m
+
+
+def small_batch(n=24, seed=3):
+    fields = uneven_fields(n=n, seed=seed, sides=(64, 96, 128, 360, 512))
+    fields[0]["dims"] = (1000, 1024)     # one big field
+    fields[1]["dims"] = (1024, 64)
+    fields[2]["cov"] = "gaussian"
+    fields[3]["cov"] = "exponential"
+    fields[4]["lengths"] = (2.0, 0.5)
+    return fields
+
+
+def test_batch_matches_plans_oracle_and_plain(grf):
+    fields = small_batch()
+    print("batch dims:", [f["dims"] for f in fields], flush=True)
+    b = grf.Batch(fields)
+    out = b.sample()
+    plain = b.sample(plain=True)
+    torch.cuda.synchronize()
+    assert torch.equal(out, plain)
+    kinds = {"matern": spectra.MATERN, "gaussian": spectra.GAUSSIAN, "exponential": spectra.EXPONENTIAL}
+    for f, d in enumerate(fields):
+        plan = grf.Plan(d["dims"], lengths=d["lengths"], alg=2, cov=d["cov"], sigma=d["sigma"],
+                        length_scale=d["length_scale"], nu=d["nu"])
+        ref = plan.sample(seed=d["seed"], batch=1)[0]
+        assert torch.equal(b.field(out, f), ref), f
+        if f < 8:
+            o = ogrf.sample(d["dims"], d["lengths"], kinds[d["cov"]], d["sigma"], d["length_scale"], d["nu"],
+                            seed=d["seed"], batch=1, alg=2)[0]
+            got = b.field(out, f).double().cpu().numpy()
+            assert np.abs(got - o).max() / np.abs(o).max() <= 1e-5
+
+
+def test_graph_replays_agree(grf):
+    b = grf.Batch(small_batch(16, seed=5))
+    out = b.empty()
+    b.sample(out=out)
+    first = out.clone()
+    scratch = torch.empty(1 << 20, device="cuda")
+    for k in range(4):
+        out.fill_(float("nan"))
+        scratch.normal_()                      # unrelated eager work between replays
+        _ = scratch.sum().item()
+        b.sample(out=out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, first), k
+
+
+def test_tuning_keeps_results(grf, tmp_path, monkeypatch):
+    monkeypatch.setenv("GRF_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    fields = small_batch(12, seed=7)
+    b = grf.Batch(fields)
+    ref = b.sample().clone()
+    b.tune()
+    got = b.sample()
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    lines = (tmp_path / "tune.txt").read_text().split("\n")
+    assert any(" col " in l for l in lines) and any(" row " in l for l in lines)
+    # a new batch reads the cache; a corrupt line is ignored
+    with open(tmp_path / "tune.txt", "a") as fh:
+        fh.write("gfx950 col 512 7\ngarbage\n")
+    b2 = grf.Batch(fields)
+    assert torch.equal(b2.sample(), ref)
