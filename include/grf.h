@@ -131,8 +131,9 @@ grf_status grf_sample_from_noise(grf_plan plan, const void* noise, int64_t batch
  * complex-to-real; d = 3 adds the middle-axis inverse transform; two-FFT:
  * last-axis noise + real-to-complex, column forward/filter/inverse, last-axis
  * complex-to-real; with the environment variable GRF_FUSE=1 a one-FFT d = 2
- * batch of a square grid instead runs chunk by chunk, each launch pairing the
- * column pass of one chunk with the last-axis pass of the previous chunk).
+ * batch of two or more fields on a supported grid runs chunk by chunk instead,
+ * each launch pairing the column pass of one chunk with the last-axis pass of
+ * the previous chunk, GRF_CHUNK_BYTES setting the chunk size).
  * grf_sample_stage_count returns the number of launches for a batch of
  * `batch` fields (host pointer); grf_sample_stage runs only launch `stage`
  * (0-based) with the arguments of grf_sample, so that each kernel can be

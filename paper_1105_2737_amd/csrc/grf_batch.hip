@@ -19,7 +19,7 @@ namespace grf {
   X(360, 5, 3) X(500, 4, 2) X(512, 4, 2) X(1000, 2, 1) X(1024, 2, 1)
 // (half-length, rows variant 0, variant 1)
 #define GRF_BATCH_ROW(X) X(32, 128, 64) X(48, 64, 32) X(64, 64, 32) X(96, 42, 21) X(128, 64, 32) \
-  X(180, 14, 7) X(256, 32, 16) X(360, 11, 5) X(500, 10, 5) X(512, 8, 4)
+  X(180, 14, 7) X(256, 16, 8) X(360, 11, 5) X(500, 10, 5) X(512, 8, 4)
 
 template <int L, int CP>
 using BColPass = ColPass<float, L, typename ColCfg<L>::Rad, CP, ColCfg<L>::PAD, SRC_GEN, +1>;
@@ -58,6 +58,7 @@ __device__ __forceinline__ Args batch_args(const BatchField& f, const BatchField
   a.recs = &F[field].rec;
   a.tw = tw + f.tw1;
   a.tw2 = tw + f.twd;
+  a.htab = nullptr;            // per-field parameters: h is computed on the fly
   a.seed = f.seed;
   a.field_stride = (long long)f.n1 * f.M;
   a.stride_ax = f.M;

@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/grf.h"
+#include "grf.h"
 #include "grf_batch.hpp"
 #include "grf_dispatch.hpp"
 #include "grf_host.hpp"

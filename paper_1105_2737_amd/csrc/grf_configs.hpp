@@ -28,10 +28,17 @@ GRF_COLCFG(180, 8, 4, 1, 5, 6, 6)
 GRF_COLCFG(256, 8, 4, 1, 8, 8, 4)
 GRF_COLCFG(360, 8, 4, 1, 8, 5, 9)
 GRF_COLCFG(500, 4, 2, 1, 10, 10, 5)
-GRF_COLCFG(512, 8, 4, 1, 8, 8, 8)
+GRF_COLCFG(512, 4, 2, 0, 8, 8, 8)
 GRF_COLCFG(1000, 4, 2, 0, 10, 10, 10)
 GRF_COLCFG(1024, 4, 2, 0, 8, 8, 4, 4)
 #undef GRF_COLCFG
+
+// Column passes that load a stored spectrum and transform it forward (the
+// two-FFT filter pass and the adjoint): same radices, their own tile shapes.
+template <int L> struct ColCfgF : ColCfg<L> {};
+template <> struct ColCfgF<512> : ColCfg<512> {
+  static constexpr int CP32 = 8, CP64 = 4, PAD = 1;
+};
 
 // Row (last-axis) transforms of half-length M.
 template <int M> struct RowCfg;
@@ -51,10 +58,18 @@ GRF_ROWCFG(64, 16, 16, 8, 8)
 GRF_ROWCFG(96, 16, 8, 8, 12)
 GRF_ROWCFG(128, 16, 8, 16, 8)
 GRF_ROWCFG(180, 4, 4, 5, 6, 6)
-GRF_ROWCFG(256, 16, 8, 16, 16)
+GRF_ROWCFG(256, 8, 8, 8, 8, 4)
 GRF_ROWCFG(360, 4, 4, 8, 5, 9)
 GRF_ROWCFG(500, 4, 2, 10, 10, 5)
 GRF_ROWCFG(512, 4, 4, 8, 8, 8)
 #undef GRF_ROWCFG
+
+// Last-axis real-to-complex passes (white noise generation, upstream
+// gradient): their own radix order and tile shape where measured faster.
+template <int M> struct RowCfgG : RowCfg<M> {};
+template <> struct RowCfgG<256> {
+  using Rad = Radices<16, 16>;
+  static constexpr int RB32 = 16, RB64 = 8, PADR = 0;
+};
 
 }  // namespace grf

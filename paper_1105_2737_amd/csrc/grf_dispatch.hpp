@@ -7,6 +7,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "grf.h"
 #include "grf_common.hpp"
 
 namespace grf {
@@ -67,12 +68,15 @@ hipError_t launch_col_f32(int pass, int L, const Args& a, long long nblocks, hip
 hipError_t launch_col_f64(int pass, int L, const Args& a, long long nblocks, hipStream_t s);
 hipError_t launch_row_f32(int pass, int M, const Args& a, long long nblocks, hipStream_t s);
 hipError_t launch_row_f64(int pass, int M, const Args& a, long long nblocks, hipStream_t s);
-Geom geom_col_f32(int L);
-Geom geom_col_f64(int L);
-Geom geom_row_f32(int M);
-Geom geom_row_f64(int M);
+Geom geom_col_f32(int pass, int L);
+Geom geom_col_f64(int pass, int L);
+Geom geom_row_f32(int pass, int M);
+Geom geom_row_f64(int pass, int M);
 
 // helper kernels (grf_util.hip)
+// Device table of h for the record a.recs[0] over the plan's (row, m) grid,
+// row stride M + 2, allocated into *out (synchronous).
+grf_status build_filter_table(int dtype, Args a, double scale, void** out);
 hipError_t launch_prep_recs(const double* theta, int batch, int kind, int d, double vol, FieldRec* out, int* err,
                             hipStream_t s);
 hipError_t launch_reduce_partials(const double* partial, int batch, int nper, double* grad, hipStream_t s);

@@ -5,7 +5,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/grf.h"
+#include "grf.h"
 
 namespace grf {
 namespace host {

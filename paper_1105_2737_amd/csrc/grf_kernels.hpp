@@ -35,6 +35,7 @@ struct Args {
   const FieldRec* recs;       // per-field constants
   const void* tw;             // twiddle table W_L of the transform length (complex)
   const void* tw2;            // row passes: table W_{N_d} (complex)
+  const void* htab;           // optional filter table h[row][m], row stride M + 2 (one record for all fields)
   unsigned long long seed;
   long long field_stride;     // complex elements per field
   long long stride_ax;        // complex stride along the transformed axis
@@ -170,19 +171,34 @@ __device__ __forceinline__ void gen_pair(const Args& a, const Filt<T>& f, const 
   const int row = kk1 * a.no + o;
   T z[4];
   load_z4<T>(a, zsrc, b, row, m0, k0, k1, z);
-  const int q1 = wrapk(kk1, a.n1), qo = wrapk(o, a.no);
-  const T p2b = (T)(q1 * q1) * (T)a.il2[0] + (T)(qo * qo) * (T)a.il2[1];
-  const T il2d = (T)a.il2[2];
   const T s = (T)0.70710678118654752440;
-  const T h1 = filt_h(f, p2b + (T)((m0 + 1) * (m0 + 1)) * il2d);
+  const T* ht = (const T*)a.htab;
+  const T* hrow = ht ? ht + (long long)row * (a.M + 2) : nullptr;
+  T p2b = 0, il2d = 0;
+  if (!ht) {
+    const int q1 = wrapk(kk1, a.n1), qo = wrapk(o, a.no);
+    p2b = (T)(q1 * q1) * (T)a.il2[0] + (T)(qo * qo) * (T)a.il2[1];
+    il2d = (T)a.il2[2];
+  }
+  // h at (row, m): the table holds exactly these float values
+  auto hval = [&](int m) -> T { return hrow ? hrow[m] : filt_h(f, p2b + (T)(m * m) * il2d); };
+  T h0, h1;
+  if (hrow) {   // m0 even and an even row stride: one aligned pair load
+    struct alignas(2 * sizeof(T)) P2 { T x, y; };
+    const P2 hp = *reinterpret_cast<const P2*>(hrow + m0);
+    h0 = hp.x;
+    h1 = hp.y;
+  } else {
+    h0 = hval(m0);
+    h1 = hval(m0 + 1);
+  }
   A1 = mk<T>(h1 * s * z[2], h1 * s * z[3]);
   if (m0 > 0) {
-    const T h0 = filt_h(f, p2b + (T)(m0 * m0) * il2d);
     A0 = mk<T>(h0 * s * z[0], h0 * s * z[1]);
   } else {
     const int nrow = ((a.n1 - kk1) % a.n1) * a.no + (a.no - o) % a.no;
-    const T hz = filt_h(f, p2b);
-    const T hn = filt_h(f, p2b + (T)a.M * (T)a.M * il2d);
+    const T hz = h0;
+    const T hn = hval(a.M);
     C<T> x0, xn;
     if (nrow == row) {
       x0 = mk<T>(z[0], (T)0);
@@ -201,6 +217,29 @@ __device__ __forceinline__ void gen_pair(const Args& a, const Filt<T>& f, const 
     // A(k, 0) + i A(k, N_d/2)
     A0 = mk<T>(hz * x0.x - hn * xn.y, hz * x0.y + hn * xn.x);
   }
+}
+
+// Filter table h[row][m], m = 0..M, row stride M + 2, for one record: the
+// values gen_pair would compute (same float expressions), so that a sample is
+// bit-identical with and without the table.
+template <typename T>
+__global__ void k_filter_table(Args a, T* out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int HS = a.M + 2;
+  const long long n = (long long)a.n1 * a.no * HS;
+  if (i >= n) return;
+  const int m = (int)(i % HS);
+  const long long row = i / HS;
+  if (m > a.M) {
+    out[i] = (T)0;
+    return;
+  }
+  const int kk1 = (int)(row / a.no), o = (int)(row % a.no);
+  const Filt<T> f = load_filt<T>(a.recs[0], a.scale);
+  const int q1 = wrapk(kk1, a.n1), qo = wrapk(o, a.no);
+  const T p2b = (T)(q1 * q1) * (T)a.il2[0] + (T)(qo * qo) * (T)a.il2[1];
+  const T il2d = (T)a.il2[2];
+  out[i] = filt_h(f, p2b + (T)(m * m) * il2d);
 }
 
 // Column-pair global access: one 16-byte (float32) / 32-byte (float64) access
@@ -315,10 +354,23 @@ k_colf(Args a) {
   const bool al = (a.M & 1) == 0;
   V* base = (V*)a.data + (long long)b * a.field_stride + m0;
   V x[2][EN::REG];
+  // filter values of this thread's entries, fetched before the forward
+  // transform so that their latency is hidden behind it
+  T hp[R0][3];
+  const T* ht = (const T*)a.htab;
   if (act) {
 #pragma unroll
     for (int m = 0; m < R0; ++m)
       ld_pair<T>(base + (long long)(t + m * NT) * a.stride_ax, two, al, x[0][m], x[1][m]);
+    if (ht) {
+#pragma unroll
+      for (int m = 0; m < R0; ++m) {
+        const T* hrow = ht + (long long)(t + m * NT) * (a.M + 2);
+        hp[m][0] = hrow[m0];
+        hp[m][1] = hrow[m0 + 1];
+        hp[m][2] = m0 == 0 ? hrow[a.M] : (T)0;
+      }
+    }
   }
   auto lds = [&](int i) -> E& { return sm[i * RS + cp]; };
   auto to_lds = [&](int i, const E& e) { sm[i * RS + cp] = e; };
@@ -333,10 +385,10 @@ k_colf(Args a) {
       const int q1 = wrapk(k1, L);
       const T p2b = (T)(q1 * q1) * (T)a.il2[0];
       const E e = sm[k1 * RS + cp];
-      const T h1 = filt_h(f, p2b + (T)((m0 + 1) * (m0 + 1)) * il2d);
+      const T h1 = ht ? hp[m][1] : filt_h(f, p2b + (T)((m0 + 1) * (m0 + 1)) * il2d);
       x[1][m] = cscale(e.v[1], h1);
       if (m0 > 0) {
-        const T h0 = filt_h(f, p2b + (T)(m0 * m0) * il2d);
+        const T h0 = ht ? hp[m][0] : filt_h(f, p2b + (T)(m0 * m0) * il2d);
         x[0][m] = cscale(e.v[0], h0);
       } else {
         const V w = e.v[0];
@@ -344,8 +396,8 @@ k_colf(Args a) {
         // F[X0] = (w + conj wm)/2, F[XN] = (w - conj wm)/(2i)
         const V f0 = mk<T>((T)0.5 * (w.x + wm.x), (T)0.5 * (w.y - wm.y));
         const V fn = mk<T>((T)0.5 * (w.y + wm.y), (T)-0.5 * (w.x - wm.x));
-        const T hz = filt_h(f, p2b);
-        const T hn = filt_h(f, p2b + (T)a.M * (T)a.M * il2d);
+        const T hz = ht ? hp[m][0] : filt_h(f, p2b);
+        const T hn = ht ? hp[m][2] : filt_h(f, p2b + (T)a.M * (T)a.M * il2d);
         const V a0 = cscale(f0, hz), an = cscale(fn, hn);
         x[0][m] = mk<T>(a0.x - an.y, a0.y + an.x);
       }
@@ -439,9 +491,10 @@ k_colg(Args a) {
       const double p2b = (double)(q1 * q1) * a.il2[0];
       const E e = sm[kk1 * RS + cp];
       T* gzr = gz ? gz + (long long)b * a.field_stride * 2 + (long long)row * a.nd + 2 * m0 : nullptr;
+      const T* hrow = a.htab ? (const T*)a.htab + (long long)row * (a.M + 2) : nullptr;
       if (two) {
         const double p2 = p2b + (double)((m0 + 1) * (m0 + 1)) * il2d;
-        const T h = filt_h(f, (T)p2);
+        const T h = hrow ? hrow[m0 + 1] : filt_h(f, (T)p2);
         add(2.0, (double)h, p2, mk<T>(s * z[2], s * z[3]), e.v[1]);
         if (gzr) {
           gzr[2] = (T)(s2 * (double)h * (double)e.v[1].x);
@@ -450,7 +503,7 @@ k_colg(Args a) {
       }
       if (m0 > 0) {
         const double p2 = p2b + (double)(m0 * m0) * il2d;
-        const T h = filt_h(f, (T)p2);
+        const T h = hrow ? hrow[m0] : filt_h(f, (T)p2);
         add(2.0, (double)h, p2, mk<T>(s * z[0], s * z[1]), e.v[0]);
         if (gzr) {
           gzr[0] = (T)(s2 * (double)h * (double)e.v[0].x);
@@ -463,8 +516,8 @@ k_colg(Args a) {
         const V gn = mk<T>((T)0.5 * (w.y + wm.y), (T)-0.5 * (w.x - wm.x));
         const int nrow = (L - kk1) % L;
         const double p2n = p2b + (double)a.M * (double)a.M * il2d;
-        const T hz = filt_h(f, (T)p2b);
-        const T hn = filt_h(f, (T)p2n);
+        const T hz = hrow ? hrow[0] : filt_h(f, (T)p2b);
+        const T hn = hrow ? hrow[a.M] : filt_h(f, (T)p2n);
         V x0, xn;
         if (nrow == row) {
           x0 = mk<T>(z[0], (T)0);

@@ -2,6 +2,7 @@
 // deterministic per-field reduction of adjoint partial sums, raw Philox output
 // and the noise array of the contract.
 #include "grf_dispatch.hpp"
+#include "grf_host.hpp"
 #include "grf_kernels.hpp"
 
 namespace grf {
@@ -60,6 +61,23 @@ __global__ void k_noise(unsigned long long seed, int tag, int rows, int nd, int 
   for (int l = 0; l < 4 && 4 * q + l < nd; ++l) p[l] = z[l];
 }
 
+
+grf_status build_filter_table(int dtype, Args a, double scale, void** out) {
+  a.scale = scale;
+  const long long n = (long long)a.n1 * a.no * (a.M + 2);
+  const size_t es = dtype == 0 ? 4 : 8;
+  hipError_t e = hipMalloc(out, n * es);
+  if (e != hipSuccess) return host::fail(GRF_ENOMEM, "hipMalloc of filter table failed");
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_filter_table<float>, grid, block, 0, 0, a, (float*)*out);
+  else
+    hipLaunchKernelGGL(k_filter_table<double>, grid, block, 0, 0, a, (double*)*out);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return host::hip_fail(e, "filter table");
+  return GRF_OK;
+}
 
 hipError_t launch_prep_recs(const double* theta, int batch, int kind, int d, double vol, FieldRec* out, int* err,
                             hipStream_t s) {

@@ -211,18 +211,23 @@ def test_autograd_function(grf):
 
 @pytest.mark.parametrize("dims", [(512, 512), (96, 96)])
 def test_fused_schedule_matches_separate_passes(grf, dims):
-    """The opt-in chunked schedule (GRF_FUSE=1) gives the same bits."""
+    """The chunked fused schedule (GRF_FUSE=1) gives the same bits as the
+    separate passes, also with a ragged last chunk."""
     import os
     plan = grf.Plan(dims, alg=2)
-    ref = plan.sample(seed=5, batch=9)
     old = dict(os.environ)
     try:
+        os.environ.pop("GRF_FUSE", None)
+        ref = plan.sample(seed=5, batch=9)
+        assert grf.grf_sample_stage_count(plan.handle, 9) == 2
         os.environ["GRF_FUSE"] = "1"
-        os.environ["GRF_CHUNK_BYTES"] = str(3 * dims[0] * dims[1] * 4)   # 3 fields per chunk, ragged tail
+        os.environ["GRF_CHUNK_BYTES"] = str(3 * dims[0] * dims[1] * 4)   # 3 fields per chunk
         got = plan.sample(seed=5, batch=9)
-        n = grf.grf_sample_stage_count(plan.handle, 9)
+        assert grf.grf_sample_stage_count(plan.handle, 9) == 4
+        os.environ["GRF_CHUNK_BYTES"] = str(4 * dims[0] * dims[1] * 4)   # 4, 4, 1
+        got2 = plan.sample(seed=5, batch=9)
     finally:
         os.environ.clear()
         os.environ.update(old)
-    assert n == 4
     assert torch.equal(got, ref)
+    assert torch.equal(got2, ref)
