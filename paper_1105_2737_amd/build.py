@@ -17,7 +17,9 @@ LIB = os.path.join(HERE, "libgrf.so")
 ARCH = os.environ.get("GRF_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
-COMMON = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
+# -ffp-contract=off: the kernels write every fused multiply-add explicitly, so
+# that a value is rounded the same way on every code path that computes it.
+COMMON = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument"]
 

@@ -179,6 +179,12 @@ Args base_args(const grf_plan_s* p, long long batch) {
   return a;
 }
 
+// Column passes take their tiles in XCD-grouped order (GRF_XCD=0 turns it off).
+int xcd_order() {
+  const char* e = std::getenv("GRF_XCD");
+  return (e && e[0] == '0') ? 0 : 1;
+}
+
 grf_status run_pass(const grf_plan_s* p, int pass, int L, Args a, long long nfixed_blocks_per_field,
                     long long batch, hipStream_t s) {
   (void)nfixed_blocks_per_field;
@@ -190,6 +196,7 @@ grf_status run_pass(const grf_plan_s* p, int pass, int L, Args a, long long nfix
   } else {
     a.ntile = (a.M + 2 * g.per_wg - 1) / (2 * g.per_wg);
     nblocks = (long long)a.ntile * a.nfixed * batch;
+    a.order = xcd_order();
   }
   if (nblocks <= 0) return GRF_OK;
   if (nblocks > 0x7fffffffLL) return fail(GRF_EINVAL, "batch too large for one launch");

@@ -78,6 +78,7 @@ __device__ __forceinline__ Args batch_args(const BatchField& f, const BatchField
   a.nfixed = 1;
   a.rows_per_field = f.n1;
   a.tag = 1;
+  a.order = 0;
   return a;
 }
 

@@ -30,8 +30,15 @@ template <typename T> using C = typename cvec<T>::type;
 template <typename T> __device__ __forceinline__ C<T> mk(T x, T y) { C<T> r; r.x = x; r.y = y; return r; }
 template <typename V> __device__ __forceinline__ V cadd(V a, V b) { a.x += b.x; a.y += b.y; return a; }
 template <typename V> __device__ __forceinline__ V csub(V a, V b) { a.x -= b.x; a.y -= b.y; return a; }
+// Fused multiply-add.  The library is compiled without automatic
+// contraction (-ffp-contract=off): every fma is written out, so that the
+// rounding of each value is fixed by the source and identical on every code
+// path that computes it (plans, batches, fused launches).
+__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
-  V r; r.x = a.x * b.x - a.y * b.y; r.y = a.x * b.y + a.y * b.x; return r;
+  V r; r.x = fmat(a.x, b.x, -(a.y * b.y)); r.y = fmat(a.x, b.y, a.y * b.x); return r;
 }
 template <typename V> __device__ __forceinline__ V cconj(V a) { a.y = -a.y; return a; }
 template <typename V, typename T> __device__ __forceinline__ V cscale(V a, T s) { a.x *= s; a.y *= s; return a; }
@@ -44,8 +51,8 @@ template <int DIR, typename V> __device__ __forceinline__ V cmuli(V a) {
 // multiply by twiddle w (DIR=+1) or conj(w) (DIR=-1)
 template <int DIR, typename V> __device__ __forceinline__ V ctw(V a, V w) {
   V r;
-  if (DIR > 0) { r.x = a.x * w.x - a.y * w.y; r.y = a.x * w.y + a.y * w.x; }
-  else         { r.x = a.x * w.x + a.y * w.y; r.y = a.y * w.x - a.x * w.y; }
+  if (DIR > 0) { r.x = fmat(a.x, w.x, -(a.y * w.y)); r.y = fmat(a.x, w.y, a.y * w.x); }
+  else         { r.x = fmat(a.x, w.x, a.y * w.y);    r.y = fmat(a.y, w.x, -(a.x * w.y)); }
   return r;
 }
 
@@ -103,7 +110,7 @@ template <int DIR, typename V> struct Dft<3, DIR, V> {
     V s = cadd(x[1], x[2]);
     V d = csub(x[1], x[2]);
     V y0 = cadd(x[0], s);
-    V t = x[0]; t.x -= (T)0.5 * s.x; t.y -= (T)0.5 * s.y;
+    V t; t.x = fmat((T)-0.5, s.x, x[0].x); t.y = fmat((T)-0.5, s.y, x[0].y);
     V u = cmuli<DIR>(cscale(d, c));
     x[0] = y0; x[1] = cadd(t, u); x[2] = csub(t, u);
   }
@@ -125,11 +132,11 @@ template <int DIR, typename V> struct Dft<5, DIR, V> {
     V p23 = cadd(x[2], x[3]), m23 = csub(x[2], x[3]);
     V y0 = cadd(x[0], cadd(p14, p23));
     V a1, a2, b1, b2;
-    a1.x = x[0].x + c1 * p14.x + c2 * p23.x; a1.y = x[0].y + c1 * p14.y + c2 * p23.y;
-    a2.x = x[0].x + c2 * p14.x + c1 * p23.x; a2.y = x[0].y + c2 * p14.y + c1 * p23.y;
+    a1.x = fmat(c2, p23.x, fmat(c1, p14.x, x[0].x)); a1.y = fmat(c2, p23.y, fmat(c1, p14.y, x[0].y));
+    a2.x = fmat(c1, p23.x, fmat(c2, p14.x, x[0].x)); a2.y = fmat(c1, p23.y, fmat(c2, p14.y, x[0].y));
     V t1, t2;
-    t1.x = s1 * m14.x + s2 * m23.x; t1.y = s1 * m14.y + s2 * m23.y;
-    t2.x = s2 * m14.x - s1 * m23.x; t2.y = s2 * m14.y - s1 * m23.y;
+    t1.x = fmat(s1, m14.x, s2 * m23.x); t1.y = fmat(s1, m14.y, s2 * m23.y);
+    t2.x = fmat(s2, m14.x, -(s1 * m23.x)); t2.y = fmat(s2, m14.y, -(s1 * m23.y));
     b1 = cmuli<DIR>(t1); b2 = cmuli<DIR>(t2);
     x[0] = y0; x[1] = cadd(a1, b1); x[4] = csub(a1, b1); x[2] = cadd(a2, b2); x[3] = csub(a2, b2);
   }

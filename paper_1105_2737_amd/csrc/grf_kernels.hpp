@@ -50,7 +50,22 @@ struct Args {
   int nfixed;                 // number of fixed indices
   int rows_per_field;
   int tag;
+  int order;                  // column passes: 1 = XCD-grouped workgroup-to-tile order (col_block)
 };
+
+// Tile index of this workgroup in a column pass.  Workgroups are dispatched to
+// the 8 XCDs round-robin (workgroup i on XCD i mod 8), and a column tile
+// writes only 16 CP bytes of each row, so adjacent tiles share cache lines.
+// With order = 1 the first n8 = gridDim.x rounded down to a multiple of 8
+// workgroups are mapped so that each XCD takes a contiguous run of tiles
+// (i -> (i mod 8) (n8 / 8) + i / 8, a bijection of [0, n8)); its L2 then
+// assembles whole lines before they are written back.
+__device__ __forceinline__ int col_block(int order) {
+  const int i = blockIdx.x, n = gridDim.x;
+  if (!order) return i;
+  const int n8 = n & ~7;
+  return i < n8 ? (i & 7) * (n8 >> 3) + (i >> 3) : i;
+}
 
 // ---------------------------------------------------------------------------
 // Block FFT engine: NC interleaved length-L transforms per thread group.
@@ -215,7 +230,7 @@ __device__ __forceinline__ void gen_pair(const Args& a, const Filt<T>& f, const 
       }
     }
     // A(k, 0) + i A(k, N_d/2)
-    A0 = mk<T>(hz * x0.x - hn * xn.y, hz * x0.y + hn * xn.x);
+    A0 = mk<T>(fmat(hz, x0.x, -(hn * xn.y)), fmat(hz, x0.y, hn * xn.x));
   }
 }
 
@@ -265,6 +280,29 @@ __device__ __forceinline__ void st_pair(C<T>* p, bool two, bool al, const Vec<T,
   }
 }
 
+// Twiddle table W_L, global -> LDS, in two steps: load() issues every global
+// load of the thread into registers, store() writes them to LDS later, so that
+// the load latency overlaps other work instead of being waited on at once.
+template <typename V, int L, int NTHR>
+struct TwFill {
+  static constexpr int N = (L + NTHR - 1) / NTHR;
+  V r[N];
+  __device__ __forceinline__ void load(const V* g, int tid) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const int i = tid + k * NTHR;
+      if (i < L) r[k] = g[i];
+    }
+  }
+  __device__ __forceinline__ void store(V* s, int tid) const {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const int i = tid + k * NTHR;
+      if (i < L) s[i] = r[k];
+    }
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Column pass over a leading axis.
 enum { SRC_GEN = 0, SRC_LOAD = 1 };
@@ -278,7 +316,51 @@ struct ColPass {
   static constexpr int RS = CP + PAD;
   static constexpr int R0 = Rad::get(0);
   static constexpr int LDS_BYTES = L * RS * (int)sizeof(E) + L * (int)sizeof(V);
+  // Straight-line generation (gen_fast) for long columns, where LDS bounds the
+  // occupancy anyway; for short columns its extra registers cost occupancy
+  // (measured: 18% slower at L = 96, 22% faster at L = 1000 and 1024).
+  static constexpr bool GEN_STRAIGHT = L >= 500;
   using EN = Eng<T, L, Rad, NT, 2, 1>;
+
+  // Noise generation of tile `tile` of field b (fixed index fx) straight into
+  // x, for the common case of generated noise and a filter table: the table
+  // loads of all rows are issued first and the R0 Philox blocks are
+  // independent, so they interleave.  Only the lanes holding the packed plane
+  // slot (m0 = 0, first tile) take the general route afterwards.
+  __device__ __forceinline__ static void gen_fast(const Args& a, int tile, int fx, int b, int t, int m0, bool act,
+                                                  V (&x)[2][EN::REG]) {
+    if (!act) return;
+    const unsigned long long key = a.seed + (unsigned long long)b;
+    const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
+    const T* ht = (const T*)a.htab;
+    struct alignas(2 * sizeof(T)) P2 { T x, y; };
+    P2 hp[R0];
+#pragma unroll
+    for (int m = 0; m < R0; ++m) {
+      const int row = (t + m * NT) * a.no + fx;
+      hp[m] = *reinterpret_cast<const P2*>(ht + (long long)row * (a.M + 2) + m0);
+    }
+    T z[R0][4];
+#pragma unroll
+    for (int m = 0; m < R0; ++m) {
+      const int row = (t + m * NT) * a.no + fx;
+      normals4<T, true>((uint32_t)(m0 >> 1), (uint32_t)row, (uint32_t)a.tag, k0, k1, z[m]);
+    }
+    // all noise first, then the products that wait for the table loads
+    __builtin_amdgcn_sched_barrier(0);
+    const T s = (T)0.70710678118654752440;
+#pragma unroll
+    for (int m = 0; m < R0; ++m) {
+      const T g0 = hp[m].x * s, g1 = hp[m].y * s;
+      x[0][m] = mk<T>(g0 * z[m][0], g0 * z[m][1]);
+      x[1][m] = mk<T>(g1 * z[m][2], g1 * z[m][3]);
+    }
+    if (tile == 0 && m0 == 0) {
+      const Filt<T> f = load_filt<T>(a.recs[0], a.scale);
+#pragma unroll
+      for (int m = 0; m < R0; ++m) gen_pair<T>(a, f, nullptr, b, k0, k1, t + m * NT, fx, 0, x[0][m], x[1][m]);
+    }
+  }
 
   // Workgroup `bid` of the pass; smem holds LDS_BYTES (16-byte aligned).
   __device__ __forceinline__ static void run(const Args& a, int bid, char* smem) {
@@ -291,13 +373,25 @@ struct ColPass {
     bid /= a.ntile;
     const int fx = bid % a.nfixed;
     const int b = bid / a.nfixed;
-    for (int i = tid; i < L; i += blockDim.x) tw[i] = ((const V*)a.tw)[i];
     const int m0 = (tile * CP + cp) * 2;
     const bool act = (t < NT) && (m0 < a.M);
     const bool two = (m0 + 1) < a.M;
     const bool al = (a.M & 1) == 0;
     V* base = (V*)a.data + (long long)b * a.field_stride + (long long)fx * a.stride_fixed + m0;
     V x[2][EN::REG];
+    if constexpr (SRC == SRC_GEN && GEN_STRAIGHT) {
+      if (a.src == nullptr && a.htab != nullptr) {
+        TwFill<V, L, THREADS> twf;
+        if (tid < THREADS) twf.load((const V*)a.tw, tid);
+        gen_fast(a, tile, fx, b, t, m0, act, x);
+        if (tid < THREADS) twf.store(tw, tid);   // first read after the stage-0 barrier
+        auto lds = [&](int i) -> E& { return sm[i * RS + cp]; };
+        auto out = [&](int i, const E& e) { st_pair<T>(base + (long long)i * a.stride_ax, two, al, e); };
+        EN::template run<DIR>(x, t, act, lds, tw, out);
+        return;
+      }
+    }
+    for (int i = tid; i < L; i += blockDim.x) tw[i] = ((const V*)a.tw)[i];
     if (act) {
       if constexpr (SRC == SRC_GEN) {
         const FieldRec& rec = a.recs[b * a.rec_stride];
@@ -324,7 +418,7 @@ __global__ void __launch_bounds__((ColPass<T, L, Rad, CP, PAD, SRC, DIR>::THREAD
 k_col(Args a) {
   using PS = ColPass<T, L, Rad, CP, PAD, SRC, DIR>;
   __shared__ __align__(16) char smem[PS::LDS_BYTES];
-  PS::run(a, blockIdx.x, smem);
+  PS::run(a, col_block(a.order), smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -344,7 +438,7 @@ k_colf(Args a) {
   const int tid = threadIdx.x;
   const int cp = tid % CP;
   const int t = tid / CP;
-  int bid = blockIdx.x;
+  int bid = col_block(a.order);
   const int tile = bid % a.ntile;
   const int b = bid / a.ntile;
   for (int i = tid; i < L; i += blockDim.x) tw[i] = ((const V*)a.tw)[i];
@@ -431,7 +525,7 @@ k_colg(Args a) {
   const int tid = threadIdx.x;
   const int cp = tid % CP;
   const int t = tid / CP;
-  int bid = blockIdx.x;
+  int bid = col_block(a.order);
   const int tile = bid % a.ntile;
   const int b = bid / a.ntile;
   for (int i = tid; i < L; i += blockDim.x) tw[i] = ((const V*)a.tw)[i];
