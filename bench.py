@@ -8,12 +8,16 @@ fields with seeds 0..1023, output resident in HBM.  value = grid points per
 second (2^28 points per step / seconds per step).
 
 Printed alongside on the same JSON line:
-  roofline      the dominant kernel of the step: algorithmic bytes per launch /
-                its mean duration (HIP events on the launch stream) vs 8 TB/s
+  roofline      the dominant kernel of the step (the pass with the largest total
+                time): algorithmic bytes per launch / its mean launch duration,
+                from HIP events recorded between the launches of the sampler
+                run in sequence on the launch stream, vs 8 TB/s; the per-pass
+                table; the opt-in fused schedule and the unchunked schedule
   cpu_baseline  the float64 oracle on a bounded sample of the same workload
   extra         two-FFT algorithm on the same workload, the 256^3 x 16
-                exponential workload, forward+adjoint vs forward at 1024^2 x 64,
-                and the float32-vs-float64 error of sampled fields
+                exponential workload, 4096 fields of uneven sizes in one
+                batch, forward+adjoint vs forward at 1024^2 x 64, and the
+                float32-vs-float64 error of sampled fields
 """
 import argparse
 import json
@@ -26,10 +30,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch of the headline step's kernels, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (KiB per dispatch) scaled by the same counters on a 1 GiB device copy
-# (FETCH x2, WRITE x1); profiles/grf_sample_512x512x1024_f32.md.  Set an entry to
-# None when its kernel changes.
+# HBM bytes per launch of the headline step's kernels (one launch = one cache-sized
+# chunk of 256 fields), from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
+# scaled by the same counters on a 1 GiB device copy (FETCH x2, WRITE x1); see
+# profiles/.  Set an entry to None when its kernel changes.
 MEASURED_TRAFFIC = {
     "column noise+inverse FFT (axis 1)": None,
     "last-axis C2R": None,
@@ -39,8 +43,8 @@ MEASURED_TRAFFIC = {
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -107,36 +111,61 @@ def event_ms(fn, reps, torch):
     return e0.elapsed_time(e1) / reps
 
 
-def stage_table(plan, batch, torch, grf, reps):
-    """Per-stage mean kernel time (ms) of plan.sample, each stage launched alone."""
+PASS_NAMES = {0: "column noise+inverse FFT (axis 1)", 1: "inverse FFT (axis 2)", 2: "forward FFT (axis 2)",
+              3: "column fwd FFT x h x inv FFT", 4: "column adjoint", 5: "last-axis C2R",
+              6: "last-axis noise+R2C", 7: "last-axis R2C", -1: "fused column gen | last-axis C2R"}
+
+
+def pass_bytes(kind, field_bytes):
+    """Algorithmic HBM bytes of one field through pass `kind` (output-sized packed spectrum)."""
+    return field_bytes * (1 if kind in (0, 6) else 2)
+
+
+def launch_table(plan, batch, torch, grf, reps):
+    """Each launch of plan.sample, run in sequence as in the sampler with HIP events
+    recorded between launches on the launch stream: per launch (kind, fields, mean ms)."""
     import ctypes
     n = grf.grf_sample_stage_count(plan.handle, batch)
+    info = [grf.grf_sample_stage_info(plan.handle, batch, st) for st in range(n)]
     out = torch.empty((batch,) + plan.dims, dtype=plan.dtype, device="cuda")
-    times = []
-    for st in range(n):
-        def f(st=st):
-            grf.grf_sample_stage(plan.handle, st, 0, batch, None, ctypes.c_void_p(out.data_ptr()), None, 0,
-                                 ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
-        times.append(event_ms(f, reps, torch))
+    s = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(s.cuda_stream)
+    op = ctypes.c_void_p(out.data_ptr())
+
+    def one(evs=None):
+        for st in range(n):
+            if evs is not None:
+                evs[st].record(s)
+            grf.grf_sample_stage(plan.handle, st, 0, batch, None, op, None, 0, sp)
+        if evs is not None:
+            evs[n].record(s)
+    one()
+    tot = [0.0] * n
+    for _ in range(reps):
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+        one(evs)
+        torch.cuda.synchronize()
+        for st in range(n):
+            tot[st] += evs[st].elapsed_time(evs[st + 1])
     del out
-    return times
+    return [(k, c, t / reps) for (k, f, c), t in zip(info, tot)]
 
 
-def algorithmic_bytes(plan, batch):
-    """Bytes each stage must move per launch (packed spectrum = output size)."""
-    P = 1
-    for n in plan.dims:
-        P *= n
-    esz = 4 if plan.dtype.itemsize == 4 else 8
-    field = P * esz
-    if plan.alg == 2:
-        per = [field] + [2 * field] * (len(plan.dims) - 2) + [2 * field]
-        names = ["column noise+inverse FFT (axis 1)"] + ["inverse FFT (axis 2)"] * (len(plan.dims) - 2) + \
-                ["last-axis C2R"]
-    else:
-        per = [field, 2 * field, 2 * field]
-        names = ["last-axis noise+R2C", "column fwd FFT x h x inv FFT", "last-axis C2R"]
-    return [b * batch for b in per], names
+def by_kind(table, field_bytes):
+    """Aggregate a launch table per pass kind: launches, total ms, algorithmic bytes."""
+    agg = {}
+    for k, c, t in table:
+        a = agg.setdefault(k, {"launches": 0, "ms": 0.0, "bytes": 0})
+        a["launches"] += 1
+        a["ms"] += t
+        a["bytes"] += pass_bytes(k, field_bytes) * c
+    return agg
+
+
+def kind_rows(agg):
+    return [{"kernel": PASS_NAMES[k], "launches": a["launches"], "ms": round(a["ms"], 4),
+             "algorithmic_GB": round(a["bytes"] / 1e9, 4), "GBps": round(a["bytes"] / (a["ms"] * 1e-3) / 1e9, 1)}
+            for k, a in agg.items()]
 
 
 def main():
@@ -165,28 +194,34 @@ def main():
     sec = timed(lambda: plan.sample(seed=0, batch=batch, out=out), args.steps, args.warmup, torch)
     value = P * batch / sec
 
-    # per-kernel times and roofline of the dominant kernel
-    st_ms = stage_table(plan, batch, torch, grf, max(args.steps, 10))
+    # per-launch times in sequence; roofline of the dominant kernel (the pass with the
+    # largest total time per step), per launch: algorithmic bytes / mean launch duration
+    fbytes = P * 4
+    table = launch_table(plan, batch, torch, grf, max(args.steps // 5, 20))
+    agg = by_kind(table, fbytes)
+    dom = max(agg, key=lambda k: agg[k]["ms"])
+    d = agg[dom]
+    kname, kms, kbytes = PASS_NAMES[dom], d["ms"] / d["launches"], d["bytes"] / d["launches"]
     total_bytes = 12 * P * batch                       # packed spectrum write + read, output write
-    abytes, names = algorithmic_bytes(plan, batch)
-    stages = [{"kernel": nm, "ms": round(t, 4), "algorithmic_GB": round(b / 1e9, 4),
-               "GBps": round(b / (t * 1e-3) / 1e9, 1)} for nm, t, b in zip(names, st_ms, abytes)]
-    dom = int(np.argmax(st_ms))
-    kname, kms, kbytes = names[dom], st_ms[dom], abytes[dom]
-    # the chunked schedule that pairs the two passes in one launch (opt-in), for reference
+    # the chunk schedule that pairs the two passes in one launch (opt-in), for reference
     os.environ["GRF_FUSE"] = "1"
     fused_step = timed(lambda: plan.sample(seed=0, batch=batch, out=out), args.steps, args.warmup, torch)
     del os.environ["GRF_FUSE"]
+    # one launch per pass over the whole batch (no cache-sized chunks), for reference
+    os.environ["GRF_CHUNK_BYTES"] = str(1 << 40)
+    unchunked_step = timed(lambda: plan.sample(seed=0, batch=batch, out=out), args.steps, args.warmup, torch)
+    del os.environ["GRF_CHUNK_BYTES"]
     achieved = kbytes / (kms * 1e-3) / 1e9
     traffic = MEASURED_TRAFFIC.get(kname)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic / 1e9, 4), "traffic_unit": "GB/launch",
-                "kernel": kname, "kernel_ms": round(kms, 4), "launches_per_step": len(st_ms),
+                "kernel": kname, "kernel_ms_per_launch": round(kms, 4), "launches_per_step": len(table),
                 "algorithmic_bytes_per_launch": int(kbytes),
                 "whole_step_model_GBps": round(total_bytes / sec / 1e9, 1),
                 "whole_step_model_frac": round(total_bytes / sec / 1e9 / HBM_PEAK_GBS, 4),
-                "stages": stages, "fused_schedule_step_ms": round(fused_step * 1e3, 4)}
+                "passes": kind_rows(agg), "fused_schedule_step_ms": round(fused_step * 1e3, 4),
+                "unchunked_step_ms": round(unchunked_step * 1e3, 4)}
 
     result = {
         "metric": "GRF points/s + HBM-roofline % (512^2, 256^3 FP32); batched & fwd+adjoint vs plain",
@@ -211,7 +246,7 @@ def main():
         extra["two_fft_512"] = {"points_per_s": round(P * batch / s1, 1), "ms_per_step": round(s1 * 1e3, 4),
                                 "model_frac": round(20 * P * batch / s1 / 1e9 / HBM_PEAK_GBS, 4),
                                 "time_ratio_vs_one_fft": round(s1 / sec, 3),
-                                "stages_ms": [round(t, 4) for t in stage_table(p1, batch, torch, grf, 10)]}
+                                "passes": kind_rows(by_kind(launch_table(p1, batch, torch, grf, 10), P * 4))}
         del o1
         # error vs float64 of sampled fields (both algorithms)
         errs = {}
@@ -231,13 +266,11 @@ def main():
         p3 = grf.Plan(d3, alg=2, dtype=torch.float32, cov="exponential", sigma=1.0, length_scale=0.05)
         o3 = torch.empty((b3,) + d3, dtype=torch.float32, device="cuda")
         s3 = timed(lambda: p3.sample(seed=0, batch=b3, out=o3), max(args.steps // 2, 5), 2, torch)
-        ab3, nm3 = algorithmic_bytes(p3, b3)
-        st3 = stage_table(p3, b3, torch, grf, 5)
+        ab3 = 20 * 2 ** 24 * b3
         extra["one_fft_256cubed_x16"] = {
             "points_per_s": round(2 ** 24 * b3 / s3, 1), "ms_per_step": round(s3 * 1e3, 4),
-            "model_GBps": round(sum(ab3) / s3 / 1e9, 1), "model_frac": round(sum(ab3) / s3 / 1e9 / HBM_PEAK_GBS, 4),
-            "stages": [{"kernel": n, "ms": round(t, 4), "GBps": round(b / (t * 1e-3) / 1e9, 1)}
-                       for n, t, b in zip(nm3, st3, ab3)]}
+            "model_GBps": round(ab3 / s3 / 1e9, 1), "model_frac": round(ab3 / s3 / 1e9 / HBM_PEAK_GBS, 4),
+            "passes": kind_rows(by_kind(launch_table(p3, b3, torch, grf, 5), 2 ** 24 * 4))}
         p3_64 = grf.Plan(d3, alg=2, dtype=torch.float64, cov="exponential", sigma=1.0, length_scale=0.05)
         f64 = p3_64.sample(seed=0, batch=1)
         extra["one_fft_256cubed_x16"]["max_rel_err_vs_fp64"] = float(
@@ -254,7 +287,7 @@ def main():
         bt.tune(out=ob)
         t_tune = time.perf_counter() - t0
         sb_graph = timed(lambda: bt.sample(out=ob), args.steps, args.warmup, torch)
-        sb_plain = timed(lambda: bt.sample(out=ob, plain=True), max(args.steps // 4, 3), 1, torch)
+        sb_plain = timed(lambda: bt.sample(out=ob, plain=True), 3, 1, torch)
         npts = bt.offsets[-1]
         bt.sample(out=ob)
         errs = []

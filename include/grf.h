@@ -126,22 +126,41 @@ grf_status grf_sample(grf_plan plan, uint64_t seed, int64_t batch, const double*
 grf_status grf_sample_from_noise(grf_plan plan, const void* noise, int64_t batch, const double* theta,
                                  void* out, void* workspace, size_t workspace_bytes, void* stream);
 
-/* Measurement support: grf_sample runs a fixed sequence of kernel launches
- * (one-FFT d = 2: column generation + inverse transform, then last-axis
- * complex-to-real; d = 3 adds the middle-axis inverse transform; two-FFT:
- * last-axis noise + real-to-complex, column forward/filter/inverse, last-axis
- * complex-to-real; with the environment variable GRF_FUSE=1 a one-FFT d = 2
- * batch of two or more fields on a supported grid runs chunk by chunk instead,
- * each launch pairing the column pass of one chunk with the last-axis pass of
- * the previous chunk, GRF_CHUNK_BYTES setting the chunk size).
+/* Measurement support.  grf_sample runs its passes chunk by chunk: the batch
+ * is cut into chunks of fields sized to the device's 256 MB last-level cache
+ * (the environment variable GRF_CHUNK_BYTES sets another size), and every
+ * pass of a chunk runs before the next chunk, so that a pass reads what the
+ * previous one wrote from that cache.  Passes of a chunk: one-FFT d = 2:
+ * column generation + inverse transform, then last-axis complex-to-real;
+ * d = 3 adds the middle-axis inverse transform; two-FFT: last-axis noise +
+ * real-to-complex, column forward/filter/inverse, last-axis complex-to-real.
+ * With GRF_FUSE=1 a one-FFT d = 2 batch of two or more fields on a supported
+ * grid pairs, in each launch, the column pass of one chunk with the last-axis
+ * pass of the previous chunk (GRF_PASS_FUSED).
  * grf_sample_stage_count returns the number of launches for a batch of
  * `batch` fields (host pointer); grf_sample_stage runs only launch `stage`
  * (0-based) with the arguments of grf_sample, so that each kernel can be
  * timed on its own.  Run alone, a later stage transforms whatever `out`
- * holds. */
+ * holds.  grf_sample_stage_info reports, for launch `stage` of a batch of
+ * `batch` fields, the pass it runs (*kind, one of GRF_PASS_*) and the fields
+ * first .. first + count - 1 it covers (for a fused launch, those of its
+ * column pass); host pointers, any may be NULL. */
+enum {
+  GRF_PASS_FUSED = -1,
+  GRF_PASS_COL_GEN_INV = 0,   /* noise + filter + inverse transform along axis 1 (one-FFT) */
+  GRF_PASS_COL_LOAD_INV = 1,  /* inverse transform along the middle axis (d = 3) */
+  GRF_PASS_COL_LOAD_FWD = 2,  /* forward transform along the middle axis */
+  GRF_PASS_COL_FILTER = 3,    /* forward transform, filter, inverse transform along axis 1 (two-FFT) */
+  GRF_PASS_COL_GRAD = 4,      /* forward transform and adjoint reduction along axis 1 */
+  GRF_PASS_ROW_C2R = 5,       /* last-axis complex-to-real inverse transform */
+  GRF_PASS_ROW_R2C_GEN = 6,   /* last-axis white noise + real-to-complex forward transform (two-FFT) */
+  GRF_PASS_ROW_R2C_LOAD = 7   /* last-axis real-to-complex forward transform of stored rows */
+};
 grf_status grf_sample_stage_count(grf_plan plan, int64_t batch, int32_t* count);
 grf_status grf_sample_stage(grf_plan plan, int32_t stage, uint64_t seed, int64_t batch, const double* theta,
                             void* out, void* workspace, size_t workspace_bytes, void* stream);
+grf_status grf_sample_stage_info(grf_plan plan, int64_t batch, int32_t stage, int32_t* kind, int64_t* first,
+                                 int64_t* count);
 
 /* Write the noise z of the contract for fields seed..seed+batch-1 (device,
  * same shape and dtype as the output). */

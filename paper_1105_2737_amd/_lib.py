@@ -12,12 +12,14 @@ GRF_ALG_TWO_FFT, GRF_ALG_ONE_FFT = 1, 2
 GRF_F32, GRF_F64 = 0, 1
 GRF_COV_GAUSSIAN, GRF_COV_MATERN, GRF_COV_EXPONENTIAL = 0, 1, 2
 GRF_OP_SAMPLE, GRF_OP_BACKWARD = 0, 1
+GRF_PASS_FUSED, GRF_PASS_COL_GEN_INV, GRF_PASS_COL_LOAD_INV, GRF_PASS_COL_LOAD_FWD = -1, 0, 1, 2
+GRF_PASS_COL_FILTER, GRF_PASS_COL_GRAD, GRF_PASS_ROW_C2R, GRF_PASS_ROW_R2C_GEN, GRF_PASS_ROW_R2C_LOAD = 3, 4, 5, 6, 7
 
 STATUS_NAMES = {0: "GRF_OK", -1: "GRF_EINVAL", -2: "GRF_ENOMEM", -3: "GRF_EDEVICE", -4: "GRF_EUNSUPPORTED"}
 
 # every symbol include/grf.h declares
 EXPORTS = ["grf_plan_create", "grf_plan_destroy", "grf_workspace_size", "grf_sample",
-           "grf_sample_stage_count", "grf_sample_stage", "grf_sample_from_noise", "grf_noise", "grf_backward", "grf_debug_philox",
+           "grf_sample_stage_count", "grf_sample_stage", "grf_sample_stage_info", "grf_sample_from_noise", "grf_noise", "grf_backward", "grf_debug_philox",
            "grf_batch_create", "grf_batch_offsets", "grf_batch_sample", "grf_batch_sample_plain",
            "grf_batch_tune", "grf_batch_destroy", "grf_last_error", "grf_version"]
 
@@ -53,6 +55,8 @@ def _load():
         "grf_sample": (ctypes.c_int, [vp, u64, c64, vp, vp, vp, sz, vp]),
         "grf_sample_stage_count": (ctypes.c_int, [vp, c64, ctypes.POINTER(i32)]),
         "grf_sample_stage": (ctypes.c_int, [vp, i32, u64, c64, vp, vp, vp, sz, vp]),
+        "grf_sample_stage_info": (ctypes.c_int, [vp, c64, i32, ctypes.POINTER(i32), ctypes.POINTER(c64),
+                                                 ctypes.POINTER(c64)]),
         "grf_sample_from_noise": (ctypes.c_int, [vp, vp, c64, vp, vp, vp, sz, vp]),
         "grf_noise": (ctypes.c_int, [vp, u64, c64, vp, vp]),
         "grf_backward": (ctypes.c_int, [vp, u64, vp, c64, vp, vp, vp, vp, vp, sz, vp]),
@@ -112,6 +116,13 @@ def grf_sample_stage_count(plan, batch):
 
 def grf_sample_stage(plan, stage, seed, batch, theta, out, workspace, workspace_bytes, stream):
     return check(lib.grf_sample_stage(plan, stage, seed, batch, theta, out, workspace, workspace_bytes, stream))
+
+
+def grf_sample_stage_info(plan, batch, stage):
+    """(kind, first, count) of launch `stage` for a batch of `batch` fields."""
+    kind, first, count = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+    check(lib.grf_sample_stage_info(plan, batch, stage, ctypes.byref(kind), ctypes.byref(first), ctypes.byref(count)))
+    return kind.value, first.value, count.value
 
 
 def grf_sample_from_noise(plan, noise, batch, theta, out, workspace, workspace_bytes, stream):

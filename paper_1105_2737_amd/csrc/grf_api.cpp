@@ -212,16 +212,19 @@ struct PassLaunch {
   int pass;
   int L;
   Args a;
+  long long first = 0;        // fields first .. first + count - 1 of the call
+  long long count = 0;
   int M2 = 0;
   Args b{};
   bool hasA = true, hasB = true;
 };
 
-// Fields per chunk of the fused schedule: the packed spectra of a chunk
-// (written by one launch, read by the next) are sized to stay in the
-// 256 MB last-level cache.  GRF_CHUNK_BYTES overrides.
+// Fields per chunk: the sampler runs all its passes on one chunk of fields
+// before the next, and a chunk is sized to the 256 MB last-level cache
+// (Infinity Cache) of the device, so that each pass reads what the previous
+// one wrote from that cache rather than from HBM.  GRF_CHUNK_BYTES overrides.
 long long chunk_fields(const grf_plan_s* p, long long batch) {
-  long long bytes = 64ll << 20;
+  long long bytes = 256ll << 20;
   if (const char* e = std::getenv("GRF_CHUNK_BYTES")) {
     const long long v = std::atoll(e);
     if (v > 0) bytes = v;
@@ -240,8 +243,8 @@ bool fuse_enabled() {
   return e && e[0] == '1';
 }
 
-grf_status run_launch(const grf_plan_s* p, const PassLaunch& pl, long long batch, hipStream_t s) {
-  if (pl.pass >= 0) return run_pass(p, pl.pass, pl.L, pl.a, 0, batch, s);
+grf_status run_launch(const grf_plan_s* p, const PassLaunch& pl, hipStream_t s) {
+  if (pl.pass >= 0) return run_pass(p, pl.pass, pl.L, pl.a, 0, pl.count, s);
   const grf::FusedGeom g = grf::fused_geom(p->dtype, pl.L, pl.M2);
   if (g.threads <= 0) return fail(GRF_EUNSUPPORTED, "no fused kernel for this shape");
   Args a = pl.a;
@@ -255,60 +258,28 @@ grf_status run_launch(const grf_plan_s* p, const PassLaunch& pl, long long batch
   return GRF_OK;
 }
 
-// The pass sequence of the sampler (zsrc == nullptr generates the noise).
-std::vector<PassLaunch> sample_passes(const grf_plan_s* p, uint64_t seed, const void* zsrc, long long batch,
-                                      const FieldRec* recs, int rstride, void* out) {
-  std::vector<PassLaunch> v;
-  Args a = base_args(p, batch);
-  a.data = out;
-  a.src = zsrc;
-  a.recs = recs;
+// The passes of the sampler over fields c0 .. c0 + nb - 1 (zsrc == nullptr
+// generates the noise); field c0 + j uses key seed + c0 + j, so a chunk gives
+// the same bits as the same fields in a larger call.
+void chunk_passes(const grf_plan_s* p, uint64_t seed, const void* zsrc, long long c0, long long nb,
+                  const FieldRec* recs, int rstride, void* out, std::vector<PassLaunch>& v) {
+  const size_t fbytes = (size_t)p->P * p->esz;
+  Args a = base_args(p, nb);
+  a.data = (char*)out + c0 * fbytes;
+  a.src = zsrc ? (const char*)zsrc + c0 * fbytes : nullptr;
+  a.recs = rstride ? recs + c0 : recs;
   a.rec_stride = rstride;
-  a.seed = seed;
+  a.seed = seed + (uint64_t)c0;
   a.htab = rstride == 0 ? p->htab : nullptr;
-  if (p->desc.alg == GRF_ALG_ONE_FFT && p->d == 2 && fuse_enabled() && batch >= 2 &&
-      grf::fused_geom(p->dtype, p->n1, p->M).threads > 0) {
-    // Chunked schedule: launch k runs the column generation pass of chunk k
-    // and the last-axis pass of chunk k-1, so that the VALU-heavy and the
-    // memory-heavy passes share the CUs.
-    a.tag = 1;
-    a.tw = p->tw_col1;
-    a.stride_ax = p->M;
-    a.stride_fixed = p->M;
-    a.nfixed = 1;
-    Args rb = a;
-    rb.src = nullptr;
-    rb.tw2 = p->tw_row;
-    const long long C = chunk_fields(p, batch);
-    const long long nch = (batch + C - 1) / C;
-    const size_t fbytes = (size_t)p->P * p->esz;
-    auto chunk = [&](long long k, Args x, bool gen) {
-      const long long c0 = k * C;
-      const long long nb = std::min(C, batch - c0);
-      x.data = (char*)out + c0 * fbytes;
-      if (gen) {
-        x.seed = seed + (uint64_t)c0;
-        x.batch = (int)nb;
-        if (rstride) x.recs = recs + c0;
-        if (zsrc) x.src = (const char*)zsrc + c0 * fbytes;
-      } else {
-        x.rows = nb * (long long)p->n1;
-      }
-      return x;
-    };
-    for (long long k = 0; k <= nch; ++k) {
-      PassLaunch pl;
-      pl.pass = -1;
-      pl.L = p->n1;
-      pl.M2 = p->M;
-      pl.hasA = k < nch;
-      pl.hasB = k >= 1;
-      pl.a = pl.hasA ? chunk(k, a, true) : a;
-      pl.b = pl.hasB ? chunk(k - 1, rb, false) : rb;
-      v.push_back(pl);
-    }
-    return v;
-  }
+  auto push = [&](int pass, int L, const Args& x) {
+    PassLaunch pl;
+    pl.pass = pass;
+    pl.L = L;
+    pl.a = x;
+    pl.first = c0;
+    pl.count = nb;
+    v.push_back(pl);
+  };
   if (p->desc.alg == GRF_ALG_ONE_FFT) {
     a.tag = 1;
     a.tw = p->tw_col1;
@@ -321,7 +292,7 @@ std::vector<PassLaunch> sample_passes(const grf_plan_s* p, uint64_t seed, const 
       a.stride_fixed = p->M;
       a.nfixed = p->no;
     }
-    v.push_back({grf::PASS_COL_GEN_INV, p->n1, a});
+    push(grf::PASS_COL_GEN_INV, p->n1, a);
     if (p->d == 3) {
       Args m = a;
       m.src = nullptr;
@@ -329,14 +300,14 @@ std::vector<PassLaunch> sample_passes(const grf_plan_s* p, uint64_t seed, const 
       m.stride_ax = p->M;
       m.stride_fixed = (long long)p->no * p->M;
       m.nfixed = p->n1;
-      v.push_back({grf::PASS_COL_LOAD_INV, p->no, m});
+      push(grf::PASS_COL_LOAD_INV, p->no, m);
     }
   } else {
     Args r = a;
     r.tag = 0;
     r.tw2 = p->tw_row;
-    r.rows = batch * (long long)p->n1;
-    v.push_back({zsrc ? grf::PASS_ROW_R2C_LOAD : grf::PASS_ROW_R2C_GEN, p->M, r});
+    r.rows = nb * (long long)p->n1;
+    push(zsrc ? grf::PASS_ROW_R2C_LOAD : grf::PASS_ROW_R2C_GEN, p->M, r);
     Args c = a;
     c.src = nullptr;
     c.tw = p->tw_col1;
@@ -345,13 +316,45 @@ std::vector<PassLaunch> sample_passes(const grf_plan_s* p, uint64_t seed, const 
     c.nfixed = 1;
     c.scale = 1.0 / std::sqrt((double)p->P);
     c.htab = nullptr;   // this pass has VALU to spare: h on the fly beats a table load
-    v.push_back({grf::PASS_COL_FILTER, p->n1, c});
+    push(grf::PASS_COL_FILTER, p->n1, c);
   }
   Args b = a;
   b.src = nullptr;
   b.tw2 = p->tw_row;
-  b.rows = batch * (p->P / p->nd);
-  v.push_back({grf::PASS_ROW_C2R, p->M, b});
+  b.rows = nb * (p->P / p->nd);
+  push(grf::PASS_ROW_C2R, p->M, b);
+}
+
+// The launch sequence of the sampler (zsrc == nullptr generates the noise).
+std::vector<PassLaunch> sample_passes(const grf_plan_s* p, uint64_t seed, const void* zsrc, long long batch,
+                                      const FieldRec* recs, int rstride, void* out) {
+  std::vector<PassLaunch> v;
+  const long long C = chunk_fields(p, batch);
+  const long long nch = (batch + C - 1) / C;
+  if (p->desc.alg == GRF_ALG_ONE_FFT && p->d == 2 && fuse_enabled() && batch >= 2 &&
+      grf::fused_geom(p->dtype, p->n1, p->M).threads > 0) {
+    // Fused chunk schedule: launch k runs the column generation pass of
+    // chunk k and the last-axis pass of chunk k-1, so that the VALU-heavy and
+    // the memory-heavy passes share the CUs.
+    std::vector<PassLaunch> parts;
+    for (long long k = 0; k < nch; ++k)
+      chunk_passes(p, seed, zsrc, k * C, std::min(C, batch - k * C), recs, rstride, out, parts);
+    for (long long k = 0; k <= nch; ++k) {
+      PassLaunch pl;
+      pl.pass = -1;
+      pl.L = p->n1;
+      pl.M2 = p->M;
+      pl.hasA = k < nch;
+      pl.hasB = k >= 1;
+      pl.a = pl.hasA ? parts[2 * k].a : parts[0].a;
+      pl.b = pl.hasB ? parts[2 * k - 1].a : parts[1].a;
+      pl.first = pl.hasA ? parts[2 * k].first : 0;
+      pl.count = pl.hasA ? parts[2 * k].count : 0;
+      v.push_back(pl);
+    }
+    return v;
+  }
+  for (long long k = 0; k < nch; ++k) chunk_passes(p, seed, zsrc, k * C, std::min(C, batch - k * C), recs, rstride, out, v);
   return v;
 }
 
@@ -374,7 +377,7 @@ grf_status sample_impl(grf_plan p, uint64_t seed, const void* zsrc, int64_t batc
   if (stage >= (int)v.size()) return fail(GRF_EINVAL, "stage out of range");
   for (int i = 0; i < (int)v.size(); ++i) {
     if (stage >= 0 && i != stage) continue;
-    st = run_launch(p, v[i], batch, s);
+    st = run_launch(p, v[i], s);
     if (st != GRF_OK) return st;
   }
   return GRF_OK;
@@ -543,6 +546,19 @@ grf_status grf_sample_stage_count(grf_plan p, int64_t batch, int32_t* count) {
   if (p == nullptr || count == nullptr) return fail(GRF_EINVAL, "null argument");
   if (batch < 1) return fail(GRF_EINVAL, "batch must be positive");
   *count = (int32_t)sample_passes(p, 0, nullptr, batch, p->rec_dev, 0, nullptr).size();
+  return GRF_OK;
+}
+
+grf_status grf_sample_stage_info(grf_plan p, int64_t batch, int32_t stage, int32_t* kind, int64_t* first,
+                                 int64_t* count) {
+  if (p == nullptr) return fail(GRF_EINVAL, "null plan");
+  if (batch < 1) return fail(GRF_EINVAL, "batch must be positive");
+  const std::vector<PassLaunch> v = sample_passes(p, 0, nullptr, batch, p->rec_dev, 0, nullptr);
+  if (stage < 0 || stage >= (int)v.size()) return fail(GRF_EINVAL, "stage out of range");
+  const PassLaunch& pl = v[stage];
+  if (kind) *kind = pl.pass >= 0 ? pl.pass : GRF_PASS_FUSED;
+  if (first) *first = pl.first;
+  if (count) *count = pl.count;
   return GRF_OK;
 }
 

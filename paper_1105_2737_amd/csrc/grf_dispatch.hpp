@@ -24,15 +24,16 @@ struct Args;
 // can share one launch (chunk c's row pass with chunk c+1's column pass).
 #define GRF_FUSED_PAIRS(X) X(64, 32) X(96, 48) X(128, 64) X(256, 128) X(360, 180) X(512, 256) X(1000, 500) X(1024, 512)
 
+// The passes (values as the GRF_PASS_* constants of the C interface).
 enum PassKind {
-  PASS_COL_GEN_INV = 0,   // noise generation + inverse transform (one-FFT algorithm, axis 1)
-  PASS_COL_LOAD_INV = 1,  // inverse transform of a stored spectrum (middle axis)
-  PASS_COL_LOAD_FWD = 2,  // forward transform (adjoint, middle axis)
-  PASS_COL_FILTER = 3,    // forward, filter, inverse (two-FFT algorithm, axis 1)
-  PASS_COL_GRAD = 4,      // forward transform + adjoint reduction (axis 1)
-  PASS_ROW_C2R = 5,       // last axis, complex-to-real inverse
-  PASS_ROW_R2C_GEN = 6,   // last axis, white noise + real-to-complex forward
-  PASS_ROW_R2C_LOAD = 7,  // last axis, stored real rows + real-to-complex forward
+  PASS_COL_GEN_INV = GRF_PASS_COL_GEN_INV,     // noise generation + inverse transform (one-FFT algorithm, axis 1)
+  PASS_COL_LOAD_INV = GRF_PASS_COL_LOAD_INV,   // inverse transform of a stored spectrum (middle axis)
+  PASS_COL_LOAD_FWD = GRF_PASS_COL_LOAD_FWD,   // forward transform (adjoint, middle axis)
+  PASS_COL_FILTER = GRF_PASS_COL_FILTER,       // forward, filter, inverse (two-FFT algorithm, axis 1)
+  PASS_COL_GRAD = GRF_PASS_COL_GRAD,           // forward transform + adjoint reduction (axis 1)
+  PASS_ROW_C2R = GRF_PASS_ROW_C2R,             // last axis, complex-to-real inverse
+  PASS_ROW_R2C_GEN = GRF_PASS_ROW_R2C_GEN,     // last axis, white noise + real-to-complex forward
+  PASS_ROW_R2C_LOAD = GRF_PASS_ROW_R2C_LOAD,   // last axis, stored real rows + real-to-complex forward
 };
 
 // Workgroup geometry of a pass at a given length (for grid sizing).

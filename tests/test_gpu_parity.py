@@ -231,3 +231,48 @@ def test_fused_schedule_matches_separate_passes(grf, dims):
         os.environ.update(old)
     assert torch.equal(got, ref)
     assert torch.equal(got2, ref)
+
+
+def _with_env(env, fn):
+    import os
+    old = dict(os.environ)
+    try:
+        os.environ.update(env)
+        return fn()
+    finally:
+        os.environ.clear()
+        os.environ.update(old)
+
+
+CHUNK_CASES = [((512, 512), 2, torch.float32), ((96, 128), 1, torch.float32), ((32, 48, 64), 2, torch.float32),
+               ((64, 96), 2, torch.float64), ((64, 96), 1, torch.float64)]
+
+
+@pytest.mark.parametrize("dims,alg,dtype", CHUNK_CASES, ids=lambda c: str(c))
+def test_chunked_schedule_matches_unchunked(grf, dims, alg, dtype):
+    """Cache-sized chunks (here 3 fields, last chunk ragged) give the same bits as
+    one launch per pass, with shared and per-field theta and with supplied noise."""
+    P = int(np.prod(dims))
+    esz = 4 if dtype == torch.float32 else 8
+    B = 7
+    cov = "exponential" if len(dims) == 3 else "matern"
+    plan = grf.Plan(dims, alg=alg, dtype=dtype, cov=cov)
+    g = torch.Generator().manual_seed(3)
+    theta = torch.stack([1 + torch.rand(B, generator=g), 0.05 + 0.1 * torch.rand(B, generator=g),
+                         0.5 + 2 * torch.rand(B, generator=g)], 1).double()
+    z = plan.noise(seed=40, batch=B)
+    big = {"GRF_CHUNK_BYTES": str(1 << 40)}
+    small = {"GRF_CHUNK_BYTES": str(3 * P * esz)}
+    for run in (lambda: plan.sample(seed=11, batch=B), lambda: plan.sample(seed=11, batch=B, theta=theta),
+                lambda: plan.sample_from_noise(z)):
+        ref = _with_env(big, run)
+        got = _with_env(small, run)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref)
+    nper = 2 if (alg == 2 and len(dims) == 2) else 3
+    n = _with_env(small, lambda: grf.grf_sample_stage_count(plan.handle, B))
+    assert n == 3 * nper
+    info = _with_env(small, lambda: [grf.grf_sample_stage_info(plan.handle, B, s) for s in range(n)])
+    assert [(f, c) for _, f, c in info[::nper]] == [(0, 3), (3, 3), (6, 1)]
+    assert info[nper - 1][0] == grf.GRF_PASS_ROW_C2R
+    assert _with_env(big, lambda: grf.grf_sample_stage_count(plan.handle, B)) == nper
