@@ -49,7 +49,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-stage", type=int, default=None,
-                    help="profiling mode: launch only this stage of the headline step, --steps times")
+                    help="profiling mode: launch only this stage of the headline step (-1: the whole "
+                         "sampler), --steps times")
     ap.add_argument("--profile-alg", type=int, default=2, help="algorithm for --profile-stage")
     ap.add_argument("--profile-dims", type=str, default="512,512", help="grid for --profile-stage")
     ap.add_argument("--profile-batch", type=int, default=1024)
@@ -81,8 +82,11 @@ def profile_mode(args):
     out = torch.empty((batch,) + dims, dtype=torch.float32, device="cuda")
     stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     for _ in range(args.warmup + args.steps):
-        grf.grf_sample_stage(plan.handle, args.profile_stage, 0, batch, None, ctypes.c_void_p(out.data_ptr()),
-                             None, 0, stream)
+        if args.profile_stage < 0:   # every launch of the sampler, in sequence
+            grf.grf_sample(plan.handle, 0, batch, None, ctypes.c_void_p(out.data_ptr()), None, 0, stream)
+        else:
+            grf.grf_sample_stage(plan.handle, args.profile_stage, 0, batch, None, ctypes.c_void_p(out.data_ptr()),
+                                 None, 0, stream)
     torch.cuda.synchronize()
     print(f"profiled stage {args.profile_stage} of alg {args.profile_alg} on {dims} x {batch}", flush=True)
 

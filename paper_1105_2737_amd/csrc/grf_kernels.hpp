@@ -67,11 +67,29 @@ __device__ __forceinline__ int col_block(int order) {
   return i < n8 ? (i & 7) * (n8 >> 3) + (i >> 3) : i;
 }
 
+// Synchronisation of the threads that exchange data through LDS between two
+// FFT stages.  When all of them lie in one wavefront (WAVE), the wave's LDS
+// operations complete in order, so a fence at wavefront scope (wait for the
+// wave's own LDS stores) and a compiler barrier suffice; otherwise the
+// workgroup barrier.
+template <bool WAVE>
+__device__ __forceinline__ void stage_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Block FFT engine: NC interleaved length-L transforms per thread group.
 // x[c][b*R + m] holds the inputs of butterfly b (j = t + b NT) of the current
 // stage.  Stage 0 inputs must be in registers (NB(0) == 1, NT = L / R_0).
-template <typename T, int L, class Rad, int NT, int NC, int TWS>
+// WAVE: the NT threads of one transform lie in one wavefront and share their
+// LDS region with no other threads (stage_sync<true>).
+template <typename T, int L, class Rad, int NT, int NC, int TWS, bool WAVE = false>
 struct Eng {
   using V = C<T>;
   using E = Vec<T, NC>;
@@ -132,7 +150,7 @@ struct Eng {
       }
     }
     if constexpr (!last) {
-      __syncthreads();
+      stage_sync<WAVE>();
       constexpr int R2 = Rad::get(s + 1), nb2 = NB(s + 1), LR2 = L / R2;
       if (act) {
 #pragma unroll
@@ -148,7 +166,7 @@ struct Eng {
           }
         }
       }
-      __syncthreads();
+      stage_sync<WAVE>();
       stage<s + 1, DIR>(x, t, act, lds, tw, out);
     }
   }
@@ -710,8 +728,11 @@ __device__ __forceinline__ void copy_in(const C<T>* __restrict__ g, E* sm, int c
 // Row data X_k (k = 0..M-1, X_0 slot = (X_0, X_M)) become
 //   Z_k = E_k + i O_k,  E_k = X_k + conj X_{M-k},  O_k = (X_k - conj X_{M-k}) w^k,
 // w = exp(2 pi i / N_d); z = inverse length-M transform of Z; and
-// x[2n] = Re z_n, x[2n+1] = Im z_n.  Z is formed while loading the first
-// stage's inputs.
+// x[2n] = Re z_n, x[2n+1] = Im z_n.  Each thread loads the entries of its
+// first-stage butterfly (k = t + m NT) and their partners X_{M-k} straight
+// from global memory (coalesced, the partners in reverse order) and forms Z
+// in registers; the only workgroup barrier publishes the twiddle table.  When
+// a row's NT threads lie in one wavefront, the stages synchronise per wave.
 template <typename T, int M, class Rad, int RB, int PADR>
 struct RowC2R {
   using V = C<T>;
@@ -720,9 +741,10 @@ struct RowC2R {
   static constexpr int NT = M / Rad::get(0);
   static constexpr int THREADS = (NT * RB + 63) / 64 * 64;
   static constexpr int R0 = Rad::get(0);
+  static constexpr bool WAVE = (64 % NT) == 0;
   static constexpr int LDS_BYTES = RB * RL::STRIDE * (int)sizeof(E) + 2 * M * (int)sizeof(V);
   static_assert(PADR == 0, "row passes use the RowLds layout");
-  using EN = Eng<T, M, Rad, NT, 1, 2>;
+  using EN = Eng<T, M, Rad, NT, 1, 2, WAVE>;
 
   __device__ __forceinline__ static void run(const Args& a, int bid, char* smem) {
     E* sm = reinterpret_cast<E*>(smem);
@@ -733,33 +755,37 @@ struct RowC2R {
     const long long row0 = (long long)bid * RB;
     const long long left = a.rows - row0;
     const int nrows = left < RB ? (int)left : RB;
-    V* g = (V*)a.data + row0 * M;
-    if (tid < THREADS) {
-      copy_in<T, M, RB * M, THREADS>(g, sm, nrows * M, tid);
-      for (int i = tid; i < 2 * M; i += THREADS) tw[i] = ((const V*)a.tw2)[i];
-    }
-    __syncthreads();
-    const bool act = (r < nrows) && (t < NT);
-    V x[1][EN::REG];
+    V* o = (V*)a.data + (row0 + r) * M;
+    const bool act = r < nrows;
+    TwFill<V, 2 * M, THREADS> twf;
+    if (tid < THREADS) twf.load((const V*)a.tw2, tid);
+    V xk[R0], xm[R0];
     if (act) {
-      const E* rowp = sm + r * RL::STRIDE;
 #pragma unroll
       for (int m = 0; m < R0; ++m) {
         const int k = t + m * NT;
-        const V xk = rowp[RL::idx(k)].v[0];
+        xk[m] = o[k];
+        xm[m] = o[k == 0 ? 0 : M - k];
+      }
+    }
+    if (tid < THREADS) twf.store(tw, tid);
+    __syncthreads();
+    V x[1][EN::REG];
+    if (act) {
+#pragma unroll
+      for (int m = 0; m < R0; ++m) {
+        const int k = t + m * NT;
         if (k == 0) {
-          x[0][m] = mk<T>(xk.x + xk.y, xk.x - xk.y);
+          x[0][m] = mk<T>(xk[m].x + xk[m].y, xk[m].x - xk[m].y);
         } else {
-          const V xm = cconj(rowp[RL::idx(M - k)].v[0]);
-          const V ek = cadd(xk, xm);
-          const V ok = cmul(csub(xk, xm), tw[k]);
+          const V c = cconj(xm[m]);
+          const V ek = cadd(xk[m], c);
+          const V ok = cmul(csub(xk[m], c), tw[k]);
           x[0][m] = mk<T>(ek.x - ok.y, ek.y + ok.x);
         }
       }
     }
-    __syncthreads();
     auto lds = [&](int i) -> E& { return sm[r * RL::STRIDE + RL::idx(i)]; };
-    V* o = g + (long long)r * M;
     auto out = [&](int i, const E& e) { o[i] = e.v[0]; };
     EN::template run<+1>(x, t, act, lds, tw, out);
   }
@@ -778,13 +804,15 @@ k_row_c2r(Args a) {
 // One launch that interleaves the workgroups of two independent passes: nA
 // workgroups of PA (arguments aa) and nB of PB (arguments ab), spread evenly
 // over the grid, so that a memory-bound and a VALU-bound pass share the CUs.
+// The workgroups are first mapped XCD-grouped (col_block), so that each XCD
+// takes a contiguous run of column tiles and of rows.
 template <class PA, class PB>
 __global__ void __launch_bounds__(PA::THREADS > PB::THREADS ? PA::THREADS : PB::THREADS)
 k_fused(Args aa, Args ab, int nA, int nB) {
   constexpr int LDS = PA::LDS_BYTES > PB::LDS_BYTES ? PA::LDS_BYTES : PB::LDS_BYTES;
   __shared__ __align__(16) char smem[LDS];
   const long long n = (long long)nA + nB;
-  const long long b = blockIdx.x;
+  const long long b = col_block(1);
   const int ia = (int)(b * nA / n);
   const int ia1 = (int)((b + 1) * nA / n);
   if (ia1 > ia)
