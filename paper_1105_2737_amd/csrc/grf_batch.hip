@@ -1,9 +1,10 @@
 // Persistent launches for batches of fields of different sizes (d = 2,
 // one-FFT algorithm, float32).  See grf_batch.hpp.
 //
-// Both passes reuse the kernel bodies of the single-plan sampler
-// (ColPass / RowC2R), so a field sampled in a batch has the same bits as the
-// same field sampled by a plan.  Column workgroups have 256 threads and at most
+// Both passes reuse the kernel bodies of the single-plan sampler (ColPass,
+// and RowC2RStaged, the LDS-staged form of RowC2R with the same arithmetic),
+// so a field sampled in a batch has the same bits as the same field sampled
+// by a plan.  Column workgroups have 256 threads and at most
 // ~48 KB of LDS (three per CU at the column bodies' register use); row
 // workgroups 512 threads and at most ~70 KB (two per CU).  Each length has two
 // tile shapes (the second with half the columns / rows per workgroup) between
@@ -24,7 +25,7 @@ namespace grf {
 template <int L, int CP>
 using BColPass = ColPass<float, L, typename ColCfg<L>::Rad, CP, ColCfg<L>::PAD, SRC_GEN, +1>;
 template <int M, int RB>
-using BRowPass = RowC2R<float, M, typename RowCfg<M>::Rad, RB, 0>;
+using BRowPass = RowC2RStaged<float, M, typename RowCfg<M>::Rad, RB, 0>;
 
 // LDS of the largest body
 #define GRF_COL_LDS(L_, A_, B_) (BColPass<L_, A_>::LDS_BYTES > BColPass<L_, B_>::LDS_BYTES ? BColPass<L_, A_>::LDS_BYTES : BColPass<L_, B_>::LDS_BYTES),
@@ -107,24 +108,35 @@ __device__ __forceinline__ int next_item(int* counter, int n, int* s_item) {
   return i < n ? i : -1;
 }
 
+// Column items come in XCD_QUEUES queues (queue q = items[qoff[q] .. qoff[q+1]),
+// counter counters[q]): a workgroup starts on the queue of its XCD (workgroup
+// i runs on XCD i mod 8 under round-robin dispatch), so that the adjacent
+// tiles of a field, which share cache lines, meet in one L2; when its queue is
+// drained it helps with the others.
 __global__ void __launch_bounds__(BATCH_COL_THREADS)
-k_batch_col(const BatchField* __restrict__ F, const BatchItem* __restrict__ items, int n, const float2* tw,
-            float* out, int* counter) {
+k_batch_col(const BatchField* __restrict__ F, const BatchItem* __restrict__ items, const int* __restrict__ qoff,
+            const float2* tw, float* out, int* counters) {
   __shared__ __align__(16) char smem[COL_LDS];
   __shared__ int s_item;
-  for (int i = next_item(counter, n, &s_item); i >= 0; i = next_item(counter, n, &s_item)) {
-    const BatchItem w = items[i];
-    const BatchField& f = F[w.field];
-    const int key = f.n1 * 4 + f.cvar;
-    switch (key) {
+  const int x0 = (int)(blockIdx.x % XCD_QUEUES);
+  for (int j = 0; j < XCD_QUEUES; ++j) {
+    const int q = (x0 + j) % XCD_QUEUES;
+    const int base = qoff[q], n = qoff[q + 1] - base;
+    int* counter = counters + q;
+    for (int i = next_item(counter, n, &s_item); i >= 0; i = next_item(counter, n, &s_item)) {
+      const BatchItem w = items[base + i];
+      const BatchField& f = F[w.field];
+      const int key = f.n1 * 4 + f.cvar;
+      switch (key) {
 #define GRF_CASE(L_, A_, B_)                                                  \
   case L_ * 4 + 0: bcol_body<L_, A_>(F, w.field, w.sub, out, tw, smem); break; \
   case L_ * 4 + 1: bcol_body<L_, B_>(F, w.field, w.sub, out, tw, smem); break;
-      GRF_BATCH_COL(GRF_CASE)
+        GRF_BATCH_COL(GRF_CASE)
 #undef GRF_CASE
-      default: break;
+        default: break;
+      }
+      __syncthreads();  // the next item reuses the LDS
     }
-    __syncthreads();  // the next item reuses the LDS
   }
 }
 
@@ -174,10 +186,10 @@ int batch_row_rb(int M, int var) {
 bool batch_col_supported(int L) { return batch_col_cp(L, 0) > 0; }
 bool batch_row_supported(int M) { return batch_row_rb(M, 0) > 0; }
 
-hipError_t launch_batch_col(const BatchField* fields, const BatchItem* items, int nitems, const void* twpool,
-                            float* out, int* counter, int nwg, hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_col, dim3(nwg), dim3(BATCH_COL_THREADS), 0, s, fields, items, nitems,
-                     (const float2*)twpool, out, counter);
+hipError_t launch_batch_col(const BatchField* fields, const BatchItem* items, const int* qoff, const void* twpool,
+                            float* out, int* counters, int nwg, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_col, dim3(nwg), dim3(BATCH_COL_THREADS), 0, s, fields, items, qoff,
+                     (const float2*)twpool, out, counters);
   return hipGetLastError();
 }
 hipError_t launch_batch_row(const BatchField* fields, const BatchItem* items, int nitems, const void* twpool,

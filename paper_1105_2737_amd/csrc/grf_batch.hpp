@@ -32,6 +32,8 @@ struct BatchItem {
 constexpr int BATCH_COL_THREADS = 256;
 constexpr int BATCH_ROW_THREADS = 512;
 constexpr int BATCH_VARIANTS = 2;
+constexpr int XCD_QUEUES = 8;         // column work queues, one per XCD
+constexpr int BATCH_COUNTERS = XCD_QUEUES + 1;   // column queues, then the row queue
 
 // Geometry of a variant: column pairs per column workgroup / rows per row workgroup.
 int batch_col_cp(int L, int var);
@@ -39,9 +41,12 @@ int batch_row_rb(int M, int var);
 bool batch_col_supported(int L);
 bool batch_row_supported(int M);
 
-// One persistent launch over `nitems` items (grid = nwg workgroups).
-hipError_t launch_batch_col(const BatchField* fields, const BatchItem* items, int nitems, const void* twpool,
-                            float* out, int* counter, int nwg, hipStream_t s);
+// One persistent launch (grid = nwg workgroups, a multiple of XCD_QUEUES for
+// the XCD grouping to hold) over the column items in XCD_QUEUES queues
+// (device offsets qoff[0..XCD_QUEUES], counters[0..XCD_QUEUES-1]) or over
+// `nitems` row items.
+hipError_t launch_batch_col(const BatchField* fields, const BatchItem* items, const int* qoff, const void* twpool,
+                            float* out, int* counters, int nwg, hipStream_t s);
 hipError_t launch_batch_row(const BatchField* fields, const BatchItem* items, int nitems, const void* twpool,
                             float* out, int* counter, int nwg, hipStream_t s);
 hipError_t launch_reset_counters(int* counters, int n, hipStream_t s);

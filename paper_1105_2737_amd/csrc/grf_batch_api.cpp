@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -32,6 +33,7 @@ struct grf_batch_s {
   BatchField* d_fields = nullptr;
   BatchItem* d_col = nullptr;
   BatchItem* d_row = nullptr;
+  int* d_qoff = nullptr;               // column queue offsets, XCD_QUEUES + 1
   int ncol = 0, nrow = 0;
   void* d_tw = nullptr;
   int* d_counters = nullptr;
@@ -59,10 +61,34 @@ struct WItem {
   long long cost;
 };
 
+// Column work items of the given fields (field, tiles, cost) in XCD_QUEUES
+// queues: fields in decreasing order of cost go to the least-loaded queue,
+// all tiles of a field together and in order, so that adjacent tiles run on
+// one XCD.  qoff receives the XCD_QUEUES + 1 queue offsets.
+void col_queues(std::vector<std::array<long long, 3>> fl, std::vector<BatchItem>& items, std::vector<int>& qoff) {
+  std::stable_sort(fl.begin(), fl.end(), [](const std::array<long long, 3>& x, const std::array<long long, 3>& y) {
+    return x[2] > y[2];
+  });
+  std::vector<std::vector<BatchItem>> q(grf::XCD_QUEUES);
+  std::vector<long long> load(grf::XCD_QUEUES, 0);
+  for (const auto& f : fl) {
+    const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    for (long long t = 0; t < f[1]; ++t) q[x].push_back({(int)f[0], (int)t});
+    load[x] += f[2];
+  }
+  items.clear();
+  qoff.assign(grf::XCD_QUEUES + 1, 0);
+  for (int x = 0; x < grf::XCD_QUEUES; ++x) {
+    items.insert(items.end(), q[x].begin(), q[x].end());
+    qoff[x + 1] = (int)items.size();
+  }
+}
+
 // (Re)build field records and work queues for the current variants; upload.
 grf_status build_queues(grf_batch_s* b) {
   const int n = (int)b->desc.size();
-  std::vector<WItem> col, row;
+  std::vector<WItem> row;
+  std::vector<std::array<long long, 3>> cf;
   for (int f = 0; f < n; ++f) {
     BatchField& r = b->fields[f];
     r.cvar = b->cvar[r.n1];
@@ -70,7 +96,7 @@ grf_status build_queues(grf_batch_s* b) {
     const int cp = grf::batch_col_cp(r.n1, r.cvar);
     const int rb = grf::batch_row_rb(r.M, r.rvar);
     r.ntile = (r.M + 2 * cp - 1) / (2 * cp);
-    for (int t = 0; t < r.ntile; ++t) col.push_back({{f, t}, (long long)r.n1 * 2 * cp});
+    cf.push_back({f, r.ntile, (long long)r.ntile * r.n1 * 2 * cp});
     const int nrb = (r.n1 + rb - 1) / rb;
     for (int k = 0; k < nrb; ++k) row.push_back({{f, k}, (long long)r.M * 2 * rb});
   }
@@ -79,10 +105,10 @@ grf_status build_queues(grf_batch_s* b) {
     if (x.it.field != y.it.field) return x.it.field < y.it.field;
     return x.it.sub < y.it.sub;
   };
-  std::stable_sort(col.begin(), col.end(), by_cost);
   std::stable_sort(row.begin(), row.end(), by_cost);
-  std::vector<BatchItem> hc(col.size()), hr(row.size());
-  for (size_t i = 0; i < col.size(); ++i) hc[i] = col[i].it;
+  std::vector<BatchItem> hc, hr(row.size());
+  std::vector<int> qoff;
+  col_queues(cf, hc, qoff);
   for (size_t i = 0; i < row.size(); ++i) hr[i] = row[i].it;
   if (b->d_col) (void)hipFree(b->d_col);
   if (b->d_row) (void)hipFree(b->d_row);
@@ -94,6 +120,7 @@ grf_status build_queues(grf_batch_s* b) {
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_row, std::max<size_t>(1, hr.size()) * sizeof(BatchItem));
   if (e != hipSuccess) return fail(GRF_ENOMEM, "hipMalloc of work queues failed");
   e = hipMemcpy(b->d_col, hc.data(), hc.size() * sizeof(BatchItem), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_qoff, qoff.data(), qoff.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->d_row, hr.data(), hr.size() * sizeof(BatchItem), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(b->d_fields, b->fields.data(), b->fields.size() * sizeof(BatchField), hipMemcpyHostToDevice);
@@ -103,12 +130,12 @@ grf_status build_queues(grf_batch_s* b) {
 }
 
 grf_status enqueue(grf_batch_s* b, void* out, hipStream_t s) {
-  hipError_t e = grf::launch_reset_counters(b->d_counters, 2, s);
+  hipError_t e = grf::launch_reset_counters(b->d_counters, grf::BATCH_COUNTERS, s);
   if (e == hipSuccess)
-    e = grf::launch_batch_col(b->d_fields, b->d_col, b->ncol, b->d_tw, (float*)out, b->d_counters, b->nwg_col, s);
+    e = grf::launch_batch_col(b->d_fields, b->d_col, b->d_qoff, b->d_tw, (float*)out, b->d_counters, b->nwg_col, s);
   if (e == hipSuccess)
-    e = grf::launch_batch_row(b->d_fields, b->d_row, b->nrow, b->d_tw, (float*)out, b->d_counters + 1, b->nwg_row,
-                              s);
+    e = grf::launch_batch_row(b->d_fields, b->d_row, b->nrow, b->d_tw, (float*)out,
+                              b->d_counters + grf::XCD_QUEUES, b->nwg_row, s);
   if (e != hipSuccess) return hip_fail(e, "batch launch");
   return GRF_OK;
 }
@@ -217,7 +244,8 @@ grf_status grf_batch_create(const grf_field_desc* fields, int64_t nfields, grf_b
   e = hipMalloc(&b->d_tw, pool.size() * sizeof(float));
   if (e == hipSuccess) e = hipMemcpy(b->d_tw, pool.data(), pool.size() * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_fields, b->fields.size() * sizeof(BatchField));
-  if (e == hipSuccess) e = hipMalloc((void**)&b->d_counters, 2 * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_counters, grf::BATCH_COUNTERS * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_qoff, (grf::XCD_QUEUES + 1) * sizeof(int));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
   if (e != hipSuccess) st = hip_fail(e, "batch allocation");
   if (st == GRF_OK) st = build_queues(b);
@@ -327,27 +355,36 @@ grf_status grf_batch_tune(grf_batch b, void* out, void* stream) {
     vm[len] = var;
     grf_status st = build_queues(b);
     if (st != GRF_OK) return st;
-    // work items of this length only: a prefix-free filter on the host copies
+    // work items of this length only (column items in their XCD queues)
     std::vector<BatchItem> items;
+    std::vector<std::array<long long, 3>> cf;
     for (size_t f = 0; f < b->fields.size(); ++f) {
       const BatchField& r = b->fields[f];
       if ((colpass ? r.n1 : r.M) != len) continue;
       const int per = colpass ? grf::batch_col_cp(len, var) : grf::batch_row_rb(len, var);
       const int nsub = colpass ? (r.M + 2 * per - 1) / (2 * per) : (r.n1 + per - 1) / per;
-      for (int k = 0; k < nsub; ++k) items.push_back({(int)f, k});
+      if (colpass)
+        cf.push_back({(long long)f, nsub, (long long)nsub * r.n1 * 2 * per});
+      else
+        for (int k = 0; k < nsub; ++k) items.push_back({(int)f, k});
     }
+    std::vector<int> qoff;
+    if (colpass) col_queues(cf, items, qoff);
     BatchItem* d_items = nullptr;
-    hipError_t e = hipMalloc((void**)&d_items, items.size() * sizeof(BatchItem));
+    int* d_q = nullptr;
+    hipError_t e = hipMalloc((void**)&d_items, std::max<size_t>(1, items.size()) * sizeof(BatchItem));
+    if (e == hipSuccess) e = hipMalloc((void**)&d_q, (grf::XCD_QUEUES + 1) * sizeof(int));
     if (e == hipSuccess) e = hipMemcpy(d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice);
+    if (e == hipSuccess && colpass) e = hipMemcpy(d_q, qoff.data(), qoff.size() * sizeof(int), hipMemcpyHostToDevice);
     float best = 1e30f;
     for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
-      e = grf::launch_reset_counters(b->d_counters, 2, s);
+      e = grf::launch_reset_counters(b->d_counters, grf::BATCH_COUNTERS, s);
       if (e == hipSuccess) e = hipEventRecord(e0, s);
       if (e == hipSuccess)
-        e = colpass ? grf::launch_batch_col(b->d_fields, d_items, (int)items.size(), b->d_tw, (float*)out,
-                                            b->d_counters, b->nwg_col, s)
+        e = colpass ? grf::launch_batch_col(b->d_fields, d_items, d_q, b->d_tw, (float*)out, b->d_counters,
+                                            b->nwg_col, s)
                     : grf::launch_batch_row(b->d_fields, d_items, (int)items.size(), b->d_tw, (float*)out,
-                                            b->d_counters + 1, b->nwg_row, s);
+                                            b->d_counters + grf::XCD_QUEUES, b->nwg_row, s);
       if (e == hipSuccess) e = hipEventRecord(e1, s);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float t = 0;
@@ -355,6 +392,7 @@ grf_status grf_batch_tune(grf_batch b, void* out, void* stream) {
       if (rep > 0) best = std::min(best, t);   // first run warms up
     }
     if (d_items) (void)hipFree(d_items);
+    if (d_q) (void)hipFree(d_q);
     vm = saved;
     if (e != hipSuccess) return hip_fail(e, "tuning run");
     *ms = best;
@@ -401,6 +439,7 @@ grf_status grf_batch_destroy(grf_batch b) {
   if (b->d_fields) (void)hipFree(b->d_fields);
   if (b->d_col) (void)hipFree(b->d_col);
   if (b->d_row) (void)hipFree(b->d_row);
+  if (b->d_qoff) (void)hipFree(b->d_qoff);
   if (b->d_tw) (void)hipFree(b->d_tw);
   if (b->d_counters) (void)hipFree(b->d_counters);
   delete b;

@@ -791,6 +791,63 @@ struct RowC2R {
   }
 };
 
+// The same pass with the rows staged through LDS first (copy_in) and
+// workgroup barriers between stages: fewer live registers than RowC2R, for
+// the persistent batch kernel, whose register budget is the maximum over all
+// its bodies.  Same arithmetic, so the same bits.
+template <typename T, int M, class Rad, int RB, int PADR>
+struct RowC2RStaged {
+  using V = C<T>;
+  using E = Vec<T, 1>;
+  using RL = RowLds<M>;
+  static constexpr int NT = M / Rad::get(0);
+  static constexpr int THREADS = (NT * RB + 63) / 64 * 64;
+  static constexpr int R0 = Rad::get(0);
+  static constexpr int LDS_BYTES = RB * RL::STRIDE * (int)sizeof(E) + 2 * M * (int)sizeof(V);
+  static_assert(PADR == 0, "row passes use the RowLds layout");
+  using EN = Eng<T, M, Rad, NT, 1, 2>;
+
+  __device__ __forceinline__ static void run(const Args& a, int bid, char* smem) {
+    E* sm = reinterpret_cast<E*>(smem);
+    V* tw = reinterpret_cast<V*>(smem + RB * RL::STRIDE * sizeof(E));
+    const int tid = threadIdx.x;
+    const int r = tid / NT;
+    const int t = tid % NT;
+    const long long row0 = (long long)bid * RB;
+    const long long left = a.rows - row0;
+    const int nrows = left < RB ? (int)left : RB;
+    V* g = (V*)a.data + row0 * M;
+    if (tid < THREADS) {
+      copy_in<T, M, RB * M, THREADS>(g, sm, nrows * M, tid);
+      for (int i = tid; i < 2 * M; i += THREADS) tw[i] = ((const V*)a.tw2)[i];
+    }
+    __syncthreads();
+    const bool act = (r < nrows) && (t < NT);
+    V x[1][EN::REG];
+    if (act) {
+      const E* rowp = sm + r * RL::STRIDE;
+#pragma unroll
+      for (int m = 0; m < R0; ++m) {
+        const int k = t + m * NT;
+        const V xk = rowp[RL::idx(k)].v[0];
+        if (k == 0) {
+          x[0][m] = mk<T>(xk.x + xk.y, xk.x - xk.y);
+        } else {
+          const V xm = cconj(rowp[RL::idx(M - k)].v[0]);
+          const V ek = cadd(xk, xm);
+          const V ok = cmul(csub(xk, xm), tw[k]);
+          x[0][m] = mk<T>(ek.x - ok.y, ek.y + ok.x);
+        }
+      }
+    }
+    __syncthreads();
+    auto lds = [&](int i) -> E& { return sm[r * RL::STRIDE + RL::idx(i)]; };
+    V* o = g + (long long)r * M;
+    auto out = [&](int i, const E& e) { o[i] = e.v[0]; };
+    EN::template run<+1>(x, t, act, lds, tw, out);
+  }
+};
+
 // Kernel wrapper of RowC2R.
 template <typename T, int M, class Rad, int RB, int PADR>
 __global__ void __launch_bounds__((RowC2R<T, M, Rad, RB, PADR>::THREADS))
