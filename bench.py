@@ -48,12 +48,13 @@ def gen_pass_ops_per_point(n1):
     return 10 + 7.5 + 1.5 + (7 * s + 3.5 * (s - 1)) / 2
 
 # HBM bytes per launch of the headline step's kernels (one launch = one cache-sized
-# chunk of 256 fields), from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
-# scaled by the same counters on a 1 GiB device copy (FETCH x2, WRITE x1); see
-# profiles/.  Set an entry to None when its kernel changes.
+# chunk of 256 fields), from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch,
+# launches in sequence) scaled by the same counters on a 1 GiB device copy (FETCH x2,
+# WRITE x1); profiles/grf_sample_512x512x1024_f32.md.  Set an entry to None when its
+# kernel changes.
 MEASURED_TRAFFIC = {
-    "column noise+inverse FFT (axis 1)": None,
-    "last-axis C2R": None,
+    "column noise+inverse FFT (axis 1)": (2396 * 2 + 281030) * 1024,
+    "last-axis C2R": (131139 * 2 + 262144) * 1024,
 }
 
 
@@ -65,6 +66,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--unchunked-ref", action="store_true",
+                    help="also time the sampler with one launch per pass over the whole batch")
     ap.add_argument("--profile-stage", type=int, default=None,
                     help="profiling mode: launch only this stage of the headline step (-1: the whole "
                          "sampler), --steps times")
@@ -232,9 +235,11 @@ def main():
     fused_step = timed(lambda: plan.sample(seed=0, batch=batch, out=out), args.steps, args.warmup, torch)
     del os.environ["GRF_FUSE"]
     # one launch per pass over the whole batch (no cache-sized chunks), for reference
-    os.environ["GRF_CHUNK_BYTES"] = str(1 << 40)
-    unchunked_step = timed(lambda: plan.sample(seed=0, batch=batch, out=out), args.steps, args.warmup, torch)
-    del os.environ["GRF_CHUNK_BYTES"]
+    unchunked_step = None
+    if args.unchunked_ref:
+        os.environ["GRF_CHUNK_BYTES"] = str(1 << 40)
+        unchunked_step = timed(lambda: plan.sample(seed=0, batch=batch, out=out), args.steps, args.warmup, torch)
+        del os.environ["GRF_CHUNK_BYTES"]
     traffic = MEASURED_TRAFFIC.get(kname)
     if dom == 0:
         # VALU-bound (noise generation in registers): algorithmic lane-ops vs the VALU issue peak
@@ -255,7 +260,7 @@ def main():
         "whole_step_model_GBps": round(total_bytes / sec / 1e9, 1),
         "whole_step_model_frac": round(total_bytes / sec / 1e9 / HBM_PEAK_GBS, 4),
         "passes": kind_rows(agg), "fused_schedule_step_ms": round(fused_step * 1e3, 4),
-        "unchunked_step_ms": round(unchunked_step * 1e3, 4)})
+        "unchunked_step_ms": None if unchunked_step is None else round(unchunked_step * 1e3, 4)})
 
     result = {
         "metric": "GRF points/s + HBM-roofline % (512^2, 256^3 FP32); batched & fwd+adjoint vs plain",

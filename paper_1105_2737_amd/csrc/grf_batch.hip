@@ -162,7 +162,7 @@ k_batch_row(const BatchField* __restrict__ F, const BatchItem* __restrict__ item
 }
 
 __global__ void k_reset_counters(int* c, int n) {
-  if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0;
 }
 
 int batch_col_cp(int L, int var) {
