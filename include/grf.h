@@ -66,7 +66,7 @@ typedef enum {
 enum { GRF_ALG_TWO_FFT = 1, GRF_ALG_ONE_FFT = 2 };
 enum { GRF_F32 = 0, GRF_F64 = 1 };
 enum { GRF_COV_GAUSSIAN = 0, GRF_COV_MATERN = 1, GRF_COV_EXPONENTIAL = 2 };
-enum { GRF_OP_SAMPLE = 0, GRF_OP_BACKWARD = 1 };
+enum { GRF_OP_SAMPLE = 0, GRF_OP_BACKWARD = 1, GRF_OP_COVARIANCE = 2 };
 
 /*
  * Plan description.
@@ -107,7 +107,8 @@ grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out);
 grf_status grf_plan_destroy(grf_plan plan);
 
 /* Bytes of device workspace that grf_sample / grf_sample_from_noise
- * (op = GRF_OP_SAMPLE) or grf_backward (op = GRF_OP_BACKWARD) need for
+ * (op = GRF_OP_SAMPLE), grf_backward (op = GRF_OP_BACKWARD) or
+ * grf_covariance (op = GRF_OP_COVARIANCE, batch = number of samples) need for
  * `batch` fields (host pointer `bytes`).  The sampler runs in place in the
  * output buffer; its workspace only holds per-field constants. */
 grf_status grf_workspace_size(grf_plan plan, int64_t batch, int32_t op, size_t* bytes);
@@ -154,13 +155,28 @@ enum {
   GRF_PASS_COL_GRAD = 4,      /* forward transform and adjoint reduction along axis 1 */
   GRF_PASS_ROW_C2R = 5,       /* last-axis complex-to-real inverse transform */
   GRF_PASS_ROW_R2C_GEN = 6,   /* last-axis white noise + real-to-complex forward transform (two-FFT) */
-  GRF_PASS_ROW_R2C_LOAD = 7   /* last-axis real-to-complex forward transform of stored rows */
+  GRF_PASS_ROW_R2C_LOAD = 7,  /* last-axis real-to-complex forward transform of stored rows */
+  GRF_PASS_ROW_GEN_C2R = 8    /* d = 1: noise + filter + complex-to-real transform of whole fields */
 };
 grf_status grf_sample_stage_count(grf_plan plan, int64_t batch, int32_t* count);
 grf_status grf_sample_stage(grf_plan plan, int32_t stage, uint64_t seed, int64_t batch, const double* theta,
                             void* out, void* workspace, size_t workspace_bytes, void* stream);
 grf_status grf_sample_stage_info(grf_plan plan, int64_t batch, int32_t stage, int32_t* kind, int64_t* first,
                                  int64_t* count);
+
+/* Statistical covariance of the sampler, the estimator of Section 4:
+ *   cov[j] = (1/nsamples) sum_{b < nsamples} phi_b(x_0) phi_b(x_j)
+ * for every grid point x_j, where phi_b is field seed+b exactly as grf_sample
+ * returns it with the plan's parameters (x_0 is the grid's first point).  cov:
+ * device, float64, one value per grid point (the field's shape).  d = 1
+ * accumulates in the sampler's last pass (the fields are never written); d = 2
+ * and 3 sample cache-sized chunks of fields into the workspace and
+ * accumulate them.  The sums are taken in a fixed order (float64), so the
+ * result does not depend on scheduling.  workspace: device, at least
+ * grf_workspace_size(plan, nsamples, GRF_OP_COVARIANCE) bytes.  Errors:
+ * GRF_EINVAL (null pointer, nsamples < 1, workspace too small). */
+grf_status grf_covariance(grf_plan plan, uint64_t seed, int64_t nsamples, double* cov, void* workspace,
+                          size_t workspace_bytes, void* stream);
 
 /* Write the noise z of the contract for fields seed..seed+batch-1 (device,
  * same shape and dtype as the output). */

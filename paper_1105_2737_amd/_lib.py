@@ -11,16 +11,17 @@ GRF_OK, GRF_EINVAL, GRF_ENOMEM, GRF_EDEVICE, GRF_EUNSUPPORTED = 0, -1, -2, -3, -
 GRF_ALG_TWO_FFT, GRF_ALG_ONE_FFT = 1, 2
 GRF_F32, GRF_F64 = 0, 1
 GRF_COV_GAUSSIAN, GRF_COV_MATERN, GRF_COV_EXPONENTIAL = 0, 1, 2
-GRF_OP_SAMPLE, GRF_OP_BACKWARD = 0, 1
+GRF_OP_SAMPLE, GRF_OP_BACKWARD, GRF_OP_COVARIANCE = 0, 1, 2
 GRF_PASS_FUSED, GRF_PASS_COL_GEN_INV, GRF_PASS_COL_LOAD_INV, GRF_PASS_COL_LOAD_FWD = -1, 0, 1, 2
 GRF_PASS_COL_FILTER, GRF_PASS_COL_GRAD, GRF_PASS_ROW_C2R, GRF_PASS_ROW_R2C_GEN, GRF_PASS_ROW_R2C_LOAD = 3, 4, 5, 6, 7
+GRF_PASS_ROW_GEN_C2R = 8
 
 STATUS_NAMES = {0: "GRF_OK", -1: "GRF_EINVAL", -2: "GRF_ENOMEM", -3: "GRF_EDEVICE", -4: "GRF_EUNSUPPORTED"}
 
 # every symbol include/grf.h declares
 EXPORTS = ["grf_plan_create", "grf_plan_destroy", "grf_workspace_size", "grf_sample",
            "grf_sample_stage_count", "grf_sample_stage", "grf_sample_stage_info", "grf_sample_from_noise", "grf_noise", "grf_backward", "grf_debug_philox",
-           "grf_batch_create", "grf_batch_offsets", "grf_batch_sample", "grf_batch_sample_plain",
+           "grf_covariance", "grf_batch_create", "grf_batch_offsets", "grf_batch_sample", "grf_batch_sample_plain",
            "grf_batch_tune", "grf_batch_destroy", "grf_last_error", "grf_version"]
 
 
@@ -61,6 +62,7 @@ def _load():
         "grf_noise": (ctypes.c_int, [vp, u64, c64, vp, vp]),
         "grf_backward": (ctypes.c_int, [vp, u64, vp, c64, vp, vp, vp, vp, vp, sz, vp]),
         "grf_debug_philox": (ctypes.c_int, [u64, vp, c64, vp, vp]),
+        "grf_covariance": (ctypes.c_int, [vp, u64, c64, vp, vp, sz, vp]),
         "grf_batch_create": (ctypes.c_int, [ctypes.POINTER(grf_field_desc), c64, ctypes.POINTER(vp)]),
         "grf_batch_offsets": (ctypes.c_int, [vp, ctypes.POINTER(c64)]),
         "grf_batch_sample": (ctypes.c_int, [vp, vp, vp]),
@@ -137,6 +139,10 @@ def grf_backward(plan, seed, noise, batch, theta, grad_out, grad_theta, grad_noi
                  workspace_bytes, stream):
     return check(lib.grf_backward(plan, seed, noise, batch, theta, grad_out, grad_theta, grad_noise,
                                   workspace, workspace_bytes, stream))
+
+
+def grf_covariance(plan, seed, nsamples, cov, workspace, workspace_bytes, stream):
+    return check(lib.grf_covariance(plan, seed, nsamples, cov, workspace, workspace_bytes, stream))
 
 
 def grf_debug_philox(seed, counters, n, out, stream):

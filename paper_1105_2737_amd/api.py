@@ -23,8 +23,8 @@ def _stream():
 class Plan:
     """A sampling plan: grid, domain, algorithm, precision and covariance family.
 
-    dims: (N_1, ..., N_d), d in {2, 3}, all even; lengths: edge lengths
-    (default the unit torus); alg: 2 = one-FFT (Hermitian), 1 = two-FFT;
+    dims: (N_1, ..., N_d), d in {1, 2, 3}, all even; lengths: edge lengths
+    (default the unit torus); alg: 2 = one-FFT (Hermitian), 1 = two-FFT (d = 2);
     dtype: torch.float32 or torch.float64; cov: 'gaussian' | 'matern' |
     'exponential' with default parameters sigma, length_scale, nu.
     """
@@ -100,6 +100,14 @@ class Plan:
         ws, n = self._workspace(batch, L.GRF_OP_SAMPLE)
         L.grf_sample_from_noise(self.handle, _ptr(noise), batch, _ptr(th), _ptr(out), _ptr(ws), n, _stream())
         return out
+
+    def covariance(self, seed=0, nsamples=1):
+        """Statistical covariance (1/n) sum_b phi_b(x_0) phi_b(x) over fields
+        seed .. seed+n-1 (float64 tensor of the field's shape)."""
+        cov = torch.empty(self.dims, dtype=torch.float64, device=self.device)
+        ws, n = self._workspace(int(nsamples), L.GRF_OP_COVARIANCE)
+        L.grf_covariance(self.handle, int(seed) & (2 ** 64 - 1), int(nsamples), _ptr(cov), _ptr(ws), n, _stream())
+        return cov
 
     def noise(self, seed=0, batch=1):
         out = self._empty(batch)

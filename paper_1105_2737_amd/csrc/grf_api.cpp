@@ -280,6 +280,14 @@ void chunk_passes(const grf_plan_s* p, uint64_t seed, const void* zsrc, long lon
     pl.count = nb;
     v.push_back(pl);
   };
+  if (p->d == 1) {
+    // one launch: noise, filter and complex-to-real transform of whole fields
+    a.tag = 1;
+    a.tw2 = p->tw_row;
+    a.rows = nb;
+    push(grf::PASS_ROW_GEN_C2R, p->M, a);
+    return;
+  }
   if (p->desc.alg == GRF_ALG_ONE_FFT) {
     a.tag = 1;
     a.tw = p->tw_col1;
@@ -358,6 +366,33 @@ std::vector<PassLaunch> sample_passes(const grf_plan_s* p, uint64_t seed, const 
   return v;
 }
 
+// Covariance estimator: workgroups of the one-dimensional epilogue (a fixed
+// number, so that the result does not depend on the device) and the
+// workspace layout: d = 1 [partials: groups * P float64]; d >= 2
+// [acc: P float64][chunk of sampled fields].
+constexpr long long COV_GROUPS = 2048;
+
+struct CovLayout {
+  long long groups, chunk;
+  size_t acc, buf, total;
+};
+
+CovLayout cov_layout(const grf_plan_s* p, long long n) {
+  CovLayout c{};
+  if (p->d == 1) {
+    const grf::Geom g = grf::geom_gen1d(p->dtype, p->M);
+    const long long rb = g.per_wg > 0 ? g.per_wg : 1;
+    c.groups = std::min<long long>((n + rb - 1) / rb, COV_GROUPS);
+    c.total = align256((size_t)c.groups * p->P * sizeof(double));
+  } else {
+    c.chunk = chunk_fields(p, n);
+    c.acc = 0;
+    c.buf = align256((size_t)p->P * sizeof(double));
+    c.total = c.buf + align256((size_t)c.chunk * p->P * p->esz);
+  }
+  return c;
+}
+
 // stage < 0: run every pass; otherwise only that one.
 grf_status sample_impl(grf_plan p, uint64_t seed, const void* zsrc, int64_t batch, const double* theta, void* out,
                        void* workspace, size_t ws_bytes, void* stream, int stage = -1) {
@@ -410,6 +445,7 @@ bool row_length_supported(int M) {
 }
 
 Geom pass_geom(int pass, int dtype, int L) {
+  if (pass == PASS_ROW_GEN_C2R) return geom_gen1d(dtype, L);
   if (pass >= PASS_ROW_C2R) return dtype == 0 ? geom_row_f32(pass, L) : geom_row_f64(pass, L);
   return dtype == 0 ? geom_col_f32(pass, L) : geom_col_f64(pass, L);
 }
@@ -421,6 +457,7 @@ hipError_t launch_fused(int dtype, int L, int M, const Args& aA, const Args& aB,
 }
 
 hipError_t launch_pass(int pass, int dtype, int L, const Args& a, long long nblocks, hipStream_t s) {
+  if (pass == PASS_ROW_GEN_C2R) return launch_gen1d(dtype, L, a, nblocks, nullptr, s);
   if (pass >= PASS_ROW_C2R)
     return dtype == 0 ? launch_row_f32(pass, L, a, nblocks, s) : launch_row_f64(pass, L, a, nblocks, s);
   return dtype == 0 ? launch_col_f32(pass, L, a, nblocks, s) : launch_col_f64(pass, L, a, nblocks, s);
@@ -438,7 +475,7 @@ grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out) {
   if (desc == nullptr || out == nullptr) return fail(GRF_EINVAL, "null argument");
   *out = nullptr;
   const grf_plan_desc& d = *desc;
-  if (d.ndim < 2 || d.ndim > 3) return fail(GRF_EUNSUPPORTED, "ndim must be 2 or 3");
+  if (d.ndim < 1 || d.ndim > 3) return fail(GRF_EINVAL, "ndim must be 1, 2 or 3");
   if (d.alg != GRF_ALG_TWO_FFT && d.alg != GRF_ALG_ONE_FFT) return fail(GRF_EINVAL, "unknown algorithm");
   if (d.dtype != GRF_F32 && d.dtype != GRF_F64) return fail(GRF_EINVAL, "unknown dtype");
   if (d.cov_kind < GRF_COV_GAUSSIAN || d.cov_kind > GRF_COV_EXPONENTIAL)
@@ -455,22 +492,23 @@ grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out) {
   if (d.alg == GRF_ALG_TWO_FFT && d.ndim != 2)
     return fail(GRF_EUNSUPPORTED, "two-FFT algorithm implemented for d = 2");
   const int last = d.ndim - 1;
-  if (!grf::col_length_supported((int)d.dims[0]) || (d.ndim == 3 && !grf::col_length_supported((int)d.dims[1])) ||
-      d.dims[last] > 2 * 512 || !grf::row_length_supported((int)(d.dims[last] / 2)))
+  if ((d.ndim >= 2 && !grf::col_length_supported((int)d.dims[0])) ||
+      (d.ndim == 3 && !grf::col_length_supported((int)d.dims[1])) || d.dims[last] > (1ll << 30) ||
+      !grf::row_length_supported((int)(d.dims[last] / 2)))
     return fail(GRF_EUNSUPPORTED, "grid length not in the supported list");
 
   grf_plan_s* p = new (std::nothrow) grf_plan_s();
   if (p == nullptr) return fail(GRF_ENOMEM, "host allocation failed");
   p->desc = d;
   p->d = d.ndim;
-  p->n1 = (int)d.dims[0];
+  p->n1 = d.ndim >= 2 ? (int)d.dims[0] : 1;   // d = 1: a field is one row
   p->no = d.ndim == 3 ? (int)d.dims[1] : 1;
   p->nd = (int)d.dims[last];
   p->M = p->nd / 2;
   p->P = (long long)p->n1 * p->no * p->nd;
   p->vol = 1.0;
   for (int i = 0; i < d.ndim; ++i) p->vol *= d.lengths[i];
-  p->il2[0] = 1.0 / (d.lengths[0] * d.lengths[0]);
+  p->il2[0] = d.ndim >= 2 ? 1.0 / (d.lengths[0] * d.lengths[0]) : 0.0;
   p->il2[1] = d.ndim == 3 ? 1.0 / (d.lengths[1] * d.lengths[1]) : 0.0;
   p->il2[2] = 1.0 / (d.lengths[last] * d.lengths[last]);
   p->dtype = d.dtype;
@@ -485,7 +523,7 @@ grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out) {
     delete p;
     return fail(GRF_EINVAL, "invalid covariance parameters");
   }
-  grf_status st = make_table(p->n1, p->dtype, &p->tw_col1);
+  grf_status st = d.ndim >= 2 ? make_table(p->n1, p->dtype, &p->tw_col1) : GRF_OK;
   if (st == GRF_OK && d.ndim == 3) st = make_table(p->no, p->dtype, &p->tw_col2);
   if (st == GRF_OK) st = make_table(p->nd, p->dtype, &p->tw_row);
   if (st == GRF_OK) {
@@ -525,8 +563,49 @@ grf_status grf_plan_destroy(grf_plan p) {
 grf_status grf_workspace_size(grf_plan p, int64_t batch, int32_t op, size_t* bytes) {
   if (p == nullptr || bytes == nullptr) return fail(GRF_EINVAL, "null argument");
   if (batch < 0) return fail(GRF_EINVAL, "negative batch");
-  if (op != GRF_OP_SAMPLE && op != GRF_OP_BACKWARD) return fail(GRF_EINVAL, "unknown op");
-  *bytes = ws_layout(p, batch, op).total;
+  if (op != GRF_OP_SAMPLE && op != GRF_OP_BACKWARD && op != GRF_OP_COVARIANCE) return fail(GRF_EINVAL, "unknown op");
+  *bytes = op == GRF_OP_COVARIANCE ? (batch > 0 ? cov_layout(p, batch).total : 0) : ws_layout(p, batch, op).total;
+  return GRF_OK;
+}
+
+grf_status grf_covariance(grf_plan p, uint64_t seed, int64_t nsamples, double* cov, void* workspace,
+                          size_t workspace_bytes, void* stream) {
+  if (p == nullptr || cov == nullptr) return fail(GRF_EINVAL, "null argument");
+  if (nsamples < 1) return fail(GRF_EINVAL, "nsamples must be >= 1");
+  grf_status st = check_stream_device(p);
+  if (st != GRF_OK) return st;
+  const CovLayout c = cov_layout(p, nsamples);
+  if (workspace == nullptr || workspace_bytes < c.total) return fail(GRF_EINVAL, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  const double scale = 1.0 / (double)nsamples;
+  if (p->d == 1) {
+    double* partial = (double*)workspace;
+    Args a = base_args(p, nsamples);
+    a.recs = p->rec_dev;
+    a.rec_stride = 0;
+    a.seed = seed;
+    a.tag = 1;
+    a.tw2 = p->tw_row;
+    a.rows = nsamples;
+    hipError_t e = grf::launch_gen1d(p->dtype, p->M, a, c.groups, partial, s);
+    if (e == hipSuccess) e = grf::launch_cov_reduce(partial, (int)c.groups, p->P, scale, cov, s);
+    if (e != hipSuccess) return hip_fail(e, "covariance launch");
+    return GRF_OK;
+  }
+  double* acc = (double*)workspace;
+  void* buf = (char*)workspace + c.buf;
+  // acc = 0 (a reduction over no partial sums)
+  hipError_t e = grf::launch_cov_reduce(nullptr, 0, p->P, 0.0, acc, s);
+  if (e != hipSuccess) return hip_fail(e, "covariance launch");
+  for (long long c0 = 0; c0 < nsamples; c0 += c.chunk) {
+    const long long nb = std::min(c.chunk, nsamples - c0);
+    st = sample_impl(p, seed + (uint64_t)c0, nullptr, nb, nullptr, buf, nullptr, 0, stream);
+    if (st != GRF_OK) return st;
+    e = grf::launch_cov_accum(p->dtype, buf, (int)nb, p->P, acc, s);
+    if (e != hipSuccess) return hip_fail(e, "covariance launch");
+  }
+  e = grf::launch_cov_reduce(acc, 1, p->P, scale, cov, s);
+  if (e != hipSuccess) return hip_fail(e, "covariance launch");
   return GRF_OK;
 }
 

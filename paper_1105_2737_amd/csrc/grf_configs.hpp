@@ -47,6 +47,7 @@ template <int M> struct RowCfg;
     using Rad = Radices<__VA_ARGS__>;                      \
     static constexpr int RB32 = RB32_, RB64 = RB64_, PADR = 0; \
   };
+GRF_ROWCFG(2, 64, 64, 2)
 GRF_ROWCFG(4, 64, 64, 4)
 GRF_ROWCFG(8, 64, 64, 8)
 GRF_ROWCFG(12, 32, 32, 3, 4)
@@ -62,6 +63,8 @@ GRF_ROWCFG(256, 8, 8, 8, 8, 4)
 GRF_ROWCFG(360, 4, 4, 8, 5, 9)
 GRF_ROWCFG(500, 4, 2, 10, 10, 5)
 GRF_ROWCFG(512, 4, 4, 8, 8, 8)
+GRF_ROWCFG(1024, 4, 2, 16, 8, 8)
+GRF_ROWCFG(2048, 2, 1, 16, 16, 8)
 #undef GRF_ROWCFG
 
 // Last-axis real-to-complex passes (white noise generation, upstream

@@ -18,7 +18,7 @@ struct Args;
 //   column (leading-axis) lengths: GRF_COL_LENGTHS
 //   row half-lengths M = N_d / 2:  GRF_ROW_LENGTHS
 #define GRF_COL_LENGTHS(X) X(4) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(180) X(256) X(360) X(500) X(512) X(1000) X(1024)
-#define GRF_ROW_LENGTHS(X) X(4) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(180) X(256) X(360) X(500) X(512)
+#define GRF_ROW_LENGTHS(X) X(2) X(4) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(180) X(256) X(360) X(500) X(512) X(1024) X(2048)
 
 // Square grids (N_1 = 2 M) whose column generation pass and last-axis pass
 // can share one launch (chunk c's row pass with chunk c+1's column pass).
@@ -34,6 +34,7 @@ enum PassKind {
   PASS_ROW_C2R = GRF_PASS_ROW_C2R,             // last axis, complex-to-real inverse
   PASS_ROW_R2C_GEN = GRF_PASS_ROW_R2C_GEN,     // last axis, white noise + real-to-complex forward
   PASS_ROW_R2C_LOAD = GRF_PASS_ROW_R2C_LOAD,   // last axis, stored real rows + real-to-complex forward
+  PASS_ROW_GEN_C2R = GRF_PASS_ROW_GEN_C2R,     // d = 1: whole fields, noise + filter + complex-to-real
 };
 
 // Workgroup geometry of a pass at a given length (for grid sizing).
@@ -74,7 +75,22 @@ Geom geom_col_f64(int pass, int L);
 Geom geom_row_f32(int pass, int M);
 Geom geom_row_f64(int pass, int M);
 
+// One-dimensional sampler (fields of N = 2M points, RB per workgroup): with
+// partial == nullptr, workgroup w writes fields w*RB ..; otherwise the
+// covariance epilogue, nblocks workgroups each writing 2M float64 partial sums.
+hipError_t launch_gen1d(int dtype, int M, const Args& a, long long nblocks, double* partial, hipStream_t s);
+hipError_t launch_gen1d_f32(int M, const Args& a, long long nblocks, double* partial, hipStream_t s);
+hipError_t launch_gen1d_f64(int M, const Args& a, long long nblocks, double* partial, hipStream_t s);
+Geom geom_gen1d(int dtype, int M);
+Geom geom_gen1d_f32(int M);
+Geom geom_gen1d_f64(int M);
+
 // helper kernels (grf_util.hip)
+// out[x] = scale * sum_{w < nw} partial[w * n + x], the sum taken in order of w.
+hipError_t launch_cov_reduce(const double* partial, int nw, long long n, double scale, double* out, hipStream_t s);
+// acc[x] += sum_{b < nb} f[b][0] * f[b][x] (fields of P values of the working
+// precision, in float64, in order of b).
+hipError_t launch_cov_accum(int dtype, const void* fields, int nb, long long P, double* acc, hipStream_t s);
 // Device table of h for the record a.recs[0] over the plan's (row, m) grid,
 // row stride M + 2, allocated into *out (synchronous).
 grf_status build_filter_table(int dtype, Args a, double scale, void** out);

@@ -1,0 +1,4 @@
+// one-dimensional kernels, float64
+#define GRF_T double
+#define GRF_SUFFIX f64
+#include "grf_inst_1d.inc"

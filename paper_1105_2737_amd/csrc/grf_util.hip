@@ -1,6 +1,7 @@
 // Helper kernels: per-field constants from device-resident parameters, the
-// deterministic per-field reduction of adjoint partial sums, raw Philox output
-// and the noise array of the contract.
+// deterministic per-field reduction of adjoint partial sums, raw Philox output,
+// the noise array of the contract, and the reductions of the covariance
+// estimator.
 #include "grf_dispatch.hpp"
 #include "grf_host.hpp"
 #include "grf_kernels.hpp"
@@ -107,5 +108,46 @@ hipError_t launch_noise(int dtype, unsigned long long seed, int tag, int rows, i
     hipLaunchKernelGGL(k_noise<double>, grid, block, 0, s, seed, tag, rows, nd, batch, (double*)out);
   return hipGetLastError();
 }
+
+// out[x] = scale * sum_w partial[w * n + x], w in increasing order.
+__global__ void k_cov_reduce(const double* partial, int nw, long long n, double scale, double* out) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  double acc = 0.0;
+  for (int w = 0; w < nw; ++w) acc += partial[(long long)w * n + x];
+  out[x] = acc * scale;
+}
+
+// acc[x] += sum_b f[b][0] f[b][x], b in increasing order, in float64.
+template <typename T>
+__global__ void k_cov_accum(const T* f, int nb, long long P, double* acc) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= P) return;
+  double s = acc[x];
+  for (int b = 0; b < nb; ++b) s += (double)f[(long long)b * P] * (double)f[(long long)b * P + x];
+  acc[x] = s;
+}
+
+hipError_t launch_cov_reduce(const double* partial, int nw, long long n, double scale, double* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cov_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, partial, nw, n, scale, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cov_accum(int dtype, const void* fields, int nb, long long P, double* acc, hipStream_t s) {
+  if (P <= 0 || nb <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((P + 255) / 256)), block(256);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_cov_accum<float>, grid, block, 0, s, (const float*)fields, nb, P, acc);
+  else
+    hipLaunchKernelGGL(k_cov_accum<double>, grid, block, 0, s, (const double*)fields, nb, P, acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_gen1d(int dtype, int M, const Args& a, long long nblocks, double* partial, hipStream_t s) {
+  return dtype == 0 ? launch_gen1d_f32(M, a, nblocks, partial, s) : launch_gen1d_f64(M, a, nblocks, partial, s);
+}
+
+Geom geom_gen1d(int dtype, int M) { return dtype == 0 ? geom_gen1d_f32(M) : geom_gen1d_f64(M); }
 
 }  // namespace grf

@@ -64,10 +64,14 @@ def _desc(**kw):
     (dict(alg=3), -1),
     (dict(dtype=7), -1),
     (dict(cov_kind=9), -1),
-    (dict(ndim=4), -4),
+    (dict(ndim=4), -1),
+    (dict(ndim=0), -1),
     (dict(dims=(2048, 64)), -4),          # length not in the list
-    (dict(dims=(64, 4096)), -4),
+    (dict(dims=(64, 8192)), -4),
     (dict(ndim=3, alg=1, dims=(16, 16, 16)), -4),
+    (dict(ndim=1, dims=(14,)), -1),
+    (dict(ndim=1, dims=(8192,)), -4),
+    (dict(ndim=1, alg=1, dims=(64,)), -4),  # two-FFT algorithm: d = 2 only
 ])
 def test_invalid_descriptors_are_rejected_on_the_host(kw, status):
     from paper_1105_2737_amd import _lib as L
@@ -86,6 +90,7 @@ def test_null_arguments():
     assert L.lib.grf_workspace_size(None, 1, 0, ctypes.byref(n)) == L.GRF_EINVAL
     assert L.lib.grf_sample(None, 0, 1, None, None, None, 0, None) == L.GRF_EINVAL
     assert L.lib.grf_backward(None, 0, None, 1, None, None, None, None, None, 0, None) == L.GRF_EINVAL
+    assert L.lib.grf_covariance(None, 0, 1, None, None, 0, None) == L.GRF_EINVAL
     assert L.lib.grf_debug_philox(0, None, -1, None, None) == L.GRF_EINVAL
     assert L.lib.grf_debug_philox(0, None, 0, None, None) == L.GRF_OK
     assert L.grf_version().startswith("grf-mi355x")
