@@ -16,7 +16,8 @@ Printed alongside on the same JSON line:
   cpu_baseline  the float64 oracle on a bounded sample of the same workload
   extra         two-FFT algorithm on the same workload, the 256^3 x 16
                 exponential workload, 4096 fields of uneven sizes in one
-                batch, forward+adjoint vs forward at 1024^2 x 64, and the
+                batch, forward+adjoint vs forward at 1024^2 x 64, d = 1
+                sampling, the convergence study of Section 4, and the
                 float32-vs-float64 error of sampled fields
 """
 import argparse
@@ -384,6 +385,30 @@ def main():
                                      "loss": "L = sum w phi^2, w ~ U[0,1] from numpy.random.default_rng(1)"}
         del w, o5, g
         torch.cuda.empty_cache()
+
+        # d = 1: sampling throughput (65536 fields of 4096 points, 1 GiB written) and the
+        # convergence study of Section 4 (10^8 samples per grid, n = 2..12, estimator fused
+        # into the sampler)
+        p1d = grf.Plan((4096,), lengths=(2 * 3.141592653589793,), alg=2, dtype=torch.float32, cov="matern",
+                       sigma=1.0, length_scale=0.07 ** 0.5, nu=3.5)
+        o1d = torch.empty((65536, 4096), dtype=torch.float32, device="cuda")
+        s1d = timed(lambda: p1d.sample(seed=0, batch=65536, out=o1d), args.steps // 5, args.warmup // 5, torch)
+        f64 = grf.Plan((4096,), lengths=(2 * 3.141592653589793,), alg=2, dtype=torch.float64, cov="matern",
+                       sigma=1.0, length_scale=0.07 ** 0.5, nu=3.5).sample(seed=0, batch=1)[0]
+        extra["one_fft_1d_4096_x65536"] = {
+            "points_per_s": round(2 ** 28 / s1d, 1), "ms_per_step": round(s1d * 1e3, 4),
+            "GBps_written": round(2 ** 30 / s1d / 1e9, 1), "model_frac": round(2 ** 30 / s1d / 1e9 / HBM_PEAK_GBS, 4),
+            "max_rel_err_vs_fp64_field0": float((o1d[0].double() - f64).abs().max() / f64.abs().max())}
+        del o1d
+        torch.cuda.empty_cache()
+        from paper_1105_2737_amd import study
+        rows, summary = study.run(samples=10 ** 8, nmin=2, nmax=12, out=lambda line: None)
+        extra["section4_convergence_study"] = {
+            "samples_per_grid": 10 ** 8, "e_n": {r["N"]: r["e_n"] for r in rows},
+            "slopes_per_doubling": summary["slopes_per_doubling"],
+            "monte_carlo_error_scale": summary["monte_carlo_error_scale"],
+            "total_seconds": round(sum(r["seconds"] for r in rows), 3),
+            "points_per_s_at_N4096": rows[-1]["points_per_s"]}
     result["extra"] = extra
 
     if not args.no_cpu:
