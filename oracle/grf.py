@@ -97,13 +97,15 @@ def hermitian_extend(half, dims):
     return full
 
 
-def alg2_from_noise(z, lengths, kind, sigma, ell, nu=0.5, return_parts=False):
-    """One-FFT (Hermitian) algorithm on given normals z (field-shaped)."""
+def alg2_from_noise(z, lengths, kind, sigma, ell, nu=0.5, return_parts=False, h=None):
+    """One-FFT (Hermitian) algorithm on given normals z (field-shaped).  h: the
+    half-spectrum filter, instead of the family (kind, sigma, ell, nu)."""
     z = np.asarray(z, dtype=np.float64)
     dims = z.shape
     P = int(np.prod(dims, dtype=np.int64))
     xi = hermitian_noise(z)
-    h = filter_h(dims, lengths, kind, sigma, ell, nu, half=True)
+    if h is None:
+        h = filter_h(dims, lengths, kind, sigma, ell, nu, half=True)
     A = h * xi
     phi = P * np.fft.irfftn(A, s=dims, axes=tuple(range(len(dims))))
     if return_parts:
@@ -111,13 +113,14 @@ def alg2_from_noise(z, lengths, kind, sigma, ell, nu=0.5, return_parts=False):
     return phi
 
 
-def alg1_from_noise(z, lengths, kind, sigma, ell, nu=0.5, return_parts=False):
-    """Two-FFT algorithm on given white noise z (field-shaped)."""
+def alg1_from_noise(z, lengths, kind, sigma, ell, nu=0.5, return_parts=False, h=None):
+    """Two-FFT algorithm on given white noise z (field-shaped); h as above."""
     z = np.asarray(z, dtype=np.float64)
     dims = z.shape
     P = int(np.prod(dims, dtype=np.int64))
     Z = np.fft.rfftn(z)
-    h = filter_h(dims, lengths, kind, sigma, ell, nu, half=True)
+    if h is None:
+        h = filter_h(dims, lengths, kind, sigma, ell, nu, half=True)
     A = h * Z / np.sqrt(P)
     phi = P * np.fft.irfftn(A, s=dims, axes=tuple(range(len(dims))))
     if return_parts:
@@ -136,22 +139,24 @@ def alg2_full_complex(z, lengths, kind, sigma, ell, nu=0.5):
     return P * np.fft.ifftn(full)
 
 
-def sample(dims, lengths, kind, sigma, ell, nu=0.5, seed=0, batch=1, alg=2):
-    """Fields seed..seed+batch-1 of algorithm ``alg`` (1 or 2), float64."""
+def sample(dims, lengths, kind, sigma, ell, nu=0.5, seed=0, batch=1, alg=2, h=None):
+    """Fields seed..seed+batch-1 of algorithm ``alg`` (1 or 2), float64; h: an
+    explicit half-spectrum filter instead of the family."""
     dims = tuple(int(n) for n in dims)
     tag = _noise.TAG_ALG2 if alg == 2 else _noise.TAG_ALG1
     f = alg2_from_noise if alg == 2 else alg1_from_noise
     out = np.empty((batch,) + dims)
     for b in range(batch):
         z = _noise.field_noise(dims, (int(seed) + b) & 0xFFFFFFFFFFFFFFFF, tag)
-        out[b] = f(z, lengths, kind, sigma, ell, nu)
+        out[b] = f(z, lengths, kind, sigma, ell, nu, h=h)
     return out
 
 
-def discrete_covariance(dims, lengths, kind, sigma, ell, nu=0.5):
+def discrete_covariance(dims, lengths, kind, sigma, ell, nu=0.5, h_full=None):
     """C_N(j) = (1/|D|) sum_k S(p_k) e^{2 pi i k.j/N}: the exact covariance of
-    both algorithms' output between grid points 0 and j (field-shaped)."""
+    both algorithms' output between grid points 0 and j (field-shaped).
+    h_full: an explicit filter on the full spectrum instead of the family."""
     dims = tuple(int(n) for n in dims)
     P = int(np.prod(dims, dtype=np.int64))
-    hf = filter_h(dims, lengths, kind, sigma, ell, nu, half=False)
+    hf = filter_h(dims, lengths, kind, sigma, ell, nu, half=False) if h_full is None else h_full
     return np.real(np.fft.ifftn(hf ** 2)) * P

@@ -12,6 +12,10 @@ Families (sigma = marginal standard deviation, ell = length scale):
                     * (2nu/ell^2 + 4 pi^2 |p|^2)^{-(nu+d/2)}
              (Rasmussen & Williams 2006, eq. 4.14/4.15)
 * Exponential C(r) = sigma^2 exp(-r/ell)   (the Matern case nu = 1/2)
+* The family of Section 4, eq. (5) (written there for d = 2, here for any d):
+             S(p) = (m^{kl} + (sum_i p_i^{2k})^l)^{-n},  k, l, n >= 1, m > 0;
+             anisotropic for k >= 2.  With sigma, S is scaled by sigma^2.
+* A tabulated S: values of S at the grid frequencies of the half-spectrum.
 
 The adjoint needs d log S / d theta for theta = (sigma, ell, nu); those are
 written out below from the formulas above.
@@ -118,3 +122,47 @@ def filter_h(dims, lengths, kind, sigma, ell, nu=0.5, half=True):
     vol = float(np.prod(lengths))
     p2 = freq2_grid(dims, lengths, half=half)
     return np.sqrt(spectral_density(kind, p2, d, sigma, ell, nu) / vol)
+
+
+def freq_components(dims, lengths, half=True):
+    """Per-axis frequencies p_i = kappa(k_i) / l_i on the (half-)spectrum grid,
+    as broadcastable arrays (one per axis)."""
+    dims = tuple(int(n) for n in dims)
+    d = len(dims)
+    comps = []
+    for i, (n, l) in enumerate(zip(dims, lengths)):
+        kap = wrapped_index(n)
+        if half and i == d - 1:
+            kap = kap[: n // 2 + 1].copy()
+            kap[n // 2] = -(n // 2)
+        shape = [1] * d
+        shape[i] = kap.size
+        comps.append(kap.reshape(shape) / float(l))
+    return comps
+
+
+def paper_density(m, k, l, n):
+    """S of Section 4, eq. (5), as a function of the per-axis frequencies."""
+    m, k, l, n = float(m), int(k), int(l), int(n)
+
+    def S(comps):
+        q = 0.0
+        for p in comps:
+            q = q + p ** (2 * k)
+        return (m ** (k * l) + q ** l) ** (-n)
+    return S
+
+
+def density_on_grid(dims, lengths, density, half=True):
+    """S(p_k) on the (half-)spectrum grid for a density given as a function of
+    the per-axis frequencies."""
+    comps = freq_components(dims, lengths, half=half)
+    shape = tuple(int(n) for n in dims[:-1]) + ((int(dims[-1]) // 2 + 1) if half else int(dims[-1]),)
+    return np.broadcast_to(np.asarray(density(comps), dtype=np.float64), shape).copy()
+
+
+def filter_from_density(dims, lengths, S, sigma=1.0):
+    """h_k = sigma sqrt(S_k / |D|) from S on the same grid (half or full)."""
+    vol = float(np.prod(lengths))
+    return float(sigma) * np.sqrt(np.asarray(S, dtype=np.float64) / vol)
+
