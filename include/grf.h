@@ -65,24 +65,39 @@ typedef enum {
 
 enum { GRF_ALG_TWO_FFT = 1, GRF_ALG_ONE_FFT = 2 };
 enum { GRF_F32 = 0, GRF_F64 = 1 };
-enum { GRF_COV_GAUSSIAN = 0, GRF_COV_MATERN = 1, GRF_COV_EXPONENTIAL = 2 };
+enum { GRF_COV_GAUSSIAN = 0, GRF_COV_MATERN = 1, GRF_COV_EXPONENTIAL = 2, GRF_COV_PAPER = 3, GRF_COV_TABULATED = 4 };
 enum { GRF_OP_SAMPLE = 0, GRF_OP_BACKWARD = 1, GRF_OP_COVARIANCE = 2 };
 
 /*
  * Plan description.
- *   ndim      2 or 3 (the grid's dimension d).
+ *   ndim      1, 2 or 3 (the grid's dimension d).
  *   dims      N_1..N_d: each even (Section 2 requires even N_i).  Leading
  *             lengths N_1 (and N_2 for d = 3) from {4, 8, 12, 16, 24, 32, 48,
  *             64, 96, 128, 180, 256, 360, 500, 512, 1000, 1024}; the last
- *             length N_d with N_d/2 from {4, ..., 512} of the same list.
+ *             length N_d with N_d/2 from {2, 4, ..., 512, 1024, 2048} (the
+ *             same list with 2, 1024 and 2048).
  *   lengths   l_1..l_d > 0 (edge lengths of D; the unit torus is all 1).
- *   alg       GRF_ALG_TWO_FFT (d = 2 only in this build) or GRF_ALG_ONE_FFT.
+ *   alg       GRF_ALG_ONE_FFT, or GRF_ALG_TWO_FFT (d = 2 only in this build).
  *   dtype     GRF_F32 (complex64 arithmetic, twiddles from float64) or GRF_F64.
- *   cov_kind  covariance family:
+ *   cov_kind  covariance family (S = the spectral density in cycles,
+ *             C(x) = integral of S(p) exp(-2 pi i p.x) dp, Section 2):
  *               GAUSSIAN    C(r) = sigma^2 exp(-r^2 / (2 ell^2))
  *               MATERN      C(r) = sigma^2 2^{1-nu}/Gamma(nu) (sqrt(2nu) r/ell)^nu K_nu(sqrt(2nu) r/ell)
  *               EXPONENTIAL C(r) = sigma^2 exp(-r/ell)   (nu ignored)
+ *               PAPER       S(p) = sigma^2 (m^{kl} + (sum_i p_i^{2k})^l)^{-n}, the family
+ *                           of Section 4, eq. (5) (k, l, n >= 1, m > 0; any d)
+ *               TABULATED   S given at the grid frequencies of the half-spectrum:
+ *                           `spectrum` is a host float64 array [N_1]..[N_{d-1}][N_d/2 + 1]
+ *                           (row-major; frequency index k_i stands for p_i = kappa(k_i)/l_i
+ *                           with kappa(k) = k for k < N_i/2 and k - N_i otherwise), S >= 0,
+ *                           equal on mirrored entries of the planes k_d = 0 and N_d/2
+ *                           (S(p) = S(-p)); copied at plan creation; scaled by sigma^2.
+ *             PAPER and TABULATED have no length scale or nu: their filter is a
+ *             table built at plan creation, per-field theta is not accepted
+ *             (GRF_EUNSUPPORTED), and the adjoint's d/d(ell, nu) are 0.
  *   sigma, length_scale, nu   default parameters (> 0).
+ *   m, k, l, n   parameters of GRF_COV_PAPER (ignored otherwise).
+ *   spectrum  GRF_COV_TABULATED only (NULL otherwise).
  */
 typedef struct {
   int32_t ndim;
@@ -94,6 +109,10 @@ typedef struct {
   double sigma;
   double length_scale;
   double nu;
+  double m;
+  int32_t k, l, n;
+  int32_t reserved;
+  const double* spectrum;
 } grf_plan_desc;
 
 /* Create a plan: validates the description, builds float64 twiddle tables

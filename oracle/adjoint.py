@@ -68,7 +68,7 @@ def grad_theta_alg1(z, g, lengths, kind, sigma, ell, nu=0.5):
     return np.array([np.sum(0.5 * h * dl * core) for dl in dlog])
 
 
-def grad_noise_alg2(g, lengths, kind, sigma, ell, nu=0.5):
+def grad_noise_alg2(g, lengths, kind, sigma, ell, nu=0.5, h=None):
     """dL/dz (field-shaped) for the one-FFT algorithm."""
     g = np.asarray(g, dtype=np.float64)
     dims = g.shape
@@ -76,7 +76,9 @@ def grad_noise_alg2(g, lengths, kind, sigma, ell, nu=0.5):
     m = nd // 2
     rows = int(np.prod(dims[:-1], dtype=np.int64)) if len(dims) > 1 else 1
     G = np.fft.rfftn(g).reshape(rows, m + 1)
-    h = filter_h(dims, lengths, kind, sigma, ell, nu, half=True).reshape(rows, m + 1)
+    if h is None:
+        h = filter_h(dims, lengths, kind, sigma, ell, nu, half=True)
+    h = np.asarray(h).reshape(rows, m + 1)
     gz = np.zeros((rows, nd))
     s2 = np.sqrt(2.0)
     if m > 1:

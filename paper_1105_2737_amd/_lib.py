@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(HERE, "libgrf.so")
 GRF_OK, GRF_EINVAL, GRF_ENOMEM, GRF_EDEVICE, GRF_EUNSUPPORTED = 0, -1, -2, -3, -4
 GRF_ALG_TWO_FFT, GRF_ALG_ONE_FFT = 1, 2
 GRF_F32, GRF_F64 = 0, 1
-GRF_COV_GAUSSIAN, GRF_COV_MATERN, GRF_COV_EXPONENTIAL = 0, 1, 2
+GRF_COV_GAUSSIAN, GRF_COV_MATERN, GRF_COV_EXPONENTIAL, GRF_COV_PAPER, GRF_COV_TABULATED = 0, 1, 2, 3, 4
 GRF_OP_SAMPLE, GRF_OP_BACKWARD, GRF_OP_COVARIANCE = 0, 1, 2
 GRF_PASS_FUSED, GRF_PASS_COL_GEN_INV, GRF_PASS_COL_LOAD_INV, GRF_PASS_COL_LOAD_FWD = -1, 0, 1, 2
 GRF_PASS_COL_FILTER, GRF_PASS_COL_GRAD, GRF_PASS_ROW_C2R, GRF_PASS_ROW_R2C_GEN, GRF_PASS_ROW_R2C_LOAD = 3, 4, 5, 6, 7
@@ -28,7 +28,9 @@ EXPORTS = ["grf_plan_create", "grf_plan_destroy", "grf_workspace_size", "grf_sam
 class grf_plan_desc(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("alg", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("cov_kind", ctypes.c_int32), ("dims", ctypes.c_int64 * 3), ("lengths", ctypes.c_double * 3),
-                ("sigma", ctypes.c_double), ("length_scale", ctypes.c_double), ("nu", ctypes.c_double)]
+                ("sigma", ctypes.c_double), ("length_scale", ctypes.c_double), ("nu", ctypes.c_double),
+                ("m", ctypes.c_double), ("k", ctypes.c_int32), ("l", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("spectrum", ctypes.c_void_p)]
 
 
 class grf_field_desc(ctypes.Structure):

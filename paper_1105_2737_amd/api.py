@@ -8,7 +8,8 @@ import torch
 
 from . import _lib as L
 
-COV_KINDS = {"gaussian": L.GRF_COV_GAUSSIAN, "matern": L.GRF_COV_MATERN, "exponential": L.GRF_COV_EXPONENTIAL}
+COV_KINDS = {"gaussian": L.GRF_COV_GAUSSIAN, "matern": L.GRF_COV_MATERN, "exponential": L.GRF_COV_EXPONENTIAL,
+             "paper": L.GRF_COV_PAPER, "tabulated": L.GRF_COV_TABULATED}
 ALGS = {1: L.GRF_ALG_TWO_FFT, 2: L.GRF_ALG_ONE_FFT, "two_fft": L.GRF_ALG_TWO_FFT, "one_fft": L.GRF_ALG_ONE_FFT}
 
 
@@ -26,11 +27,14 @@ class Plan:
     dims: (N_1, ..., N_d), d in {1, 2, 3}, all even; lengths: edge lengths
     (default the unit torus); alg: 2 = one-FFT (Hermitian), 1 = two-FFT (d = 2);
     dtype: torch.float32 or torch.float64; cov: 'gaussian' | 'matern' |
-    'exponential' with default parameters sigma, length_scale, nu.
+    'exponential' with default parameters sigma, length_scale, nu; 'paper'
+    (the family of Section 4, eq. (5): S = sigma^2 (m^{kl} + (sum p_i^{2k})^l)^{-n},
+    parameters m, k, l, n); 'tabulated' (S at the half-spectrum frequencies,
+    `spectrum` of shape dims[:-1] + (N_d/2 + 1,), float64).
     """
 
     def __init__(self, dims, lengths=None, alg=2, dtype=torch.float32, cov="matern", sigma=1.0,
-                 length_scale=0.1, nu=1.5, device=None):
+                 length_scale=0.1, nu=1.5, device=None, m=1.0, k=1, l=1, n=1, spectrum=None):
         dims = tuple(int(n) for n in dims)
         lengths = tuple(float(v) for v in (lengths or (1.0,) * len(dims)))
         if len(lengths) != len(dims):
@@ -48,12 +52,21 @@ class Plan:
         if dtype not in (torch.float32, torch.float64):
             raise ValueError("dtype must be float32 or float64")
         d.cov_kind = COV_KINDS[cov]
-        for i, (n, l) in enumerate(zip(dims, lengths)):
-            d.dims[i] = n
-            d.lengths[i] = l
+        for i, (ni, li) in enumerate(zip(dims, lengths)):
+            d.dims[i] = ni
+            d.lengths[i] = li
         d.sigma, d.length_scale, d.nu = self.params
+        d.m, d.k, d.l, d.n = float(m), int(k), int(l), int(n)
+        spec = None
+        if cov == "tabulated":
+            import numpy as np
+            spec = np.ascontiguousarray(np.asarray(spectrum, dtype=np.float64))
+            want = dims[:-1] + (dims[-1] // 2 + 1,)
+            if spec.shape != want:
+                raise ValueError(f"spectrum must have shape {want}, got {spec.shape}")
+            d.spectrum = spec.ctypes.data
         with torch.cuda.device(self.device):
-            self.handle = L.grf_plan_create(d)
+            self.handle = L.grf_plan_create(d)   # the library copies the spectrum
 
     def __del__(self):
         h = getattr(self, "handle", None)

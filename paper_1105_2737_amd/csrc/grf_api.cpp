@@ -45,7 +45,8 @@ struct grf_plan_s {
   void* tw_col2 = nullptr;  // W_{N_2} (d = 3)
   void* tw_row = nullptr;   // W_{N_d}
   FieldRec* rec_dev = nullptr;
-  void* htab = nullptr;     // filter table of the default parameters (d = 2)
+  void* htab = nullptr;     // filter table h[row][m] (row stride M + 2) of the default parameters
+  bool table_only = false;  // PAPER / TABULATED: h exists only as the table
   int device = 0;
 };
 
@@ -151,6 +152,7 @@ grf_status field_records(const grf_plan_s* p, const double* theta, long long bat
     *stride = 0;
     return GRF_OK;
   }
+  if (p->table_only) return fail(GRF_EUNSUPPORTED, "per-field parameters need a parametric covariance family");
   if (workspace == nullptr || ws_bytes < (size_t)batch * sizeof(FieldRec))
     return fail(GRF_EINVAL, "workspace too small for per-field parameters");
   FieldRec* out = (FieldRec*)workspace;
@@ -323,7 +325,9 @@ void chunk_passes(const grf_plan_s* p, uint64_t seed, const void* zsrc, long lon
     c.stride_fixed = p->M;
     c.nfixed = 1;
     c.scale = 1.0 / std::sqrt((double)p->P);
-    c.htab = nullptr;   // this pass has VALU to spare: h on the fly beats a table load
+    // this pass has VALU to spare: h on the fly beats a table load, except for the
+    // families whose filter exists only as a table (built with the 1/sqrt(P) factor)
+    c.htab = p->table_only ? p->htab : nullptr;
     push(grf::PASS_COL_FILTER, p->n1, c);
   }
   Args b = a;
@@ -364,6 +368,64 @@ std::vector<PassLaunch> sample_passes(const grf_plan_s* p, uint64_t seed, const 
   }
   for (long long k = 0; k < nch; ++k) chunk_passes(p, seed, zsrc, k * C, std::min(C, batch - k * C), recs, rstride, out, v);
   return v;
+}
+
+// Filter table of a family given by its density (PAPER, TABULATED), built on
+// the host in float64: h[row][m] = scale sigma sqrt(S(p) / |D|) over the
+// half-spectrum (rows = N_1 ... N_{d-1}, m = 0 .. N_d/2; row stride M + 2, the
+// extra slot 0), then rounded once to the working precision.
+grf_status build_density_table(grf_plan_s* p, const grf_plan_desc& d, double scale) {
+  const int rows = p->n1 * p->no;
+  const int M = p->M, HS = M + 2;
+  std::vector<double> h((size_t)rows * HS, 0.0);
+  auto kappa = [](int k, int n) { return 2 * k < n ? k : k - n; };
+  const int last = p->d - 1;
+  for (int row = 0; row < rows; ++row) {
+    const int kk1 = row / p->no, o = row % p->no;
+    double pc[3] = {0, 0, 0};
+    int np = 0;
+    if (p->d >= 2) pc[np++] = kappa(kk1, p->n1) / d.lengths[0];
+    if (p->d == 3) pc[np++] = kappa(o, p->no) / d.lengths[1];
+    for (int m = 0; m <= M; ++m) {
+      const double pl = (m == M ? -M : m) / d.lengths[last];
+      double S;
+      if (d.cov_kind == GRF_COV_PAPER) {
+        double q = std::pow(pl * pl, d.k);
+        for (int i = 0; i < np; ++i) q += std::pow(pc[i] * pc[i], d.k);
+        S = std::pow(std::pow(d.m, (double)d.k * d.l) + std::pow(q, d.l), -(double)d.n);
+      } else {
+        S = d.spectrum[(size_t)row * (M + 1) + m];
+      }
+      h[(size_t)row * HS + m] = scale * d.sigma * std::sqrt(S / p->vol);
+    }
+  }
+  const size_t n = h.size();
+  const size_t bytes = n * p->esz;
+  hipError_t e = hipMalloc(&p->htab, bytes);
+  if (e != hipSuccess) return fail(GRF_ENOMEM, "hipMalloc of the filter table failed");
+  if (p->dtype == GRF_F32) {
+    std::vector<float> f(h.begin(), h.end());
+    e = hipMemcpy(p->htab, f.data(), bytes, hipMemcpyHostToDevice);
+  } else {
+    e = hipMemcpy(p->htab, h.data(), bytes, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return hip_fail(e, "filter table upload");
+  return GRF_OK;
+}
+
+// Checks of a tabulated density: finite, >= 0, and S(p) = S(-p) on the two
+// planes k_d = 0 and N_d/2, where both entries are stored.
+bool tabulated_ok(const grf_plan_desc& d, int n1, int no, int M) {
+  const int rows = n1 * no;
+  for (long long i = 0; i < (long long)rows * (M + 1); ++i)
+    if (!(d.spectrum[i] >= 0) || !std::isfinite(d.spectrum[i])) return false;
+  for (int row = 0; row < rows; ++row) {
+    const int kk1 = row / no, o = row % no;
+    const int mr = ((n1 - kk1) % n1) * no + (no - o) % no;
+    for (int m : {0, M})
+      if (d.spectrum[(size_t)row * (M + 1) + m] != d.spectrum[(size_t)mr * (M + 1) + m]) return false;
+  }
+  return true;
 }
 
 // Covariance estimator: workgroups of the one-dimensional epilogue (a fixed
@@ -478,14 +540,20 @@ grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out) {
   if (d.ndim < 1 || d.ndim > 3) return fail(GRF_EINVAL, "ndim must be 1, 2 or 3");
   if (d.alg != GRF_ALG_TWO_FFT && d.alg != GRF_ALG_ONE_FFT) return fail(GRF_EINVAL, "unknown algorithm");
   if (d.dtype != GRF_F32 && d.dtype != GRF_F64) return fail(GRF_EINVAL, "unknown dtype");
-  if (d.cov_kind < GRF_COV_GAUSSIAN || d.cov_kind > GRF_COV_EXPONENTIAL)
+  if (d.cov_kind < GRF_COV_GAUSSIAN || d.cov_kind > GRF_COV_TABULATED)
     return fail(GRF_EINVAL, "unknown covariance kind");
+  const bool table_only = d.cov_kind == GRF_COV_PAPER || d.cov_kind == GRF_COV_TABULATED;
+  if (d.cov_kind == GRF_COV_PAPER &&
+      (!(d.m > 0) || !std::isfinite(d.m) || d.k < 1 || d.l < 1 || d.n < 1 || d.k > 64 || d.l > 64 || d.n > 64))
+    return fail(GRF_EINVAL, "the family of Section 4 needs m > 0 and 1 <= k, l, n <= 64");
+  if (d.cov_kind == GRF_COV_TABULATED && d.spectrum == nullptr) return fail(GRF_EINVAL, "null spectrum");
   for (int i = 0; i < d.ndim; ++i) {
     if (d.dims[i] <= 0 || (d.dims[i] % 2) != 0) return fail(GRF_EINVAL, "grid sizes must be positive and even");
     if (!smooth235(d.dims[i])) return fail(GRF_EINVAL, "grid sizes must factor into 2, 3 and 5");
     if (!(d.lengths[i] > 0) || !std::isfinite(d.lengths[i])) return fail(GRF_EINVAL, "edge lengths must be > 0");
   }
-  if (!(d.sigma > 0) || !(d.length_scale > 0) || !std::isfinite(d.sigma) || !std::isfinite(d.length_scale))
+  if (!(d.sigma > 0) || !std::isfinite(d.sigma) ||
+      (!table_only && (!(d.length_scale > 0) || !std::isfinite(d.length_scale))))
     return fail(GRF_EINVAL, "sigma and length_scale must be > 0");
   if (d.cov_kind == GRF_COV_MATERN && (!(d.nu > 0) || !std::isfinite(d.nu)))
     return fail(GRF_EINVAL, "nu must be > 0");
@@ -519,7 +587,14 @@ grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out) {
     return hip_fail(e, "hipGetDevice");
   }
   FieldRec rec;
-  if (grf::make_field_rec(d.cov_kind, d.ndim, p->vol, d.sigma, d.length_scale, d.nu, &rec) != 0) {
+  if (table_only) {
+    if (d.cov_kind == GRF_COV_TABULATED && !tabulated_ok(d, p->n1, p->no, p->M)) {
+      delete p;
+      return fail(GRF_EINVAL, "tabulated density must be finite, >= 0 and symmetric on the planes k_d = 0, N_d/2");
+    }
+    grf::make_table_rec(d.sigma, &rec);
+    p->table_only = true;
+  } else if (grf::make_field_rec(d.cov_kind, d.ndim, p->vol, d.sigma, d.length_scale, d.nu, &rec) != 0) {
     delete p;
     return fail(GRF_EINVAL, "invalid covariance parameters");
   }
@@ -534,7 +609,9 @@ grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out) {
       if (e != hipSuccess) st = hip_fail(e, "record upload");
     }
   }
-  if (st == GRF_OK && d.ndim == 2 && d.alg == GRF_ALG_ONE_FFT) {
+  if (st == GRF_OK && table_only) {
+    st = build_density_table(p, d, d.alg == GRF_ALG_TWO_FFT ? 1.0 / std::sqrt((double)p->P) : 1.0);
+  } else if (st == GRF_OK && d.ndim == 2 && d.alg == GRF_ALG_ONE_FFT) {
     // filter table: h of every (row, m) for the default parameters, computed by
     // the kernels' own float expressions (read by the generation and adjoint passes)
     Args t = base_args(p, 1);
@@ -587,6 +664,7 @@ grf_status grf_covariance(grf_plan p, uint64_t seed, int64_t nsamples, double* c
     a.tag = 1;
     a.tw2 = p->tw_row;
     a.rows = nsamples;
+    a.htab = p->table_only ? p->htab : nullptr;
     hipError_t e = grf::launch_gen1d(p->dtype, p->M, a, c.groups, partial, s);
     if (e == hipSuccess) e = grf::launch_cov_reduce(partial, (int)c.groups, p->P, scale, cov, s);
     if (e != hipSuccess) return hip_fail(e, "covariance launch");

@@ -47,6 +47,22 @@ __host__ __device__ inline double digamma_pos(double x) {
   return acc + log(x) - 0.5 / x - s;
 }
 
+// Record of a family whose filter exists only as a table (the family of
+// Section 4, eq. (5), or a tabulated density): sigma is the one parameter
+// (dlogS/dsigma = 2/sigma); the filter constant is NaN, so that a pass that
+// evaluated h from the record instead of the table would produce NaN.
+__host__ __device__ inline void make_table_rec(double sigma, FieldRec* r) {
+  r->kind = COV_GAUSSIAN;
+  r->has_nu = 0;
+  r->sigma = sigma;
+  r->ell = 0.0;
+  r->nu = 0.0;
+  r->c0 = __builtin_nan("");
+  r->a = r->b = r->e = 0.0;
+  r->gs = 2.0 / sigma;
+  r->gl0 = r->gl1 = r->gn0 = r->gn1 = 0.0;
+}
+
 // Fills a record from (kind, d, |D|, sigma, ell, nu).  Returns 0 on success,
 // -1 on invalid parameters.
 __host__ __device__ inline int make_field_rec(int kind, int d, double vol, double sigma, double ell,

@@ -55,16 +55,19 @@ struct Gen1D {
         const unsigned long long key = a.seed + (unsigned long long)b;
         normals4<T, false>((uint32_t)q, 0u, (uint32_t)a.tag, (uint32_t)key, (uint32_t)(key >> 32), z);
       }
+      // h from the plan's table (families given by their density) or on the fly
+      const T* ht = (const T*)a.htab;
+      auto hk = [&](int k) -> T { return ht ? ht[k] : filt_h(f, (T)(k * k) * il2); };
       const int k1 = 2 * q + 1;
-      const T h1 = filt_h(f, (T)(k1 * k1) * il2);
+      const T h1 = hk(k1);
       E* row = sm + rr * RL::STRIDE;
       row[RL::idx(k1)].v[0] = mk<T>(h1 * s * z[2], h1 * s * z[3]);
       const int k0 = 2 * q;
       if (k0 > 0) {
-        const T h0 = filt_h(f, (T)(k0 * k0) * il2);
+        const T h0 = hk(k0);
         row[RL::idx(k0)].v[0] = mk<T>(h0 * s * z[0], h0 * s * z[1]);
       } else {
-        const T hz = filt_h(f, (T)0 * il2), hn = filt_h(f, (T)(M * M) * il2);
+        const T hz = hk(0), hn = hk(M);
         row[0].v[0] = mk<T>(hz * z[0], hn * z[1]);   // A_0 + i A_M
       }
     }

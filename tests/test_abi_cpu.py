@@ -72,6 +72,11 @@ def _desc(**kw):
     (dict(ndim=1, dims=(14,)), -1),
     (dict(ndim=1, dims=(8192,)), -4),
     (dict(ndim=1, alg=1, dims=(64,)), -4),  # two-FFT algorithm: d = 2 only
+    (dict(cov_kind=3, m=0.0, k=1, l=1, n=1), -1),   # the family of Section 4 needs m > 0
+    (dict(cov_kind=3, m=1.0, k=0, l=1, n=1), -1),   # and k, l, n >= 1
+    (dict(cov_kind=3, m=1.0, k=1, l=1, n=65), -1),
+    (dict(cov_kind=4), -1),                          # tabulated density without a table
+    (dict(cov_kind=5), -1),
 ])
 def test_invalid_descriptors_are_rejected_on_the_host(kw, status):
     from paper_1105_2737_amd import _lib as L
