@@ -113,7 +113,9 @@ using grf::host::smooth235;
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-// Workspace layout: [records][partials][spectrum]
+long long chunk_fields(const grf_plan_s* p, long long batch);
+
+// Workspace layout: [records][partials][spectrum of one chunk of fields]
 struct WsLayout {
   size_t recs, partial, spec, total;
 };
@@ -128,7 +130,7 @@ WsLayout ws_layout(const grf_plan_s* p, long long batch, int op) {
     const long long ntile = (p->M + 2 * g.per_wg - 1) / (2 * g.per_wg);
     off += align256((size_t)batch * ntile * 3 * sizeof(double));
     w.spec = off;
-    off += align256((size_t)batch * p->P * p->esz);
+    off += align256((size_t)chunk_fields(p, batch) * p->P * p->esz);
   } else {
     w.spec = off;
   }
@@ -757,33 +759,39 @@ grf_status grf_backward(grf_plan p, uint64_t seed, const void* noise, int64_t ba
   int rstride;
   st = field_records(p, theta, batch, ws + w.recs, w.partial, s, &recs, &rstride);
   if (st != GRF_OK) return st;
-  Args a = base_args(p, batch);
-  a.recs = recs;
-  a.rec_stride = rstride;
-  a.seed = seed;
-  a.tag = 1;
-  a.htab = rstride == 0 ? p->htab : nullptr;   // one-FFT: the sampler's h is unscaled
-  // G = F[g]: last axis real-to-complex, then axis 1 forward inside the reduction pass
-  Args r = a;
-  r.data = ws + w.spec;
-  r.src = grad_out;
-  r.tw2 = p->tw_row;
-  r.rows = batch * (long long)p->n1;
-  st = run_pass(p, grf::PASS_ROW_R2C_LOAD, p->M, r, 0, batch, s);
-  if (st != GRF_OK) return st;
-  Args c = a;
-  c.data = ws + w.spec;
-  c.src = noise;
-  c.aux = grad_noise;
-  c.partial = (double*)(ws + w.partial);
-  c.tw = p->tw_col1;
-  c.stride_ax = p->M;
-  c.stride_fixed = p->M;
-  c.nfixed = 1;
-  st = run_pass(p, grf::PASS_COL_GRAD, p->n1, c, 0, batch, s);
-  if (st != GRF_OK) return st;
+  // G = F[g]: last axis real-to-complex, then axis 1 forward inside the
+  // reduction pass; chunk by chunk (cache-sized, as the sampler), so that the
+  // reduction pass reads the chunk's spectrum from the last-level cache
   const grf::Geom g = grf::pass_geom(grf::PASS_COL_GRAD, p->dtype, p->n1);
   const int ntile = (p->M + 2 * g.per_wg - 1) / (2 * g.per_wg);
+  const long long C = chunk_fields(p, batch);
+  const size_t fbytes = (size_t)p->P * p->esz;
+  for (long long c0 = 0; c0 < batch; c0 += C) {
+    const long long nb = std::min(C, batch - c0);
+    Args r = base_args(p, nb);
+    r.data = ws + w.spec;
+    r.src = (const char*)grad_out + c0 * fbytes;
+    r.tw2 = p->tw_row;
+    r.rows = nb * (long long)p->n1;
+    st = run_pass(p, grf::PASS_ROW_R2C_LOAD, p->M, r, 0, nb, s);
+    if (st != GRF_OK) return st;
+    Args c = base_args(p, nb);
+    c.recs = rstride ? recs + c0 : recs;
+    c.rec_stride = rstride;
+    c.seed = seed + (uint64_t)c0;
+    c.tag = 1;
+    c.htab = rstride == 0 ? p->htab : nullptr;   // one-FFT: the sampler's h is unscaled
+    c.data = ws + w.spec;
+    c.src = noise ? (const char*)noise + c0 * fbytes : nullptr;
+    c.aux = grad_noise ? (char*)grad_noise + c0 * fbytes : nullptr;
+    c.partial = (double*)(ws + w.partial) + c0 * ntile * 3;
+    c.tw = p->tw_col1;
+    c.stride_ax = p->M;
+    c.stride_fixed = p->M;
+    c.nfixed = 1;
+    st = run_pass(p, grf::PASS_COL_GRAD, p->n1, c, 0, nb, s);
+    if (st != GRF_OK) return st;
+  }
   hipError_t e = grf::launch_reduce_partials((const double*)(ws + w.partial), (int)batch, ntile, grad_theta, s);
   if (e != hipSuccess) return hip_fail(e, "reduction");
   return GRF_OK;

@@ -553,6 +553,10 @@ k_colg(Args a) {
   const bool al = (a.M & 1) == 0;
   V* base = (V*)a.data + (long long)b * a.field_stride + m0;
   V x[2][EN::REG];
+  // Straight-line route for the common case (generated noise, filter table,
+  // a column pair away from the packed plane slot): the filter-table loads of
+  // all rows are issued together and the R0 Philox blocks are independent.
+  const bool straight = a.src == nullptr && a.htab != nullptr && m0 > 0;
   if (act) {
 #pragma unroll
     for (int m = 0; m < R0; ++m)
@@ -571,28 +575,98 @@ k_colg(Args a) {
     const T* zsrc = (const T*)a.src;
     T* gz = (T*)a.aux;
     const double il2d = a.il2[2];
-    const double s2 = 1.4142135623730950488;
-    // d log S / d theta at squared frequency p2 (float64)
-    auto dlog = [&](double p2, double& dl, double& dn) {
-      if (rec.kind == COV_GAUSSIAN) {
-        dl = rec.gl0 + rec.gl1 * p2;
-        dn = 0.0;
+    const T s2 = (T)1.4142135623730950488;
+    // Entry k adds c = w (h/2) Re(xi conj G) times d log S / d theta at its
+    // squared frequency p2 (dlogS/dsigma = gs is applied once per workgroup).
+    // float32 plans form c and d log S in float32 (hardware log2 and
+    // reciprocal) and sum in float64; float64 plans do everything in float64.
+    // the record's constants in registers (the stores of dL/dz below could
+    // alias it, which would otherwise force a reload per entry)
+    const bool gauss = rec.kind == COV_GAUSSIAN, has_nu = rec.has_nu != 0;
+    const double ra = rec.a, rb = rec.b, gl0 = rec.gl0, gl1 = rec.gl1, gn0 = rec.gn0, gn1 = rec.gn1;
+    const float raf = (float)ra, rbf = (float)rb, gl0f = (float)gl0, gl1f = (float)gl1, gn0f = (float)gn0,
+                gn1f = (float)gn1;
+    auto add = [&](double w, double h, double p2, V xi, V G) {
+      if constexpr (sizeof(T) == 4) {
+        const float pf = (float)p2;
+        float dl, dn = 0.0f;
+        if (gauss) {
+          dl = fmaf(gl1f, pf, gl0f);
+        } else {
+          const float u = fmaf(rbf, pf, raf);
+          const float iu = __builtin_amdgcn_rcpf(u);
+          dl = fmaf(gl1f, iu, gl0f);
+          if (has_nu) dn = gn0f - __builtin_amdgcn_logf(u) * 0.693147180559945309f - gn1f * iu;
+        }
+        const float c = (float)w * 0.5f * (float)h * fmaf((float)xi.x, (float)G.x, (float)xi.y * (float)G.y);
+        acc0 += (double)c;
+        acc1 += (double)(c * dl);
+        acc2 += (double)(c * dn);
       } else {
-        const double u = rec.a + rec.b * p2;
-        const double iu = 1.0 / u;
-        dl = rec.gl0 + rec.gl1 * iu;
-        dn = rec.has_nu ? (rec.gn0 - log(u) - rec.gn1 * iu) : 0.0;
+        double dl, dn = 0.0;
+        if (gauss) {
+          dl = gl0 + gl1 * p2;
+        } else {
+          const double u = ra + rb * p2;
+          const double iu = 1.0 / u;
+          dl = gl0 + gl1 * iu;
+          if (has_nu) dn = gn0 - log(u) - gn1 * iu;
+        }
+        const double c = w * 0.5 * h * ((double)xi.x * (double)G.x + (double)xi.y * (double)G.y);
+        acc0 += c;
+        acc1 += c * dl;
+        acc2 += c * dn;
       }
     };
-    auto add = [&](double w, double h, double p2, V xi, V G) {
-      double dl, dn;
-      dlog(p2, dl, dn);
-      const double c = w * 0.5 * h * ((double)xi.x * (double)G.x + (double)xi.y * (double)G.y);
-      acc0 += c * rec.gs;
-      acc1 += c * dl;
-      acc2 += c * dn;
-    };
     const T s = (T)0.70710678118654752440;
+    if (straight) {
+      struct alignas(2 * sizeof(T)) P2 { T x, y; };
+#pragma unroll 2
+      for (int m = 0; m < R0; ++m) {
+        const P2 hq = *reinterpret_cast<const P2*>((const T*)a.htab + (long long)(t + m * NT) * (a.M + 2) + m0);
+        T zq[4];
+        normals4<T, true>((uint32_t)(m0 >> 1), (uint32_t)(t + m * NT), (uint32_t)a.tag, k0, k1, zq);
+        const int kk1 = t + m * NT;
+        const int q1 = wrapk(kk1, L);
+        const double p2b = (double)(q1 * q1) * a.il2[0];
+        const E e = sm[kk1 * RS + cp];
+        const double p21 = p2b + (double)((m0 + 1) * (m0 + 1)) * il2d;
+        const double p20 = p2b + (double)(m0 * m0) * il2d;
+        if constexpr (sizeof(T) == 4) {
+          // both entries of the row in float32, one float64 add per row
+          const float pf1 = (float)p21, pf0 = (float)p20;
+          float dl1, dl0, dn1 = 0.0f, dn0 = 0.0f;
+          if (gauss) {
+            dl1 = fmaf(gl1f, pf1, gl0f);
+            dl0 = fmaf(gl1f, pf0, gl0f);
+          } else {
+            const float u1 = fmaf(rbf, pf1, raf), u0 = fmaf(rbf, pf0, raf);
+            const float iu1 = __builtin_amdgcn_rcpf(u1), iu0 = __builtin_amdgcn_rcpf(u0);
+            dl1 = fmaf(gl1f, iu1, gl0f);
+            dl0 = fmaf(gl1f, iu0, gl0f);
+            if (has_nu) {
+              dn1 = gn0f - __builtin_amdgcn_logf(u1) * 0.693147180559945309f - gn1f * iu1;
+              dn0 = gn0f - __builtin_amdgcn_logf(u0) * 0.693147180559945309f - gn1f * iu0;
+            }
+          }
+          const float c1 = hq.y * s * fmaf(zq[2], e.v[1].x, zq[3] * e.v[1].y);
+          const float c0 = hq.x * s * fmaf(zq[0], e.v[0].x, zq[1] * e.v[0].y);
+          acc0 += (double)(c1 + c0);
+          acc1 += (double)fmaf(c1, dl1, c0 * dl0);
+          acc2 += (double)fmaf(c1, dn1, c0 * dn0);
+        } else {
+          add(2.0, (double)hq.y, p21, mk<T>(s * zq[2], s * zq[3]), e.v[1]);
+          add(2.0, (double)hq.x, p20, mk<T>(s * zq[0], s * zq[1]), e.v[0]);
+        }
+        if (gz) {
+          T* gzr = gz + (long long)b * a.field_stride * 2 + (long long)kk1 * a.nd + 2 * m0;
+          gzr[0] = s2 * hq.x * e.v[0].x;
+          gzr[1] = s2 * hq.x * e.v[0].y;
+          gzr[2] = s2 * hq.y * e.v[1].x;
+          gzr[3] = s2 * hq.y * e.v[1].y;
+        }
+      }
+    } else
 #pragma unroll
     for (int m = 0; m < R0; ++m) {
       const int kk1 = t + m * NT;
@@ -609,8 +683,8 @@ k_colg(Args a) {
         const T h = hrow ? hrow[m0 + 1] : filt_h(f, (T)p2);
         add(2.0, (double)h, p2, mk<T>(s * z[2], s * z[3]), e.v[1]);
         if (gzr) {
-          gzr[2] = (T)(s2 * (double)h * (double)e.v[1].x);
-          gzr[3] = (T)(s2 * (double)h * (double)e.v[1].y);
+          gzr[2] = s2 * h * e.v[1].x;
+          gzr[3] = s2 * h * e.v[1].y;
         }
       }
       if (m0 > 0) {
@@ -618,8 +692,8 @@ k_colg(Args a) {
         const T h = hrow ? hrow[m0] : filt_h(f, (T)p2);
         add(2.0, (double)h, p2, mk<T>(s * z[0], s * z[1]), e.v[0]);
         if (gzr) {
-          gzr[0] = (T)(s2 * (double)h * (double)e.v[0].x);
-          gzr[1] = (T)(s2 * (double)h * (double)e.v[0].y);
+          gzr[0] = s2 * h * e.v[0].x;
+          gzr[1] = s2 * h * e.v[0].y;
         }
       } else {
         const V w = e.v[0];
@@ -635,8 +709,8 @@ k_colg(Args a) {
           x0 = mk<T>(z[0], (T)0);
           xn = mk<T>(z[1], (T)0);
           if (gzr) {
-            gzr[0] = (T)((double)hz * (double)g0.x);
-            gzr[1] = (T)((double)hn * (double)gn.x);
+            gzr[0] = hz * g0.x;
+            gzr[1] = hn * gn.x;
           }
         } else {
           T zz[4];
@@ -645,15 +719,15 @@ k_colg(Args a) {
             x0 = mk<T>(s * z[0], s * z[1]);
             xn = mk<T>(s * zz[0], s * zz[1]);
             if (gzr) {
-              gzr[0] = (T)(s2 * (double)hz * (double)g0.x);
-              gzr[1] = (T)(s2 * (double)hz * (double)g0.y);
+              gzr[0] = s2 * hz * g0.x;
+              gzr[1] = s2 * hz * g0.y;
             }
           } else {
             x0 = mk<T>(s * zz[0], -s * zz[1]);
             xn = mk<T>(s * z[0], -s * z[1]);
             if (gzr) {   // slots of a mirrored row carry the Nyquist plane of its partner
-              gzr[0] = (T)(s2 * (double)hn * (double)gn.x);
-              gzr[1] = (T)(-s2 * (double)hn * (double)gn.y);
+              gzr[0] = s2 * hn * gn.x;
+              gzr[1] = -s2 * hn * gn.y;
             }
           }
         }
@@ -662,6 +736,7 @@ k_colg(Args a) {
       }
     }
   }
+  acc0 *= act ? a.recs[b * a.rec_stride].gs : 0.0;
   // workgroup reduction in a fixed order (deterministic)
   for (int off = 32; off > 0; off >>= 1) {
     acc0 += __shfl_xor(acc0, off);
