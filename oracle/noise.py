@@ -11,7 +11,9 @@ contract:
   s the index along the last axis;
 * z[row, s] is lane (s mod 4) of the Philox-4x32-10 block with counter
   (s div 4, row, tag, 0); tag 0 is the white noise of the two-FFT algorithm,
-  tag 1 the Fourier-space noise of the one-FFT (Hermitian) algorithm;
+  tag 1 the Fourier-space noise of the one-FFT (Hermitian) algorithm, tag 2
+  the slot coefficients of the cosine / sine transforms (reflecting
+  boundaries);
 * the 32-bit outputs x become uniforms u = (x + 1/2) 2^-32 in (0, 1);
 * Box and Muller (1958): lanes (0,1) and (2,3) of a block are pairs
   (u_a, u_b) -> sqrt(-2 ln u_a) (cos 2 pi u_b, sin 2 pi u_b).
@@ -22,6 +24,7 @@ from .philox import philox4x32, key_of
 
 TAG_ALG1 = 0
 TAG_ALG2 = 1
+TAG_REFLECT = 2
 
 
 def uniforms(x):
