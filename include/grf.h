@@ -67,6 +67,7 @@ enum { GRF_ALG_TWO_FFT = 1, GRF_ALG_ONE_FFT = 2 };
 enum { GRF_F32 = 0, GRF_F64 = 1 };
 enum { GRF_COV_GAUSSIAN = 0, GRF_COV_MATERN = 1, GRF_COV_EXPONENTIAL = 2, GRF_COV_PAPER = 3, GRF_COV_TABULATED = 4 };
 enum { GRF_OP_SAMPLE = 0, GRF_OP_BACKWARD = 1, GRF_OP_COVARIANCE = 2 };
+enum { GRF_BC_PERIODIC = 0, GRF_BC_NEUMANN = 1, GRF_BC_DIRICHLET = 2 };
 
 /*
  * Plan description.
@@ -98,6 +99,23 @@ enum { GRF_OP_SAMPLE = 0, GRF_OP_BACKWARD = 1, GRF_OP_COVARIANCE = 2 };
  *   sigma, length_scale, nu   default parameters (> 0).
  *   m, k, l, n   parameters of GRF_COV_PAPER (ignored otherwise).
  *   spectrum  GRF_COV_TABULATED only (NULL otherwise).
+ *   bc        boundary condition of each axis i < ndim: GRF_BC_PERIODIC (0,
+ *             the FFT algorithms of Section 3), or GRF_BC_NEUMANN (1) /
+ *             GRF_BC_DIRICHLET (2), the cosine / sine transform variant that
+ *             the introduction and Section 3 name for these boundaries.  Either
+ *             every axis is periodic or none is (else GRF_EUNSUPPORTED); the
+ *             reflecting variant needs alg = GRF_ALG_ONE_FFT (it has a single
+ *             transform; GRF_EUNSUPPORTED otherwise).  Reflecting fields live
+ *             on the cell centres x_j = (j + 1/2) l_i / N_i of [0, l_i] and are
+ *             sums over slots n (same shape as the field) of a_n z_n times
+ *             prod_i cos(pi n_i (j_i + 1/2) / N_i) on Neumann axes and
+ *             sin(pi (N_i - n_i)(j_i + 1/2) / N_i) on Dirichlet axes, with
+ *             frequency p_i = n_i / (2 l_i) resp. (N_i - n_i) / (2 l_i),
+ *             a_n = sigma sqrt(S(p) prod_i c(n_i) / |D|), c(0) = 1, c(n >= 1) = 2,
+ *             and z the Philox normals of tag 2 indexed by slot (the
+ *             covariance is the method-of-images sum of the periodic one on
+ *             the doubled grid).  TABULATED then gives S on the slot grid,
+ *             [N_1]..[N_d] (field layout).
  */
 typedef struct {
   int32_t ndim;
@@ -113,6 +131,8 @@ typedef struct {
   int32_t k, l, n;
   int32_t reserved;
   const double* spectrum;
+  int32_t bc[3];
+  int32_t reserved2;
 } grf_plan_desc;
 
 /* Create a plan: validates the description, builds float64 twiddle tables
@@ -175,7 +195,11 @@ enum {
   GRF_PASS_ROW_C2R = 5,       /* last-axis complex-to-real inverse transform */
   GRF_PASS_ROW_R2C_GEN = 6,   /* last-axis white noise + real-to-complex forward transform (two-FFT) */
   GRF_PASS_ROW_R2C_LOAD = 7,  /* last-axis real-to-complex forward transform of stored rows */
-  GRF_PASS_ROW_GEN_C2R = 8    /* d = 1: noise + filter + complex-to-real transform of whole fields */
+  GRF_PASS_ROW_GEN_C2R = 8,   /* d = 1: noise + filter + complex-to-real transform of whole fields */
+  GRF_PASS_R2R_COL_GEN = 9,   /* reflecting boundaries: coefficients + cosine transform along axis 1 */
+  GRF_PASS_R2R_COL_LOAD = 10, /* reflecting boundaries: cosine transform along the middle axis (d = 3) */
+  GRF_PASS_R2R_ROW_LOAD = 11, /* reflecting boundaries: cosine transform along the last axis */
+  GRF_PASS_R2R_ROW_GEN = 12   /* reflecting boundaries, d = 1: coefficients + cosine transform of whole fields */
 };
 grf_status grf_sample_stage_count(grf_plan plan, int64_t batch, int32_t* count);
 grf_status grf_sample_stage(grf_plan plan, int32_t stage, uint64_t seed, int64_t batch, const double* theta,
@@ -198,7 +222,8 @@ grf_status grf_covariance(grf_plan plan, uint64_t seed, int64_t nsamples, double
                           size_t workspace_bytes, void* stream);
 
 /* Write the noise z of the contract for fields seed..seed+batch-1 (device,
- * same shape and dtype as the output). */
+ * same shape and dtype as the output; tag 0 two-FFT, 1 one-FFT, 2 reflecting
+ * boundaries, where z is indexed by slot). */
 grf_status grf_noise(grf_plan plan, uint64_t seed, int64_t batch, void* noise_out, void* stream);
 
 /* Adjoint of the one-FFT sampler.  Given the upstream gradient

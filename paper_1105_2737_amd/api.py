@@ -8,6 +8,7 @@ import torch
 
 from . import _lib as L
 
+BOUNDARIES = {"periodic": L.GRF_BC_PERIODIC, "neumann": L.GRF_BC_NEUMANN, "dirichlet": L.GRF_BC_DIRICHLET}
 COV_KINDS = {"gaussian": L.GRF_COV_GAUSSIAN, "matern": L.GRF_COV_MATERN, "exponential": L.GRF_COV_EXPONENTIAL,
              "paper": L.GRF_COV_PAPER, "tabulated": L.GRF_COV_TABULATED}
 ALGS = {1: L.GRF_ALG_TWO_FFT, 2: L.GRF_ALG_ONE_FFT, "two_fft": L.GRF_ALG_TWO_FFT, "one_fft": L.GRF_ALG_ONE_FFT}
@@ -31,10 +32,14 @@ class Plan:
     (the family of Section 4, eq. (5): S = sigma^2 (m^{kl} + (sum p_i^{2k})^l)^{-n},
     parameters m, k, l, n); 'tabulated' (S at the half-spectrum frequencies,
     `spectrum` of shape dims[:-1] + (N_d/2 + 1,), float64).
+    boundary: 'periodic' (default), or per axis 'neumann' / 'dirichlet' (one
+    string for all axes or a sequence): the cosine / sine transform variant
+    on the cell-centred grid of [0, l_i] (one-transform method only); a
+    tabulated S then has the field's shape (the slot grid).
     """
 
     def __init__(self, dims, lengths=None, alg=2, dtype=torch.float32, cov="matern", sigma=1.0,
-                 length_scale=0.1, nu=1.5, device=None, m=1.0, k=1, l=1, n=1, spectrum=None):
+                 length_scale=0.1, nu=1.5, device=None, m=1.0, k=1, l=1, n=1, spectrum=None, boundary="periodic"):
         dims = tuple(int(n) for n in dims)
         lengths = tuple(float(v) for v in (lengths or (1.0,) * len(dims)))
         if len(lengths) != len(dims):
@@ -57,11 +62,18 @@ class Plan:
             d.lengths[i] = li
         d.sigma, d.length_scale, d.nu = self.params
         d.m, d.k, d.l, d.n = float(m), int(k), int(l), int(n)
+        bcs = (boundary,) * len(dims) if isinstance(boundary, str) else tuple(boundary)
+        if len(bcs) != len(dims):
+            raise ValueError("boundary must be one name or one per axis")
+        for i, b in enumerate(bcs):
+            d.bc[i] = BOUNDARIES[b]
+        self.boundary = bcs
+        self.reflect = any(b != "periodic" for b in bcs)
         spec = None
         if cov == "tabulated":
             import numpy as np
             spec = np.ascontiguousarray(np.asarray(spectrum, dtype=np.float64))
-            want = dims[:-1] + (dims[-1] // 2 + 1,)
+            want = dims if self.reflect else dims[:-1] + (dims[-1] // 2 + 1,)
             if spec.shape != want:
                 raise ValueError(f"spectrum must have shape {want}, got {spec.shape}")
             d.spectrum = spec.ctypes.data

@@ -47,6 +47,13 @@ struct grf_plan_s {
   FieldRec* rec_dev = nullptr;
   void* htab = nullptr;     // filter table h[row][m] (row stride M + 2) of the default parameters
   bool table_only = false;  // PAPER / TABULATED: h exists only as the table
+  // reflecting boundaries (cosine / sine transforms); htab then holds a_n / z_n
+  // over the slot grid [rows][N_d]
+  bool reflect = false;
+  int sinemask = 0;         // sine axes: bit 0 axis 1, bit 1 middle axis, bit 2 last axis
+  void* tq_col1 = nullptr;  // (1/2) e^{i pi k / (2N)} of each axis
+  void* tq_col2 = nullptr;
+  void* tq_row = nullptr;
   int device = 0;
 };
 
@@ -100,6 +107,28 @@ grf_status make_table(int L, int dtype, void** out) {
   return GRF_OK;
 }
 
+// Pre-twiddles (1/2) e^{i pi k / (2N)}, k = 0 .. count - 1, of the cosine
+// transform of length N, in float64, stored in the working precision.
+grf_status make_qtable(int N, int count, int dtype, void** out) {
+  std::vector<double> w(2 * (size_t)count);
+  for (int k = 0; k < count; ++k) {
+    const double ang = M_PI * (double)k / (2.0 * (double)N);
+    w[2 * k] = 0.5 * std::cos(ang);
+    w[2 * k + 1] = 0.5 * std::sin(ang);
+  }
+  const size_t bytes = (size_t)count * 2 * (dtype == GRF_F32 ? 4 : 8);
+  hipError_t e = hipMalloc(out, bytes);
+  if (e != hipSuccess) return fail(GRF_ENOMEM, "hipMalloc of twiddle table failed");
+  if (dtype == GRF_F32) {
+    std::vector<float> f(w.begin(), w.end());
+    e = hipMemcpy(*out, f.data(), bytes, hipMemcpyHostToDevice);
+  } else {
+    e = hipMemcpy(*out, w.data(), bytes, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return hip_fail(e, "twiddle upload");
+  return GRF_OK;
+}
+
 }  // namespace host
 }  // namespace grf
 
@@ -108,6 +137,7 @@ namespace {
 using grf::host::fail;
 using grf::host::g_err;
 using grf::host::hip_fail;
+using grf::host::make_qtable;
 using grf::host::make_table;
 using grf::host::smooth235;
 
@@ -195,7 +225,7 @@ grf_status run_pass(const grf_plan_s* p, int pass, int L, Args a, long long nfix
   const grf::Geom g = grf::pass_geom(pass, p->dtype, L);
   if (g.threads <= 0) return fail(GRF_EUNSUPPORTED, "no kernel for this length");
   long long nblocks;
-  if (pass >= grf::PASS_ROW_C2R) {
+  if (grf::is_row_pass(pass)) {
     nblocks = (a.rows + g.per_wg - 1) / g.per_wg;
   } else {
     a.ntile = (a.M + 2 * g.per_wg - 1) / (2 * g.per_wg);
@@ -284,6 +314,43 @@ void chunk_passes(const grf_plan_s* p, uint64_t seed, const void* zsrc, long lon
     pl.count = nb;
     v.push_back(pl);
   };
+  if (p->reflect) {
+    // cosine / sine transforms: coefficients + axis 1, (middle axis,) last axis
+    a.tag = 2;
+    a.bcmask = p->sinemask;
+    Args r = a;
+    r.tw2 = p->tw_row;
+    r.tq = p->tq_row;
+    r.sine = (p->sinemask >> 2) & 1;
+    if (p->d == 1) {
+      r.rows = nb;
+      push(grf::PASS_R2R_ROW_GEN, p->M, r);
+      return;
+    }
+    Args c = a;
+    c.tw = p->tw_col1;
+    c.tq = p->tq_col1;
+    c.sine = p->sinemask & 1;
+    c.stride_ax = (long long)p->no * p->M;
+    c.stride_fixed = p->M;
+    c.nfixed = p->no;
+    push(grf::PASS_R2R_COL_GEN, p->n1, c);
+    if (p->d == 3) {
+      Args m = c;
+      m.src = nullptr;
+      m.tw = p->tw_col2;
+      m.tq = p->tq_col2;
+      m.sine = (p->sinemask >> 1) & 1;
+      m.stride_ax = p->M;
+      m.stride_fixed = (long long)p->no * p->M;
+      m.nfixed = p->n1;
+      push(grf::PASS_R2R_COL_LOAD, p->no, m);
+    }
+    r.src = nullptr;
+    r.rows = nb * (p->P / p->nd);
+    push(grf::PASS_R2R_ROW_LOAD, p->M, r);
+    return;
+  }
   if (p->d == 1) {
     // one launch: noise, filter and complex-to-real transform of whole fields
     a.tag = 1;
@@ -345,7 +412,7 @@ std::vector<PassLaunch> sample_passes(const grf_plan_s* p, uint64_t seed, const 
   std::vector<PassLaunch> v;
   const long long C = chunk_fields(p, batch);
   const long long nch = (batch + C - 1) / C;
-  if (p->desc.alg == GRF_ALG_ONE_FFT && p->d == 2 && fuse_enabled() && batch >= 2 &&
+  if (!p->reflect && p->desc.alg == GRF_ALG_ONE_FFT && p->d == 2 && fuse_enabled() && batch >= 2 &&
       grf::fused_geom(p->dtype, p->n1, p->M).threads > 0) {
     // Fused chunk schedule: launch k runs the column generation pass of
     // chunk k and the last-axis pass of chunk k-1, so that the VALU-heavy and
@@ -415,6 +482,57 @@ grf_status build_density_table(grf_plan_s* p, const grf_plan_desc& d, double sca
   return GRF_OK;
 }
 
+// Coefficient table a_n / z_n over the slot grid of a reflecting plan whose
+// family is given by its density (PAPER, TABULATED), built on the host in
+// float64: a_n = sigma sqrt(S(p_n) prod_i c(n_i) / |D|) at the frequencies
+// p_i = k_i / (2 l_i), k_i = n_i (cosine axis) or N_i - n_i (sine axis), then
+// rounded once to the working precision.
+grf_status build_reflect_density_table(grf_plan_s* p, const grf_plan_desc& d) {
+  const int rows = p->n1 * p->no, nd = p->nd;
+  std::vector<double> h((size_t)rows * nd);
+  // semantic axes: 0 = axis 1, 1 = middle, 2 = last; their lengths and l
+  const int len[3] = {p->n1, p->no, p->nd};
+  double l[3] = {1.0, 1.0, d.lengths[p->d - 1]};
+  if (p->d >= 2) l[0] = d.lengths[0];
+  if (p->d == 3) l[1] = d.lengths[1];
+  const bool have[3] = {p->d >= 2, p->d == 3, true};
+  for (int row = 0; row < rows; ++row) {
+    const int n[2] = {row / p->no, row % p->no};
+    for (int s = 0; s < nd; ++s) {
+      const int slot[3] = {n[0], n[1], s};
+      double pc[3];
+      int np = 0;
+      double c = 1.0;
+      for (int ax = 0; ax < 3; ++ax) {
+        if (!have[ax]) continue;
+        const int k = ((p->sinemask >> ax) & 1) ? len[ax] - slot[ax] : slot[ax];
+        pc[np++] = k / (2.0 * l[ax]);
+        if (slot[ax] > 0) c *= 2.0;
+      }
+      double S;
+      if (d.cov_kind == GRF_COV_PAPER) {
+        double q = 0.0;
+        for (int i = 0; i < np; ++i) q += std::pow(pc[i] * pc[i], d.k);
+        S = std::pow(std::pow(d.m, (double)d.k * d.l) + std::pow(q, d.l), -(double)d.n);
+      } else {
+        S = d.spectrum[(size_t)row * nd + s];
+      }
+      h[(size_t)row * nd + s] = d.sigma * std::sqrt(S * c / p->vol);
+    }
+  }
+  const size_t bytes = h.size() * p->esz;
+  hipError_t e = hipMalloc(&p->htab, bytes);
+  if (e != hipSuccess) return fail(GRF_ENOMEM, "hipMalloc of the coefficient table failed");
+  if (p->dtype == GRF_F32) {
+    std::vector<float> f(h.begin(), h.end());
+    e = hipMemcpy(p->htab, f.data(), bytes, hipMemcpyHostToDevice);
+  } else {
+    e = hipMemcpy(p->htab, h.data(), bytes, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return hip_fail(e, "coefficient table upload");
+  return GRF_OK;
+}
+
 // Checks of a tabulated density: finite, >= 0, and S(p) = S(-p) on the two
 // planes k_d = 0 and N_d/2, where both entries are stored.
 bool tabulated_ok(const grf_plan_desc& d, int n1, int no, int M) {
@@ -432,7 +550,7 @@ bool tabulated_ok(const grf_plan_desc& d, int n1, int no, int M) {
 
 // Covariance estimator: workgroups of the one-dimensional epilogue (a fixed
 // number, so that the result does not depend on the device) and the
-// workspace layout: d = 1 [partials: groups * P float64]; d >= 2
+// workspace layout: periodic d = 1 [partials: groups * P float64]; otherwise
 // [acc: P float64][chunk of sampled fields].
 constexpr long long COV_GROUPS = 2048;
 
@@ -443,7 +561,7 @@ struct CovLayout {
 
 CovLayout cov_layout(const grf_plan_s* p, long long n) {
   CovLayout c{};
-  if (p->d == 1) {
+  if (p->d == 1 && !p->reflect) {
     const grf::Geom g = grf::geom_gen1d(p->dtype, p->M);
     const long long rb = g.per_wg > 0 ? g.per_wg : 1;
     c.groups = std::min<long long>((n + rb - 1) / rb, COV_GROUPS);
@@ -509,6 +627,7 @@ bool row_length_supported(int M) {
 }
 
 Geom pass_geom(int pass, int dtype, int L) {
+  if (is_r2r_pass(pass)) return geom_r2r(pass, dtype, L);
   if (pass == PASS_ROW_GEN_C2R) return geom_gen1d(dtype, L);
   if (pass >= PASS_ROW_C2R) return dtype == 0 ? geom_row_f32(pass, L) : geom_row_f64(pass, L);
   return dtype == 0 ? geom_col_f32(pass, L) : geom_col_f64(pass, L);
@@ -521,6 +640,7 @@ hipError_t launch_fused(int dtype, int L, int M, const Args& aA, const Args& aB,
 }
 
 hipError_t launch_pass(int pass, int dtype, int L, const Args& a, long long nblocks, hipStream_t s) {
+  if (is_r2r_pass(pass)) return launch_r2r(pass, dtype, L, a, nblocks, s);
   if (pass == PASS_ROW_GEN_C2R) return launch_gen1d(dtype, L, a, nblocks, nullptr, s);
   if (pass >= PASS_ROW_C2R)
     return dtype == 0 ? launch_row_f32(pass, L, a, nblocks, s) : launch_row_f64(pass, L, a, nblocks, s);
@@ -559,6 +679,16 @@ grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out) {
     return fail(GRF_EINVAL, "sigma and length_scale must be > 0");
   if (d.cov_kind == GRF_COV_MATERN && (!(d.nu > 0) || !std::isfinite(d.nu)))
     return fail(GRF_EINVAL, "nu must be > 0");
+  int nreflect = 0;
+  for (int i = 0; i < d.ndim; ++i) {
+    if (d.bc[i] < GRF_BC_PERIODIC || d.bc[i] > GRF_BC_DIRICHLET) return fail(GRF_EINVAL, "unknown boundary condition");
+    nreflect += d.bc[i] != GRF_BC_PERIODIC;
+  }
+  const bool reflect = nreflect > 0;
+  if (reflect && nreflect != d.ndim)
+    return fail(GRF_EUNSUPPORTED, "periodic and reflecting axes cannot be mixed");
+  if (reflect && d.alg != GRF_ALG_ONE_FFT)
+    return fail(GRF_EUNSUPPORTED, "reflecting boundaries use the one-transform method (GRF_ALG_ONE_FFT)");
   if (d.alg == GRF_ALG_TWO_FFT && d.ndim != 2)
     return fail(GRF_EUNSUPPORTED, "two-FFT algorithm implemented for d = 2");
   const int last = d.ndim - 1;
@@ -583,6 +713,14 @@ grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out) {
   p->il2[2] = 1.0 / (d.lengths[last] * d.lengths[last]);
   p->dtype = d.dtype;
   p->esz = d.dtype == GRF_F32 ? 4 : 8;
+  p->reflect = reflect;
+  if (reflect) {
+    for (int i = 0; i < d.ndim; ++i) {
+      // semantic axis of descriptor axis i: 0 = axis 1, 1 = middle, 2 = last
+      const int ax = (i == d.ndim - 1) ? 2 : i;
+      if (d.bc[i] == GRF_BC_DIRICHLET) p->sinemask |= 1 << ax;
+    }
+  }
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) {
     delete p;
@@ -590,7 +728,13 @@ grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out) {
   }
   FieldRec rec;
   if (table_only) {
-    if (d.cov_kind == GRF_COV_TABULATED && !tabulated_ok(d, p->n1, p->no, p->M)) {
+    if (d.cov_kind == GRF_COV_TABULATED && reflect) {
+      for (long long i = 0; i < p->P; ++i)
+        if (!(d.spectrum[i] >= 0) || !std::isfinite(d.spectrum[i])) {
+          delete p;
+          return fail(GRF_EINVAL, "tabulated density must be finite and >= 0");
+        }
+    } else if (d.cov_kind == GRF_COV_TABULATED && !tabulated_ok(d, p->n1, p->no, p->M)) {
       delete p;
       return fail(GRF_EINVAL, "tabulated density must be finite, >= 0 and symmetric on the planes k_d = 0, N_d/2");
     }
@@ -603,6 +747,11 @@ grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out) {
   grf_status st = d.ndim >= 2 ? make_table(p->n1, p->dtype, &p->tw_col1) : GRF_OK;
   if (st == GRF_OK && d.ndim == 3) st = make_table(p->no, p->dtype, &p->tw_col2);
   if (st == GRF_OK) st = make_table(p->nd, p->dtype, &p->tw_row);
+  if (st == GRF_OK && reflect) {
+    if (d.ndim >= 2) st = make_qtable(p->n1, p->n1, p->dtype, &p->tq_col1);
+    if (st == GRF_OK && d.ndim == 3) st = make_qtable(p->no, p->no, p->dtype, &p->tq_col2);
+    if (st == GRF_OK) st = make_qtable(p->nd, p->M + 1, p->dtype, &p->tq_row);
+  }
   if (st == GRF_OK) {
     e = hipMalloc((void**)&p->rec_dev, sizeof(FieldRec));
     if (e != hipSuccess) st = fail(GRF_ENOMEM, "hipMalloc of field record failed");
@@ -611,7 +760,26 @@ grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out) {
       if (e != hipSuccess) st = hip_fail(e, "record upload");
     }
   }
-  if (st == GRF_OK && table_only) {
+  if (st == GRF_OK && reflect && table_only) {
+    st = build_reflect_density_table(p, d);
+  } else if (st == GRF_OK && reflect && d.ndim <= 2) {
+    // a_n / z_n of every slot for the default parameters, by the kernels' own
+    // float expressions (the generation passes read it)
+    Args t = base_args(p, 1);
+    t.recs = p->rec_dev;
+    t.bcmask = p->sinemask;
+    const size_t bytes = (size_t)p->P * p->esz;
+    e = hipMalloc(&p->htab, bytes);
+    if (e != hipSuccess) {
+      st = fail(GRF_ENOMEM, "hipMalloc of the coefficient table failed");
+    } else {
+      e = grf::launch_r2r_table(p->dtype, t, p->htab, nullptr);
+      if (e == hipSuccess) e = hipDeviceSynchronize();
+      if (e != hipSuccess) st = hip_fail(e, "coefficient table");
+    }
+  } else if (st == GRF_OK && reflect) {
+    // d = 3: coefficients on the fly
+  } else if (st == GRF_OK && table_only) {
     st = build_density_table(p, d, d.alg == GRF_ALG_TWO_FFT ? 1.0 / std::sqrt((double)p->P) : 1.0);
   } else if (st == GRF_OK && d.ndim == 2 && d.alg == GRF_ALG_ONE_FFT) {
     // filter table: h of every (row, m) for the default parameters, computed by
@@ -635,6 +803,9 @@ grf_status grf_plan_destroy(grf_plan p) {
   if (p->tw_row) (void)hipFree(p->tw_row);
   if (p->rec_dev) (void)hipFree(p->rec_dev);
   if (p->htab) (void)hipFree(p->htab);
+  if (p->tq_col1) (void)hipFree(p->tq_col1);
+  if (p->tq_col2) (void)hipFree(p->tq_col2);
+  if (p->tq_row) (void)hipFree(p->tq_row);
   delete p;
   return GRF_OK;
 }
@@ -657,7 +828,7 @@ grf_status grf_covariance(grf_plan p, uint64_t seed, int64_t nsamples, double* c
   if (workspace == nullptr || workspace_bytes < c.total) return fail(GRF_EINVAL, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
   const double scale = 1.0 / (double)nsamples;
-  if (p->d == 1) {
+  if (p->d == 1 && !p->reflect) {
     double* partial = (double*)workspace;
     Args a = base_args(p, nsamples);
     a.recs = p->rec_dev;
@@ -732,7 +903,7 @@ grf_status grf_noise(grf_plan p, uint64_t seed, int64_t batch, void* noise_out, 
   if (batch < 0) return fail(GRF_EINVAL, "negative batch");
   if (batch == 0) return GRF_OK;
   if (noise_out == nullptr) return fail(GRF_EINVAL, "null output");
-  const int tag = p->desc.alg == GRF_ALG_ONE_FFT ? 1 : 0;
+  const int tag = p->reflect ? 2 : (p->desc.alg == GRF_ALG_ONE_FFT ? 1 : 0);
   hipError_t e = grf::launch_noise(p->dtype, seed, tag, (int)(p->P / p->nd), p->nd, (int)batch, noise_out,
                                    (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "noise kernel");
@@ -743,8 +914,8 @@ grf_status grf_backward(grf_plan p, uint64_t seed, const void* noise, int64_t ba
                         const void* grad_out, double* grad_theta, void* grad_noise, void* workspace,
                         size_t workspace_bytes, void* stream) {
   if (p == nullptr) return fail(GRF_EINVAL, "null plan");
-  if (p->desc.alg != GRF_ALG_ONE_FFT || p->d != 2)
-    return fail(GRF_EUNSUPPORTED, "adjoint implemented for the one-FFT algorithm with d = 2");
+  if (p->desc.alg != GRF_ALG_ONE_FFT || p->d != 2 || p->reflect)
+    return fail(GRF_EUNSUPPORTED, "adjoint implemented for the periodic one-FFT algorithm with d = 2");
   if (batch < 0) return fail(GRF_EINVAL, "negative batch");
   if (batch == 0) return GRF_OK;
   if (grad_out == nullptr || grad_theta == nullptr) return fail(GRF_EINVAL, "null gradient pointer");

@@ -35,7 +35,17 @@ enum PassKind {
   PASS_ROW_R2C_GEN = GRF_PASS_ROW_R2C_GEN,     // last axis, white noise + real-to-complex forward
   PASS_ROW_R2C_LOAD = GRF_PASS_ROW_R2C_LOAD,   // last axis, stored real rows + real-to-complex forward
   PASS_ROW_GEN_C2R = GRF_PASS_ROW_GEN_C2R,     // d = 1: whole fields, noise + filter + complex-to-real
+  PASS_R2R_COL_GEN = GRF_PASS_R2R_COL_GEN,     // reflecting: coefficients + cosine transform, axis 1
+  PASS_R2R_COL_LOAD = GRF_PASS_R2R_COL_LOAD,   // reflecting: cosine transform, middle axis
+  PASS_R2R_ROW_LOAD = GRF_PASS_R2R_ROW_LOAD,   // reflecting: cosine transform, last axis
+  PASS_R2R_ROW_GEN = GRF_PASS_R2R_ROW_GEN,     // reflecting, d = 1: coefficients + cosine transform
 };
+
+inline bool is_r2r_pass(int p) { return p >= PASS_R2R_COL_GEN; }
+// passes that take rows (last axis) rather than column tiles
+inline bool is_row_pass(int p) {
+  return is_r2r_pass(p) ? (p == PASS_R2R_ROW_LOAD || p == PASS_R2R_ROW_GEN) : p >= PASS_ROW_C2R;
+}
 
 // Workgroup geometry of a pass at a given length (for grid sizing).
 struct Geom {
@@ -84,6 +94,20 @@ hipError_t launch_gen1d_f64(int M, const Args& a, long long nblocks, double* par
 Geom geom_gen1d(int dtype, int M);
 Geom geom_gen1d_f32(int M);
 Geom geom_gen1d_f64(int M);
+
+// Reflecting boundaries (cosine / sine transforms): launch and geometry of the
+// PASS_R2R_* passes (L: column length, or half-length M = N_d / 2 of a row
+// pass), and the table a_n / z_n over the slot grid for a.recs[0] (out holds
+// n1 * no * nd values of the working precision).
+hipError_t launch_r2r(int pass, int dtype, int L, const Args& a, long long nblocks, hipStream_t s);
+Geom geom_r2r(int pass, int dtype, int L);
+hipError_t launch_r2r_table(int dtype, const Args& a, void* out, hipStream_t s);
+hipError_t launch_r2r_f32(int pass, int L, const Args& a, long long nblocks, hipStream_t s);
+hipError_t launch_r2r_f64(int pass, int L, const Args& a, long long nblocks, hipStream_t s);
+Geom geom_r2r_f32(int pass, int L);
+Geom geom_r2r_f64(int pass, int L);
+hipError_t launch_r2r_table_f32(const Args& a, void* out, hipStream_t s);
+hipError_t launch_r2r_table_f64(const Args& a, void* out, hipStream_t s);
 
 // helper kernels (grf_util.hip)
 // out[x] = scale * sum_{w < nw} partial[w * n + x], the sum taken in order of w.

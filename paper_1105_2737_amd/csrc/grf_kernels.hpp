@@ -51,6 +51,10 @@ struct Args {
   int rows_per_field;
   int tag;
   int order;                  // column passes: 1 = XCD-grouped workgroup-to-tile order (col_block)
+  // reflecting boundaries (cosine / sine transforms)
+  const void* tq;             // (1/2) e^{i pi k / (2N)}, k < N (column) or k <= N/2 (row), of the pass's axis
+  int sine;                   // the pass's axis is a sine axis (output sign (-1)^j)
+  int bcmask;                 // sine axes: bit 0 axis 1, bit 1 middle axis, bit 2 last axis
 };
 
 // Tile index of this workgroup in a column pass.  Workgroups are dispatched to

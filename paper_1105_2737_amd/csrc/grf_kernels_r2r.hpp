@@ -1,0 +1,306 @@
+// Reflecting boundaries: cosine (Neumann) and sine (Dirichlet) transforms in
+// place of the FFT, the variant named in the introduction and at the start of
+// Section 3.
+//
+// On the cell-centred grid x_j = (j + 1/2) l / N of each axis, a field is
+//     phi_j = sum_n a_n z_n prod_i b_i(n_i, j_i)
+// over the slot grid (the field's own shape).  Slot n of a cosine axis is the
+// mode cos(pi n (j + 1/2) / N) of frequency n / (2l); slot n of a sine axis is
+// the mode sin(pi (N - n)(j + 1/2) / N) of frequency (N - n) / (2l); and
+// a_n = h(p_n) prod_i sqrt(c(n_i)), c(0) = 1, c(n >= 1) = 2, with h the
+// periodic filter sigma sqrt(S(p) / |D|).  z: Philox normals with tag 2,
+// indexed by slot as the periodic noise is indexed by point.
+//
+// sin(pi (N - n)(j + 1/2) / N) = (-1)^j cos(pi n (j + 1/2) / N), so every axis
+// is the DCT-III  x_j = sum_{k<N} X_k cos(pi k (j + 1/2) / N)  of the slots,
+// with the sign (-1)^j on the output of a sine axis.  A DCT-III of length N
+// is one inverse DFT of length N (Makhoul, IEEE Trans. ASSP 28 (1980)):
+//     Y_0 = X_0,  Y_k = (1/2) e^{i pi k / (2N)} (X_k - i X_{N-k}),
+//     v_m = sum_k Y_k e^{2 pi i k m / N},  x_{2n} = v_n,  x_{2n+1} = v_{N-1-n}.
+// Y is linear over the complex numbers in X, so a column pass transforms two
+// real columns at once as the real and imaginary parts of one complex column
+// (the column pair layout of the periodic passes, unchanged).  Along the last
+// axis X is real, Y is Hermitian (Y_{N-k} = conj Y_k, Y_{N/2} = X_{N/2} / sqrt 2)
+// and the DFT is the half-length complex-to-real transform of the periodic
+// path.
+//
+// Layout: the field's own (real, last axis contiguous), in place in the
+// output.  Passes: generation + axis-1 DCT (column pass), middle-axis DCT
+// (d = 3, column pass), last-axis DCT (row pass); d = 1 is one row pass that
+// generates its rows.
+#pragma once
+#include "grf_kernels.hpp"
+
+namespace grf {
+
+// sqrt(c(n)): 1 for slot 0, sqrt 2 otherwise.
+template <typename T>
+__device__ __forceinline__ T slot_w(int n) {
+  return n == 0 ? (T)1 : (T)1.4142135623730950488;
+}
+
+// a_n / z_n at slot (n1, no, nd) (axis 1, middle, last); the three factors
+// and h in a fixed order, so that the table and the on-the-fly route give the
+// same bits.
+template <typename T>
+__device__ __forceinline__ T r2r_coef(const Args& a, const Filt<T>& f, int n1, int no, int nd) {
+  const int k1 = (a.bcmask & 1) ? a.n1 - n1 : n1;
+  const int ko = (a.bcmask & 2) ? a.no - no : no;
+  const int kd = (a.bcmask & 4) ? a.nd - nd : nd;
+  // p^2 = sum (k_i / (2 l_i))^2
+  const T p2 = (T)0.25 * ((T)(k1 * k1) * (T)a.il2[0] + (T)(ko * ko) * (T)a.il2[1] + (T)(kd * kd) * (T)a.il2[2]);
+  T w = slot_w<T>(nd);
+  if (a.n1 > 1) w = w * slot_w<T>(n1);
+  if (a.no > 1) w = w * slot_w<T>(no);
+  return filt_h(f, p2) * w;
+}
+
+// Four consecutive coefficients of row `row` (= n1 * no + no index), last-axis
+// slots s .. s + 3 (s a multiple of 4) of field b.  UNIFORM_KEY: every lane of
+// the wavefront works on the same field (column passes).
+template <typename T, bool UNIFORM_KEY>
+__device__ __forceinline__ void r2r_gen4(const Args& a, const Filt<T>& f, int b, uint32_t k0, uint32_t k1, int n1,
+                                         int no, int s, T* x) {
+  const int row = n1 * a.no + no;
+  T z[4];
+  if (a.src == nullptr) {
+    normals4<T, UNIFORM_KEY>((uint32_t)(s >> 2), (uint32_t)row, (uint32_t)a.tag, k0, k1, z);
+  } else {
+    const T* p = (const T*)a.src + (long long)b * a.field_stride * 2 + (long long)row * a.nd + s;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) z[e] = p[e];
+  }
+  if (a.htab != nullptr) {
+    struct alignas(4 * sizeof(T)) P4 { T v[4]; };
+    const P4 h = *reinterpret_cast<const P4*>((const T*)a.htab + (long long)row * a.nd + s);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) x[e] = h.v[e] * z[e];
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) x[e] = r2r_coef<T>(a, f, n1, no, s + e) * z[e];
+  }
+}
+
+// Table of a_n / z_n over the slot grid ([rows][N_d], the field's layout) for
+// the record a.recs[0].
+template <typename T>
+__global__ void k_r2r_table(Args a, T* out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long P = (long long)a.n1 * a.no * a.nd;
+  if (i >= P) return;
+  const int s = (int)(i % a.nd);
+  const long long row = i / a.nd;
+  const Filt<T> f = load_filt<T>(a.recs[0], 1.0);
+  out[i] = r2r_coef<T>(a, f, (int)(row / a.no), (int)(row % a.no), s);
+}
+
+// Column pass: DCT-III along a leading axis of length L over tiles of CP
+// column pairs (4 reals of the last axis per thread and row).  SRC_GEN
+// generates the coefficients (axis 1); SRC_LOAD reads the field.
+template <typename T, int L, class Rad, int CP, int PAD, int SRC>
+struct R2RCol {
+  using V = C<T>;
+  using E = Vec<T, 2>;
+  static constexpr int NT = L / Rad::get(0);
+  static constexpr int THREADS = (NT * CP + 63) / 64 * 64;
+  static constexpr int RS = CP + PAD;
+  static constexpr int R0 = Rad::get(0);
+  static constexpr int LDS_BYTES = L * RS * (int)sizeof(E) + 2 * L * (int)sizeof(V);
+  using EN = Eng<T, L, Rad, NT, 2, 1>;
+  static_assert(L % 2 == 0, "even lengths only");
+
+  __device__ __forceinline__ static void run(const Args& a, int bid, char* smem) {
+    E* sm = reinterpret_cast<E*>(smem);
+    V* tw = reinterpret_cast<V*>(smem + L * RS * sizeof(E));
+    V* tq = tw + L;
+    const int tid = threadIdx.x;
+    const int cp = tid % CP;
+    const int t = tid / CP;
+    const int tile = bid % a.ntile;
+    bid /= a.ntile;
+    const int fx = bid % a.nfixed;
+    const int b = bid / a.nfixed;
+    const int m0 = (tile * CP + cp) * 2;
+    const bool act = (t < NT) && (m0 < a.M);
+    const bool two = (m0 + 1) < a.M;
+    const bool al = (a.M & 1) == 0;
+    V* base = (V*)a.data + (long long)b * a.field_stride + (long long)fx * a.stride_fixed + m0;
+    for (int i = tid; i < L; i += blockDim.x) {
+      tw[i] = ((const V*)a.tw)[i];
+      tq[i] = ((const V*)a.tq)[i];
+    }
+    V x[2][EN::REG];
+    if (act) {
+      if constexpr (SRC == SRC_GEN) {
+        const Filt<T> f = load_filt<T>(a.recs[b * a.rec_stride], 1.0);
+        const unsigned long long key = a.seed + (unsigned long long)b;
+        const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
+#pragma unroll
+        for (int m = 0; m < R0; ++m) {
+          T v[4];
+          r2r_gen4<T, true>(a, f, b, k0, k1, t + m * NT, fx, 2 * m0, v);
+          x[0][m] = mk<T>(v[0], v[1]);
+          x[1][m] = mk<T>(v[2], v[3]);
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < R0; ++m)
+          ld_pair<T>(base + (long long)(t + m * NT) * a.stride_ax, two, al, x[0][m], x[1][m]);
+      }
+#pragma unroll
+      for (int m = 0; m < R0; ++m) {
+        E e;
+        e.v[0] = x[0][m];
+        e.v[1] = x[1][m];
+        sm[(t + m * NT) * RS + cp] = e;
+      }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int m = 0; m < R0; ++m) {
+        const int k = t + m * NT;
+        if (k > 0) {
+          const E pr = sm[(L - k) * RS + cp];
+          const V q = tq[k];
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const V xk = x[c][m], xp = pr.v[c];
+            x[c][m] = cmul(mk<T>(xk.x + xp.y, xk.y - xp.x), q);   // (X_k - i X_{L-k}) q
+          }
+        }
+      }
+    }
+    __syncthreads();
+    const bool neg = a.sine != 0;
+    auto lds = [&](int i) -> E& { return sm[i * RS + cp]; };
+    auto out = [&](int i, const E& e) {
+      const int j = 2 * i < L ? 2 * i : 2 * (L - 1 - i) + 1;
+      E o = e;
+      if (neg && (j & 1)) {
+        o.v[0] = mk<T>(-e.v[0].x, -e.v[0].y);
+        o.v[1] = mk<T>(-e.v[1].x, -e.v[1].y);
+      }
+      st_pair<T>(base + (long long)j * a.stride_ax, two, al, o);
+    };
+    EN::template run<+1>(x, t, act, lds, tw, out);
+  }
+};
+
+template <typename T, int L, class Rad, int CP, int PAD, int SRC>
+__global__ void __launch_bounds__((R2RCol<T, L, Rad, CP, PAD, SRC>::THREADS)) k_r2r_col(Args a) {
+  using PS = R2RCol<T, L, Rad, CP, PAD, SRC>;
+  __shared__ __align__(16) char smem[PS::LDS_BYTES];
+  PS::run(a, col_block(a.order), smem);
+}
+
+// Row pass: DCT-III along the last axis (N = 2M reals per row), RB rows per
+// workgroup.  SRC_GEN (d = 1: a row is a field) generates the coefficients,
+// SRC_LOAD reads the rows.  The rows are staged in LDS (the DCT reads X_k with
+// X_{N-k}, X_{M-k} and X_{M+k}); the half-length inverse DFT keeps its outputs
+// v_{2i} + i v_{2i+1} in registers, they go back to LDS, and each thread
+// writes output pairs (x_{2n}, x_{2n+1}) = (v_n, +-v_{N-1-n}) as one vector.
+template <typename T, int M, class Rad, int RB, int SRC>
+struct R2RRow {
+  using V = C<T>;
+  using E = Vec<T, 1>;
+  using RL = RowLds<M>;
+  static constexpr int N = 2 * M;
+  static constexpr int NT = M / Rad::get(0);
+  static constexpr int THREADS = (NT * RB + 63) / 64 * 64;
+  static constexpr int R0 = Rad::get(0);
+  static constexpr bool WAVE = (64 % NT) == 0;
+  static constexpr int ROWS_BYTES = RB * RL::STRIDE * (int)sizeof(E);
+  static constexpr int LDS_BYTES = ROWS_BYTES + (N + M + 1) * (int)sizeof(V);
+  using EN = Eng<T, M, Rad, NT, 1, 2, WAVE>;
+  static_assert(M % 2 == 0, "a Philox block fills two complex slots");
+
+  __device__ __forceinline__ static void run(const Args& a, int bid, char* smem) {
+    E* sm = reinterpret_cast<E*>(smem);
+    V* tw = reinterpret_cast<V*>(smem + ROWS_BYTES);
+    V* tq = tw + N;
+    const int tid = threadIdx.x;
+    const int r = tid / NT, t = tid % NT;
+    const long long row0 = (long long)bid * RB;
+    const long long left = a.rows - row0;
+    const int nrows = left < RB ? (int)left : RB;
+    for (int i = tid; i < N; i += blockDim.x) tw[i] = ((const V*)a.tw2)[i];
+    for (int i = tid; i <= M; i += blockDim.x) tq[i] = ((const V*)a.tq)[i];
+    V* g = (V*)a.data + row0 * M;
+    if constexpr (SRC == SRC_GEN) {
+      constexpr int NQ = M / 2;   // Philox blocks per row
+      for (int i = tid; i < nrows * NQ; i += blockDim.x) {
+        const int rr = i / NQ, q = i % NQ;
+        const int b = (int)(row0 + rr);
+        const Filt<T> f = load_filt<T>(a.recs[b * a.rec_stride], 1.0);
+        const unsigned long long key = a.seed + (unsigned long long)b;
+        T v[4];
+        r2r_gen4<T, false>(a, f, b, (uint32_t)key, (uint32_t)(key >> 32), 0, 0, 4 * q, v);
+        E* rowp = sm + rr * RL::STRIDE;
+        rowp[RL::idx(2 * q)].v[0] = mk<T>(v[0], v[1]);
+        rowp[RL::idx(2 * q + 1)].v[0] = mk<T>(v[2], v[3]);
+      }
+    } else {
+      if (tid < THREADS) copy_in<T, M, RB * M, THREADS>(g, sm, nrows * M, tid);
+    }
+    __syncthreads();
+    const bool act = r < nrows;
+    const E* rowp = sm + r * RL::STRIDE;
+    auto X = [&](int i) -> T {
+      const V c = rowp[RL::idx(i >> 1)].v[0];
+      return (i & 1) ? c.y : c.x;
+    };
+    // Y_k for 0 < k < M
+    auto Y = [&](int k) -> V { return cmul(mk<T>(X(k), -X(N - k)), tq[k]); };
+    V x[1][EN::REG];
+    if (act) {
+#pragma unroll
+      for (int m = 0; m < R0; ++m) {
+        const int k = t + m * NT;
+        if (k == 0) {
+          const T y0 = X(0), ym = X(M) * (T)0.70710678118654752440;
+          x[0][m] = mk<T>(y0 + ym, y0 - ym);
+        } else {
+          const V yk = Y(k);
+          const V ym = cconj(Y(M - k));
+          const V ek = cadd(yk, ym);
+          const V ok = cmul(csub(yk, ym), tw[k]);
+          x[0][m] = mk<T>(ek.x - ok.y, ek.y + ok.x);
+        }
+      }
+    }
+    __syncthreads();
+    auto lds = [&](int i) -> E& { return sm[r * RL::STRIDE + RL::idx(i)]; };
+    auto none = [&](int, const E&) {};
+    EN::template run<+1>(x, t, act, lds, tw, none);
+    // x holds the outputs i = t + b NT + m LRL of the last stage at x[0][b R + m]
+    constexpr int LAST = Rad::count - 1;
+    constexpr int RL_ = Rad::get(LAST), NBL = EN::NB(LAST), LRL = M / RL_;
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int b = 0; b < NBL; ++b) {
+        const int j = t + b * NT;
+        if (NBL * NT == LRL || j < LRL) {
+#pragma unroll
+          for (int m = 0; m < RL_; ++m) sm[r * RL::STRIDE + RL::idx(j + m * LRL)].v[0] = x[0][b * RL_ + m];
+        }
+      }
+    }
+    __syncthreads();
+    if (act) {
+      const T sg = a.sine ? (T)-1 : (T)1;
+      V* o = g + (long long)r * M;
+      for (int n = t; n < M; n += NT) o[n] = mk<T>(X(n), sg * X(N - 1 - n));
+    }
+  }
+};
+
+template <typename T, int M, class Rad, int RB, int SRC>
+__global__ void __launch_bounds__((R2RRow<T, M, Rad, RB, SRC>::THREADS)) k_r2r_row(Args a) {
+  using PS = R2RRow<T, M, Rad, RB, SRC>;
+  __shared__ __align__(16) char smem[PS::LDS_BYTES];
+  PS::run(a, blockIdx.x, smem);
+}
+
+}  // namespace grf

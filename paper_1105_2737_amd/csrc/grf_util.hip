@@ -150,4 +150,14 @@ hipError_t launch_gen1d(int dtype, int M, const Args& a, long long nblocks, doub
 
 Geom geom_gen1d(int dtype, int M) { return dtype == 0 ? geom_gen1d_f32(M) : geom_gen1d_f64(M); }
 
+hipError_t launch_r2r(int pass, int dtype, int L, const Args& a, long long nblocks, hipStream_t s) {
+  return dtype == 0 ? launch_r2r_f32(pass, L, a, nblocks, s) : launch_r2r_f64(pass, L, a, nblocks, s);
+}
+
+Geom geom_r2r(int pass, int dtype, int L) { return dtype == 0 ? geom_r2r_f32(pass, L) : geom_r2r_f64(pass, L); }
+
+hipError_t launch_r2r_table(int dtype, const Args& a, void* out, hipStream_t s) {
+  return dtype == 0 ? launch_r2r_table_f32(a, out, s) : launch_r2r_table_f64(a, out, s);
+}
+
 }  // namespace grf

@@ -48,6 +48,9 @@ def _desc(**kw):
         elif k == "lengths":
             for i, n in enumerate(v):
                 d.lengths[i] = n
+        elif k == "bc":
+            for i, n in enumerate(v):
+                d.bc[i] = n
         else:
             setattr(d, k, v)
     return d
@@ -77,6 +80,11 @@ def _desc(**kw):
     (dict(cov_kind=3, m=1.0, k=1, l=1, n=65), -1),
     (dict(cov_kind=4), -1),                          # tabulated density without a table
     (dict(cov_kind=5), -1),
+    (dict(bc=(3, 3)), -1),                           # unknown boundary condition
+    (dict(bc=(-1, 1)), -1),
+    (dict(bc=(1, 0)), -4),                           # periodic and reflecting axes mixed
+    (dict(ndim=3, dims=(16, 16, 16), bc=(2, 0, 2)), -4),
+    (dict(alg=1, bc=(1, 1)), -4),                    # reflecting: one-transform method only
 ])
 def test_invalid_descriptors_are_rejected_on_the_host(kw, status):
     from paper_1105_2737_amd import _lib as L
