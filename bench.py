@@ -138,12 +138,14 @@ def event_ms(fn, reps, torch):
 
 PASS_NAMES = {0: "column noise+inverse FFT (axis 1)", 1: "inverse FFT (axis 2)", 2: "forward FFT (axis 2)",
               3: "column fwd FFT x h x inv FFT", 4: "column adjoint", 5: "last-axis C2R",
-              6: "last-axis noise+R2C", 7: "last-axis R2C", -1: "fused column gen | last-axis C2R"}
+              6: "last-axis noise+R2C", 7: "last-axis R2C", -1: "fused column gen | last-axis C2R",
+              9: "reflecting: column coefficients+DCT (axis 1)", 10: "reflecting: DCT (axis 2)",
+              11: "reflecting: last-axis DCT", 12: "reflecting: 1D coefficients+DCT"}
 
 
 def pass_bytes(kind, field_bytes):
     """Algorithmic HBM bytes of one field through pass `kind` (output-sized packed spectrum)."""
-    return field_bytes * (1 if kind in (0, 6) else 2)
+    return field_bytes * (1 if kind in (0, 6, 9, 12) else 2)
 
 
 def launch_table(plan, batch, torch, grf, reps):
@@ -400,6 +402,30 @@ def main():
                                            "max_rel_err_vs_fp64": max(ep)}
         del op
         torch.cuda.empty_cache()
+
+        # reflecting boundaries (cosine / sine transforms) on the headline grid and batch
+        # and on 256^3 x 16: Neumann and Dirichlet on every axis
+        refl = {}
+        for rdims, rb, rfam in (((512, 512), batch, dict(cov="matern", sigma=1.0, length_scale=0.1, nu=1.5)),
+                                ((256, 256, 256), 16, dict(cov="exponential", sigma=1.0, length_scale=0.05))):
+            orf = torch.empty((rb,) + rdims, dtype=torch.float32, device="cuda")
+            npts = orf.numel()
+            for bc in ("neumann", "dirichlet"):
+                pr = grf.Plan(rdims, alg=2, dtype=torch.float32, boundary=bc, **rfam)
+                sr = timed(lambda: pr.sample(seed=0, batch=rb, out=orf), max(args.steps // 5, 5), max(args.warmup // 5, 2), torch)
+                pr64 = grf.Plan(rdims, alg=2, dtype=torch.float64, boundary=bc, **rfam)
+                er = []
+                for b in (0, rb - 1):
+                    f64 = pr64.sample(seed=b, batch=1)[0]
+                    er.append(float((orf[b].double() - f64).abs().max() / f64.abs().max()))
+                key = "x".join(str(v) for v in rdims) + f"_x{rb}_{bc}"
+                refl[key] = {"points_per_s": round(npts / sr, 1), "ms_per_step": round(sr * 1e3, 4),
+                             "max_rel_err_vs_fp64": max(er), "error_fields": [0, rb - 1],
+                             "passes": kind_rows(by_kind(launch_table(pr, rb, torch, grf, 5), (npts // rb) * 4))}
+                del pr, pr64, f64
+            del orf
+            torch.cuda.empty_cache()
+        extra["reflecting_boundaries"] = refl
 
         # d = 1: sampling throughput (65536 fields of 4096 points, 1 GiB written) and the
         # convergence study of Section 4 (10^8 samples per grid, n = 2..12, estimator fused
