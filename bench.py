@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--profile-alg", type=int, default=2, help="algorithm for --profile-stage")
     ap.add_argument("--profile-dims", type=str, default="512,512", help="grid for --profile-stage")
     ap.add_argument("--profile-batch", type=int, default=1024)
+    ap.add_argument("--profile-boundary", type=str, default="periodic",
+                    help="boundary for --profile-stage: periodic | neumann | dirichlet")
     ap.add_argument("--copy-calib", action="store_true",
                     help="profiling mode: device copy of 1 GiB, --steps times (counter calibration)")
     return ap.parse_args()
@@ -98,7 +100,7 @@ def profile_mode(args):
     dims = tuple(int(x) for x in args.profile_dims.split(","))
     cov = "exponential" if len(dims) == 3 else "matern"
     plan = grf.Plan(dims, alg=args.profile_alg, dtype=torch.float32, cov=cov, sigma=1.0,
-                    length_scale=0.05 if len(dims) == 3 else 0.1, nu=1.5)
+                    length_scale=0.05 if len(dims) == 3 else 0.1, nu=1.5, boundary=args.profile_boundary)
     batch = args.profile_batch
     out = torch.empty((batch,) + dims, dtype=torch.float32, device="cuda")
     stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -109,7 +111,8 @@ def profile_mode(args):
             grf.grf_sample_stage(plan.handle, args.profile_stage, 0, batch, None, ctypes.c_void_p(out.data_ptr()),
                                  None, 0, stream)
     torch.cuda.synchronize()
-    print(f"profiled stage {args.profile_stage} of alg {args.profile_alg} on {dims} x {batch}", flush=True)
+    print(f"profiled stage {args.profile_stage} of alg {args.profile_alg} on {dims} x {batch}, "
+          f"{args.profile_boundary} boundary", flush=True)
 
 
 def timed(fn, steps, warmup, torch):
