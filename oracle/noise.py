@@ -13,7 +13,8 @@ contract:
   (s div 4, row, tag, 0); tag 0 is the white noise of the two-FFT algorithm,
   tag 1 the Fourier-space noise of the one-FFT (Hermitian) algorithm, tag 2
   the slot coefficients of the cosine / sine transforms (reflecting
-  boundaries);
+  boundaries), tag 3 the sequential stream of the recursive algorithm (its
+  j-th draw is z in row-major order);
 * the 32-bit outputs x become uniforms u = (x + 1/2) 2^-32 in (0, 1);
 * Box and Muller (1958): lanes (0,1) and (2,3) of a block are pairs
   (u_a, u_b) -> sqrt(-2 ln u_a) (cos 2 pi u_b, sin 2 pi u_b).
@@ -25,6 +26,7 @@ from .philox import philox4x32, key_of
 TAG_ALG1 = 0
 TAG_ALG2 = 1
 TAG_REFLECT = 2
+TAG_RECURSIVE = 3
 
 
 def uniforms(x):
