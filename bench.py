@@ -143,12 +143,13 @@ PASS_NAMES = {0: "column noise+inverse FFT (axis 1)", 1: "inverse FFT (axis 2)",
               3: "column fwd FFT x h x inv FFT", 4: "column adjoint", 5: "last-axis C2R",
               6: "last-axis noise+R2C", 7: "last-axis R2C", -1: "fused column gen | last-axis C2R",
               9: "reflecting: column coefficients+DCT (axis 1)", 10: "reflecting: DCT (axis 2)",
-              11: "reflecting: last-axis DCT", 12: "reflecting: 1D coefficients+DCT"}
+              11: "reflecting: last-axis DCT", 12: "reflecting: 1D coefficients+DCT",
+              13: "column noise (recursive order)+inverse FFT (axis 1)"}
 
 
 def pass_bytes(kind, field_bytes):
     """Algorithmic HBM bytes of one field through pass `kind` (output-sized packed spectrum)."""
-    return field_bytes * (1 if kind in (0, 6, 9, 12) else 2)
+    return field_bytes * (1 if kind in (0, 6, 9, 12, 13) else 2)
 
 
 def launch_table(plan, batch, torch, grf, reps):

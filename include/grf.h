@@ -68,6 +68,7 @@ enum { GRF_F32 = 0, GRF_F64 = 1 };
 enum { GRF_COV_GAUSSIAN = 0, GRF_COV_MATERN = 1, GRF_COV_EXPONENTIAL = 2, GRF_COV_PAPER = 3, GRF_COV_TABULATED = 4 };
 enum { GRF_OP_SAMPLE = 0, GRF_OP_BACKWARD = 1, GRF_OP_COVARIANCE = 2 };
 enum { GRF_BC_PERIODIC = 0, GRF_BC_NEUMANN = 1, GRF_BC_DIRICHLET = 2 };
+enum { GRF_DRAW_COUNTER = 0, GRF_DRAW_RECURSIVE = 1 };
 
 /*
  * Plan description.
@@ -116,6 +117,19 @@ enum { GRF_BC_PERIODIC = 0, GRF_BC_NEUMANN = 1, GRF_BC_DIRICHLET = 2 };
  *             covariance is the method-of-images sum of the periodic one on
  *             the doubled grid).  TABULATED then gives S on the slot grid,
  *             [N_1]..[N_d] (field layout).
+ *   draw_order GRF_DRAW_COUNTER (0): each normal of the one-FFT algorithm is
+ *             addressed by its entry (tag 1), any order of work; or
+ *             GRF_DRAW_RECURSIVE (1): the normals are the sequence R() of the
+ *             recursive algorithm of Section 3 (exactly P draws per field),
+ *             draw j being the value of the field-shaped tag-3 noise at
+ *             row-major index j (grf_noise writes it; grf_sample_from_noise
+ *             takes it), so a sequential implementation of that algorithm fed
+ *             the same sequence gives the same field.  Order of the draws:
+ *             the entries with 1 <= k_d < N_d/2 (row-major, k_d fastest; real
+ *             then imaginary part), then the plane k_d = 0, then k_d = N_d/2,
+ *             each by the same rule over the axes before d; on axis 1 the
+ *             real entries k_1 = 0 and N_1/2 come last.  GRF_ALG_ONE_FFT with
+ *             periodic axes only; no adjoint (GRF_EUNSUPPORTED).
  */
 typedef struct {
   int32_t ndim;
@@ -132,7 +146,7 @@ typedef struct {
   int32_t reserved;
   const double* spectrum;
   int32_t bc[3];
-  int32_t reserved2;
+  int32_t draw_order;
 } grf_plan_desc;
 
 /* Create a plan: validates the description, builds float64 twiddle tables
@@ -199,7 +213,8 @@ enum {
   GRF_PASS_R2R_COL_GEN = 9,   /* reflecting boundaries: coefficients + cosine transform along axis 1 */
   GRF_PASS_R2R_COL_LOAD = 10, /* reflecting boundaries: cosine transform along the middle axis (d = 3) */
   GRF_PASS_R2R_ROW_LOAD = 11, /* reflecting boundaries: cosine transform along the last axis */
-  GRF_PASS_R2R_ROW_GEN = 12   /* reflecting boundaries, d = 1: coefficients + cosine transform of whole fields */
+  GRF_PASS_R2R_ROW_GEN = 12,  /* reflecting boundaries, d = 1: coefficients + cosine transform of whole fields */
+  GRF_PASS_COL_SEQ_INV = 13   /* as GRF_PASS_COL_GEN_INV, normals in the recursive algorithm's draw order */
 };
 grf_status grf_sample_stage_count(grf_plan plan, int64_t batch, int32_t* count);
 grf_status grf_sample_stage(grf_plan plan, int32_t stage, uint64_t seed, int64_t batch, const double* theta,
@@ -223,7 +238,8 @@ grf_status grf_covariance(grf_plan plan, uint64_t seed, int64_t nsamples, double
 
 /* Write the noise z of the contract for fields seed..seed+batch-1 (device,
  * same shape and dtype as the output; tag 0 two-FFT, 1 one-FFT, 2 reflecting
- * boundaries, where z is indexed by slot). */
+ * boundaries, where z is indexed by slot, 3 the recursive draw order, where
+ * z in row-major order is the sequence of draws). */
 grf_status grf_noise(grf_plan plan, uint64_t seed, int64_t batch, void* noise_out, void* stream);
 
 /* Adjoint of the one-FFT sampler.  Given the upstream gradient

@@ -18,4 +18,4 @@ from ._lib import (GRFError, grf_plan_create, grf_plan_destroy, grf_workspace_si
                    grf_last_error, grf_version, GRF_PASS_FUSED, GRF_PASS_COL_GEN_INV,
                    GRF_PASS_COL_LOAD_INV, GRF_PASS_COL_FILTER, GRF_PASS_ROW_C2R, GRF_PASS_ROW_R2C_GEN, GRF_PASS_ROW_GEN_C2R,
                    GRF_PASS_R2R_COL_GEN, GRF_PASS_R2R_COL_LOAD, GRF_PASS_R2R_ROW_LOAD, GRF_PASS_R2R_ROW_GEN,
-                   GRF_BC_PERIODIC, GRF_BC_NEUMANN, GRF_BC_DIRICHLET)
+                   GRF_BC_PERIODIC, GRF_BC_NEUMANN, GRF_BC_DIRICHLET, GRF_DRAW_COUNTER, GRF_DRAW_RECURSIVE)

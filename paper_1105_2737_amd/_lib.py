@@ -16,7 +16,9 @@ GRF_PASS_FUSED, GRF_PASS_COL_GEN_INV, GRF_PASS_COL_LOAD_INV, GRF_PASS_COL_LOAD_F
 GRF_PASS_COL_FILTER, GRF_PASS_COL_GRAD, GRF_PASS_ROW_C2R, GRF_PASS_ROW_R2C_GEN, GRF_PASS_ROW_R2C_LOAD = 3, 4, 5, 6, 7
 GRF_PASS_ROW_GEN_C2R = 8
 GRF_PASS_R2R_COL_GEN, GRF_PASS_R2R_COL_LOAD, GRF_PASS_R2R_ROW_LOAD, GRF_PASS_R2R_ROW_GEN = 9, 10, 11, 12
+GRF_PASS_COL_SEQ_INV = 13
 GRF_BC_PERIODIC, GRF_BC_NEUMANN, GRF_BC_DIRICHLET = 0, 1, 2
+GRF_DRAW_COUNTER, GRF_DRAW_RECURSIVE = 0, 1
 
 STATUS_NAMES = {0: "GRF_OK", -1: "GRF_EINVAL", -2: "GRF_ENOMEM", -3: "GRF_EDEVICE", -4: "GRF_EUNSUPPORTED"}
 
@@ -33,7 +35,7 @@ class grf_plan_desc(ctypes.Structure):
                 ("sigma", ctypes.c_double), ("length_scale", ctypes.c_double), ("nu", ctypes.c_double),
                 ("m", ctypes.c_double), ("k", ctypes.c_int32), ("l", ctypes.c_int32), ("n", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("spectrum", ctypes.c_void_p), ("bc", ctypes.c_int32 * 3),
-                ("reserved2", ctypes.c_int32)]
+                ("draw_order", ctypes.c_int32)]
 
 
 class grf_field_desc(ctypes.Structure):

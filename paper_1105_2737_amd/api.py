@@ -8,6 +8,7 @@ import torch
 
 from . import _lib as L
 
+DRAW_ORDERS = {"counter": L.GRF_DRAW_COUNTER, "recursive": L.GRF_DRAW_RECURSIVE}
 BOUNDARIES = {"periodic": L.GRF_BC_PERIODIC, "neumann": L.GRF_BC_NEUMANN, "dirichlet": L.GRF_BC_DIRICHLET}
 COV_KINDS = {"gaussian": L.GRF_COV_GAUSSIAN, "matern": L.GRF_COV_MATERN, "exponential": L.GRF_COV_EXPONENTIAL,
              "paper": L.GRF_COV_PAPER, "tabulated": L.GRF_COV_TABULATED}
@@ -36,10 +37,14 @@ class Plan:
     string for all axes or a sequence): the cosine / sine transform variant
     on the cell-centred grid of [0, l_i] (one-transform method only); a
     tabulated S then has the field's shape (the slot grid).
+    draw_order: 'counter' (default), or 'recursive': the normals in the draw
+    order of the recursive algorithm of Section 3, from one sequence per field
+    (plan.noise(seed) in row-major order; one-FFT, periodic).
     """
 
     def __init__(self, dims, lengths=None, alg=2, dtype=torch.float32, cov="matern", sigma=1.0,
-                 length_scale=0.1, nu=1.5, device=None, m=1.0, k=1, l=1, n=1, spectrum=None, boundary="periodic"):
+                 length_scale=0.1, nu=1.5, device=None, m=1.0, k=1, l=1, n=1, spectrum=None, boundary="periodic",
+                 draw_order="counter"):
         dims = tuple(int(n) for n in dims)
         lengths = tuple(float(v) for v in (lengths or (1.0,) * len(dims)))
         if len(lengths) != len(dims):
@@ -68,6 +73,7 @@ class Plan:
         for i, b in enumerate(bcs):
             d.bc[i] = BOUNDARIES[b]
         self.boundary = bcs
+        d.draw_order = DRAW_ORDERS[draw_order]
         self.reflect = any(b != "periodic" for b in bcs)
         spec = None
         if cov == "tabulated":

@@ -351,16 +351,19 @@ void chunk_passes(const grf_plan_s* p, uint64_t seed, const void* zsrc, long lon
     push(grf::PASS_R2R_ROW_LOAD, p->M, r);
     return;
   }
+  const bool seq = p->desc.draw_order == GRF_DRAW_RECURSIVE;
   if (p->d == 1) {
     // one launch: noise, filter and complex-to-real transform of whole fields
-    a.tag = 1;
+    a.tag = seq ? 3 : 1;
+    a.seq = seq;
     a.tw2 = p->tw_row;
     a.rows = nb;
     push(grf::PASS_ROW_GEN_C2R, p->M, a);
     return;
   }
   if (p->desc.alg == GRF_ALG_ONE_FFT) {
-    a.tag = 1;
+    a.tag = seq ? 3 : 1;
+    a.seq = seq;
     a.tw = p->tw_col1;
     if (p->d == 2) {
       a.stride_ax = p->M;
@@ -371,7 +374,7 @@ void chunk_passes(const grf_plan_s* p, uint64_t seed, const void* zsrc, long lon
       a.stride_fixed = p->M;
       a.nfixed = p->no;
     }
-    push(grf::PASS_COL_GEN_INV, p->n1, a);
+    push(seq ? grf::PASS_COL_SEQ_INV : grf::PASS_COL_GEN_INV, p->n1, a);
     if (p->d == 3) {
       Args m = a;
       m.src = nullptr;
@@ -412,7 +415,8 @@ std::vector<PassLaunch> sample_passes(const grf_plan_s* p, uint64_t seed, const 
   std::vector<PassLaunch> v;
   const long long C = chunk_fields(p, batch);
   const long long nch = (batch + C - 1) / C;
-  if (!p->reflect && p->desc.alg == GRF_ALG_ONE_FFT && p->d == 2 && fuse_enabled() && batch >= 2 &&
+  if (!p->reflect && p->desc.draw_order == GRF_DRAW_COUNTER && p->desc.alg == GRF_ALG_ONE_FFT && p->d == 2 &&
+      fuse_enabled() && batch >= 2 &&
       grf::fused_geom(p->dtype, p->n1, p->M).threads > 0) {
     // Fused chunk schedule: launch k runs the column generation pass of
     // chunk k and the last-axis pass of chunk k-1, so that the VALU-heavy and
@@ -629,7 +633,7 @@ bool row_length_supported(int M) {
 Geom pass_geom(int pass, int dtype, int L) {
   if (is_r2r_pass(pass)) return geom_r2r(pass, dtype, L);
   if (pass == PASS_ROW_GEN_C2R) return geom_gen1d(dtype, L);
-  if (pass >= PASS_ROW_C2R) return dtype == 0 ? geom_row_f32(pass, L) : geom_row_f64(pass, L);
+  if (is_row_pass(pass)) return dtype == 0 ? geom_row_f32(pass, L) : geom_row_f64(pass, L);
   return dtype == 0 ? geom_col_f32(pass, L) : geom_col_f64(pass, L);
 }
 
@@ -642,7 +646,7 @@ hipError_t launch_fused(int dtype, int L, int M, const Args& aA, const Args& aB,
 hipError_t launch_pass(int pass, int dtype, int L, const Args& a, long long nblocks, hipStream_t s) {
   if (is_r2r_pass(pass)) return launch_r2r(pass, dtype, L, a, nblocks, s);
   if (pass == PASS_ROW_GEN_C2R) return launch_gen1d(dtype, L, a, nblocks, nullptr, s);
-  if (pass >= PASS_ROW_C2R)
+  if (is_row_pass(pass))
     return dtype == 0 ? launch_row_f32(pass, L, a, nblocks, s) : launch_row_f64(pass, L, a, nblocks, s);
   return dtype == 0 ? launch_col_f32(pass, L, a, nblocks, s) : launch_col_f64(pass, L, a, nblocks, s);
 }
@@ -687,6 +691,10 @@ grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out) {
   const bool reflect = nreflect > 0;
   if (reflect && nreflect != d.ndim)
     return fail(GRF_EUNSUPPORTED, "periodic and reflecting axes cannot be mixed");
+  if (d.draw_order != GRF_DRAW_COUNTER && d.draw_order != GRF_DRAW_RECURSIVE)
+    return fail(GRF_EINVAL, "unknown draw order");
+  if (d.draw_order == GRF_DRAW_RECURSIVE && (reflect || d.alg != GRF_ALG_ONE_FFT))
+    return fail(GRF_EUNSUPPORTED, "the recursive draw order is that of the periodic one-FFT algorithm");
   if (reflect && d.alg != GRF_ALG_ONE_FFT)
     return fail(GRF_EUNSUPPORTED, "reflecting boundaries use the one-transform method (GRF_ALG_ONE_FFT)");
   if (d.alg == GRF_ALG_TWO_FFT && d.ndim != 2)
@@ -834,7 +842,8 @@ grf_status grf_covariance(grf_plan p, uint64_t seed, int64_t nsamples, double* c
     a.recs = p->rec_dev;
     a.rec_stride = 0;
     a.seed = seed;
-    a.tag = 1;
+    a.seq = p->desc.draw_order == GRF_DRAW_RECURSIVE;
+    a.tag = a.seq ? 3 : 1;
     a.tw2 = p->tw_row;
     a.rows = nsamples;
     a.htab = p->table_only ? p->htab : nullptr;
@@ -903,7 +912,7 @@ grf_status grf_noise(grf_plan p, uint64_t seed, int64_t batch, void* noise_out, 
   if (batch < 0) return fail(GRF_EINVAL, "negative batch");
   if (batch == 0) return GRF_OK;
   if (noise_out == nullptr) return fail(GRF_EINVAL, "null output");
-  const int tag = p->reflect ? 2 : (p->desc.alg == GRF_ALG_ONE_FFT ? 1 : 0);
+  const int tag = p->reflect ? 2 : p->desc.draw_order == GRF_DRAW_RECURSIVE ? 3 : (p->desc.alg == GRF_ALG_ONE_FFT ? 1 : 0);
   hipError_t e = grf::launch_noise(p->dtype, seed, tag, (int)(p->P / p->nd), p->nd, (int)batch, noise_out,
                                    (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "noise kernel");
@@ -914,8 +923,8 @@ grf_status grf_backward(grf_plan p, uint64_t seed, const void* noise, int64_t ba
                         const void* grad_out, double* grad_theta, void* grad_noise, void* workspace,
                         size_t workspace_bytes, void* stream) {
   if (p == nullptr) return fail(GRF_EINVAL, "null plan");
-  if (p->desc.alg != GRF_ALG_ONE_FFT || p->d != 2 || p->reflect)
-    return fail(GRF_EUNSUPPORTED, "adjoint implemented for the periodic one-FFT algorithm with d = 2");
+  if (p->desc.alg != GRF_ALG_ONE_FFT || p->d != 2 || p->reflect || p->desc.draw_order != GRF_DRAW_COUNTER)
+    return fail(GRF_EUNSUPPORTED, "adjoint implemented for the periodic one-FFT algorithm with d = 2 (counter draws)");
   if (batch < 0) return fail(GRF_EINVAL, "negative batch");
   if (batch == 0) return GRF_OK;
   if (grad_out == nullptr || grad_theta == nullptr) return fail(GRF_EINVAL, "null gradient pointer");

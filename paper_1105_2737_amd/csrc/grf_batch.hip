@@ -80,6 +80,10 @@ __device__ __forceinline__ Args batch_args(const BatchField& f, const BatchField
   a.rows_per_field = f.n1;
   a.tag = 1;
   a.order = 0;
+  a.tq = nullptr;
+  a.sine = 0;
+  a.bcmask = 0;
+  a.seq = 0;
   return a;
 }
 

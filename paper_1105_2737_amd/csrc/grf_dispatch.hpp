@@ -39,11 +39,13 @@ enum PassKind {
   PASS_R2R_COL_LOAD = GRF_PASS_R2R_COL_LOAD,   // reflecting: cosine transform, middle axis
   PASS_R2R_ROW_LOAD = GRF_PASS_R2R_ROW_LOAD,   // reflecting: cosine transform, last axis
   PASS_R2R_ROW_GEN = GRF_PASS_R2R_ROW_GEN,     // reflecting, d = 1: coefficients + cosine transform
+  PASS_COL_SEQ_INV = GRF_PASS_COL_SEQ_INV,     // as PASS_COL_GEN_INV, normals in the recursive draw order
 };
 
-inline bool is_r2r_pass(int p) { return p >= PASS_R2R_COL_GEN; }
+inline bool is_r2r_pass(int p) { return p >= PASS_R2R_COL_GEN && p <= PASS_R2R_ROW_GEN; }
 // passes that take rows (last axis) rather than column tiles
 inline bool is_row_pass(int p) {
+  if (p == PASS_COL_SEQ_INV) return false;
   return is_r2r_pass(p) ? (p == PASS_R2R_ROW_LOAD || p == PASS_R2R_ROW_GEN) : p >= PASS_ROW_C2R;
 }
 

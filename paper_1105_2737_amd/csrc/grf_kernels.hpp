@@ -55,6 +55,7 @@ struct Args {
   const void* tq;             // (1/2) e^{i pi k / (2N)}, k < N (column) or k <= N/2 (row), of the pass's axis
   int sine;                   // the pass's axis is a sine axis (output sign (-1)^j)
   int bcmask;                 // sine axes: bit 0 axis 1, bit 1 middle axis, bit 2 last axis
+  int seq;                    // 1: normals in the draw order of the recursive algorithm (seq_draw)
 };
 
 // Tile index of this workgroup in a column pass.  Workgroups are dispatched to
@@ -202,10 +203,100 @@ __device__ __forceinline__ void load_z4(const Args& a, const T* zsrc, int b, int
   }
 }
 
+// The recursive algorithm of Section 3 draws its P normals from one sequence
+// per field: the entries with 1 <= k_d < N_d/2 first (two draws each,
+// real and imaginary part; row-major, the last-axis index fastest), then the
+// plane k_d = 0 and then the plane k_d = N_d/2, each by the same rule one
+// dimension lower; on axis 1 the last two draws are the real entries
+// k_1 = 0 and k_1 = N_1/2.  seq_draw gives the first draw j of entry
+// (k1, o, m) of the half-spectrum and whether the entry is set directly
+// (kind 0: A = (z_j + i z_{j+1}) h / sqrt 2), is the mirror of such an entry
+// (kind 1: the conjugate) or is real (kind 2: A = z_j h).  Draw j of the
+// sequence is the noise value at row j / N_d, last-axis index j mod N_d.
+struct SeqDraw {
+  long long j;
+  int kind;
+};
+
+__device__ __forceinline__ SeqDraw seq_draw(const Args& a, int k1, int o, int m) {
+  const long long R = (long long)a.n1 * a.no;
+  const int M = a.M;
+  if (m >= 1 && m < M) return SeqDraw{2 * ((long long)(k1 * a.no + o) * (M - 1) + (m - 1)), 0};
+  long long off = 2 * R * (M - 1) + (m == M ? R : 0);
+  if (a.no > 1) {   // d = 3: the middle axis, axis 1 before it
+    const int Mo = a.no / 2;
+    if (o >= 1 && o < Mo) return SeqDraw{off + 2 * ((long long)k1 * (Mo - 1) + (o - 1)), 0};
+    if (o > Mo) return SeqDraw{off + 2 * ((long long)((a.n1 - k1) % a.n1) * (Mo - 1) + (a.no - o - 1)), 1};
+    off += 2LL * a.n1 * (Mo - 1) + (o == Mo ? a.n1 : 0);
+  }
+  if (a.n1 > 1) {   // axis 1
+    const int M1 = a.n1 / 2;
+    if (k1 >= 1 && k1 < M1) return SeqDraw{off + 2 * (k1 - 1), 0};
+    if (k1 > M1) return SeqDraw{off + 2 * (a.n1 - k1 - 1), 1};
+    off += 2 * (M1 - 1) + (k1 == M1 ? 1 : 0);
+  }
+  return SeqDraw{off, 2};
+}
+
+// Draws j & ~1 and (j & ~1) + 1 of field b's sequence: one Box-Muller pair of
+// the Philox block that holds them, or the given noise array.
+template <typename T, bool UNIFORM_KEY>
+__device__ __forceinline__ void seq_pair(const Args& a, const T* zsrc, int b, long long j, uint32_t k0, uint32_t k1,
+                                         T& x, T& y) {
+  j &= ~1LL;
+  if (zsrc != nullptr) {
+    const T* p = zsrc + (long long)b * a.field_stride * 2 + j;
+    x = p[0];
+    y = p[1];
+    return;
+  }
+  const long long row = j / a.nd;
+  const int s = (int)(j - row * a.nd);
+  const uint4 r = philox4x32_10<UNIFORM_KEY>(make_uint4((uint32_t)(s >> 2), (uint32_t)row, (uint32_t)a.tag, 0u), k0, k1);
+  if (s & 2)
+    box_muller(r.z, r.w, x, y);
+  else
+    box_muller(r.x, r.y, x, y);
+}
+
+// A of entry (k1, o, m) in the draw order of the recursive algorithm, h given.
 template <typename T>
+__device__ __forceinline__ C<T> seq_entry(const Args& a, const T* zsrc, int b, uint32_t k0, uint32_t k1, int kk1,
+                                          int o, int m, T h) {
+  const SeqDraw d = seq_draw(a, kk1, o, m);
+  T x, y;
+  seq_pair<T, true>(a, zsrc, b, d.j, k0, k1, x, y);
+  const T s = (T)0.70710678118654752440;
+  if (d.kind == 2) return mk<T>(h * ((d.j & 1) ? y : x), (T)0);
+  const T g = h * s;
+  return mk<T>(g * x, d.kind == 1 ? -(g * y) : g * y);
+}
+
+// SEQ: the normals in the draw order of the recursive algorithm (its own
+// kernel instantiation, so that the default route keeps its registers).
+template <typename T, bool SEQ = false>
 __device__ __forceinline__ void gen_pair(const Args& a, const Filt<T>& f, const T* zsrc, int b, uint32_t k0,
                                          uint32_t k1, int kk1, int o, int m0, C<T>& A0, C<T>& A1) {
   const int row = kk1 * a.no + o;
+  if constexpr (SEQ) {
+    const T* hr = a.htab ? (const T*)a.htab + (long long)row * (a.M + 2) : nullptr;
+    T p2b = 0, il2d = 0;
+    if (!hr) {
+      const int q1 = wrapk(kk1, a.n1), qo = wrapk(o, a.no);
+      p2b = (T)(q1 * q1) * (T)a.il2[0] + (T)(qo * qo) * (T)a.il2[1];
+      il2d = (T)a.il2[2];
+    }
+    auto hv = [&](int m) -> T { return hr ? hr[m] : filt_h(f, p2b + (T)(m * m) * il2d); };
+    A1 = (m0 + 1 < a.M) ? seq_entry<T>(a, zsrc, b, k0, k1, kk1, o, m0 + 1, hv(m0 + 1)) : mk<T>((T)0, (T)0);
+    if (m0 > 0) {
+      A0 = seq_entry<T>(a, zsrc, b, k0, k1, kk1, o, m0, hv(m0));
+    } else {
+      const C<T> az = seq_entry<T>(a, zsrc, b, k0, k1, kk1, o, 0, hv(0));
+      const C<T> an = seq_entry<T>(a, zsrc, b, k0, k1, kk1, o, a.M, hv(a.M));
+      A0 = mk<T>(az.x - an.y, az.y + an.x);   // A(k, 0) + i A(k, N_d/2)
+    }
+    return;
+  }
   T z[4];
   load_z4<T>(a, zsrc, b, row, m0, k0, k1, z);
   const T s = (T)0.70710678118654752440;
@@ -327,7 +418,8 @@ struct TwFill {
 
 // ---------------------------------------------------------------------------
 // Column pass over a leading axis.
-enum { SRC_GEN = 0, SRC_LOAD = 1 };
+// SRC_SEQ: generation with the normals in the recursive algorithm's draw order.
+enum { SRC_GEN = 0, SRC_LOAD = 1, SRC_SEQ = 2 };
 
 template <typename T, int L, class Rad, int CP, int PAD, int SRC, int DIR>
 struct ColPass {
@@ -415,14 +507,15 @@ struct ColPass {
     }
     for (int i = tid; i < L; i += blockDim.x) tw[i] = ((const V*)a.tw)[i];
     if (act) {
-      if constexpr (SRC == SRC_GEN) {
+      if constexpr (SRC == SRC_GEN || SRC == SRC_SEQ) {
         const FieldRec& rec = a.recs[b * a.rec_stride];
         const Filt<T> f = load_filt<T>(rec, a.scale);
         const unsigned long long key = a.seed + (unsigned long long)b;
         const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
         const T* zsrc = (const T*)a.src;
 #pragma unroll
-        for (int m = 0; m < R0; ++m) gen_pair<T>(a, f, zsrc, b, k0, k1, t + m * NT, fx, m0, x[0][m], x[1][m]);
+        for (int m = 0; m < R0; ++m)
+          gen_pair<T, SRC == SRC_SEQ>(a, f, zsrc, b, k0, k1, t + m * NT, fx, m0, x[0][m], x[1][m]);
       } else {
 #pragma unroll
         for (int m = 0; m < R0; ++m)

@@ -58,9 +58,24 @@ struct Gen1D {
       // h from the plan's table (families given by their density) or on the fly
       const T* ht = (const T*)a.htab;
       auto hk = [&](int k) -> T { return ht ? ht[k] : filt_h(f, (T)(k * k) * il2); };
+      E* row = sm + rr * RL::STRIDE;
+      if (a.seq) {
+        // draw order of the recursive algorithm: block q holds draws 4q .. 4q+3,
+        // i.e. entries 2q+1 and 2q+2 (real and imaginary parts), or for the
+        // last block the real entries 0 and M (draws N - 2, N - 1)
+        const int ka = 2 * q + 1, kb = 2 * q + 2;
+        const T ha = hk(ka);
+        row[RL::idx(ka)].v[0] = mk<T>(ha * s * z[0], ha * s * z[1]);
+        if (kb < M) {
+          const T hb = hk(kb);
+          row[RL::idx(kb)].v[0] = mk<T>(hb * s * z[2], hb * s * z[3]);
+        } else {
+          row[0].v[0] = mk<T>(hk(0) * z[2], hk(M) * z[3]);
+        }
+        continue;
+      }
       const int k1 = 2 * q + 1;
       const T h1 = hk(k1);
-      E* row = sm + rr * RL::STRIDE;
       row[RL::idx(k1)].v[0] = mk<T>(h1 * s * z[2], h1 * s * z[3]);
       const int k0 = 2 * q;
       if (k0 > 0) {

@@ -85,6 +85,9 @@ def _desc(**kw):
     (dict(bc=(1, 0)), -4),                           # periodic and reflecting axes mixed
     (dict(ndim=3, dims=(16, 16, 16), bc=(2, 0, 2)), -4),
     (dict(alg=1, bc=(1, 1)), -4),                    # reflecting: one-transform method only
+    (dict(draw_order=2), -1),                        # unknown draw order
+    (dict(draw_order=1, alg=1), -4),                 # recursive order: one-FFT algorithm only
+    (dict(draw_order=1, bc=(2, 2)), -4),             # and periodic axes
 ])
 def test_invalid_descriptors_are_rejected_on_the_host(kw, status):
     from paper_1105_2737_amd import _lib as L
