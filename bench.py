@@ -431,6 +431,28 @@ def main():
             torch.cuda.empty_cache()
         extra["reflecting_boundaries"] = refl
 
+        # the recursive algorithm's draw order (Section 3): each entry computes the
+        # index of its draws in the field's sequence; headline grid and batch, and 256^3
+        rec = {}
+        for rdims, rb, rfam in (((512, 512), batch, dict(cov="matern", sigma=1.0, length_scale=0.1, nu=1.5)),
+                                ((256, 256, 256), 16, dict(cov="exponential", sigma=1.0, length_scale=0.05))):
+            orc = torch.empty((rb,) + rdims, dtype=torch.float32, device="cuda")
+            npts = orc.numel()
+            pq = grf.Plan(rdims, alg=2, dtype=torch.float32, draw_order="recursive", **rfam)
+            sq = timed(lambda: pq.sample(seed=0, batch=rb, out=orc), max(args.steps // 5, 5), max(args.warmup // 5, 2), torch)
+            pq64 = grf.Plan(rdims, alg=2, dtype=torch.float64, draw_order="recursive", **rfam)
+            eq = []
+            for b in (0, rb - 1):
+                f64 = pq64.sample(seed=b, batch=1)[0]
+                eq.append(float((orc[b].double() - f64).abs().max() / f64.abs().max()))
+            key = "x".join(str(v) for v in rdims) + f"_x{rb}"
+            rec[key] = {"points_per_s": round(npts / sq, 1), "ms_per_step": round(sq * 1e3, 4),
+                        "max_rel_err_vs_fp64": max(eq), "error_fields": [0, rb - 1],
+                        "passes": kind_rows(by_kind(launch_table(pq, rb, torch, grf, 5), (npts // rb) * 4))}
+            del pq, pq64, f64, orc
+            torch.cuda.empty_cache()
+        extra["recursive_draw_order"] = rec
+
         # d = 1: sampling throughput (65536 fields of 4096 points, 1 GiB written) and the
         # convergence study of Section 4 (10^8 samples per grid, n = 2..12, estimator fused
         # into the sampler)

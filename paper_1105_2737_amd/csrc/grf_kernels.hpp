@@ -21,9 +21,23 @@
 //   row  : last-axis complex-to-real (inverse) or real-to-complex (forward,
 //          with noise generation or a global load), one row per NT threads.
 #pragma once
+#include <utility>
+
 #include "grf_device.hpp"
 
 namespace grf {
+
+// f(std::integral_constant<int, i>) for i = 0 .. N-1, unrolled by construction
+// (for loop bodies too large for the unroller, whose array indices must stay
+// static so that the arrays stay in registers).
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 template <typename T, int NC> struct alignas(sizeof(C<T>) * NC) Vec { C<T> v[NC]; };
 
@@ -513,9 +527,15 @@ struct ColPass {
         const unsigned long long key = a.seed + (unsigned long long)b;
         const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
         const T* zsrc = (const T*)a.src;
+        if constexpr (SRC == SRC_SEQ) {
+          static_for<R0>([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            gen_pair<T, true>(a, f, zsrc, b, k0, k1, t + m * NT, fx, m0, x[0][m], x[1][m]);
+          });
+        } else {
 #pragma unroll
-        for (int m = 0; m < R0; ++m)
-          gen_pair<T, SRC == SRC_SEQ>(a, f, zsrc, b, k0, k1, t + m * NT, fx, m0, x[0][m], x[1][m]);
+          for (int m = 0; m < R0; ++m) gen_pair<T>(a, f, zsrc, b, k0, k1, t + m * NT, fx, m0, x[0][m], x[1][m]);
+        }
       } else {
 #pragma unroll
         for (int m = 0; m < R0; ++m)
