@@ -146,9 +146,26 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 long long chunk_fields(const grf_plan_s* p, long long batch);
 
 // Workspace layout: [records][partials][spectrum of one chunk of fields]
+// [d = 3 adjoint: plane values Z of one chunk]
 struct WsLayout {
-  size_t recs, partial, spec, total;
+  size_t recs, partial, spec, plane, total;
 };
+
+// Adjoint: workgroups of the reduction pass per field (each leaves three
+// partial sums) and, for d = 1, 2, its column tiles.
+struct AdjTiles {
+  int ntile;     // tiles per fixed index (d = 2, 3) or per field (d = 1)
+  int nper;      // partial sums per field / 3
+};
+AdjTiles adj_tiles(const grf_plan_s* p) {
+  if (p->d == 1) {
+    const int nt = (p->M / 2 + 255) / 256;
+    return AdjTiles{nt, nt};
+  }
+  const grf::Geom g = grf::pass_geom(p->d == 3 ? grf::PASS_COL_GRAD3 : grf::PASS_COL_GRAD, p->dtype, p->n1);
+  const int nt = (p->M + 2 * g.per_wg - 1) / (2 * g.per_wg);
+  return AdjTiles{nt, nt * p->no};
+}
 
 WsLayout ws_layout(const grf_plan_s* p, long long batch, int op) {
   WsLayout w{};
@@ -156,13 +173,15 @@ WsLayout ws_layout(const grf_plan_s* p, long long batch, int op) {
   size_t off = align256((size_t)batch * sizeof(FieldRec));
   w.partial = off;
   if (op == GRF_OP_BACKWARD) {
-    const grf::Geom g = grf::pass_geom(grf::PASS_COL_GRAD, p->dtype, p->n1);
-    const long long ntile = (p->M + 2 * g.per_wg - 1) / (2 * g.per_wg);
-    off += align256((size_t)batch * ntile * 3 * sizeof(double));
+    off += align256((size_t)batch * adj_tiles(p).nper * 3 * sizeof(double));
     w.spec = off;
-    off += align256((size_t)chunk_fields(p, batch) * p->P * p->esz);
+    const long long C = chunk_fields(p, batch);
+    off += align256((size_t)C * p->P * p->esz);
+    w.plane = off;
+    if (p->d == 3) off += align256((size_t)C * p->n1 * p->no * 2 * p->esz);
   } else {
     w.spec = off;
+    w.plane = off;
   }
   w.total = off;
   return w;
@@ -923,8 +942,8 @@ grf_status grf_backward(grf_plan p, uint64_t seed, const void* noise, int64_t ba
                         const void* grad_out, double* grad_theta, void* grad_noise, void* workspace,
                         size_t workspace_bytes, void* stream) {
   if (p == nullptr) return fail(GRF_EINVAL, "null plan");
-  if (p->desc.alg != GRF_ALG_ONE_FFT || p->d != 2 || p->reflect || p->desc.draw_order != GRF_DRAW_COUNTER)
-    return fail(GRF_EUNSUPPORTED, "adjoint implemented for the periodic one-FFT algorithm with d = 2 (counter draws)");
+  if (p->desc.alg != GRF_ALG_ONE_FFT || p->reflect || p->desc.draw_order != GRF_DRAW_COUNTER)
+    return fail(GRF_EUNSUPPORTED, "adjoint implemented for the periodic one-FFT algorithm (counter draws)");
   if (batch < 0) return fail(GRF_EINVAL, "negative batch");
   if (batch == 0) return GRF_OK;
   if (grad_out == nullptr || grad_theta == nullptr) return fail(GRF_EINVAL, "null gradient pointer");
@@ -939,11 +958,11 @@ grf_status grf_backward(grf_plan p, uint64_t seed, const void* noise, int64_t ba
   int rstride;
   st = field_records(p, theta, batch, ws + w.recs, w.partial, s, &recs, &rstride);
   if (st != GRF_OK) return st;
-  // G = F[g]: last axis real-to-complex, then axis 1 forward inside the
-  // reduction pass; chunk by chunk (cache-sized, as the sampler), so that the
-  // reduction pass reads the chunk's spectrum from the last-level cache
-  const grf::Geom g = grf::pass_geom(grf::PASS_COL_GRAD, p->dtype, p->n1);
-  const int ntile = (p->M + 2 * g.per_wg - 1) / (2 * g.per_wg);
+  // G = F[g]: last axis real-to-complex, (d = 3: middle axis forward,) then
+  // axis 1 forward inside the reduction pass (d = 1: the reduction reads the
+  // last-axis spectrum); chunk by chunk (cache-sized, as the sampler), so that
+  // each pass reads the previous one's output from the last-level cache
+  const AdjTiles at = adj_tiles(p);
   const long long C = chunk_fields(p, batch);
   const size_t fbytes = (size_t)p->P * p->esz;
   for (long long c0 = 0; c0 < batch; c0 += C) {
@@ -952,7 +971,7 @@ grf_status grf_backward(grf_plan p, uint64_t seed, const void* noise, int64_t ba
     r.data = ws + w.spec;
     r.src = (const char*)grad_out + c0 * fbytes;
     r.tw2 = p->tw_row;
-    r.rows = nb * (long long)p->n1;
+    r.rows = nb * (p->P / p->nd);
     st = run_pass(p, grf::PASS_ROW_R2C_LOAD, p->M, r, 0, nb, s);
     if (st != GRF_OK) return st;
     Args c = base_args(p, nb);
@@ -964,15 +983,36 @@ grf_status grf_backward(grf_plan p, uint64_t seed, const void* noise, int64_t ba
     c.data = ws + w.spec;
     c.src = noise ? (const char*)noise + c0 * fbytes : nullptr;
     c.aux = grad_noise ? (char*)grad_noise + c0 * fbytes : nullptr;
-    c.partial = (double*)(ws + w.partial) + c0 * ntile * 3;
+    c.partial = (double*)(ws + w.partial) + c0 * at.nper * 3;
+    if (p->d == 1) {
+      c.ntile = at.ntile;
+      hipError_t e = grf::launch_grad1d(p->dtype, c, nb * at.ntile, s);
+      if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+      continue;
+    }
+    if (p->d == 3) {
+      Args m = base_args(p, nb);
+      m.data = ws + w.spec;
+      m.tw = p->tw_col2;
+      m.stride_ax = p->M;
+      m.stride_fixed = (long long)p->no * p->M;
+      m.nfixed = p->n1;
+      st = run_pass(p, grf::PASS_COL_LOAD_FWD, p->no, m, 0, nb, s);
+      if (st != GRF_OK) return st;
+      c.plane = grad_noise ? ws + w.plane : nullptr;
+    }
     c.tw = p->tw_col1;
-    c.stride_ax = p->M;
+    c.stride_ax = (long long)p->no * p->M;
     c.stride_fixed = p->M;
-    c.nfixed = 1;
-    st = run_pass(p, grf::PASS_COL_GRAD, p->n1, c, 0, nb, s);
+    c.nfixed = p->no;
+    st = run_pass(p, p->d == 3 ? grf::PASS_COL_GRAD3 : grf::PASS_COL_GRAD, p->n1, c, 0, nb, s);
     if (st != GRF_OK) return st;
+    if (p->d == 3 && grad_noise) {
+      hipError_t e = grf::launch_grad_plane(p->dtype, c, s);
+      if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+    }
   }
-  hipError_t e = grf::launch_reduce_partials((const double*)(ws + w.partial), (int)batch, ntile, grad_theta, s);
+  hipError_t e = grf::launch_reduce_partials((const double*)(ws + w.partial), (int)batch, at.nper, grad_theta, s);
   if (e != hipSuccess) return hip_fail(e, "reduction");
   return GRF_OK;
 }

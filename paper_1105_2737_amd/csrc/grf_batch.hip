@@ -84,6 +84,7 @@ __device__ __forceinline__ Args batch_args(const BatchField& f, const BatchField
   a.sine = 0;
   a.bcmask = 0;
   a.seq = 0;
+  a.plane = nullptr;
   return a;
 }
 

@@ -40,13 +40,14 @@ enum PassKind {
   PASS_R2R_ROW_LOAD = GRF_PASS_R2R_ROW_LOAD,   // reflecting: cosine transform, last axis
   PASS_R2R_ROW_GEN = GRF_PASS_R2R_ROW_GEN,     // reflecting, d = 1: coefficients + cosine transform
   PASS_COL_SEQ_INV = GRF_PASS_COL_SEQ_INV,     // as PASS_COL_GEN_INV, normals in the recursive draw order
+  PASS_COL_GRAD3 = 100,                        // PASS_COL_GRAD for d = 3 (internal: adjoint only)
 };
 
 inline bool is_r2r_pass(int p) { return p >= PASS_R2R_COL_GEN && p <= PASS_R2R_ROW_GEN; }
 // passes that take rows (last axis) rather than column tiles
 inline bool is_row_pass(int p) {
-  if (p == PASS_COL_SEQ_INV) return false;
-  return is_r2r_pass(p) ? (p == PASS_R2R_ROW_LOAD || p == PASS_R2R_ROW_GEN) : p >= PASS_ROW_C2R;
+  return p == PASS_ROW_C2R || p == PASS_ROW_R2C_GEN || p == PASS_ROW_R2C_LOAD || p == PASS_ROW_GEN_C2R ||
+         p == PASS_R2R_ROW_LOAD || p == PASS_R2R_ROW_GEN;
 }
 
 // Workgroup geometry of a pass at a given length (for grid sizing).
@@ -123,6 +124,11 @@ grf_status build_filter_table(int dtype, Args a, double scale, void** out);
 hipError_t launch_prep_recs(const double* theta, int batch, int kind, int d, double vol, FieldRec* out, int* err,
                             hipStream_t s);
 hipError_t launch_reduce_partials(const double* partial, int batch, int nper, double* grad, hipStream_t s);
+// Adjoint helpers: d = 1 reduction over the last-axis spectrum (nblocks =
+// a.batch * a.ntile workgroups of 256 threads, one Philox block per thread),
+// and the d = 3 noise gradient of the planes k_d = 0, N_d/2 from a.plane.
+hipError_t launch_grad1d(int dtype, const Args& a, long long nblocks, hipStream_t s);
+hipError_t launch_grad_plane(int dtype, const Args& a, hipStream_t s);
 hipError_t launch_philox_raw(unsigned long long seed, const uint32_t* ctr, long long n, uint32_t* out, hipStream_t s);
 hipError_t launch_noise(int dtype, unsigned long long seed, int tag, int rows, int nd, int batch, void* out,
                         hipStream_t s);

@@ -70,6 +70,7 @@ struct Args {
   int sine;                   // the pass's axis is a sine axis (output sign (-1)^j)
   int bcmask;                 // sine axes: bit 0 axis 1, bit 1 middle axis, bit 2 last axis
   int seq;                    // 1: normals in the draw order of the recursive algorithm (seq_draw)
+  void* plane;                // 3D adjoint: Z = G(k, 0) + i G(k, N_d/2) per (field, row), or null
 };
 
 // Tile index of this workgroup in a column pass.  Workgroups are dispatched to
@@ -638,13 +639,92 @@ k_colf(Args a) {
 }
 
 // ---------------------------------------------------------------------------
+// One entry's term of the adjoint reduction: entry k adds
+// c = w (h/2) Re(xi conj G) times d log S / d theta at its squared frequency
+// p2 (d log S / d sigma = gs is applied once per workgroup).  Float32 plans
+// form c and d log S in float32 (hardware log2 and reciprocal) and sum in
+// float64; float64 plans do everything in float64.  The record's constants
+// are copied into registers (stores of dL/dz could alias the record, which
+// would otherwise force a reload per entry).
+template <typename T>
+struct AdjAcc {
+  bool gauss, has_nu;
+  double ra, rb, gl0, gl1, gn0, gn1;
+  float raf, rbf, gl0f, gl1f, gn0f, gn1f;
+  double acc0 = 0, acc1 = 0, acc2 = 0;
+  __device__ __forceinline__ explicit AdjAcc(const FieldRec& rec)
+      : gauss(rec.kind == COV_GAUSSIAN), has_nu(rec.has_nu != 0), ra(rec.a), rb(rec.b), gl0(rec.gl0),
+        gl1(rec.gl1), gn0(rec.gn0), gn1(rec.gn1), raf((float)ra), rbf((float)rb), gl0f((float)gl0),
+        gl1f((float)gl1), gn0f((float)gn0), gn1f((float)gn1) {}
+  __device__ __forceinline__ void add(double w, double h, double p2, C<T> xi, C<T> G) {
+    if constexpr (sizeof(T) == 4) {
+      const float pf = (float)p2;
+      float dl, dn = 0.0f;
+      if (gauss) {
+        dl = fmaf(gl1f, pf, gl0f);
+      } else {
+        const float u = fmaf(rbf, pf, raf);
+        const float iu = __builtin_amdgcn_rcpf(u);
+        dl = fmaf(gl1f, iu, gl0f);
+        if (has_nu) dn = gn0f - __builtin_amdgcn_logf(u) * 0.693147180559945309f - gn1f * iu;
+      }
+      const float c = (float)w * 0.5f * (float)h * fmaf((float)xi.x, (float)G.x, (float)xi.y * (float)G.y);
+      acc0 += (double)c;
+      acc1 += (double)(c * dl);
+      acc2 += (double)(c * dn);
+    } else {
+      double dl, dn = 0.0;
+      if (gauss) {
+        dl = gl0 + gl1 * p2;
+      } else {
+        const double u = ra + rb * p2;
+        const double iu = 1.0 / u;
+        dl = gl0 + gl1 * iu;
+        if (has_nu) dn = gn0 - log(u) - gn1 * iu;
+      }
+      const double c = w * 0.5 * h * ((double)xi.x * (double)G.x + (double)xi.y * (double)G.y);
+      acc0 += c;
+      acc1 += c * dl;
+      acc2 += c * dn;
+    }
+  }
+  // float32: two entries with their c = w (h/2) Re(xi conj G) already formed,
+  // at squared frequencies pf1 and pf0, one float64 add per sum
+  __device__ __forceinline__ void add2f(float pf1, float pf0, float c1, float c0) {
+    float dl1, dl0, dn1 = 0.0f, dn0 = 0.0f;
+    if (gauss) {
+      dl1 = fmaf(gl1f, pf1, gl0f);
+      dl0 = fmaf(gl1f, pf0, gl0f);
+    } else {
+      const float u1 = fmaf(rbf, pf1, raf), u0 = fmaf(rbf, pf0, raf);
+      const float iu1 = __builtin_amdgcn_rcpf(u1), iu0 = __builtin_amdgcn_rcpf(u0);
+      dl1 = fmaf(gl1f, iu1, gl0f);
+      dl0 = fmaf(gl1f, iu0, gl0f);
+      if (has_nu) {
+        dn1 = gn0f - __builtin_amdgcn_logf(u1) * 0.693147180559945309f - gn1f * iu1;
+        dn0 = gn0f - __builtin_amdgcn_logf(u0) * 0.693147180559945309f - gn1f * iu0;
+      }
+    }
+    acc0 += (double)(c1 + c0);
+    acc1 += (double)fmaf(c1, dl1, c0 * dl0);
+    acc2 += (double)fmaf(c1, dn1, c0 * dn0);
+  }
+};
+
+// ---------------------------------------------------------------------------
 // Adjoint of the one-FFT algorithm, column stage (d = 2): forward transform of
 // the row-transformed upstream gradient along axis 1 gives G = F[g]; each
 // entry then regenerates its noise xi and adds
 //   w_k (h_k / 2) dlogS/dtheta Re(xi_k conj G_k)
 // (w = 2 for interior columns, 1 in the two planes) to per-workgroup float64
 // partial sums; dL/dz is written through the Hermitian arrangement if asked.
-template <typename T, int L, class Rad, int CP, int PAD>
+// D3 (d = 3): the tiles also run over the middle index fx, and the packed
+// slot Z = G(k, 0) + i G(k, N_d/2) of the planes is used as it is:
+// sum_k Re(xi0 conj G0) = sum_k Re(xi0 conj Z) and sum_k Re(xiM conj GM) =
+// sum_k Re(i xiM conj Z), because xi0, xiM are Hermitian and h, S even, so no
+// partner column (-k lies in another workgroup's tile) is needed; dL/dz of
+// the plane slots needs it, so Z is stored to a.plane for k_grad_plane.
+template <typename T, int L, class Rad, int CP, int PAD, bool D3 = false>
 __global__ void __launch_bounds__(((L / Rad::get(0)) * CP + 63) / 64 * 64)
 k_colg(Args a) {
   using V = C<T>;
@@ -662,13 +742,17 @@ k_colg(Args a) {
   const int t = tid / CP;
   int bid = col_block(a.order);
   const int tile = bid % a.ntile;
-  const int b = bid / a.ntile;
+  const int fx = D3 ? (bid / a.ntile) % a.nfixed : 0;
+  const int b = D3 ? bid / a.ntile / a.nfixed : bid / a.ntile;
   for (int i = tid; i < L; i += blockDim.x) tw[i] = ((const V*)a.tw)[i];
   const int m0 = (tile * CP + cp) * 2;
   const bool act = (t < NT) && (m0 < a.M);
   const bool two = (m0 + 1) < a.M;
   const bool al = (a.M & 1) == 0;
-  V* base = (V*)a.data + (long long)b * a.field_stride + m0;
+  V* base = (V*)a.data + (long long)b * a.field_stride + (D3 ? (long long)fx * a.stride_fixed : 0LL) + m0;
+  // noise / table row of axis-1 index k, and the middle axis's share of p^2
+  auto rowof = [&](int k) -> int { return D3 ? k * a.no + fx : k; };
+  const double p2o = D3 ? (double)(wrapk(fx, a.no) * wrapk(fx, a.no)) * a.il2[1] : 0.0;
   V x[2][EN::REG];
   // Straight-line route for the common case (generated noise, filter table,
   // a column pair away from the packed plane slot): the filter-table loads of
@@ -693,90 +777,35 @@ k_colg(Args a) {
     T* gz = (T*)a.aux;
     const double il2d = a.il2[2];
     const T s2 = (T)1.4142135623730950488;
-    // Entry k adds c = w (h/2) Re(xi conj G) times d log S / d theta at its
-    // squared frequency p2 (dlogS/dsigma = gs is applied once per workgroup).
-    // float32 plans form c and d log S in float32 (hardware log2 and
-    // reciprocal) and sum in float64; float64 plans do everything in float64.
     // the record's constants in registers (the stores of dL/dz below could
     // alias it, which would otherwise force a reload per entry)
-    const bool gauss = rec.kind == COV_GAUSSIAN, has_nu = rec.has_nu != 0;
-    const double ra = rec.a, rb = rec.b, gl0 = rec.gl0, gl1 = rec.gl1, gn0 = rec.gn0, gn1 = rec.gn1;
-    const float raf = (float)ra, rbf = (float)rb, gl0f = (float)gl0, gl1f = (float)gl1, gn0f = (float)gn0,
-                gn1f = (float)gn1;
-    auto add = [&](double w, double h, double p2, V xi, V G) {
-      if constexpr (sizeof(T) == 4) {
-        const float pf = (float)p2;
-        float dl, dn = 0.0f;
-        if (gauss) {
-          dl = fmaf(gl1f, pf, gl0f);
-        } else {
-          const float u = fmaf(rbf, pf, raf);
-          const float iu = __builtin_amdgcn_rcpf(u);
-          dl = fmaf(gl1f, iu, gl0f);
-          if (has_nu) dn = gn0f - __builtin_amdgcn_logf(u) * 0.693147180559945309f - gn1f * iu;
-        }
-        const float c = (float)w * 0.5f * (float)h * fmaf((float)xi.x, (float)G.x, (float)xi.y * (float)G.y);
-        acc0 += (double)c;
-        acc1 += (double)(c * dl);
-        acc2 += (double)(c * dn);
-      } else {
-        double dl, dn = 0.0;
-        if (gauss) {
-          dl = gl0 + gl1 * p2;
-        } else {
-          const double u = ra + rb * p2;
-          const double iu = 1.0 / u;
-          dl = gl0 + gl1 * iu;
-          if (has_nu) dn = gn0 - log(u) - gn1 * iu;
-        }
-        const double c = w * 0.5 * h * ((double)xi.x * (double)G.x + (double)xi.y * (double)G.y);
-        acc0 += c;
-        acc1 += c * dl;
-        acc2 += c * dn;
-      }
-    };
+    AdjAcc<T> ad(rec);
+    auto add = [&](double w, double h, double p2, V xi, V G) { ad.add(w, h, p2, xi, G); };
     const T s = (T)0.70710678118654752440;
     if (straight) {
       struct alignas(2 * sizeof(T)) P2 { T x, y; };
 #pragma unroll 2
       for (int m = 0; m < R0; ++m) {
-        const P2 hq = *reinterpret_cast<const P2*>((const T*)a.htab + (long long)(t + m * NT) * (a.M + 2) + m0);
+        const P2 hq = *reinterpret_cast<const P2*>((const T*)a.htab + (long long)rowof(t + m * NT) * (a.M + 2) + m0);
         T zq[4];
-        normals4<T, true>((uint32_t)(m0 >> 1), (uint32_t)(t + m * NT), (uint32_t)a.tag, k0, k1, zq);
+        normals4<T, true>((uint32_t)(m0 >> 1), (uint32_t)rowof(t + m * NT), (uint32_t)a.tag, k0, k1, zq);
         const int kk1 = t + m * NT;
         const int q1 = wrapk(kk1, L);
-        const double p2b = (double)(q1 * q1) * a.il2[0];
+        const double p2b = (double)(q1 * q1) * a.il2[0] + p2o;
         const E e = sm[kk1 * RS + cp];
         const double p21 = p2b + (double)((m0 + 1) * (m0 + 1)) * il2d;
         const double p20 = p2b + (double)(m0 * m0) * il2d;
         if constexpr (sizeof(T) == 4) {
           // both entries of the row in float32, one float64 add per row
-          const float pf1 = (float)p21, pf0 = (float)p20;
-          float dl1, dl0, dn1 = 0.0f, dn0 = 0.0f;
-          if (gauss) {
-            dl1 = fmaf(gl1f, pf1, gl0f);
-            dl0 = fmaf(gl1f, pf0, gl0f);
-          } else {
-            const float u1 = fmaf(rbf, pf1, raf), u0 = fmaf(rbf, pf0, raf);
-            const float iu1 = __builtin_amdgcn_rcpf(u1), iu0 = __builtin_amdgcn_rcpf(u0);
-            dl1 = fmaf(gl1f, iu1, gl0f);
-            dl0 = fmaf(gl1f, iu0, gl0f);
-            if (has_nu) {
-              dn1 = gn0f - __builtin_amdgcn_logf(u1) * 0.693147180559945309f - gn1f * iu1;
-              dn0 = gn0f - __builtin_amdgcn_logf(u0) * 0.693147180559945309f - gn1f * iu0;
-            }
-          }
           const float c1 = hq.y * s * fmaf(zq[2], e.v[1].x, zq[3] * e.v[1].y);
           const float c0 = hq.x * s * fmaf(zq[0], e.v[0].x, zq[1] * e.v[0].y);
-          acc0 += (double)(c1 + c0);
-          acc1 += (double)fmaf(c1, dl1, c0 * dl0);
-          acc2 += (double)fmaf(c1, dn1, c0 * dn0);
+          ad.add2f((float)p21, (float)p20, c1, c0);
         } else {
           add(2.0, (double)hq.y, p21, mk<T>(s * zq[2], s * zq[3]), e.v[1]);
           add(2.0, (double)hq.x, p20, mk<T>(s * zq[0], s * zq[1]), e.v[0]);
         }
         if (gz) {
-          T* gzr = gz + (long long)b * a.field_stride * 2 + (long long)kk1 * a.nd + 2 * m0;
+          T* gzr = gz + (long long)b * a.field_stride * 2 + (long long)rowof(kk1) * a.nd + 2 * m0;
           gzr[0] = s2 * hq.x * e.v[0].x;
           gzr[1] = s2 * hq.x * e.v[0].y;
           gzr[2] = s2 * hq.y * e.v[1].x;
@@ -787,11 +816,11 @@ k_colg(Args a) {
 #pragma unroll
     for (int m = 0; m < R0; ++m) {
       const int kk1 = t + m * NT;
-      const int row = kk1;
+      const int row = rowof(kk1);
       T z[4];
       load_z4<T>(a, zsrc, b, row, m0, k0, k1, z);
       const int q1 = wrapk(kk1, L);
-      const double p2b = (double)(q1 * q1) * a.il2[0];
+      const double p2b = (double)(q1 * q1) * a.il2[0] + p2o;
       const E e = sm[kk1 * RS + cp];
       T* gzr = gz ? gz + (long long)b * a.field_stride * 2 + (long long)row * a.nd + 2 * m0 : nullptr;
       const T* hrow = a.htab ? (const T*)a.htab + (long long)row * (a.M + 2) : nullptr;
@@ -812,6 +841,30 @@ k_colg(Args a) {
           gzr[0] = s2 * h * e.v[0].x;
           gzr[1] = s2 * h * e.v[0].y;
         }
+      } else if constexpr (D3) {
+        const V Z = e.v[0];
+        const int nrow = ((L - kk1) % L) * a.no + (a.no - fx) % a.no;
+        const double p2n = p2b + (double)a.M * (double)a.M * il2d;
+        const T hz = hrow ? hrow[0] : filt_h(f, (T)p2b);
+        const T hn = hrow ? hrow[a.M] : filt_h(f, (T)p2n);
+        V x0, xn;
+        if (nrow == row) {
+          x0 = mk<T>(z[0], (T)0);
+          xn = mk<T>(z[1], (T)0);
+        } else {
+          T zz[4];
+          load_z4<T>(a, zsrc, b, nrow, 0, k0, k1, zz);
+          if (row < nrow) {
+            x0 = mk<T>(s * z[0], s * z[1]);
+            xn = mk<T>(s * zz[0], s * zz[1]);
+          } else {
+            x0 = mk<T>(s * zz[0], -s * zz[1]);
+            xn = mk<T>(s * z[0], -s * z[1]);
+          }
+        }
+        add(1.0, (double)hz, p2b, x0, Z);
+        add(1.0, (double)hn, p2n, mk<T>(-xn.y, xn.x), Z);
+        if (a.plane) ((V*)a.plane)[(long long)b * a.n1 * a.no + row] = Z;
       } else {
         const V w = e.v[0];
         const V wm = sm[((L - kk1) % L) * RS + cp].v[0];
@@ -852,6 +905,9 @@ k_colg(Args a) {
         add(1.0, (double)hn, p2n, xn, gn);
       }
     }
+    acc0 = ad.acc0;
+    acc1 = ad.acc1;
+    acc2 = ad.acc2;
   }
   acc0 *= act ? a.recs[b * a.rec_stride].gs : 0.0;
   // workgroup reduction in a fixed order (deterministic)
@@ -870,7 +926,7 @@ k_colg(Args a) {
   if (tid < 3) {
     double sacc = 0;
     for (int w = 0; w < NW; ++w) sacc += red[tid][w];
-    a.partial[((long long)b * a.ntile + tile) * 3 + tid] = sacc;
+    a.partial[((long long)(D3 ? b * a.nfixed + fx : b) * a.ntile + tile) * 3 + tid] = sacc;
   }
 }
 

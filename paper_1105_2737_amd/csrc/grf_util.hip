@@ -144,6 +144,145 @@ hipError_t launch_cov_accum(int dtype, const void* fields, int nb, long long P, 
   return hipGetLastError();
 }
 
+// Adjoint for d = 1: the last-axis real-to-complex pass has left G = F[g] of
+// each field at a.data (packed: slot 0 = (G_0, G_{N/2})).  Thread q of tile
+// `tile` of field b takes the entries 2q and 2q+1, i.e. the Philox block q
+// that generated them (block 0 also holds A_0 and A_{N/2}); the workgroup's
+// sums go to a.partial[(b * ntile + tile) * 3 ..].  dL/dz to a.aux if asked.
+template <typename T>
+__global__ void __launch_bounds__(256) k_grad1d(Args a) {
+  using V = C<T>;
+  const int tile = blockIdx.x % a.ntile;
+  const int b = blockIdx.x / a.ntile;
+  const int q = tile * 256 + threadIdx.x;
+  const int NQ = a.M / 2;
+  double acc0 = 0, acc1 = 0, acc2 = 0;
+  if (q < NQ) {
+    const FieldRec& rec = a.recs[b * a.rec_stride];
+    const Filt<T> f = load_filt<T>(rec, 1.0);
+    AdjAcc<T> ad(rec);
+    T z[4];
+    if (a.src == nullptr) {
+      const unsigned long long key = a.seed + (unsigned long long)b;
+      normals4<T, true>((uint32_t)q, 0u, (uint32_t)a.tag, (uint32_t)key, (uint32_t)(key >> 32), z);
+    } else {
+      const T* p = (const T*)a.src + (long long)b * a.nd + 4 * q;
+      for (int e = 0; e < 4; ++e) z[e] = p[e];
+    }
+    const double il2 = a.il2[2];
+    const T* ht = (const T*)a.htab;
+    auto hk = [&](int k) -> T { return ht ? ht[k] : filt_h(f, (T)((double)k * k * il2)); };
+    const V* G = (const V*)a.data + (long long)b * a.M;
+    T* gz = a.aux ? (T*)a.aux + (long long)b * a.nd + 4 * q : nullptr;
+    const T s = (T)0.70710678118654752440, s2 = (T)1.4142135623730950488;
+    const int ka = 2 * q + 1, kb = 2 * q;
+    const T ha = hk(ka);
+    const V Ga = G[ka];
+    ad.add(2.0, (double)ha, (double)ka * ka * il2, mk<T>(s * z[2], s * z[3]), Ga);
+    if (gz) {
+      gz[2] = s2 * ha * Ga.x;
+      gz[3] = s2 * ha * Ga.y;
+    }
+    const V Gb = G[kb];
+    if (q > 0) {
+      const T hb = hk(kb);
+      ad.add(2.0, (double)hb, (double)kb * kb * il2, mk<T>(s * z[0], s * z[1]), Gb);
+      if (gz) {
+        gz[0] = s2 * hb * Gb.x;
+        gz[1] = s2 * hb * Gb.y;
+      }
+    } else {   // the real entries A_0 = h_0 z_0 and A_{N/2} = h_{N/2} z_1
+      const T h0 = hk(0), hm = hk(a.M);
+      ad.add(1.0, (double)h0, 0.0, mk<T>(z[0], (T)0), mk<T>(Gb.x, (T)0));
+      ad.add(1.0, (double)hm, (double)a.M * a.M * il2, mk<T>(z[1], (T)0), mk<T>(Gb.y, (T)0));
+      if (gz) {
+        gz[0] = h0 * Gb.x;
+        gz[1] = hm * Gb.y;
+      }
+    }
+    acc0 = ad.acc0 * rec.gs;
+    acc1 = ad.acc1;
+    acc2 = ad.acc2;
+  }
+  __shared__ double red[3][4];
+  for (int off = 32; off > 0; off >>= 1) {
+    acc0 += __shfl_xor(acc0, off);
+    acc1 += __shfl_xor(acc1, off);
+    acc2 += __shfl_xor(acc2, off);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wv] = acc0;
+    red[1][wv] = acc1;
+    red[2][wv] = acc2;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double sacc = 0;
+    for (int w = 0; w < 4; ++w) sacc += red[threadIdx.x][w];
+    a.partial[((long long)b * a.ntile + tile) * 3 + threadIdx.x] = sacc;
+  }
+}
+
+// Adjoint for d = 3, dL/dz of the two planes k_d = 0, N_d/2: from Z(k) and
+// Z(-k) (stored by k_colg<..., D3>) G0 = (Z(k) + conj Z(-k)) / 2 and
+// GM = (Z(k) - conj Z(-k)) / (2i); then the Hermitian arrangement backwards,
+// as the d = 2 column kernel does for its plane slots.  One thread per
+// (field, row) of a.batch fields.
+template <typename T>
+__global__ void k_grad_plane(Args a) {
+  using V = C<T>;
+  const long long R = (long long)a.n1 * a.no;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)a.batch * R) return;
+  const int b = (int)(i / R), row = (int)(i % R);
+  const int k1 = row / a.no, o = row % a.no;
+  const int nrow = ((a.n1 - k1) % a.n1) * a.no + (a.no - o) % a.no;
+  const V* Zp = (const V*)a.plane + (long long)b * R;
+  const V Z = Zp[row], Zm = Zp[nrow];
+  const V g0 = mk<T>((T)0.5 * (Z.x + Zm.x), (T)0.5 * (Z.y - Zm.y));
+  const V gn = mk<T>((T)0.5 * (Z.y + Zm.y), (T)-0.5 * (Z.x - Zm.x));
+  const Filt<T> f = load_filt<T>(a.recs[b * a.rec_stride], 1.0);
+  const int q1 = wrapk(k1, a.n1), qo = wrapk(o, a.no);
+  const double p2b = (double)(q1 * q1) * a.il2[0] + (double)(qo * qo) * a.il2[1];
+  const double p2n = p2b + (double)a.M * (double)a.M * a.il2[2];
+  const T* hrow = a.htab ? (const T*)a.htab + (long long)row * (a.M + 2) : nullptr;
+  const T hz = hrow ? hrow[0] : filt_h(f, (T)p2b);
+  const T hn = hrow ? hrow[a.M] : filt_h(f, (T)p2n);
+  const T s2 = (T)1.4142135623730950488;
+  T* gzr = (T*)a.aux + (long long)b * a.field_stride * 2 + (long long)row * a.nd;
+  if (nrow == row) {
+    gzr[0] = hz * g0.x;
+    gzr[1] = hn * gn.x;
+  } else if (row < nrow) {
+    gzr[0] = s2 * hz * g0.x;
+    gzr[1] = s2 * hz * g0.y;
+  } else {   // slots of a mirrored row carry the Nyquist plane of its partner
+    gzr[0] = s2 * hn * gn.x;
+    gzr[1] = -s2 * hn * gn.y;
+  }
+}
+
+hipError_t launch_grad1d(int dtype, const Args& a, long long nblocks, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_grad1d<float>, dim3((unsigned)nblocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_grad1d<double>, dim3((unsigned)nblocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_plane(int dtype, const Args& a, hipStream_t s) {
+  const long long n = (long long)a.batch * a.n1 * a.no;
+  if (n <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_grad_plane<float>, grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL(k_grad_plane<double>, grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_gen1d(int dtype, int M, const Args& a, long long nblocks, double* partial, hipStream_t s) {
   return dtype == 0 ? launch_gen1d_f32(M, a, nblocks, partial, s) : launch_gen1d_f64(M, a, nblocks, partial, s);
 }
