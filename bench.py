@@ -392,6 +392,20 @@ def main():
         del w, w2, o5, g
         torch.cuda.empty_cache()
 
+        # the adjoint in 3D (256^3 x 16, exponential l = 0.05), with and without dL/dz
+        p3a = grf.Plan((256, 256, 256), alg=2, dtype=torch.float32, cov="exponential", sigma=1.0, length_scale=0.05)
+        o3a = torch.empty((16, 256, 256, 256), dtype=torch.float32, device="cuda")
+        s3f = timed(lambda: p3a.sample(seed=0, batch=16, out=o3a), max(args.steps // 10, 5), 2, torch)
+        g3 = o3a.clone()
+        s3b = timed(lambda: p3a.backward(g3, seed=0), max(args.steps // 10, 5), 2, torch)
+        s3z = timed(lambda: p3a.backward(g3, seed=0, need_noise_grad=True), max(args.steps // 10, 5), 2, torch)
+        extra["adjoint_256cubed_x16"] = {"fwd_ms": round(s3f * 1e3, 4), "adjoint_ms": round(s3b * 1e3, 4),
+                                         "adjoint_with_noise_grad_ms": round(s3z * 1e3, 4),
+                                         "ratio_adjoint_vs_fwd": round(s3b / s3f, 3),
+                                         "upstream_gradient": "dL/dphi = phi (L = |phi|^2 / 2)"}
+        del p3a, o3a, g3
+        torch.cuda.empty_cache()
+
         # the covariance family of Section 4, eq. (5), Figure 3(d)'s anisotropic case
         # (m = 5, k = 3, l = n = 1) on the headline grid and batch (filter from the plan's table)
         pp = grf.Plan(dims, lengths=(4.0, 4.0), alg=2, dtype=torch.float32, cov="paper", m=5.0, k=3, l=1, n=1)
