@@ -146,7 +146,7 @@ class Plan:
         return out
 
     def backward(self, grad_out, seed=0, theta=None, noise=None, need_noise_grad=False):
-        """(dL/dtheta [batch, 3] float64, dL/dz or None) for the one-FFT sampler."""
+        """(dL/dtheta [batch, 3] float64, dL/dz or None) for either algorithm."""
         grad_out = grad_out.to(device=self.device, dtype=self.dtype).contiguous()
         batch = grad_out.shape[0]
         th = self._theta(theta, batch)

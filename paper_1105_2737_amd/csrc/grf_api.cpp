@@ -146,9 +146,10 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 long long chunk_fields(const grf_plan_s* p, long long batch);
 
 // Workspace layout: [records][partials][spectrum of one chunk of fields]
-// [d = 3 adjoint: plane values Z of one chunk]
+// [d = 3 adjoint: plane values Z of one chunk | two-FFT adjoint: the white
+// noise's spectrum of one chunk]
 struct WsLayout {
-  size_t recs, partial, spec, plane, total;
+  size_t recs, partial, spec, plane, spec2, total;
 };
 
 // Adjoint: workgroups of the reduction pass per field (each leaves three
@@ -179,9 +180,12 @@ WsLayout ws_layout(const grf_plan_s* p, long long batch, int op) {
     off += align256((size_t)C * p->P * p->esz);
     w.plane = off;
     if (p->d == 3) off += align256((size_t)C * p->n1 * p->no * 2 * p->esz);
+    w.spec2 = off;
+    if (p->desc.alg == GRF_ALG_TWO_FFT) off += align256((size_t)C * p->P * p->esz);
   } else {
     w.spec = off;
     w.plane = off;
+    w.spec2 = off;
   }
   w.total = off;
   return w;
@@ -942,8 +946,8 @@ grf_status grf_backward(grf_plan p, uint64_t seed, const void* noise, int64_t ba
                         const void* grad_out, double* grad_theta, void* grad_noise, void* workspace,
                         size_t workspace_bytes, void* stream) {
   if (p == nullptr) return fail(GRF_EINVAL, "null plan");
-  if (p->desc.alg != GRF_ALG_ONE_FFT || p->reflect || p->desc.draw_order != GRF_DRAW_COUNTER)
-    return fail(GRF_EUNSUPPORTED, "adjoint implemented for the periodic one-FFT algorithm (counter draws)");
+  if (p->reflect || p->desc.draw_order != GRF_DRAW_COUNTER)
+    return fail(GRF_EUNSUPPORTED, "adjoint implemented for periodic axes and the counter draw order");
   if (batch < 0) return fail(GRF_EINVAL, "negative batch");
   if (batch == 0) return GRF_OK;
   if (grad_out == nullptr || grad_theta == nullptr) return fail(GRF_EINVAL, "null gradient pointer");
@@ -984,6 +988,40 @@ grf_status grf_backward(grf_plan p, uint64_t seed, const void* noise, int64_t ba
     c.src = noise ? (const char*)noise + c0 * fbytes : nullptr;
     c.aux = grad_noise ? (char*)grad_noise + c0 * fbytes : nullptr;
     c.partial = (double*)(ws + w.partial) + c0 * at.nper * 3;
+    if (p->desc.alg == GRF_ALG_TWO_FFT) {
+      // xi = F[z] / sqrt(P): the white noise through the same transforms (the
+      // table of a density-defined family already holds the 1/sqrt(P))
+      Args rz = base_args(p, nb);
+      rz.data = ws + w.spec2;
+      rz.src = c.src;
+      rz.recs = c.recs;
+      rz.rec_stride = rstride;
+      rz.seed = c.seed;
+      rz.tag = 0;
+      rz.tw2 = p->tw_row;
+      rz.rows = nb * (long long)p->n1;
+      st = run_pass(p, noise ? grf::PASS_ROW_R2C_LOAD : grf::PASS_ROW_R2C_GEN, p->M, rz, 0, nb, s);
+      if (st != GRF_OK) return st;
+      Args cz = base_args(p, nb);
+      cz.data = ws + w.spec2;
+      cz.tw = p->tw_col1;
+      cz.stride_ax = p->M;
+      cz.stride_fixed = p->M;
+      cz.nfixed = 1;
+      st = run_pass(p, grf::PASS_COL_LOAD_FWD, p->n1, cz, 0, nb, s);
+      if (st != GRF_OK) return st;
+      c.tag = 0;
+      c.aux = nullptr;   // dL/dz below, by the sampler's passes
+      c.src2 = ws + w.spec2;
+      c.scale = p->table_only ? 1.0 : 1.0 / std::sqrt((double)p->P);
+      c.tw = p->tw_col1;
+      c.stride_ax = p->M;
+      c.stride_fixed = p->M;
+      c.nfixed = 1;
+      st = run_pass(p, grf::PASS_COL_GRAD1, p->n1, c, 0, nb, s);
+      if (st != GRF_OK) return st;
+      continue;
+    }
     if (p->d == 1) {
       c.ntile = at.ntile;
       hipError_t e = grf::launch_grad1d(p->dtype, c, nb * at.ntile, s);
@@ -1014,6 +1052,14 @@ grf_status grf_backward(grf_plan p, uint64_t seed, const void* noise, int64_t ba
   }
   hipError_t e = grf::launch_reduce_partials((const double*)(ws + w.partial), (int)batch, at.nper, grad_theta, s);
   if (e != hipSuccess) return hip_fail(e, "reduction");
+  if (p->desc.alg == GRF_ALG_TWO_FFT && grad_noise != nullptr) {
+    // phi = F*[h F[z]] / sqrt(P) with h real and even is a symmetric operator
+    // of z, so dL/dz is the same sampler applied to g
+    for (const PassLaunch& pl : sample_passes(p, seed, grad_out, batch, recs, rstride, grad_noise)) {
+      st = run_launch(p, pl, s);
+      if (st != GRF_OK) return st;
+    }
+  }
   return GRF_OK;
 }
 

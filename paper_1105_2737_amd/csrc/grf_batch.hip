@@ -85,6 +85,7 @@ __device__ __forceinline__ Args batch_args(const BatchField& f, const BatchField
   a.bcmask = 0;
   a.seq = 0;
   a.plane = nullptr;
+  a.src2 = nullptr;
   return a;
 }
 

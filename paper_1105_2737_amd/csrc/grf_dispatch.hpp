@@ -41,6 +41,7 @@ enum PassKind {
   PASS_R2R_ROW_GEN = GRF_PASS_R2R_ROW_GEN,     // reflecting, d = 1: coefficients + cosine transform
   PASS_COL_SEQ_INV = GRF_PASS_COL_SEQ_INV,     // as PASS_COL_GEN_INV, normals in the recursive draw order
   PASS_COL_GRAD3 = 100,                        // PASS_COL_GRAD for d = 3 (internal: adjoint only)
+  PASS_COL_GRAD1 = 101,                        // PASS_COL_GRAD for the two-FFT algorithm (internal)
 };
 
 inline bool is_r2r_pass(int p) { return p >= PASS_R2R_COL_GEN && p <= PASS_R2R_ROW_GEN; }

@@ -71,6 +71,7 @@ struct Args {
   int bcmask;                 // sine axes: bit 0 axis 1, bit 1 middle axis, bit 2 last axis
   int seq;                    // 1: normals in the draw order of the recursive algorithm (seq_draw)
   void* plane;                // 3D adjoint: Z = G(k, 0) + i G(k, N_d/2) per (field, row), or null
+  const void* src2;           // two-FFT adjoint: F[z] after the column transform (packed, like data)
 };
 
 // Tile index of this workgroup in a column pass.  Workgroups are dispatched to
@@ -724,7 +725,10 @@ struct AdjAcc {
 // sum_k Re(i xiM conj Z), because xi0, xiM are Hermitian and h, S even, so no
 // partner column (-k lies in another workgroup's tile) is needed; dL/dz of
 // the plane slots needs it, so Z is stored to a.plane for k_grad_plane.
-template <typename T, int L, class Rad, int CP, int PAD, bool D3 = false>
+// XI (two-FFT algorithm, d = 2): xi = a.scale F[z] is read from a.src2 (the
+// white noise's spectrum after the same transforms) instead of being
+// regenerated; its plane slot is unpacked with the mirrored row like G's.
+template <typename T, int L, class Rad, int CP, int PAD, bool D3 = false, bool XI = false>
 __global__ void __launch_bounds__(((L / Rad::get(0)) * CP + 63) / 64 * 64)
 k_colg(Args a) {
   using V = C<T>;
@@ -757,7 +761,7 @@ k_colg(Args a) {
   // Straight-line route for the common case (generated noise, filter table,
   // a column pair away from the packed plane slot): the filter-table loads of
   // all rows are issued together and the R0 Philox blocks are independent.
-  const bool straight = a.src == nullptr && a.htab != nullptr && m0 > 0;
+  const bool straight = !XI && a.src == nullptr && a.htab != nullptr && m0 > 0;
   if (act) {
 #pragma unroll
     for (int m = 0; m < R0; ++m)
@@ -817,11 +821,42 @@ k_colg(Args a) {
     for (int m = 0; m < R0; ++m) {
       const int kk1 = t + m * NT;
       const int row = rowof(kk1);
-      T z[4];
-      load_z4<T>(a, zsrc, b, row, m0, k0, k1, z);
       const int q1 = wrapk(kk1, L);
       const double p2b = (double)(q1 * q1) * a.il2[0] + p2o;
       const E e = sm[kk1 * RS + cp];
+      if constexpr (XI) {
+        const V* zs = (const V*)a.src2 + (long long)b * a.field_stride + m0;
+        const T sc = (T)a.scale;
+        const T* hr = a.htab ? (const T*)a.htab + (long long)row * (a.M + 2) : nullptr;
+        V xa, xb;
+        ld_pair<T>(zs + (long long)kk1 * a.stride_ax, two, al, xa, xb);
+        if (two) {
+          const double p2 = p2b + (double)((m0 + 1) * (m0 + 1)) * il2d;
+          const T h = hr ? hr[m0 + 1] : filt_h(f, (T)p2);
+          add(2.0, (double)h, p2, mk<T>(sc * xb.x, sc * xb.y), e.v[1]);
+        }
+        if (m0 > 0) {
+          const double p2 = p2b + (double)(m0 * m0) * il2d;
+          const T h = hr ? hr[m0] : filt_h(f, (T)p2);
+          add(2.0, (double)h, p2, mk<T>(sc * xa.x, sc * xa.y), e.v[0]);
+        } else {
+          const V xm = zs[(long long)((L - kk1) % L) * a.stride_ax];
+          const V x0 = mk<T>((T)0.5 * sc * (xa.x + xm.x), (T)0.5 * sc * (xa.y - xm.y));
+          const V xn = mk<T>((T)0.5 * sc * (xa.y + xm.y), (T)-0.5 * sc * (xa.x - xm.x));
+          const V w = e.v[0];
+          const V wm = sm[((L - kk1) % L) * RS + cp].v[0];
+          const V g0 = mk<T>((T)0.5 * (w.x + wm.x), (T)0.5 * (w.y - wm.y));
+          const V gn = mk<T>((T)0.5 * (w.y + wm.y), (T)-0.5 * (w.x - wm.x));
+          const double p2n = p2b + (double)a.M * (double)a.M * il2d;
+          const T hz = hr ? hr[0] : filt_h(f, (T)p2b);
+          const T hn = hr ? hr[a.M] : filt_h(f, (T)p2n);
+          add(1.0, (double)hz, p2b, x0, g0);
+          add(1.0, (double)hn, p2n, xn, gn);
+        }
+        continue;
+      }
+      T z[4];
+      load_z4<T>(a, zsrc, b, row, m0, k0, k1, z);
       T* gzr = gz ? gz + (long long)b * a.field_stride * 2 + (long long)row * a.nd + 2 * m0 : nullptr;
       const T* hrow = a.htab ? (const T*)a.htab + (long long)row * (a.M + 2) : nullptr;
       if (two) {
