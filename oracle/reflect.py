@@ -129,3 +129,38 @@ def covariance_with(a, sine_axes, jp):
         shape[i] = a.shape[i]
         w = w * bj.reshape(shape)
     return apply_basis(w, sine_axes)
+
+
+# ---------------------------------------------------------------------------
+# Adjoint.  phi = B (a * z) with B the product of the axis bases, so for an
+# upstream gradient g = dL/dphi:
+#   dL/dz     = a * B^T g,
+#   dL/dtheta = sum_n (B^T g)_n z_n da_n/dtheta,  da/dtheta = (a/2) d log S/dtheta.
+# B^T along an axis is the transposed basis matrix: sum_j g_j b(n, j).
+
+def apply_basis_transpose(v, sine_axes):
+    """sum_j v_j prod_i b_i(n_i, j_i) for every slot n."""
+    out = np.asarray(v, dtype=np.float64)
+    for i, s in enumerate(sine_axes):
+        B = axis_basis(out.shape[i], s)
+        out = np.moveaxis(np.tensordot(B.T, out, axes=([1], [i])), 0, i)
+    return out
+
+
+def grad_theta(z, g, lengths, sine_axes, kind=None, sigma=1.0, ell=1.0, nu=0.5, density=None, S=None):
+    """(dL/dsigma, dL/dell, dL/dnu); a family given by a density or a table
+    has only sigma (the other two are 0)."""
+    from .spectra import dlog_spectral_density
+    dims = np.shape(z)
+    a = coefficients(dims, lengths, sine_axes, kind, sigma, ell, nu, density=density, S=S)
+    G = apply_basis_transpose(g, sine_axes)
+    core = 0.5 * a * np.asarray(z, dtype=np.float64) * G
+    if density is not None or S is not None:
+        return np.array([np.sum(core) * 2.0 / float(sigma), 0.0, 0.0])
+    p2 = sum(c ** 2 for c in slot_components(dims, lengths, sine_axes))
+    dl = dlog_spectral_density(kind, np.broadcast_to(p2, dims), len(dims), sigma, ell, nu)
+    return np.array([np.sum(core * d) for d in dl])
+
+
+def grad_noise(g, a, sine_axes):
+    return np.asarray(a) * apply_basis_transpose(g, sine_axes)

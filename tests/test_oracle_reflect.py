@@ -122,3 +122,59 @@ def test_sample_takes_the_contract_noise_with_its_own_tag():
         z = noise.field_noise(dims, 7 + b, 2)
         np.testing.assert_array_equal(phi[b], reflect.field_from_noise(z, a, sine))
     assert not np.allclose(noise.field_noise(dims, 7, 2), noise.field_noise(dims, 7, 1))
+
+
+# ---------------------------------------------------------------------------
+# adjoint
+
+@pytest.mark.parametrize("sine", [(False,), (True,), (False, True), (True, True, False)], ids=str)
+def test_basis_transpose_identity(sine):
+    dims = (6, 8, 4)[: len(sine)]
+    rng = np.random.default_rng(len(sine))
+    x, y = rng.normal(size=dims), rng.normal(size=dims)
+    lhs = np.sum(reflect.apply_basis(x, sine) * y)
+    rhs = np.sum(x * reflect.apply_basis_transpose(y, sine))
+    assert lhs == pytest.approx(rhs, rel=1e-13)
+
+
+@pytest.mark.parametrize("kind,nu", [(spectra.MATERN, 1.5), (spectra.GAUSSIAN, 0.5), (spectra.EXPONENTIAL, 0.5)])
+@pytest.mark.parametrize("dims,sine", [((8,), (True,)), ((6, 8), (False, True)), ((4, 6, 4), (True, False, True))],
+                         ids=str)
+def test_grad_theta_finite_differences(kind, nu, dims, sine):
+    lengths = tuple(1.0 + 0.3 * i for i in range(len(dims)))
+    z = noise.field_noise(dims, 3, 2)
+    w = np.random.default_rng(0).uniform(size=dims)
+
+    def loss(th):
+        a = reflect.coefficients(dims, lengths, sine, kind=kind, sigma=th[0], ell=th[1], nu=th[2])
+        return np.sum(w * reflect.field_from_noise(z, a, sine) ** 2)
+    th = np.array([1.2, 0.3, nu])
+    a = reflect.coefficients(dims, lengths, sine, kind=kind, sigma=th[0], ell=th[1], nu=th[2])
+    g = 2 * w * reflect.field_from_noise(z, a, sine)
+    got = reflect.grad_theta(z, g, lengths, sine, kind=kind, sigma=th[0], ell=th[1], nu=th[2])
+    nparam = 3 if kind == spectra.MATERN else 2
+    for i in range(nparam):
+        e = np.zeros(3)
+        e[i] = 1e-6 * th[i]
+        fd = (loss(th + e) - loss(th - e)) / (2 * e[i])
+        assert got[i] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+    if nparam == 2:
+        assert got[2] == 0.0
+
+
+def test_grad_noise_finite_differences_and_density():
+    dims, lengths, sine = (6, 8), (1.0, 2.0), (True, False)
+    dens = spectra.paper_density(5.0, 3, 1, 1)
+    a = reflect.coefficients(dims, lengths, sine, density=dens, sigma=1.3)
+    z = noise.field_noise(dims, 1, 2)
+    w = np.random.default_rng(1).uniform(size=dims)
+    g = 2 * w * reflect.field_from_noise(z, a, sine)
+    gz = reflect.grad_noise(g, a, sine)
+    d = np.random.default_rng(2).normal(size=dims)
+    loss = lambda zz: np.sum(w * reflect.field_from_noise(zz, a, sine) ** 2)
+    fd = (loss(z + 1e-6 * d) - loss(z - 1e-6 * d)) / 2e-6
+    assert np.sum(gz * d) == pytest.approx(fd, rel=1e-7)
+    # a density-defined family: phi is linear in sigma, so sigma dL/dsigma = 2 L
+    gt = reflect.grad_theta(z, g, lengths, sine, density=dens, sigma=1.3)
+    assert gt[0] * 1.3 == pytest.approx(2 * loss(z), rel=1e-12)
+    assert gt[1] == 0.0 and gt[2] == 0.0
