@@ -250,8 +250,9 @@ grf_status grf_noise(grf_plan plan, uint64_t seed, int64_t batch, void* noise_ou
  *   grad_noise    = dL/dz (device, field-shaped; NULL to skip).
  * The noise is regenerated from `seed` (noise == NULL) or read from `noise`.
  * The Fourier transform of grad_out is recomputed; no spectrum is stored by
- * the forward call.  Both algorithms (the two-FFT one with d = 2), periodic
- * axes and the counter draw order (else GRF_EUNSUPPORTED); ndim = 1, 2 or 3.
+ * the forward call.  Both algorithms (the two-FFT one with d = 2) and the
+ * reflecting boundaries (B^T g by the transposed cosine transforms), the
+ * counter draw order (else GRF_EUNSUPPORTED); ndim = 1, 2 or 3.
  * For the two-FFT algorithm xi = F[z] / sqrt(P) enters in place of the
  * Hermitian noise, and dL/dz = F*[h F[grad_out]] / sqrt(P), the sampler
  * applied to grad_out. */

@@ -159,6 +159,12 @@ struct AdjTiles {
   int nper;      // partial sums per field / 3
 };
 AdjTiles adj_tiles(const grf_plan_s* p) {
+  if (p->reflect) {
+    if (p->d == 1) return AdjTiles{1, 1};
+    const grf::Geom g = grf::pass_geom(grf::PASS_R2R_COL_FWD_RED, p->dtype, p->n1);
+    const int nt = (p->M + 2 * g.per_wg - 1) / (2 * g.per_wg);
+    return AdjTiles{nt, nt * p->no};
+  }
   if (p->d == 1) {
     const int nt = (p->M / 2 + 255) / 256;
     return AdjTiles{nt, nt};
@@ -946,8 +952,8 @@ grf_status grf_backward(grf_plan p, uint64_t seed, const void* noise, int64_t ba
                         const void* grad_out, double* grad_theta, void* grad_noise, void* workspace,
                         size_t workspace_bytes, void* stream) {
   if (p == nullptr) return fail(GRF_EINVAL, "null plan");
-  if (p->reflect || p->desc.draw_order != GRF_DRAW_COUNTER)
-    return fail(GRF_EUNSUPPORTED, "adjoint implemented for periodic axes and the counter draw order");
+  if (p->desc.draw_order != GRF_DRAW_COUNTER)
+    return fail(GRF_EUNSUPPORTED, "adjoint implemented for the counter draw order");
   if (batch < 0) return fail(GRF_EINVAL, "negative batch");
   if (batch == 0) return GRF_OK;
   if (grad_out == nullptr || grad_theta == nullptr) return fail(GRF_EINVAL, "null gradient pointer");
@@ -988,6 +994,49 @@ grf_status grf_backward(grf_plan p, uint64_t seed, const void* noise, int64_t ba
     c.src = noise ? (const char*)noise + c0 * fbytes : nullptr;
     c.aux = grad_noise ? (char*)grad_noise + c0 * fbytes : nullptr;
     c.partial = (double*)(ws + w.partial) + c0 * at.nper * 3;
+    if (p->reflect) {
+      // B^T g by transposed cosine transforms (DCT-II), last axis first; the
+      // reduction runs with the last of them (axis 1, or the row for d = 1)
+      c.tag = 2;
+      c.bcmask = p->sinemask;
+      c.src2 = c.src;   // given noise (src carries g in the row pass)
+      c.src = nullptr;
+      Args rr = c;
+      rr.src = (const char*)grad_out + c0 * fbytes;
+      rr.tw2 = p->tw_row;
+      rr.tq = p->tq_row;
+      rr.sine = (p->sinemask >> 2) & 1;
+      rr.rows = nb * (p->P / p->nd);
+      if (p->d == 1) {
+        st = run_pass(p, grf::PASS_R2R_ROW_FWD_RED, p->M, rr, 0, nb, s);
+        if (st != GRF_OK) return st;
+        continue;
+      }
+      rr.aux = nullptr;
+      st = run_pass(p, grf::PASS_R2R_ROW_FWD, p->M, rr, 0, nb, s);
+      if (st != GRF_OK) return st;
+      if (p->d == 3) {
+        Args m = c;
+        m.aux = nullptr;
+        m.tw = p->tw_col2;
+        m.tq = p->tq_col2;
+        m.sine = (p->sinemask >> 1) & 1;
+        m.stride_ax = p->M;
+        m.stride_fixed = (long long)p->no * p->M;
+        m.nfixed = p->n1;
+        st = run_pass(p, grf::PASS_R2R_COL_FWD, p->no, m, 0, nb, s);
+        if (st != GRF_OK) return st;
+      }
+      c.tw = p->tw_col1;
+      c.tq = p->tq_col1;
+      c.sine = p->sinemask & 1;
+      c.stride_ax = (long long)p->no * p->M;
+      c.stride_fixed = p->M;
+      c.nfixed = p->no;
+      st = run_pass(p, grf::PASS_R2R_COL_FWD_RED, p->n1, c, 0, nb, s);
+      if (st != GRF_OK) return st;
+      continue;
+    }
     if (p->desc.alg == GRF_ALG_TWO_FFT) {
       // xi = F[z] / sqrt(P): the white noise through the same transforms (the
       // table of a density-defined family already holds the 1/sqrt(P))

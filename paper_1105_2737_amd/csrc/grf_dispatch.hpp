@@ -42,13 +42,22 @@ enum PassKind {
   PASS_COL_SEQ_INV = GRF_PASS_COL_SEQ_INV,     // as PASS_COL_GEN_INV, normals in the recursive draw order
   PASS_COL_GRAD3 = 100,                        // PASS_COL_GRAD for d = 3 (internal: adjoint only)
   PASS_COL_GRAD1 = 101,                        // PASS_COL_GRAD for the two-FFT algorithm (internal)
+  // adjoint of the reflecting-boundary sampler (internal): cosine transforms
+  // transposed (DCT-II), last axis and leading axes, the latter optionally
+  // with the reduction (RED)
+  PASS_R2R_ROW_FWD = 102,
+  PASS_R2R_ROW_FWD_RED = 103,
+  PASS_R2R_COL_FWD = 104,
+  PASS_R2R_COL_FWD_RED = 105,
 };
 
-inline bool is_r2r_pass(int p) { return p >= PASS_R2R_COL_GEN && p <= PASS_R2R_ROW_GEN; }
+inline bool is_r2r_pass(int p) {
+  return (p >= PASS_R2R_COL_GEN && p <= PASS_R2R_ROW_GEN) || (p >= PASS_R2R_ROW_FWD && p <= PASS_R2R_COL_FWD_RED);
+}
 // passes that take rows (last axis) rather than column tiles
 inline bool is_row_pass(int p) {
   return p == PASS_ROW_C2R || p == PASS_ROW_R2C_GEN || p == PASS_ROW_R2C_LOAD || p == PASS_ROW_GEN_C2R ||
-         p == PASS_R2R_ROW_LOAD || p == PASS_R2R_ROW_GEN;
+         p == PASS_R2R_ROW_LOAD || p == PASS_R2R_ROW_GEN || p == PASS_R2R_ROW_FWD || p == PASS_R2R_ROW_FWD_RED;
 }
 
 // Workgroup geometry of a pass at a given length (for grid sizing).

@@ -333,4 +333,342 @@ __global__ void __launch_bounds__((R2RRow<T, M, Rad, RB, SRC>::THREADS)) k_r2r_r
   PS::run(a, blockIdx.x, smem);
 }
 
+
+// ---------------------------------------------------------------------------
+// Adjoint.  phi = B (a * z), B the product of the axis bases, so for an
+// upstream gradient g:  dL/dz = a * B^T g  and
+// dL/dtheta = sum_n (B^T g)_n z_n (a_n / 2) d log S / d theta (p_n).
+// B^T along an axis is the DCT-II  X_k = sum_j x_j cos(pi k (j + 1/2) / N)
+// of the axis data (times (-1)^j first on a sine axis), again one DFT of
+// length N (Makhoul): v_n = x_{2n}, v_{N-1-n} = x_{2n+1}, V = DFT(v) (forward),
+// X_k = Re(e^{-i pi k / (2N)} V_k).  Two real columns packed as one complex
+// column give A_k = (V_k + conj V_{N-k}) / 2 and B_k = (V_k - conj V_{N-k}) / (2i)
+// for the two; a real row gives V from the half-length transform, and
+// X_k = Re(W_k), X_{N-k} = -Im(W_k) with W_k = e^{-i pi k / (2N)} V_k.
+
+// squared frequency (float64) of slot (n1, no, nd), for d log S
+__device__ __forceinline__ double r2r_p2(const Args& a, int n1, int no, int nd) {
+  const int k1 = (a.bcmask & 1) ? a.n1 - n1 : n1;
+  const int ko = (a.bcmask & 2) ? a.no - no : no;
+  const int kd = (a.bcmask & 4) ? a.nd - nd : nd;
+  return 0.25 * ((double)k1 * k1 * a.il2[0] + (double)ko * ko * a.il2[1] + (double)kd * kd * a.il2[2]);
+}
+
+// The reduction step of four consecutive slots (row = n1 * no + no index,
+// last-axis slots s .. s + 3) of field b with G = (B^T g) there: regenerate
+// z (or read it from a.src2), add the terms, write dL/dz to a.aux if asked.
+template <typename T, bool UNIFORM_KEY>
+__device__ __forceinline__ void r2r_adj4(const Args& a, const Filt<T>& f, AdjAcc<T>& ad, int b, uint32_t k0,
+                                         uint32_t k1, int n1, int no, int s, const T* G, int nvalid) {
+  const int row = n1 * a.no + no;
+  T z[4];
+  if (a.src2 == nullptr) {
+    normals4<T, UNIFORM_KEY>((uint32_t)(s >> 2), (uint32_t)row, (uint32_t)a.tag, k0, k1, z);
+  } else {
+    const T* p = (const T*)a.src2 + (long long)b * a.field_stride * 2 + (long long)row * a.nd + s;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) z[e] = e < nvalid ? p[e] : (T)0;
+  }
+  T* gz = a.aux ? (T*)a.aux + (long long)b * a.field_stride * 2 + (long long)row * a.nd + s : nullptr;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    if (e < nvalid) {
+      const T c = a.htab ? ((const T*)a.htab)[(long long)row * a.nd + s + e] : r2r_coef<T>(a, f, n1, no, s + e);
+      ad.add(1.0, (double)c, r2r_p2(a, n1, no, s + e), mk<T>(z[e], (T)0), mk<T>(G[e], (T)0));
+      if (gz) gz[e] = c * G[e];
+    }
+  }
+}
+
+// Column pass: DCT-II along a leading axis, in place (RED = false) or, on
+// axis 1, followed by the reduction (RED = true: nothing is written back; the
+// workgroup's sums go to a.partial[((b * nfixed + fx) * ntile + tile) * 3 ..]).
+template <typename T, int L, class Rad, int CP, int PAD, bool RED>
+struct R2RColF {
+  using V = C<T>;
+  using E = Vec<T, 2>;
+  static constexpr int NT = L / Rad::get(0);
+  static constexpr int THREADS = (NT * CP + 63) / 64 * 64;
+  static constexpr int NW = THREADS / 64;
+  static constexpr int RS = CP + PAD;
+  static constexpr int R0 = Rad::get(0);
+  static constexpr int LDS_BYTES = L * RS * (int)sizeof(E) + 2 * L * (int)sizeof(V) + 3 * NW * (int)sizeof(double);
+  using EN = Eng<T, L, Rad, NT, 2, 1>;
+  static_assert(L % 2 == 0, "even lengths only");
+
+  __device__ __forceinline__ static void run(const Args& a, int bid, char* smem) {
+    E* sm = reinterpret_cast<E*>(smem);
+    V* tw = reinterpret_cast<V*>(smem + L * RS * sizeof(E));
+    V* tq = tw + L;
+    double* red = reinterpret_cast<double*>(tq + L);
+    const int tid = threadIdx.x;
+    const int cp = tid % CP;
+    const int t = tid / CP;
+    const int tile = bid % a.ntile;
+    const int rest = bid / a.ntile;
+    const int fx = rest % a.nfixed;
+    const int b = rest / a.nfixed;
+    const int m0 = (tile * CP + cp) * 2;
+    const bool act = (t < NT) && (m0 < a.M);
+    const bool two = (m0 + 1) < a.M;
+    const bool al = (a.M & 1) == 0;
+    V* base = (V*)a.data + (long long)b * a.field_stride + (long long)fx * a.stride_fixed + m0;
+    for (int i = tid; i < L; i += blockDim.x) {
+      tw[i] = ((const V*)a.tw)[i];
+      tq[i] = ((const V*)a.tq)[i];
+    }
+    const bool neg = a.sine != 0;
+    V x[2][EN::REG];
+    if (act) {
+#pragma unroll
+      for (int m = 0; m < R0; ++m) {
+        const int mm = t + m * NT;
+        const int j = 2 * mm < L ? 2 * mm : 2 * (L - 1 - mm) + 1;   // v_mm = x_j
+        ld_pair<T>(base + (long long)j * a.stride_ax, two, al, x[0][m], x[1][m]);
+        if (neg && (j & 1)) {
+          x[0][m] = mk<T>(-x[0][m].x, -x[0][m].y);
+          x[1][m] = mk<T>(-x[1][m].x, -x[1][m].y);
+        }
+      }
+    }
+    __syncthreads();   // the twiddle tables
+    auto lds = [&](int i) -> E& { return sm[i * RS + cp]; };
+    auto none = [&](int, const E&) {};
+    EN::template run<-1>(x, t, act, lds, tw, none);
+    constexpr int LAST = Rad::count - 1;
+    constexpr int RL_ = Rad::get(LAST), NBL = EN::NB(LAST), LRL = L / RL_;
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int bb = 0; bb < NBL; ++bb) {
+        const int j = t + bb * NT;
+        if (NBL * NT == LRL || j < LRL) {
+#pragma unroll
+          for (int m = 0; m < RL_; ++m) {
+            E e;
+            e.v[0] = x[0][bb * RL_ + m];
+            e.v[1] = x[1][bb * RL_ + m];
+            sm[(j + m * LRL) * RS + cp] = e;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    double acc0 = 0, acc1 = 0, acc2 = 0;
+    if (act) {
+      const FieldRec& rec = a.recs[b * a.rec_stride];
+      const Filt<T> f = load_filt<T>(rec, 1.0);
+      AdjAcc<T> ad(rec);
+      const unsigned long long key = a.seed + (unsigned long long)b;
+#pragma unroll
+      for (int m = 0; m < R0; ++m) {
+        const int k = t + m * NT;
+        const E vk = sm[k * RS + cp];
+        const E vm = sm[((L - k) % L) * RS + cp];
+        const V q = mk<T>((T)2 * tq[k].x, (T)-2 * tq[k].y);   // e^{-i pi k / (2L)}
+        T X[4];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const V A = mk<T>((T)0.5 * (vk.v[c].x + vm.v[c].x), (T)0.5 * (vk.v[c].y - vm.v[c].y));
+          const V B = mk<T>((T)0.5 * (vk.v[c].y + vm.v[c].y), (T)-0.5 * (vk.v[c].x - vm.v[c].x));
+          X[2 * c] = fmat(q.x, A.x, -(q.y * A.y));
+          X[2 * c + 1] = fmat(q.x, B.x, -(q.y * B.y));
+        }
+        if constexpr (RED) {
+          r2r_adj4<T, true>(a, f, ad, b, (uint32_t)key, (uint32_t)(key >> 32), k, fx, 2 * m0, X, two ? 4 : 2);
+        } else {
+          E o;
+          o.v[0] = mk<T>(X[0], X[1]);
+          o.v[1] = mk<T>(X[2], X[3]);
+          st_pair<T>(base + (long long)k * a.stride_ax, two, al, o);
+        }
+      }
+      acc0 = ad.acc0 * rec.gs;
+      acc1 = ad.acc1;
+      acc2 = ad.acc2;
+    }
+    if constexpr (RED) {
+      for (int off = 32; off > 0; off >>= 1) {
+        acc0 += __shfl_xor(acc0, off);
+        acc1 += __shfl_xor(acc1, off);
+        acc2 += __shfl_xor(acc2, off);
+      }
+      const int lane = tid & 63, wv = tid >> 6;
+      if (lane == 0) {
+        red[wv] = acc0;
+        red[NW + wv] = acc1;
+        red[2 * NW + wv] = acc2;
+      }
+      __syncthreads();
+      if (tid < 3) {
+        double sacc = 0;
+        for (int w = 0; w < NW; ++w) sacc += red[tid * NW + w];
+        a.partial[((long long)(b * a.nfixed + fx) * a.ntile + tile) * 3 + tid] = sacc;
+      }
+    }
+  }
+};
+
+template <typename T, int L, class Rad, int CP, int PAD, bool RED>
+__global__ void __launch_bounds__((R2RColF<T, L, Rad, CP, PAD, RED>::THREADS)) k_r2r_colf(Args a) {
+  using PS = R2RColF<T, L, Rad, CP, PAD, RED>;
+  __shared__ __align__(16) char smem[PS::LDS_BYTES];
+  PS::run(a, col_block(a.order), smem);
+}
+
+// Row pass: DCT-II along the last axis of the rows of a.src into a.data
+// (RED = false), or (RED = true, d = 1, a row is a field) followed by the
+// reduction: each row's sums go to a.partial[field * 3 ..].
+template <typename T, int M, class Rad, int RB, bool RED>
+struct R2RRowF {
+  using V = C<T>;
+  using E = Vec<T, 1>;
+  using RL = RowLds<M>;
+  static constexpr int N = 2 * M;
+  static constexpr int NT = M / Rad::get(0);
+  static constexpr int THREADS = (NT * RB + 63) / 64 * 64;
+  static constexpr int R0 = Rad::get(0);
+  static constexpr bool WAVE = (64 % NT) == 0;
+  static constexpr int ROWS_BYTES = RB * RL::STRIDE * (int)sizeof(E);
+  static constexpr int RED_BYTES = RED ? 3 * THREADS * (int)sizeof(double) : 0;
+  static constexpr int LDS_BYTES = ROWS_BYTES + N * (int)sizeof(V) + RED_BYTES;
+  using EN = Eng<T, M, Rad, NT, 1, 2, WAVE>;
+
+  __device__ __forceinline__ static void run(const Args& a, int bid, char* smem) {
+    E* sm = reinterpret_cast<E*>(smem);
+    V* tw = reinterpret_cast<V*>(smem + ROWS_BYTES);
+    double* red = reinterpret_cast<double*>(smem + ROWS_BYTES + N * sizeof(V));
+    const V* tq = (const V*)a.tq;
+    const int tid = threadIdx.x;
+    const int r = tid / NT, t = tid % NT;
+    const long long row0 = (long long)bid * RB;
+    const long long left = a.rows - row0;
+    const int nrows = left < RB ? (int)left : RB;
+    const bool act = r < nrows;
+    TwFill<V, N, THREADS> twf;
+    if (tid < THREADS) {
+      twf.load((const V*)a.tw2, tid);
+      copy_in<T, M, RB * M, THREADS>((const V*)a.src + row0 * M, sm, nrows * M, tid);
+      twf.store(tw, tid);
+    }
+    __syncthreads();
+    E* rowp = sm + r * RL::STRIDE;
+    auto X = [&](int i) -> T {
+      const V c = rowp[RL::idx(i >> 1)].v[0];
+      return (i & 1) ? c.y : c.x;
+    };
+    const bool neg = a.sine != 0;
+    // v_m = x_rho(m) (times (-1)^rho(m) on a sine axis), z_n = v_{2n} + i v_{2n+1}
+    auto v = [&](int m) -> T {
+      const int j = m < M ? 2 * m : 2 * (N - 1 - m) + 1;
+      const T xv = X(j);
+      return (neg && (j & 1)) ? -xv : xv;
+    };
+    V x[1][EN::REG];
+    if (act) {
+#pragma unroll
+      for (int m = 0; m < R0; ++m) {
+        const int n = t + m * NT;
+        x[0][m] = mk<T>(v(2 * n), v(2 * n + 1));
+      }
+    }
+    __syncthreads();
+    auto lds = [&](int i) -> E& { return rowp[RL::idx(i)]; };
+    auto none = [&](int, const E&) {};
+    EN::template run<-1>(x, t, act, lds, tw, none);
+    constexpr int LAST = Rad::count - 1;
+    constexpr int RL_ = Rad::get(LAST), NBL = EN::NB(LAST), LRL = M / RL_;
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int bb = 0; bb < NBL; ++bb) {
+        const int j = t + bb * NT;
+        if (NBL * NT == LRL || j < LRL) {
+#pragma unroll
+          for (int m = 0; m < RL_; ++m) rowp[RL::idx(j + m * LRL)].v[0] = x[0][bb * RL_ + m];
+        }
+      }
+    }
+    __syncthreads();
+    // V_k = E_k + e^{-2 pi i k / N} O_k from Z_k and Z_{M-k}; W_k = e^{-i pi k/(2N)} V_k
+    T xo[R0][2];
+    T xm = (T)0;
+    if (act) {
+#pragma unroll
+      for (int m = 0; m < R0; ++m) {
+        const int k = t + m * NT;
+        const V zk = rowp[RL::idx(k)].v[0];
+        const V zc = cconj(rowp[RL::idx(k == 0 ? 0 : M - k)].v[0]);
+        const V Ek = mk<T>((T)0.5 * (zk.x + zc.x), (T)0.5 * (zk.y + zc.y));
+        const V Ok = mk<T>((T)0.5 * (zk.y - zc.y), (T)-0.5 * (zk.x - zc.x));
+        const V Vk = cadd(Ek, cmul(Ok, cconj(tw[k])));
+        const V q = mk<T>((T)2 * tq[k].x, (T)-2 * tq[k].y);
+        const V W = cmul(q, Vk);
+        xo[m][0] = W.x;    // X_k
+        xo[m][1] = -W.y;   // X_{N-k} (k > 0)
+      }
+      if (t == 0) {   // k = M: V_M = Re Z_0 - Im Z_0 (real), X_M = V_M / sqrt 2
+        const V z0 = rowp[RL::idx(0)].v[0];
+        xm = (z0.x - z0.y) * (T)0.70710678118654752440;
+      }
+    }
+    __syncthreads();
+    auto Xw = [&](int i, T val) {   // real i of the row, in the RowLds layout of pairs
+      const int c = RL::idx(i >> 1);
+      reinterpret_cast<T*>(&rowp[c].v[0])[i & 1] = val;
+    };
+    if (act) {
+#pragma unroll
+      for (int m = 0; m < R0; ++m) {
+        const int k = t + m * NT;
+        Xw(k, xo[m][0]);
+        if (k > 0) Xw(N - k, xo[m][1]);
+      }
+      if (t == 0) Xw(M, xm);
+    }
+    __syncthreads();
+    if constexpr (!RED) {
+      if (act) {
+        V* o = (V*)a.data + (row0 + r) * M;
+        for (int n = t; n < M; n += NT) o[n] = rowp[RL::idx(n)].v[0];
+      }
+    } else {
+      double acc0 = 0, acc1 = 0, acc2 = 0;
+      if (act) {
+        const int b = (int)(row0 + r);
+        const FieldRec& rec = a.recs[b * a.rec_stride];
+        const Filt<T> f = load_filt<T>(rec, 1.0);
+        AdjAcc<T> ad(rec);
+        const unsigned long long key = a.seed + (unsigned long long)b;
+        for (int q4 = t; q4 < M / 2; q4 += NT) {
+          const V p0 = rowp[RL::idx(2 * q4)].v[0], p1 = rowp[RL::idx(2 * q4 + 1)].v[0];
+          const T G[4] = {p0.x, p0.y, p1.x, p1.y};
+          r2r_adj4<T, false>(a, f, ad, b, (uint32_t)key, (uint32_t)(key >> 32), 0, 0, 4 * q4, G, 4);
+        }
+        acc0 = ad.acc0 * rec.gs;
+        acc1 = ad.acc1;
+        acc2 = ad.acc2;
+      }
+      red[tid] = acc0;
+      red[THREADS + tid] = acc1;
+      red[2 * THREADS + tid] = acc2;
+      __syncthreads();
+      if (act && t == 0) {
+        for (int c = 0; c < 3; ++c) {
+          double sacc = 0;
+          for (int i = 0; i < NT; ++i) sacc += red[c * THREADS + r * NT + i];
+          a.partial[(row0 + r) * 3 + c] = sacc;
+        }
+      }
+    }
+  }
+};
+
+template <typename T, int M, class Rad, int RB, bool RED>
+__global__ void __launch_bounds__((R2RRowF<T, M, Rad, RB, RED>::THREADS)) k_r2r_rowf(Args a) {
+  using PS = R2RRowF<T, M, Rad, RB, RED>;
+  __shared__ __align__(16) char smem[PS::LDS_BYTES];
+  PS::run(a, blockIdx.x, smem);
+}
+
 }  // namespace grf

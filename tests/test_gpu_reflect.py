@@ -157,9 +157,8 @@ def test_validation(grf):
         grf.Plan((16, 16), boundary=("neumann", "periodic"))
     with pytest.raises(grf.GRFError, match="EUNSUPPORTED"):
         grf.Plan((16, 16), alg=1, boundary="neumann")
-    plan = grf.Plan((16, 16), boundary="neumann")
     with pytest.raises(grf.GRFError, match="EUNSUPPORTED"):
-        plan.backward(torch.ones((1, 16, 16), device="cuda"), seed=0)
+        grf.Plan((16, 16), boundary="neumann", draw_order="recursive")
     S = np.ones((16, 16))
     S[3, 4] = -1.0
     with pytest.raises(grf.GRFError, match="EINVAL"):
