@@ -89,3 +89,27 @@ def test_sample_reads_the_tag3_stream_in_row_major_order():
         z = noise.field_noise(dims, 5 + b, 3)
         np.testing.assert_array_equal(phi[b], recursive.alg3_from_stream(z.ravel(), dims, (1.0, 1.0),
                                                                           spectra.GAUSSIAN, 1.0, 0.2))
+
+
+# ---------------------------------------------------------------------------
+# adjoint, pinned by central finite differences of the sampler itself
+
+@pytest.mark.parametrize("dims", [(8,), (4, 6), (4, 4, 4)], ids=str)
+def test_adjoint_finite_differences(dims):
+    lengths = tuple(1.0 + 0.5 * i for i in range(len(dims)))
+    z = noise.field_noise(dims, 2, 3).ravel()
+    w = np.random.default_rng(1).uniform(size=dims)
+    th = np.array([1.1, 0.3, 1.5])
+    phi = lambda t, zz: recursive.alg3_from_stream(zz, dims, lengths, spectra.MATERN, *t)
+    loss = lambda t, zz: np.sum(w * phi(t, zz) ** 2)
+    g = 2 * w * phi(th, z)
+    got = recursive.grad_theta(z, g, lengths, spectra.MATERN, *th)
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = 1e-6 * th[i]
+        fd = (loss(th + e, z) - loss(th - e, z)) / (2 * e[i])
+        assert got[i] == pytest.approx(fd, rel=1e-6)
+    gz = recursive.grad_stream(g, lengths, spectra.MATERN, *th).ravel()
+    dz = np.random.default_rng(2).normal(size=z.size)
+    fd = (loss(th, z + 1e-6 * dz) - loss(th, z - 1e-6 * dz)) / 2e-6
+    assert np.dot(gz, dz) == pytest.approx(fd, rel=1e-7)
