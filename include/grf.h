@@ -129,7 +129,7 @@ enum { GRF_DRAW_COUNTER = 0, GRF_DRAW_RECURSIVE = 1 };
  *             then imaginary part), then the plane k_d = 0, then k_d = N_d/2,
  *             each by the same rule over the axes before d; on axis 1 the
  *             real entries k_1 = 0 and N_1/2 come last.  GRF_ALG_ONE_FFT with
- *             periodic axes only; no adjoint (GRF_EUNSUPPORTED).
+ *             periodic axes only (else GRF_EUNSUPPORTED).
  */
 typedef struct {
   int32_t ndim;
@@ -250,9 +250,10 @@ grf_status grf_noise(grf_plan plan, uint64_t seed, int64_t batch, void* noise_ou
  *   grad_noise    = dL/dz (device, field-shaped; NULL to skip).
  * The noise is regenerated from `seed` (noise == NULL) or read from `noise`.
  * The Fourier transform of grad_out is recomputed; no spectrum is stored by
- * the forward call.  Both algorithms (the two-FFT one with d = 2) and the
- * reflecting boundaries (B^T g by the transposed cosine transforms), the
- * counter draw order (else GRF_EUNSUPPORTED); ndim = 1, 2 or 3.
+ * the forward call.  Both algorithms (the two-FFT one with d = 2), the
+ * reflecting boundaries (B^T g by the transposed cosine transforms) and both
+ * draw orders (in the recursive one dL/dz is indexed like the sequence of
+ * draws); ndim = 1, 2 or 3.
  * For the two-FFT algorithm xi = F[z] / sqrt(P) enters in place of the
  * Hermitian noise, and dL/dz = F*[h F[grad_out]] / sqrt(P), the sampler
  * applied to grad_out. */

@@ -952,8 +952,6 @@ grf_status grf_backward(grf_plan p, uint64_t seed, const void* noise, int64_t ba
                         const void* grad_out, double* grad_theta, void* grad_noise, void* workspace,
                         size_t workspace_bytes, void* stream) {
   if (p == nullptr) return fail(GRF_EINVAL, "null plan");
-  if (p->desc.draw_order != GRF_DRAW_COUNTER)
-    return fail(GRF_EUNSUPPORTED, "adjoint implemented for the counter draw order");
   if (batch < 0) return fail(GRF_EINVAL, "negative batch");
   if (batch == 0) return GRF_OK;
   if (grad_out == nullptr || grad_theta == nullptr) return fail(GRF_EINVAL, "null gradient pointer");
@@ -1071,6 +1069,9 @@ grf_status grf_backward(grf_plan p, uint64_t seed, const void* noise, int64_t ba
       if (st != GRF_OK) return st;
       continue;
     }
+    const bool seq = p->desc.draw_order == GRF_DRAW_RECURSIVE;
+    c.seq = seq;
+    if (seq) c.tag = 3;
     if (p->d == 1) {
       c.ntile = at.ntile;
       hipError_t e = grf::launch_grad1d(p->dtype, c, nb * at.ntile, s);
@@ -1092,7 +1093,9 @@ grf_status grf_backward(grf_plan p, uint64_t seed, const void* noise, int64_t ba
     c.stride_ax = (long long)p->no * p->M;
     c.stride_fixed = p->M;
     c.nfixed = p->no;
-    st = run_pass(p, p->d == 3 ? grf::PASS_COL_GRAD3 : grf::PASS_COL_GRAD, p->n1, c, 0, nb, s);
+    const int gp = p->d == 3 ? (seq ? grf::PASS_COL_GRAD3_SEQ : grf::PASS_COL_GRAD3)
+                             : (seq ? grf::PASS_COL_GRAD_SEQ : grf::PASS_COL_GRAD);
+    st = run_pass(p, gp, p->n1, c, 0, nb, s);
     if (st != GRF_OK) return st;
     if (p->d == 3 && grad_noise) {
       hipError_t e = grf::launch_grad_plane(p->dtype, c, s);

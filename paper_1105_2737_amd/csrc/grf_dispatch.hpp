@@ -49,6 +49,8 @@ enum PassKind {
   PASS_R2R_ROW_FWD_RED = 103,
   PASS_R2R_COL_FWD = 104,
   PASS_R2R_COL_FWD_RED = 105,
+  PASS_COL_GRAD_SEQ = 106,                     // PASS_COL_GRAD / _GRAD3 in the recursive draw order
+  PASS_COL_GRAD3_SEQ = 107,
 };
 
 inline bool is_r2r_pass(int p) {

@@ -728,7 +728,10 @@ struct AdjAcc {
 // XI (two-FFT algorithm, d = 2): xi = a.scale F[z] is read from a.src2 (the
 // white noise's spectrum after the same transforms) instead of being
 // regenerated; its plane slot is unpacked with the mirrored row like G's.
-template <typename T, int L, class Rad, int CP, int PAD, bool D3 = false, bool XI = false>
+// SEQ: the noise in the recursive algorithm's draw order (seq_entry); dL/dz
+// of an entry goes to the positions of its own draws (a mirrored entry owns
+// none).
+template <typename T, int L, class Rad, int CP, int PAD, bool D3 = false, bool XI = false, bool SEQ = false>
 __global__ void __launch_bounds__(((L / Rad::get(0)) * CP + 63) / 64 * 64)
 k_colg(Args a) {
   using V = C<T>;
@@ -761,7 +764,7 @@ k_colg(Args a) {
   // Straight-line route for the common case (generated noise, filter table,
   // a column pair away from the packed plane slot): the filter-table loads of
   // all rows are issued together and the R0 Philox blocks are independent.
-  const bool straight = !XI && a.src == nullptr && a.htab != nullptr && m0 > 0;
+  const bool straight = !XI && !SEQ && a.src == nullptr && a.htab != nullptr && m0 > 0;
   if (act) {
 #pragma unroll
     for (int m = 0; m < R0; ++m)
@@ -824,6 +827,55 @@ k_colg(Args a) {
       const int q1 = wrapk(kk1, L);
       const double p2b = (double)(q1 * q1) * a.il2[0] + p2o;
       const E e = sm[kk1 * RS + cp];
+      if constexpr (SEQ) {
+        const T* hr = a.htab ? (const T*)a.htab + (long long)row * (a.M + 2) : nullptr;
+        auto hv = [&](int mm) -> T { return hr ? hr[mm] : filt_h(f, (T)(p2b + (double)mm * mm * il2d)); };
+        T* gzf = gz ? gz + (long long)b * a.field_stride * 2 : nullptr;
+        // dL/dz of entry (kk1, fx, mm) with xi-gradient value gv = w h G / 2 per draw
+        auto put = [&](int mm, T h, V Gv) {
+          if (!gzf) return;
+          const SeqDraw d = seq_draw(a, kk1, fx, mm);
+          if (d.kind == 0) {
+            gzf[d.j] = s2 * h * Gv.x;
+            gzf[d.j + 1] = s2 * h * Gv.y;
+          } else if (d.kind == 2) {
+            gzf[d.j] = h * Gv.x;
+          }
+        };
+        if (two) {
+          const double p2 = p2b + (double)((m0 + 1) * (m0 + 1)) * il2d;
+          const T h = hv(m0 + 1);
+          add(2.0, (double)h, p2, seq_entry<T>(a, zsrc, b, k0, k1, kk1, fx, m0 + 1, (T)1), e.v[1]);
+          put(m0 + 1, h, e.v[1]);
+        }
+        if (m0 > 0) {
+          const double p2 = p2b + (double)(m0 * m0) * il2d;
+          const T h = hv(m0);
+          add(2.0, (double)h, p2, seq_entry<T>(a, zsrc, b, k0, k1, kk1, fx, m0, (T)1), e.v[0]);
+          put(m0, h, e.v[0]);
+        } else {
+          const double p2n = p2b + (double)a.M * (double)a.M * il2d;
+          const T hz = hv(0), hn = hv(a.M);
+          const V x0 = seq_entry<T>(a, zsrc, b, k0, k1, kk1, fx, 0, (T)1);
+          const V xn = seq_entry<T>(a, zsrc, b, k0, k1, kk1, fx, a.M, (T)1);
+          if constexpr (D3) {
+            const V Z = e.v[0];
+            add(1.0, (double)hz, p2b, x0, Z);
+            add(1.0, (double)hn, p2n, mk<T>(-xn.y, xn.x), Z);
+            if (a.plane) ((V*)a.plane)[(long long)b * a.n1 * a.no + row] = Z;
+          } else {
+            const V w = e.v[0];
+            const V wm = sm[((L - kk1) % L) * RS + cp].v[0];
+            const V g0 = mk<T>((T)0.5 * (w.x + wm.x), (T)0.5 * (w.y - wm.y));
+            const V gn = mk<T>((T)0.5 * (w.y + wm.y), (T)-0.5 * (w.x - wm.x));
+            add(1.0, (double)hz, p2b, x0, g0);
+            add(1.0, (double)hn, p2n, xn, gn);
+            put(0, hz, g0);
+            put(a.M, hn, gn);
+          }
+        }
+        continue;
+      }
       if constexpr (XI) {
         const V* zs = (const V*)a.src2 + (long long)b * a.field_stride + m0;
         const T sc = (T)a.scale;

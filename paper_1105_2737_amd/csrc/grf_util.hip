@@ -175,6 +175,39 @@ __global__ void __launch_bounds__(256) k_grad1d(Args a) {
     const V* G = (const V*)a.data + (long long)b * a.M;
     T* gz = a.aux ? (T*)a.aux + (long long)b * a.nd + 4 * q : nullptr;
     const T s = (T)0.70710678118654752440, s2 = (T)1.4142135623730950488;
+    if (a.seq) {
+      // draws 4q .. 4q+3: entries 2q+1 and 2q+2, or for the last block the
+      // real entries 0 and N/2
+      const int ka = 2 * q + 1, kb = 2 * q + 2;
+      const T ha = hk(ka);
+      const V Ga = G[ka];
+      ad.add(2.0, (double)ha, (double)ka * ka * il2, mk<T>(s * z[0], s * z[1]), Ga);
+      if (gz) {
+        gz[0] = s2 * ha * Ga.x;
+        gz[1] = s2 * ha * Ga.y;
+      }
+      if (kb < a.M) {
+        const T hb = hk(kb);
+        const V Gb = G[kb];
+        ad.add(2.0, (double)hb, (double)kb * kb * il2, mk<T>(s * z[2], s * z[3]), Gb);
+        if (gz) {
+          gz[2] = s2 * hb * Gb.x;
+          gz[3] = s2 * hb * Gb.y;
+        }
+      } else {
+        const V G0 = G[0];
+        const T h0 = hk(0), hm = hk(a.M);
+        ad.add(1.0, (double)h0, 0.0, mk<T>(z[2], (T)0), mk<T>(G0.x, (T)0));
+        ad.add(1.0, (double)hm, (double)a.M * a.M * il2, mk<T>(z[3], (T)0), mk<T>(G0.y, (T)0));
+        if (gz) {
+          gz[2] = h0 * G0.x;
+          gz[3] = hm * G0.y;
+        }
+      }
+      acc0 = ad.acc0 * rec.gs;
+      acc1 = ad.acc1;
+      acc2 = ad.acc2;
+    } else {
     const int ka = 2 * q + 1, kb = 2 * q;
     const T ha = hk(ka);
     const V Ga = G[ka];
@@ -203,6 +236,7 @@ __global__ void __launch_bounds__(256) k_grad1d(Args a) {
     acc0 = ad.acc0 * rec.gs;
     acc1 = ad.acc1;
     acc2 = ad.acc2;
+    }
   }
   __shared__ double red[3][4];
   for (int off = 32; off > 0; off >>= 1) {
@@ -250,6 +284,23 @@ __global__ void k_grad_plane(Args a) {
   const T hz = hrow ? hrow[0] : filt_h(f, (T)p2b);
   const T hn = hrow ? hrow[a.M] : filt_h(f, (T)p2n);
   const T s2 = (T)1.4142135623730950488;
+  if (a.seq) {   // the draws of the plane entries (k, 0) and (k, N_d/2) of this row
+    T* gzf = (T*)a.aux + (long long)b * a.field_stride * 2;
+    const SeqDraw d0 = seq_draw(a, k1, o, 0), dn = seq_draw(a, k1, o, a.M);
+    if (d0.kind == 0) {
+      gzf[d0.j] = s2 * hz * g0.x;
+      gzf[d0.j + 1] = s2 * hz * g0.y;
+    } else if (d0.kind == 2) {
+      gzf[d0.j] = hz * g0.x;
+    }
+    if (dn.kind == 0) {
+      gzf[dn.j] = s2 * hn * gn.x;
+      gzf[dn.j + 1] = s2 * hn * gn.y;
+    } else if (dn.kind == 2) {
+      gzf[dn.j] = hn * gn.x;
+    }
+    return;
+  }
   T* gzr = (T*)a.aux + (long long)b * a.field_stride * 2 + (long long)row * a.nd;
   if (nrow == row) {
     gzr[0] = hz * g0.x;

@@ -101,8 +101,5 @@ def test_validation(grf):
         grf.Plan((16, 16), alg=1, draw_order="recursive")
     with pytest.raises(grf.GRFError, match="EUNSUPPORTED"):
         grf.Plan((16, 16), boundary="neumann", draw_order="recursive")
-    plan = grf.Plan((16, 16), draw_order="recursive")
-    with pytest.raises(grf.GRFError, match="EUNSUPPORTED"):
-        plan.backward(torch.ones((1, 16, 16), device="cuda"), seed=0)
     with pytest.raises(KeyError):
         grf.Plan((16, 16), draw_order="sequential")
