@@ -399,6 +399,21 @@ def main():
         g3 = o3a.clone()
         s3b = timed(lambda: p3a.backward(g3, seed=0), max(args.steps // 10, 5), 2, torch)
         s3z = timed(lambda: p3a.backward(g3, seed=0, need_noise_grad=True), max(args.steps // 10, 5), 2, torch)
+        # the adjoint of the other samplers on the headline grid (512^2 x 256 fields)
+        av = {}
+        oav = torch.empty((256, 512, 512), dtype=torch.float32, device="cuda")
+        for nm, kw in (("two_fft", dict(alg=1)), ("neumann", dict(boundary="neumann")),
+                       ("dirichlet", dict(boundary="dirichlet")), ("recursive_order", dict(draw_order="recursive"))):
+            pv = grf.Plan((512, 512), dtype=torch.float32, cov="matern", sigma=1.0, length_scale=0.1, nu=1.5, **kw)
+            sfv = timed(lambda: pv.sample(seed=0, batch=256, out=oav), max(args.steps // 10, 5), 2, torch)
+            gv = oav.clone()
+            sbv = timed(lambda: pv.backward(gv, seed=0), max(args.steps // 10, 5), 2, torch)
+            av[nm] = {"fwd_ms": round(sfv * 1e3, 4), "adjoint_ms": round(sbv * 1e3, 4),
+                      "ratio_adjoint_vs_fwd": round(sbv / sfv, 3)}
+            del pv, gv
+        extra["adjoint_variants_512_x256"] = av
+        del oav
+        torch.cuda.empty_cache()
         extra["adjoint_256cubed_x16"] = {"fwd_ms": round(s3f * 1e3, 4), "adjoint_ms": round(s3b * 1e3, 4),
                                          "adjoint_with_noise_grad_ms": round(s3z * 1e3, 4),
                                          "ratio_adjoint_vs_fwd": round(s3b / s3f, 3),
