@@ -108,6 +108,8 @@ struct R2RCol {
   static constexpr int LDS_BYTES = L * RS * (int)sizeof(E) + 2 * L * (int)sizeof(V);
   using EN = Eng<T, L, Rad, NT, 2, 1>;
   static_assert(L % 2 == 0, "even lengths only");
+  // straight-line generation for long columns, as in the periodic column pass
+  static constexpr bool GEN_STRAIGHT = L >= 500;
 
   __device__ __forceinline__ static void run(const Args& a, int bid, char* smem) {
     E* sm = reinterpret_cast<E*>(smem);
@@ -135,12 +137,33 @@ struct R2RCol {
         const Filt<T> f = load_filt<T>(a.recs[b * a.rec_stride], 1.0);
         const unsigned long long key = a.seed + (unsigned long long)b;
         const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
+        if (GEN_STRAIGHT && a.src == nullptr && a.htab != nullptr && al) {
+          // straight-line: the coefficient loads of all rows first, then the
+          // R0 independent Philox blocks (same products as r2r_gen4)
+          struct alignas(4 * sizeof(T)) P4 { T v[4]; };
+          P4 hc[R0];
 #pragma unroll
-        for (int m = 0; m < R0; ++m) {
-          T v[4];
-          r2r_gen4<T, true>(a, f, b, k0, k1, t + m * NT, fx, 2 * m0, v);
-          x[0][m] = mk<T>(v[0], v[1]);
-          x[1][m] = mk<T>(v[2], v[3]);
+          for (int m = 0; m < R0; ++m)
+            hc[m] = *reinterpret_cast<const P4*>((const T*)a.htab +
+                                                 (long long)((t + m * NT) * a.no + fx) * a.nd + 2 * m0);
+          T z[R0][4];
+#pragma unroll
+          for (int m = 0; m < R0; ++m)
+            normals4<T, true>((uint32_t)(m0 >> 1), (uint32_t)((t + m * NT) * a.no + fx), (uint32_t)a.tag, k0, k1,
+                              z[m]);
+#pragma unroll
+          for (int m = 0; m < R0; ++m) {
+            x[0][m] = mk<T>(hc[m].v[0] * z[m][0], hc[m].v[1] * z[m][1]);
+            x[1][m] = mk<T>(hc[m].v[2] * z[m][2], hc[m].v[3] * z[m][3]);
+          }
+        } else {
+#pragma unroll
+          for (int m = 0; m < R0; ++m) {
+            T v[4];
+            r2r_gen4<T, true>(a, f, b, k0, k1, t + m * NT, fx, 2 * m0, v);
+            x[0][m] = mk<T>(v[0], v[1]);
+            x[1][m] = mk<T>(v[2], v[3]);
+          }
         }
       } else {
 #pragma unroll
