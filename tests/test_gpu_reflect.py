@@ -167,3 +167,18 @@ def test_validation(grf):
         grf.Plan((16, 16), boundary="neumann", cov="tabulated", spectrum=np.ones((16, 9)))
     with pytest.raises(KeyError):
         grf.Plan((16, 16), boundary="robin")
+
+
+@pytest.mark.parametrize("sine", [False, True])
+def test_statistical_covariance_1d(grf, sine):
+    """d = 1: the estimator runs over sampled chunks (the fused 1D epilogue is
+    the periodic sampler's)."""
+    dims, lengths = (128,), (2.0,)
+    plan = grf.Plan(dims, lengths=lengths, boundary=bcs((sine,)), **MAT)
+    n = 100000
+    est = plan.covariance(seed=1, nsamples=n).cpu().numpy()
+    a = reflect.coefficients(dims, lengths, (sine,), kind=spectra.MATERN, sigma=1.2, ell=0.15, nu=1.5)
+    c = reflect.covariance_with(a, (sine,), (0,))
+    vx = np.array([reflect.covariance_with(a, (sine,), (i,))[i] for i in range(dims[0])])
+    se = np.sqrt((c[0] * vx + c ** 2) / n)
+    assert np.all(np.abs(est - c) <= 6 * se), np.max(np.abs(est - c) / se)
