@@ -448,8 +448,9 @@ struct ColPass {
   static constexpr int LDS_BYTES = L * RS * (int)sizeof(E) + L * (int)sizeof(V);
   // Straight-line generation (gen_fast) for long columns, where LDS bounds the
   // occupancy anyway; for short columns its extra registers cost occupancy
-  // (measured: 18% slower at L = 96, 22% faster at L = 1000 and 1024).
-  static constexpr bool GEN_STRAIGHT = L >= 500;
+  // (measured: 18% slower at L = 96, even at 256, 11% faster at 360, 22% at
+  // 1000 and 1024).
+  static constexpr bool GEN_STRAIGHT = L >= 360;
   using EN = Eng<T, L, Rad, NT, 2, 1>;
 
   // Noise generation of tile `tile` of field b (fixed index fx) straight into
