@@ -29,7 +29,13 @@ struct Gen1D {
   static constexpr int R0 = Rad::get(0);
   static constexpr bool WAVE = (64 % NT) == 0;
   static constexpr int ROWS_BYTES = RB * RL::STRIDE * (int)sizeof(E);
-  static constexpr int LDS_BYTES = ROWS_BYTES + 2 * M * (int)sizeof(V) + RB * (int)sizeof(T);
+  // Long rows read the twiddle table W_N through the caches instead of
+  // staging it in LDS: at M = 2048 the 32 KB table halved the workgroups per
+  // CU (measured: 4096-point fields 0.797 -> 0.660 ms per 65536, 3% faster at
+  // M = 1024, 2% slower at M = 256).
+  static constexpr bool TW_GLOBAL = M >= 1024;
+  static constexpr int TW_BYTES = TW_GLOBAL ? 0 : 2 * M * (int)sizeof(V);
+  static constexpr int LDS_BYTES = ROWS_BYTES + TW_BYTES + RB * (int)sizeof(T);
   using EN = Eng<T, M, Rad, NT, 1, 2, WAVE>;
   static_assert(M % 2 == 0, "a Philox block fills two complex entries");
   // the COV reduction reuses the rows area for M complex float64 values
@@ -109,13 +115,15 @@ struct Gen1D {
   // f at data + f*M + i: reals 2i and 2i+1).
   __device__ __forceinline__ static void run(const Args& a, int bid, char* smem) {
     E* sm = reinterpret_cast<E*>(smem);
-    V* tw = reinterpret_cast<V*>(smem + ROWS_BYTES);
+    V* tws = reinterpret_cast<V*>(smem + ROWS_BYTES);   // LDS copy (short rows)
+    const V* tw = TW_GLOBAL ? (const V*)a.tw2 : tws;
     const int tid = threadIdx.x;
     const int r = tid / NT, t = tid % NT;
     const long long f0 = (long long)bid * RB;
     const long long left = a.rows - f0;
     const int nrows = left < RB ? (int)left : RB;
-    for (int i = tid; i < 2 * M; i += blockDim.x) tw[i] = ((const V*)a.tw2)[i];
+    if constexpr (!TW_GLOBAL)
+      for (int i = tid; i < 2 * M; i += blockDim.x) tws[i] = ((const V*)a.tw2)[i];
     generate(a, f0, nrows, sm, tid);
     __syncthreads();
     const bool act = r < nrows;
@@ -134,8 +142,9 @@ struct Gen1D {
   // sums to partial + w * 2M.
   __device__ __forceinline__ static void run_cov(const Args& a, double* partial, char* smem) {
     E* sm = reinterpret_cast<E*>(smem);
-    V* tw = reinterpret_cast<V*>(smem + ROWS_BYTES);
-    T* phi0 = reinterpret_cast<T*>(smem + ROWS_BYTES + 2 * M * sizeof(V));
+    V* tws = reinterpret_cast<V*>(smem + ROWS_BYTES);   // LDS copy (short rows)
+    const V* tw = TW_GLOBAL ? (const V*)a.tw2 : tws;
+    T* phi0 = reinterpret_cast<T*>(smem + ROWS_BYTES + TW_BYTES);
     const int tid = threadIdx.x;
     const int r = tid / NT, t = tid % NT;
     constexpr int LAST = Rad::count - 1;
@@ -143,7 +152,8 @@ struct Gen1D {
     double acc[NBL * RL_][2];
 #pragma unroll
     for (int i = 0; i < NBL * RL_; ++i) acc[i][0] = acc[i][1] = 0.0;
-    for (int i = tid; i < 2 * M; i += blockDim.x) tw[i] = ((const V*)a.tw2)[i];
+    if constexpr (!TW_GLOBAL)
+      for (int i = tid; i < 2 * M; i += blockDim.x) tws[i] = ((const V*)a.tw2)[i];
     for (long long blk = blockIdx.x; blk * RB < a.rows; blk += gridDim.x) {
       const long long f0 = blk * RB;
       const long long left = a.rows - f0;
