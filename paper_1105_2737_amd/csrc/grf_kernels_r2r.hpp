@@ -237,7 +237,12 @@ struct R2RRow {
   static constexpr int R0 = Rad::get(0);
   static constexpr bool WAVE = (64 % NT) == 0;
   static constexpr int ROWS_BYTES = RB * RL::STRIDE * (int)sizeof(E);
-  static constexpr int LDS_BYTES = ROWS_BYTES + N * (int)sizeof(V);
+  // The d = 1 kernel (SRC_GEN) reads W_N of long rows through the caches
+  // rather than from LDS, as the periodic 1D kernel does (measured at 4096
+  // points: 0.838 -> 0.747 ms per 65536 fields); the load pass keeps the LDS
+  // copy (2.5% slower without it at 128 x 4096).
+  static constexpr bool TW_GLOBAL = SRC == SRC_GEN && M >= 1024;
+  static constexpr int LDS_BYTES = ROWS_BYTES + (TW_GLOBAL ? 0 : N * (int)sizeof(V));
   using EN = Eng<T, M, Rad, NT, 1, 2, WAVE>;
   static_assert(M % 2 == 0, "a Philox block fills two complex slots");
 
@@ -257,7 +262,8 @@ struct R2RRow {
 
   __device__ __forceinline__ static void run(const Args& a, int bid, char* smem) {
     E* sm = reinterpret_cast<E*>(smem);
-    V* tw = reinterpret_cast<V*>(smem + ROWS_BYTES);
+    V* tws = reinterpret_cast<V*>(smem + ROWS_BYTES);
+    const V* tw = TW_GLOBAL ? (const V*)a.tw2 : tws;
     const V* tq = (const V*)a.tq;
     const int tid = threadIdx.x;
     const int r = tid / NT, t = tid % NT;
@@ -266,8 +272,8 @@ struct R2RRow {
     const int nrows = left < RB ? (int)left : RB;
     const bool act = r < nrows;
     V* g = (V*)a.data + row0 * M;
-    TwFill<V, N, THREADS> twf;
-    if (tid < THREADS) twf.load((const V*)a.tw2, tid);
+    TwFill<V, TW_GLOBAL ? 1 : N, THREADS> twf;
+    if (!TW_GLOBAL && tid < THREADS) twf.load((const V*)a.tw2, tid);
     V x[1][EN::REG];
     if constexpr (SRC == SRC_GEN) {
       constexpr int NQ = M / 2;   // Philox blocks per row
@@ -282,7 +288,7 @@ struct R2RRow {
         rowp[RL::idx(2 * q)].v[0] = mk<T>(v[0], v[1]);
         rowp[RL::idx(2 * q + 1)].v[0] = mk<T>(v[2], v[3]);
       }
-      if (tid < THREADS) twf.store(tw, tid);
+      if (!TW_GLOBAL && tid < THREADS) twf.store(tws, tid);
       __syncthreads();
       const E* rowp = sm + r * RL::STRIDE;
       auto X = [&](int i) -> T {
@@ -310,7 +316,7 @@ struct R2RRow {
           xd[m] = xr[M + k];
         }
       }
-      if (tid < THREADS) twf.store(tw, tid);
+      if (!TW_GLOBAL && tid < THREADS) twf.store(tws, tid);
       __syncthreads();
       if (act) {
 #pragma unroll
@@ -554,13 +560,16 @@ struct R2RRowF {
   static constexpr bool WAVE = (64 % NT) == 0;
   static constexpr int ROWS_BYTES = RB * RL::STRIDE * (int)sizeof(E);
   static constexpr int RED_BYTES = RED ? 3 * THREADS * (int)sizeof(double) : 0;
-  static constexpr int LDS_BYTES = ROWS_BYTES + N * (int)sizeof(V) + RED_BYTES;
+  static constexpr bool TW_GLOBAL = RED && M >= 1024;   // as R2RRow: the d = 1 kernel only
+  static constexpr int TW_BYTES = TW_GLOBAL ? 0 : N * (int)sizeof(V);
+  static constexpr int LDS_BYTES = ROWS_BYTES + TW_BYTES + RED_BYTES;
   using EN = Eng<T, M, Rad, NT, 1, 2, WAVE>;
 
   __device__ __forceinline__ static void run(const Args& a, int bid, char* smem) {
     E* sm = reinterpret_cast<E*>(smem);
-    V* tw = reinterpret_cast<V*>(smem + ROWS_BYTES);
-    double* red = reinterpret_cast<double*>(smem + ROWS_BYTES + N * sizeof(V));
+    V* tws = reinterpret_cast<V*>(smem + ROWS_BYTES);
+    const V* tw = TW_GLOBAL ? (const V*)a.tw2 : tws;
+    double* red = reinterpret_cast<double*>(smem + ROWS_BYTES + TW_BYTES);
     const V* tq = (const V*)a.tq;
     const int tid = threadIdx.x;
     const int r = tid / NT, t = tid % NT;
@@ -568,11 +577,11 @@ struct R2RRowF {
     const long long left = a.rows - row0;
     const int nrows = left < RB ? (int)left : RB;
     const bool act = r < nrows;
-    TwFill<V, N, THREADS> twf;
+    TwFill<V, TW_GLOBAL ? 1 : N, THREADS> twf;
     if (tid < THREADS) {
-      twf.load((const V*)a.tw2, tid);
+      if (!TW_GLOBAL) twf.load((const V*)a.tw2, tid);
       copy_in<T, M, RB * M, THREADS>((const V*)a.src + row0 * M, sm, nrows * M, tid);
-      twf.store(tw, tid);
+      if (!TW_GLOBAL) twf.store(tws, tid);
     }
     __syncthreads();
     E* rowp = sm + r * RL::STRIDE;
