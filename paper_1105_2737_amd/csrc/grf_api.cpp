@@ -633,6 +633,136 @@ grf_status sample_impl(grf_plan p, uint64_t seed, const void* zsrc, int64_t batc
   return GRF_OK;
 }
 
+// ---- the adjoint's passes over one chunk of nb fields ----------------------
+// c: the reduction pass's arguments (records, seed, noise, dL/dz, partial sums,
+// c.data = the chunk's spectrum buffer); g: the chunk's upstream gradient.
+
+// Last-axis real-to-complex transform of g into c.data (periodic plans).
+grf_status adj_row_r2c(const grf_plan_s* p, const Args& c, const void* g, long long nb, hipStream_t s) {
+  Args r = base_args(p, nb);
+  r.data = c.data;
+  r.src = g;
+  r.tw2 = p->tw_row;
+  r.rows = nb * (p->P / p->nd);
+  return run_pass(p, grf::PASS_ROW_R2C_LOAD, p->M, r, 0, nb, s);
+}
+
+// One-FFT algorithm, periodic: G = F[g] by the last-axis R2C, (d = 3: the
+// middle axis forward,) then axis 1 forward inside the reduction pass; d = 1:
+// the reduction reads the last-axis spectrum.
+grf_status adj_chunk_one_fft(const grf_plan_s* p, Args c, const void* g, const AdjTiles& at, void* plane,
+                             long long nb, hipStream_t s) {
+  grf_status st = adj_row_r2c(p, c, g, nb, s);
+  if (st != GRF_OK) return st;
+  const bool seq = p->desc.draw_order == GRF_DRAW_RECURSIVE;
+  c.seq = seq;
+  c.tag = seq ? 3 : 1;
+  if (p->d == 1) {
+    c.ntile = at.ntile;
+    hipError_t e = grf::launch_grad1d(p->dtype, c, nb * at.ntile, s);
+    return e == hipSuccess ? GRF_OK : hip_fail(e, "adjoint launch");
+  }
+  if (p->d == 3) {
+    Args m = base_args(p, nb);
+    m.data = c.data;
+    m.tw = p->tw_col2;
+    m.stride_ax = p->M;
+    m.stride_fixed = (long long)p->no * p->M;
+    m.nfixed = p->n1;
+    st = run_pass(p, grf::PASS_COL_LOAD_FWD, p->no, m, 0, nb, s);
+    if (st != GRF_OK) return st;
+    c.plane = c.aux ? plane : nullptr;
+  }
+  c.tw = p->tw_col1;
+  c.stride_ax = (long long)p->no * p->M;
+  c.stride_fixed = p->M;
+  c.nfixed = p->no;
+  const int gp = p->d == 3 ? (seq ? grf::PASS_COL_GRAD3_SEQ : grf::PASS_COL_GRAD3)
+                           : (seq ? grf::PASS_COL_GRAD_SEQ : grf::PASS_COL_GRAD);
+  st = run_pass(p, gp, p->n1, c, 0, nb, s);
+  if (st != GRF_OK) return st;
+  if (p->d == 3 && c.aux) {
+    hipError_t e = grf::launch_grad_plane(p->dtype, c, s);
+    if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+  }
+  return GRF_OK;
+}
+
+// Two-FFT algorithm (d = 2): xi = F[z] / sqrt(P), the white noise through the
+// same transforms into spec2 (the table of a density-defined family already
+// holds the 1/sqrt(P)); dL/dz is left to the caller (the sampler applied to g).
+grf_status adj_chunk_two_fft(const grf_plan_s* p, Args c, const void* g, void* spec2, long long nb, hipStream_t s) {
+  grf_status st = adj_row_r2c(p, c, g, nb, s);
+  if (st != GRF_OK) return st;
+  Args rz = base_args(p, nb);
+  rz.data = spec2;
+  rz.src = c.src;
+  rz.recs = c.recs;
+  rz.rec_stride = c.rec_stride;
+  rz.seed = c.seed;
+  rz.tag = 0;
+  rz.tw2 = p->tw_row;
+  rz.rows = nb * (long long)p->n1;
+  st = run_pass(p, c.src ? grf::PASS_ROW_R2C_LOAD : grf::PASS_ROW_R2C_GEN, p->M, rz, 0, nb, s);
+  if (st != GRF_OK) return st;
+  Args cz = base_args(p, nb);
+  cz.data = spec2;
+  cz.tw = p->tw_col1;
+  cz.stride_ax = p->M;
+  cz.stride_fixed = p->M;
+  cz.nfixed = 1;
+  st = run_pass(p, grf::PASS_COL_LOAD_FWD, p->n1, cz, 0, nb, s);
+  if (st != GRF_OK) return st;
+  c.tag = 0;
+  c.aux = nullptr;
+  c.src2 = spec2;
+  c.scale = p->table_only ? 1.0 : 1.0 / std::sqrt((double)p->P);
+  c.tw = p->tw_col1;
+  c.stride_ax = p->M;
+  c.stride_fixed = p->M;
+  c.nfixed = 1;
+  return run_pass(p, grf::PASS_COL_GRAD1, p->n1, c, 0, nb, s);
+}
+
+// Reflecting boundaries: B^T g by transposed cosine transforms (DCT-II), last
+// axis first; the reduction runs with the last of them (axis 1, or the row
+// for d = 1).
+grf_status adj_chunk_reflect(const grf_plan_s* p, Args c, const void* g, long long nb, hipStream_t s) {
+  c.tag = 2;
+  c.bcmask = p->sinemask;
+  c.src2 = c.src;   // a given noise (src carries g in the row pass)
+  c.src = nullptr;
+  Args rr = c;
+  rr.src = g;
+  rr.tw2 = p->tw_row;
+  rr.tq = p->tq_row;
+  rr.sine = (p->sinemask >> 2) & 1;
+  rr.rows = nb * (p->P / p->nd);
+  if (p->d == 1) return run_pass(p, grf::PASS_R2R_ROW_FWD_RED, p->M, rr, 0, nb, s);
+  rr.aux = nullptr;
+  grf_status st = run_pass(p, grf::PASS_R2R_ROW_FWD, p->M, rr, 0, nb, s);
+  if (st != GRF_OK) return st;
+  if (p->d == 3) {
+    Args m = c;
+    m.aux = nullptr;
+    m.tw = p->tw_col2;
+    m.tq = p->tq_col2;
+    m.sine = (p->sinemask >> 1) & 1;
+    m.stride_ax = p->M;
+    m.stride_fixed = (long long)p->no * p->M;
+    m.nfixed = p->n1;
+    st = run_pass(p, grf::PASS_R2R_COL_FWD, p->no, m, 0, nb, s);
+    if (st != GRF_OK) return st;
+  }
+  c.tw = p->tw_col1;
+  c.tq = p->tq_col1;
+  c.sine = p->sinemask & 1;
+  c.stride_ax = (long long)p->no * p->M;
+  c.stride_fixed = p->M;
+  c.nfixed = p->no;
+  return run_pass(p, grf::PASS_R2R_COL_FWD_RED, p->n1, c, 0, nb, s);
+}
+
 }  // namespace
 
 namespace grf {
@@ -966,141 +1096,31 @@ grf_status grf_backward(grf_plan p, uint64_t seed, const void* noise, int64_t ba
   int rstride;
   st = field_records(p, theta, batch, ws + w.recs, w.partial, s, &recs, &rstride);
   if (st != GRF_OK) return st;
-  // G = F[g]: last axis real-to-complex, (d = 3: middle axis forward,) then
-  // axis 1 forward inside the reduction pass (d = 1: the reduction reads the
-  // last-axis spectrum); chunk by chunk (cache-sized, as the sampler), so that
-  // each pass reads the previous one's output from the last-level cache
+  // chunk by chunk (cache-sized, as the sampler), so that each pass reads the
+  // previous one's output from the last-level cache
   const AdjTiles at = adj_tiles(p);
   const long long C = chunk_fields(p, batch);
   const size_t fbytes = (size_t)p->P * p->esz;
   for (long long c0 = 0; c0 < batch; c0 += C) {
     const long long nb = std::min(C, batch - c0);
-    Args r = base_args(p, nb);
-    r.data = ws + w.spec;
-    r.src = (const char*)grad_out + c0 * fbytes;
-    r.tw2 = p->tw_row;
-    r.rows = nb * (p->P / p->nd);
-    st = run_pass(p, grf::PASS_ROW_R2C_LOAD, p->M, r, 0, nb, s);
-    if (st != GRF_OK) return st;
+    // the arguments of the reduction pass
     Args c = base_args(p, nb);
     c.recs = rstride ? recs + c0 : recs;
     c.rec_stride = rstride;
     c.seed = seed + (uint64_t)c0;
-    c.tag = 1;
-    c.htab = rstride == 0 ? p->htab : nullptr;   // one-FFT: the sampler's h is unscaled
+    c.htab = rstride == 0 ? p->htab : nullptr;
     c.data = ws + w.spec;
     c.src = noise ? (const char*)noise + c0 * fbytes : nullptr;
     c.aux = grad_noise ? (char*)grad_noise + c0 * fbytes : nullptr;
     c.partial = (double*)(ws + w.partial) + c0 * at.nper * 3;
-    if (p->reflect) {
-      // B^T g by transposed cosine transforms (DCT-II), last axis first; the
-      // reduction runs with the last of them (axis 1, or the row for d = 1)
-      c.tag = 2;
-      c.bcmask = p->sinemask;
-      c.src2 = c.src;   // given noise (src carries g in the row pass)
-      c.src = nullptr;
-      Args rr = c;
-      rr.src = (const char*)grad_out + c0 * fbytes;
-      rr.tw2 = p->tw_row;
-      rr.tq = p->tq_row;
-      rr.sine = (p->sinemask >> 2) & 1;
-      rr.rows = nb * (p->P / p->nd);
-      if (p->d == 1) {
-        st = run_pass(p, grf::PASS_R2R_ROW_FWD_RED, p->M, rr, 0, nb, s);
-        if (st != GRF_OK) return st;
-        continue;
-      }
-      rr.aux = nullptr;
-      st = run_pass(p, grf::PASS_R2R_ROW_FWD, p->M, rr, 0, nb, s);
-      if (st != GRF_OK) return st;
-      if (p->d == 3) {
-        Args m = c;
-        m.aux = nullptr;
-        m.tw = p->tw_col2;
-        m.tq = p->tq_col2;
-        m.sine = (p->sinemask >> 1) & 1;
-        m.stride_ax = p->M;
-        m.stride_fixed = (long long)p->no * p->M;
-        m.nfixed = p->n1;
-        st = run_pass(p, grf::PASS_R2R_COL_FWD, p->no, m, 0, nb, s);
-        if (st != GRF_OK) return st;
-      }
-      c.tw = p->tw_col1;
-      c.tq = p->tq_col1;
-      c.sine = p->sinemask & 1;
-      c.stride_ax = (long long)p->no * p->M;
-      c.stride_fixed = p->M;
-      c.nfixed = p->no;
-      st = run_pass(p, grf::PASS_R2R_COL_FWD_RED, p->n1, c, 0, nb, s);
-      if (st != GRF_OK) return st;
-      continue;
-    }
-    if (p->desc.alg == GRF_ALG_TWO_FFT) {
-      // xi = F[z] / sqrt(P): the white noise through the same transforms (the
-      // table of a density-defined family already holds the 1/sqrt(P))
-      Args rz = base_args(p, nb);
-      rz.data = ws + w.spec2;
-      rz.src = c.src;
-      rz.recs = c.recs;
-      rz.rec_stride = rstride;
-      rz.seed = c.seed;
-      rz.tag = 0;
-      rz.tw2 = p->tw_row;
-      rz.rows = nb * (long long)p->n1;
-      st = run_pass(p, noise ? grf::PASS_ROW_R2C_LOAD : grf::PASS_ROW_R2C_GEN, p->M, rz, 0, nb, s);
-      if (st != GRF_OK) return st;
-      Args cz = base_args(p, nb);
-      cz.data = ws + w.spec2;
-      cz.tw = p->tw_col1;
-      cz.stride_ax = p->M;
-      cz.stride_fixed = p->M;
-      cz.nfixed = 1;
-      st = run_pass(p, grf::PASS_COL_LOAD_FWD, p->n1, cz, 0, nb, s);
-      if (st != GRF_OK) return st;
-      c.tag = 0;
-      c.aux = nullptr;   // dL/dz below, by the sampler's passes
-      c.src2 = ws + w.spec2;
-      c.scale = p->table_only ? 1.0 : 1.0 / std::sqrt((double)p->P);
-      c.tw = p->tw_col1;
-      c.stride_ax = p->M;
-      c.stride_fixed = p->M;
-      c.nfixed = 1;
-      st = run_pass(p, grf::PASS_COL_GRAD1, p->n1, c, 0, nb, s);
-      if (st != GRF_OK) return st;
-      continue;
-    }
-    const bool seq = p->desc.draw_order == GRF_DRAW_RECURSIVE;
-    c.seq = seq;
-    if (seq) c.tag = 3;
-    if (p->d == 1) {
-      c.ntile = at.ntile;
-      hipError_t e = grf::launch_grad1d(p->dtype, c, nb * at.ntile, s);
-      if (e != hipSuccess) return hip_fail(e, "adjoint launch");
-      continue;
-    }
-    if (p->d == 3) {
-      Args m = base_args(p, nb);
-      m.data = ws + w.spec;
-      m.tw = p->tw_col2;
-      m.stride_ax = p->M;
-      m.stride_fixed = (long long)p->no * p->M;
-      m.nfixed = p->n1;
-      st = run_pass(p, grf::PASS_COL_LOAD_FWD, p->no, m, 0, nb, s);
-      if (st != GRF_OK) return st;
-      c.plane = grad_noise ? ws + w.plane : nullptr;
-    }
-    c.tw = p->tw_col1;
-    c.stride_ax = (long long)p->no * p->M;
-    c.stride_fixed = p->M;
-    c.nfixed = p->no;
-    const int gp = p->d == 3 ? (seq ? grf::PASS_COL_GRAD3_SEQ : grf::PASS_COL_GRAD3)
-                             : (seq ? grf::PASS_COL_GRAD_SEQ : grf::PASS_COL_GRAD);
-    st = run_pass(p, gp, p->n1, c, 0, nb, s);
+    const void* g = (const char*)grad_out + c0 * fbytes;
+    if (p->reflect)
+      st = adj_chunk_reflect(p, c, g, nb, s);
+    else if (p->desc.alg == GRF_ALG_TWO_FFT)
+      st = adj_chunk_two_fft(p, c, g, ws + w.spec2, nb, s);
+    else
+      st = adj_chunk_one_fft(p, c, g, at, grad_noise ? ws + w.plane : nullptr, nb, s);
     if (st != GRF_OK) return st;
-    if (p->d == 3 && grad_noise) {
-      hipError_t e = grf::launch_grad_plane(p->dtype, c, s);
-      if (e != hipSuccess) return hip_fail(e, "adjoint launch");
-    }
   }
   hipError_t e = grf::launch_reduce_partials((const double*)(ws + w.partial), (int)batch, at.nper, grad_theta, s);
   if (e != hipSuccess) return hip_fail(e, "reduction");
