@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--profile-batch", type=int, default=1024)
     ap.add_argument("--profile-boundary", type=str, default="periodic",
                     help="boundary for --profile-stage: periodic | neumann | dirichlet")
+    ap.add_argument("--profile-adjoint", action="store_true",
+                    help="profiling mode: the adjoint of the 1024^2 x 64 training step (dL/dphi = 2 w phi), "
+                         "--steps times")
     ap.add_argument("--copy-calib", action="store_true",
                     help="profiling mode: device copy of 1 GiB, --steps times (counter calibration)")
     return ap.parse_args()
@@ -89,6 +92,18 @@ def profile_mode(args):
     import torch
 
     import paper_1105_2737_amd as grf
+    if args.profile_adjoint:
+        import numpy as np
+        from synth import loss_weights
+        plan = grf.Plan((1024, 1024), alg=2, dtype=torch.float32, cov="matern", sigma=1.0, length_scale=0.1, nu=1.5)
+        phi = plan.sample(seed=0, batch=64)
+        w = torch.from_numpy(loss_weights((64, 1024, 1024), seed=1).astype(np.float32)).cuda()
+        g = 2 * w * phi
+        for _ in range(args.warmup + args.steps):
+            plan.backward(g, seed=0)
+        torch.cuda.synchronize()
+        print(f"profiled the adjoint of 1024^2 x 64, {args.steps} times", flush=True)
+        return
     if args.copy_calib:
         a = torch.empty(2 ** 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -202,7 +217,7 @@ def kind_rows(agg):
 
 def main():
     args = parse()
-    if args.profile_stage is not None or args.copy_calib:
+    if args.profile_stage is not None or args.copy_calib or args.profile_adjoint:
         if args.gpus != 1:
             sys.exit(2)
         profile_mode(args)
