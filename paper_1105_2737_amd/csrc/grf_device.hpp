@@ -53,17 +53,21 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 }
 
 // Box-Muller on one pair of 32-bit outputs, float32 arithmetic.
-// -ln u is taken from the hardware log2 except in the top 2^-7 of the
-// interval, where u = 1 - d cannot be held in float32; there the series
-// -ln(1-d) = d + d^2/2 + d^3/3 + d^4/4 (+ O(d^5) < 2^-37 relative) is used
-// with d computed from the complement ~x, which is exact.
+// r^2 = -2 ln u is taken from the hardware log2, whose result carries the
+// rounding of u to float32: an absolute error of at most 2^-24 in r^2, i.e.
+// 2^-25 / r in r.  In the top 2^-13 of the interval (d = 1 - u < 2^-13,
+// r < 2^-6) that would exceed 2e-6, so there the series
+// -2 ln(1-d) = 2d + d^2 + 2d^3/3 (+ O(d^4) < 2^-40 relative) is used with d
+// formed exactly from x read as a signed integer (d = (-x - 1/2) 2^-32).
+// A wavefront takes that branch in fewer than 1% of calls.
 __device__ __forceinline__ void box_muller(uint32_t xa, uint32_t xb, float& n0, float& n1) {
   const float u = fmaf((float)xa, 0x1p-32f, 0x1p-33f);
-  const float d = fmaf((float)(~xa), 0x1p-32f, 0x1p-33f);
-  const float lg = -__builtin_amdgcn_logf(u) * 0.693147180559945309f;
-  const float ser = d * fmaf(d, fmaf(d, fmaf(d, 0.25f, 0.333333343f), 0.5f), 1.0f);
-  const float nl = (xa >= 0xFE000000u) ? ser : lg;
-  const float r = __builtin_amdgcn_sqrtf(2.0f * nl);
+  float r2 = __builtin_amdgcn_logf(u) * -1.38629436111989061883f;   // log2(u) * (-2 ln 2)
+  if (__builtin_expect(xa >= 0xFFF80000u, 0)) {
+    const float d = fmaf((float)(int32_t)xa, -0x1p-32f, -0x1p-33f);
+    r2 = d * fmaf(d, fmaf(d, 0.666666687f, 1.0f), 2.0f);
+  }
+  const float r = __builtin_amdgcn_sqrtf(r2);
   const float t = fmaf((float)xb, 0x1p-32f, 0x1p-33f);   // revolutions
   n0 = r * __builtin_amdgcn_cosf(t);
   n1 = r * __builtin_amdgcn_sinf(t);
