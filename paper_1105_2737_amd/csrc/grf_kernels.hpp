@@ -1220,81 +1220,123 @@ k_fused(Args aa, Args ab, int nA, int nB) {
 // is read as y_n = x[2n] + i x[2n+1]; Y = forward length-M transform;
 //   X_k = E_k + w^{-k} D_k,  E_k = (Y_k + conj Y_{M-k})/2,  D_k = (Y_k - conj Y_{M-k})/(2i),
 // and the slot 0 holds (X_0, X_M) = (Re Y_0 + Im Y_0, Re Y_0 - Im Y_0).
-template <typename T, int M, class Rad, int RB, int PADR, int SRC>
-__global__ void __launch_bounds__(((M / Rad::get(0)) * RB + 63) / 64 * 64)
-k_row_r2c(Args a) {
+// A loaded row goes straight from global memory into the registers of the
+// first butterfly (y_{t + m NT} is one 8-byte word per lane, coalesced); a
+// generated one is written to LDS by whichever thread owns its Philox block.
+// When the NT threads of a row lie in one wavefront the stages, and the
+// post-twiddle that pairs Y_k with Y_{M-k}, synchronise with wavefront fences.
+template <typename T, int M, class Rad, int RB, int SRC>
+struct RowR2C {
   using V = C<T>;
   using E = Vec<T, 1>;
-  constexpr int NT = M / Rad::get(0);
-  static_assert(PADR == 0, "row passes use the RowLds layout");
   using RL = RowLds<M>;
-  constexpr int RSR = RL::STRIDE;
-  using EN = Eng<T, M, Rad, NT, 1, 2>;
-  __shared__ E sm[RB * RSR];
-  __shared__ V tw[2 * M];
-  const int tid = threadIdx.x;
-  const int r = tid / NT;
-  const int t = tid % NT;
-  const long long row0 = (long long)blockIdx.x * RB;
-  const long long left = a.rows - row0;
-  const int nrows = left < RB ? (int)left : RB;
-  V* g = (V*)a.data + row0 * M;
-  if constexpr (SRC == SRC_LOAD) {
-    constexpr int NTHR = (NT * RB + 63) / 64 * 64;
-    copy_in<T, M, RB * M, NTHR>((const V*)a.src + row0 * M, sm, nrows * M, tid);
-  } else {
-    // Philox blocks: 4 reals = 2 complex per block, NQ blocks per row
-    constexpr int NQ = (M + 1) / 2;
-    for (int i = tid; i < nrows * NQ; i += blockDim.x) {
-      const int rr = i / NQ, q = i % NQ;
-      const long long grow = row0 + rr;
-      const int b = (int)(grow / a.rows_per_field);
-      const int frow = (int)(grow % a.rows_per_field);
-      const unsigned long long key = a.seed + (unsigned long long)b;
-      T z[4];
-      normals4<T>((uint32_t)q, (uint32_t)frow, (uint32_t)a.tag, (uint32_t)key, (uint32_t)(key >> 32), z);
-      sm[rr * RSR + RL::idx(2 * q)].v[0] = mk<T>(z[0], z[1]);
-      if (2 * q + 1 < M) sm[rr * RSR + RL::idx(2 * q + 1)].v[0] = mk<T>(z[2], z[3]);
+  static constexpr int NT = M / Rad::get(0);
+  static constexpr int THREADS = (NT * RB + 63) / 64 * 64;
+  static constexpr int R0 = Rad::get(0);
+  static constexpr bool WAVE = (64 % NT) == 0;
+  static constexpr int LDS_BYTES = RB * RL::STRIDE * (int)sizeof(E) + 2 * M * (int)sizeof(V);
+  using EN = Eng<T, M, Rad, NT, 1, 2, WAVE>;
+
+  // output pair (k, M - k), 0 < k < M/2, or k = M/2 alone
+  __device__ __forceinline__ static void post(const E* rowp, const V* tw, V* o, int k) {
+    const int km = M - k;
+    const V yk = rowp[RL::idx(k)].v[0], ym = rowp[RL::idx(km)].v[0];
+    const V ek = cscale(cadd(yk, cconj(ym)), (T)0.5);
+    const V dk = cscale(csub(yk, cconj(ym)), (T)0.5);        // times 1/i below
+    const V dki = mk<T>(dk.y, -dk.x);
+    o[k] = cadd(ek, cmul(dki, cconj(tw[k])));
+    if (km != k) {
+      const V em = cscale(cadd(ym, cconj(yk)), (T)0.5);
+      const V dm = cscale(csub(ym, cconj(yk)), (T)0.5);
+      const V dmi = mk<T>(dm.y, -dm.x);
+      o[km] = cadd(em, cmul(dmi, cconj(tw[km])));
     }
   }
-  for (int i = tid; i < 2 * M; i += blockDim.x) tw[i] = ((const V*)a.tw2)[i];
-  __syncthreads();
-  const bool act = (r < nrows) && (t < NT);
-  constexpr int R0 = Rad::get(0);
-  V x[1][EN::REG];
-  if (act) {
+
+  __device__ __forceinline__ static void run(const Args& a, int bid, char* smem) {
+    E* sm = reinterpret_cast<E*>(smem);
+    V* tw = reinterpret_cast<V*>(smem + RB * RL::STRIDE * sizeof(E));
+    const int tid = threadIdx.x;
+    const int r = tid / NT;
+    const int t = tid % NT;
+    const long long row0 = (long long)bid * RB;
+    const long long left = a.rows - row0;
+    const int nrows = left < RB ? (int)left : RB;
+    const bool act = (r < nrows) && (t < NT);
+    V x[1][EN::REG];
+    TwFill<V, 2 * M, THREADS> twf;
+    if (tid < THREADS) twf.load((const V*)a.tw2, tid);
+    if constexpr (SRC == SRC_LOAD) {
+      const V* src = (const V*)a.src + (row0 + r) * M;
+      if (act) {
 #pragma unroll
-    for (int m = 0; m < R0; ++m) x[0][m] = sm[r * RSR + RL::idx(t + m * NT)].v[0];
-  }
-  __syncthreads();
-  auto lds = [&](int i) -> E& { return sm[r * RSR + RL::idx(i)]; };
-  auto to_lds = [&](int i, const E& e) { sm[r * RSR + RL::idx(i)] = e; };
-  EN::template run<-1>(x, t, act, lds, tw, to_lds);
-  __syncthreads();
-  if (act) {
-    const E* rowp = sm + r * RSR;
-    V* o = g + (long long)r * M;
-    for (int k = t; 2 * k <= M; k += NT) {
-      if (k == 0) {
-        const V y0 = rowp[0].v[0];
-        o[0] = mk<T>(y0.x + y0.y, y0.x - y0.y);
+        for (int m = 0; m < R0; ++m) x[0][m] = src[t + m * NT];
+      }
+    } else {
+      // Philox blocks: 4 reals = 2 complex per block, NQ blocks per row
+      constexpr int NQ = (M + 1) / 2;
+      for (int i = tid; i < nrows * NQ; i += THREADS) {
+        const int rr = i / NQ, q = i % NQ;
+        const long long grow = row0 + rr;
+        const int b = (int)(grow / a.rows_per_field);
+        const int frow = (int)(grow % a.rows_per_field);
+        const unsigned long long key = a.seed + (unsigned long long)b;
+        T z[4];
+        normals4<T>((uint32_t)q, (uint32_t)frow, (uint32_t)a.tag, (uint32_t)key, (uint32_t)(key >> 32), z);
+        sm[rr * RL::STRIDE + RL::idx(2 * q)].v[0] = mk<T>(z[0], z[1]);
+        if (2 * q + 1 < M) sm[rr * RL::STRIDE + RL::idx(2 * q + 1)].v[0] = mk<T>(z[2], z[3]);
+      }
+    }
+    if (tid < THREADS) twf.store(tw, tid);
+    __syncthreads();
+    if constexpr (SRC != SRC_LOAD) {
+      if (act) {
+#pragma unroll
+        for (int m = 0; m < R0; ++m) x[0][m] = sm[r * RL::STRIDE + RL::idx(t + m * NT)].v[0];
+      }
+      stage_sync<WAVE>();   // the first stage overwrites the row in LDS
+    }
+    auto lds = [&](int i) -> E& { return sm[r * RL::STRIDE + RL::idx(i)]; };
+    EN::template run<-1>(x, t, act, lds, tw, [&](int i, const E& e) { lds(i) = e; });
+    stage_sync<WAVE>();
+    if (act) {
+      const E* rowp = sm + r * RL::STRIDE;
+      V* o = (V*)a.data + (row0 + r) * M;
+      if constexpr (R0 % 2 == 0) {
+        // k = t + m NT covers [0, M/2) for m < R0/2
+#pragma unroll
+        for (int m = 0; m < R0 / 2; ++m) {
+          const int k = t + m * NT;
+          if (k == 0) {
+            const V y0 = rowp[0].v[0];
+            o[0] = mk<T>(y0.x + y0.y, y0.x - y0.y);
+          } else {
+            post(rowp, tw, o, k);
+          }
+        }
+        if (t == 0) post(rowp, tw, o, M / 2);
       } else {
-        const int km = M - k;
-        const V yk = rowp[RL::idx(k)].v[0], ym = rowp[RL::idx(km)].v[0];
-        // X_k = (Y_k + conj Y_m)/2 + conj(w^k) (Y_k - conj Y_m)/(2i)
-        const V ek = cscale(cadd(yk, cconj(ym)), (T)0.5);
-        const V dk = cscale(csub(yk, cconj(ym)), (T)0.5);        // times 1/i below
-        const V dki = mk<T>(dk.y, -dk.x);
-        o[k] = cadd(ek, cmul(dki, cconj(tw[k])));
-        if (km != k) {
-          const V em = cscale(cadd(ym, cconj(yk)), (T)0.5);
-          const V dm = cscale(csub(ym, cconj(yk)), (T)0.5);
-          const V dmi = mk<T>(dm.y, -dm.x);
-          o[km] = cadd(em, cmul(dmi, cconj(tw[km])));
+        for (int k = t; 2 * k <= M; k += NT) {
+          if (k == 0) {
+            const V y0 = rowp[0].v[0];
+            o[0] = mk<T>(y0.x + y0.y, y0.x - y0.y);
+          } else {
+            post(rowp, tw, o, k);
+          }
         }
       }
     }
   }
+};
+
+// Kernel wrapper of RowR2C.
+template <typename T, int M, class Rad, int RB, int PADR, int SRC>
+__global__ void __launch_bounds__((RowR2C<T, M, Rad, RB, SRC>::THREADS))
+k_row_r2c(Args a) {
+  static_assert(PADR == 0, "row passes use the RowLds layout");
+  using PS = RowR2C<T, M, Rad, RB, SRC>;
+  __shared__ __align__(16) char smem[PS::LDS_BYTES];
+  PS::run(a, blockIdx.x, smem);
 }
 
 }  // namespace grf

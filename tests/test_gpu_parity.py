@@ -60,6 +60,28 @@ def test_noise_matches_contract(grf, dtype, alg):
     assert np.abs(z - ref).max() <= tol * np.abs(ref).max()
 
 
+def test_noise_box_muller_tail(grf):
+    """Float32 normals stay within 4e-6 absolute of the float64 contract,
+    including the draws with u -> 1 where -2 ln u is taken from a series
+    (1 - u < 2^-13, i.e. radius r < 2^-6) and the band just above it where
+    the rounding of u to float32 costs up to 2^-25 / r.  Adjacent pairs along
+    the last axis are one Box-Muller pair; 4M normals hold ~256 pairs in the
+    series range."""
+    dims = (1024, 1024)
+    plan = grf.Plan(dims, alg=2, dtype=torch.float32)
+    z = plan.noise(seed=77, batch=4).double().cpu().numpy()
+    ref = onoise.batch_noise(dims, 77, 4, 1)
+    err = np.abs(z - ref)
+    assert err.max() <= 4e-6
+    r = np.hypot(ref[..., 0::2], ref[..., 1::2])
+    tail = r < 2.0 ** -6
+    assert tail.sum() >= 150
+    pair_err = np.maximum(err[..., 0::2], err[..., 1::2])
+    assert pair_err[tail].max() <= 1e-6
+    band = (r >= 2.0 ** -6) & (r < 2.0 ** -3)
+    assert band.sum() >= 5000 and pair_err[band].max() <= 4e-6
+
+
 CASES_2D = [
     ((64, 64), (1.0, 1.0), "matern", (1.0, 0.1, 1.5)),
     ((96, 128), (1.0, 2.0), "gaussian", (1.3, 0.07, 0.5)),
