@@ -266,9 +266,11 @@ __device__ __forceinline__ void seq_pair(const Args& a, const T* zsrc, int b, lo
     y = p[1];
     return;
   }
-  const long long row = j / a.nd;
-  const int s = (int)(j - row * a.nd);
-  const uint4 r = philox4x32_10<UNIFORM_KEY>(make_uint4((uint32_t)(s >> 2), (uint32_t)row, (uint32_t)a.tag, 0u), k0, k1);
+  // j < P <= 2^32 for every supported field: 32-bit unsigned division
+  const uint32_t ju = (uint32_t)j, ndu = (uint32_t)a.nd;
+  const uint32_t row = ju / ndu;
+  const uint32_t s = ju - row * ndu;
+  const uint4 r = philox4x32_10<UNIFORM_KEY>(make_uint4(s >> 2, row, (uint32_t)a.tag, 0u), k0, k1);
   if (s & 2)
     box_muller(r.z, r.w, x, y);
   else
@@ -1273,18 +1275,40 @@ struct RowR2C {
         for (int m = 0; m < R0; ++m) x[0][m] = src[t + m * NT];
       }
     } else {
-      // Philox blocks: 4 reals = 2 complex per block, NQ blocks per row
+      // Philox blocks: 4 reals = 2 complex per block, NQ blocks per row.
+      // Row row0 + rr is row f0 + rr of field b0 unless the workgroup's rows
+      // cross into the next field(s).
       constexpr int NQ = (M + 1) / 2;
-      for (int i = tid; i < nrows * NQ; i += THREADS) {
-        const int rr = i / NQ, q = i % NQ;
-        const long long grow = row0 + rr;
-        const int b = (int)(grow / a.rows_per_field);
-        const int frow = (int)(grow % a.rows_per_field);
-        const unsigned long long key = a.seed + (unsigned long long)b;
-        T z[4];
-        normals4<T>((uint32_t)q, (uint32_t)frow, (uint32_t)a.tag, (uint32_t)key, (uint32_t)(key >> 32), z);
+      const int rpf = a.rows_per_field;
+      const long long b0 = row0 / rpf;
+      const int f0 = (int)(row0 - b0 * rpf);
+      auto put = [&](int rr, int q, const T* z) {
         sm[rr * RL::STRIDE + RL::idx(2 * q)].v[0] = mk<T>(z[0], z[1]);
         if (2 * q + 1 < M) sm[rr * RL::STRIDE + RL::idx(2 * q + 1)].v[0] = mk<T>(z[2], z[3]);
+      };
+      if (f0 + nrows <= rpf) {
+        // one field: its key is uniform over the workgroup
+        const unsigned long long key = a.seed + (unsigned long long)b0;
+        for (int i = tid; i < nrows * NQ; i += THREADS) {
+          const int rr = i / NQ, q = i % NQ;
+          T z[4];
+          normals4<T, true>((uint32_t)q, (uint32_t)(f0 + rr), (uint32_t)a.tag, (uint32_t)key, (uint32_t)(key >> 32), z);
+          put(rr, q, z);
+        }
+      } else {
+        for (int i = tid; i < nrows * NQ; i += THREADS) {
+          const int rr = i / NQ, q = i % NQ;
+          long long b = b0;
+          int frow = f0 + rr;
+          while (frow >= rpf) {
+            frow -= rpf;
+            ++b;
+          }
+          const unsigned long long key = a.seed + (unsigned long long)b;
+          T z[4];
+          normals4<T>((uint32_t)q, (uint32_t)frow, (uint32_t)a.tag, (uint32_t)key, (uint32_t)(key >> 32), z);
+          put(rr, q, z);
+        }
       }
     }
     if (tid < THREADS) twf.store(tw, tid);
