@@ -60,7 +60,7 @@ typedef enum {
   GRF_EINVAL = -1,       /* invalid argument (nothing written) */
   GRF_ENOMEM = -2,       /* device or host allocation failed */
   GRF_EDEVICE = -3,      /* HIP runtime error */
-  GRF_EUNSUPPORTED = -4  /* valid request outside what this build implements */
+  GRF_EUNSUPPORTED = -4  /* valid request outside what the library implements */
 } grf_status;
 
 enum { GRF_ALG_TWO_FFT = 1, GRF_ALG_ONE_FFT = 2 };
@@ -79,7 +79,7 @@ enum { GRF_DRAW_COUNTER = 0, GRF_DRAW_RECURSIVE = 1 };
  *             length N_d with N_d/2 from {2, 4, ..., 512, 1024, 2048} (the
  *             same list with 2, 1024 and 2048).
  *   lengths   l_1..l_d > 0 (edge lengths of D; the unit torus is all 1).
- *   alg       GRF_ALG_ONE_FFT, or GRF_ALG_TWO_FFT (d = 2 only in this build).
+ *   alg       GRF_ALG_ONE_FFT or GRF_ALG_TWO_FFT (periodic boundaries, counter draw order).
  *   dtype     GRF_F32 (complex64 arithmetic, twiddles from float64) or GRF_F64.
  *   cov_kind  covariance family (S = the spectral density in cycles,
  *             C(x) = integral of S(p) exp(-2 pi i p.x) dp, Section 2):
@@ -153,7 +153,8 @@ typedef struct {
  * (rounded once to the working precision) and the default per-field
  * constants.  *out receives a library-owned handle.  Errors: GRF_EINVAL (bad
  * description, null pointer), GRF_EUNSUPPORTED (length not in the lists,
- * two-FFT with d = 3), GRF_ENOMEM, GRF_EDEVICE. */
+ * two-FFT with reflecting boundaries or the recursive draw order),
+ * GRF_ENOMEM, GRF_EDEVICE. */
 grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out);
 
 /* Release a plan and its device tables (NULL is accepted). */
@@ -186,8 +187,13 @@ grf_status grf_sample_from_noise(grf_plan plan, const void* noise, int64_t batch
  * pass of a chunk runs before the next chunk, so that a pass reads what the
  * previous one wrote from that cache.  Passes of a chunk: one-FFT d = 2:
  * column generation + inverse transform, then last-axis complex-to-real;
- * d = 3 adds the middle-axis inverse transform; two-FFT: last-axis noise +
- * real-to-complex, column forward/filter/inverse, last-axis complex-to-real.
+ * d = 3 adds the middle-axis inverse transform; two-FFT, d = 2: last-axis
+ * noise + real-to-complex, column forward/filter/inverse, last-axis
+ * complex-to-real; two-FFT, d = 1: last-axis noise + real-to-complex, filter
+ * (GRF_PASS_SPEC_FILTER), complex-to-real; two-FFT, d = 3: last-axis noise +
+ * real-to-complex, forward transforms along the middle axis and axis 1, the
+ * filter, inverse transforms along axis 1 and the middle axis, last-axis
+ * complex-to-real.
  * With GRF_FUSE=1 a one-FFT d = 2 batch of two or more fields on a supported
  * grid pairs, in each launch, the column pass of one chunk with the last-axis
  * pass of the previous chunk (GRF_PASS_FUSED).
@@ -214,7 +220,8 @@ enum {
   GRF_PASS_R2R_COL_LOAD = 10, /* reflecting boundaries: cosine transform along the middle axis (d = 3) */
   GRF_PASS_R2R_ROW_LOAD = 11, /* reflecting boundaries: cosine transform along the last axis */
   GRF_PASS_R2R_ROW_GEN = 12,  /* reflecting boundaries, d = 1: coefficients + cosine transform of whole fields */
-  GRF_PASS_COL_SEQ_INV = 13   /* as GRF_PASS_COL_GEN_INV, normals in the recursive algorithm's draw order */
+  GRF_PASS_COL_SEQ_INV = 13,  /* as GRF_PASS_COL_GEN_INV, normals in the recursive algorithm's draw order */
+  GRF_PASS_SPEC_FILTER = 14   /* two-FFT, d = 1 and 3: filter on the packed spectrum after the forward transforms */
 };
 grf_status grf_sample_stage_count(grf_plan plan, int64_t batch, int32_t* count);
 grf_status grf_sample_stage(grf_plan plan, int32_t stage, uint64_t seed, int64_t batch, const double* theta,
@@ -250,7 +257,7 @@ grf_status grf_noise(grf_plan plan, uint64_t seed, int64_t batch, void* noise_ou
  *   grad_noise    = dL/dz (device, field-shaped; NULL to skip).
  * The noise is regenerated from `seed` (noise == NULL) or read from `noise`.
  * The Fourier transform of grad_out is recomputed; no spectrum is stored by
- * the forward call.  Both algorithms (the two-FFT one with d = 2), the
+ * the forward call.  Both algorithms, the
  * reflecting boundaries (B^T g by the transposed cosine transforms) and both
  * draw orders (in the recursive one dL/dz is indexed like the sequence of
  * draws); ndim = 1, 2 or 3.

@@ -17,6 +17,7 @@ GRF_PASS_COL_FILTER, GRF_PASS_COL_GRAD, GRF_PASS_ROW_C2R, GRF_PASS_ROW_R2C_GEN, 
 GRF_PASS_ROW_GEN_C2R = 8
 GRF_PASS_R2R_COL_GEN, GRF_PASS_R2R_COL_LOAD, GRF_PASS_R2R_ROW_LOAD, GRF_PASS_R2R_ROW_GEN = 9, 10, 11, 12
 GRF_PASS_COL_SEQ_INV = 13
+GRF_PASS_SPEC_FILTER = 14
 GRF_BC_PERIODIC, GRF_BC_NEUMANN, GRF_BC_DIRICHLET = 0, 1, 2
 GRF_DRAW_COUNTER, GRF_DRAW_RECURSIVE = 0, 1
 

@@ -27,7 +27,7 @@ class Plan:
     """A sampling plan: grid, domain, algorithm, precision and covariance family.
 
     dims: (N_1, ..., N_d), d in {1, 2, 3}, all even; lengths: edge lengths
-    (default the unit torus); alg: 2 = one-FFT (Hermitian), 1 = two-FFT (d = 2);
+    (default the unit torus); alg: 2 = one-FFT (Hermitian), 1 = two-FFT;
     dtype: torch.float32 or torch.float64; cov: 'gaussian' | 'matern' |
     'exponential' with default parameters sigma, length_scale, nu; 'paper'
     (the family of Section 4, eq. (5): S = sigma^2 (m^{kl} + (sum p_i^{2k})^l)^{-n},

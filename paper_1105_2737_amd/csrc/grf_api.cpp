@@ -165,6 +165,11 @@ AdjTiles adj_tiles(const grf_plan_s* p) {
     const int nt = (p->M + 2 * g.per_wg - 1) / (2 * g.per_wg);
     return AdjTiles{nt, nt * p->no};
   }
+  if (p->desc.alg == GRF_ALG_TWO_FFT && p->d != 2) {
+    const long long slots = (long long)p->n1 * p->no * p->M;
+    const int nt = (int)((slots + 255) / 256);
+    return AdjTiles{nt, nt};
+  }
   if (p->d == 1) {
     const int nt = (p->M / 2 + 255) / 256;
     return AdjTiles{nt, nt};
@@ -254,7 +259,9 @@ grf_status run_pass(const grf_plan_s* p, int pass, int L, Args a, long long nfix
   const grf::Geom g = grf::pass_geom(pass, p->dtype, L);
   if (g.threads <= 0) return fail(GRF_EUNSUPPORTED, "no kernel for this length");
   long long nblocks;
-  if (grf::is_row_pass(pass)) {
+  if (pass == grf::PASS_SPEC_FILTER) {
+    nblocks = (a.rows * a.M + g.threads - 1) / g.threads;
+  } else if (grf::is_row_pass(pass)) {
     nblocks = (a.rows + g.per_wg - 1) / g.per_wg;
   } else {
     a.ntile = (a.M + 2 * g.per_wg - 1) / (2 * g.per_wg);
@@ -381,7 +388,7 @@ void chunk_passes(const grf_plan_s* p, uint64_t seed, const void* zsrc, long lon
     return;
   }
   const bool seq = p->desc.draw_order == GRF_DRAW_RECURSIVE;
-  if (p->d == 1) {
+  if (p->d == 1 && p->desc.alg == GRF_ALG_ONE_FFT) {
     // one launch: noise, filter and complex-to-real transform of whole fields
     a.tag = seq ? 3 : 1;
     a.seq = seq;
@@ -411,6 +418,38 @@ void chunk_passes(const grf_plan_s* p, uint64_t seed, const void* zsrc, long lon
       m.stride_ax = p->M;
       m.stride_fixed = (long long)p->no * p->M;
       m.nfixed = p->n1;
+      push(grf::PASS_COL_LOAD_INV, p->no, m);
+    }
+  } else if (p->d != 2) {
+    // two-FFT, d = 1 and 3: last-axis R2C, forward transforms along the
+    // leading axes, the filter on the packed spectrum, inverse transforms
+    Args r = a;
+    r.tag = 0;
+    r.tw2 = p->tw_row;
+    r.rows = nb * (p->P / p->nd);
+    push(zsrc ? grf::PASS_ROW_R2C_LOAD : grf::PASS_ROW_R2C_GEN, p->M, r);
+    Args m = a, c = a;
+    m.src = c.src = nullptr;
+    m.tw = p->tw_col2;
+    m.stride_ax = p->M;
+    m.stride_fixed = (long long)p->no * p->M;
+    m.nfixed = p->n1;
+    c.tw = p->tw_col1;
+    c.stride_ax = (long long)p->no * p->M;
+    c.stride_fixed = p->M;
+    c.nfixed = p->no;
+    if (p->d == 3) {
+      push(grf::PASS_COL_LOAD_FWD, p->no, m);
+      push(grf::PASS_COL_LOAD_FWD, p->n1, c);
+    }
+    Args f = a;
+    f.src = nullptr;
+    f.rows = nb * (p->P / p->nd);
+    f.scale = 1.0 / std::sqrt((double)p->P);   // the table, where there is one, carries it
+    f.htab = p->table_only ? p->htab : nullptr;
+    push(grf::PASS_SPEC_FILTER, 0, f);
+    if (p->d == 3) {
+      push(grf::PASS_COL_LOAD_INV, p->n1, c);
       push(grf::PASS_COL_LOAD_INV, p->no, m);
     }
   } else {
@@ -594,7 +633,7 @@ struct CovLayout {
 
 CovLayout cov_layout(const grf_plan_s* p, long long n) {
   CovLayout c{};
-  if (p->d == 1 && !p->reflect) {
+  if (p->d == 1 && !p->reflect && p->desc.alg == GRF_ALG_ONE_FFT) {
     const grf::Geom g = grf::geom_gen1d(p->dtype, p->M);
     const long long rb = g.per_wg > 0 ? g.per_wg : 1;
     c.groups = std::min<long long>((n + rb - 1) / rb, COV_GROUPS);
@@ -691,9 +730,52 @@ grf_status adj_chunk_one_fft(const grf_plan_s* p, Args c, const void* g, const A
 // Two-FFT algorithm (d = 2): xi = F[z] / sqrt(P), the white noise through the
 // same transforms into spec2 (the table of a density-defined family already
 // holds the 1/sqrt(P)); dL/dz is left to the caller (the sampler applied to g).
-grf_status adj_chunk_two_fft(const grf_plan_s* p, Args c, const void* g, void* spec2, long long nb, hipStream_t s) {
+// Forward transforms along the leading axes of a packed spectrum (d = 3:
+// middle axis, then axis 1), in place.
+grf_status fwd_leading(const grf_plan_s* p, void* data, long long nb, hipStream_t s) {
+  if (p->d != 3) return GRF_OK;
+  Args m = base_args(p, nb);
+  m.data = data;
+  m.tw = p->tw_col2;
+  m.stride_ax = p->M;
+  m.stride_fixed = (long long)p->no * p->M;
+  m.nfixed = p->n1;
+  grf_status st = run_pass(p, grf::PASS_COL_LOAD_FWD, p->no, m, 0, nb, s);
+  if (st != GRF_OK) return st;
+  Args c = m;
+  c.tw = p->tw_col1;
+  c.stride_ax = (long long)p->no * p->M;
+  c.stride_fixed = p->M;
+  c.nfixed = p->no;
+  return run_pass(p, grf::PASS_COL_LOAD_FWD, p->n1, c, 0, nb, s);
+}
+
+grf_status adj_chunk_two_fft(const grf_plan_s* p, Args c, const void* g, void* spec2, const AdjTiles& at,
+                             long long nb, hipStream_t s) {
   grf_status st = adj_row_r2c(p, c, g, nb, s);
   if (st != GRF_OK) return st;
+  if (p->d != 2) {
+    // d = 1, 3: G = F[g] and F[z] transformed along every axis, then one
+    // reduction pass over the two packed spectra
+    st = fwd_leading(p, c.data, nb, s);
+    if (st != GRF_OK) return st;
+    Args rz = base_args(p, nb);
+    rz.data = spec2;
+    rz.src = c.src;
+    rz.seed = c.seed;
+    rz.tag = 0;
+    rz.tw2 = p->tw_row;
+    rz.rows = nb * (p->P / p->nd);
+    st = run_pass(p, c.src ? grf::PASS_ROW_R2C_LOAD : grf::PASS_ROW_R2C_GEN, p->M, rz, 0, nb, s);
+    if (st != GRF_OK) return st;
+    st = fwd_leading(p, spec2, nb, s);
+    if (st != GRF_OK) return st;
+    c.src2 = spec2;
+    c.scale = p->table_only ? 1.0 : 1.0 / std::sqrt((double)p->P);
+    c.ntile = at.ntile;
+    hipError_t e = grf::launch_grad_spec(p->dtype, c, nb * at.ntile, s);
+    return e == hipSuccess ? GRF_OK : hip_fail(e, "adjoint launch");
+  }
   Args rz = base_args(p, nb);
   rz.data = spec2;
   rz.src = c.src;
@@ -790,6 +872,7 @@ bool row_length_supported(int M) {
 }
 
 Geom pass_geom(int pass, int dtype, int L) {
+  if (pass == PASS_SPEC_FILTER) return Geom{256, 0};
   if (is_r2r_pass(pass)) return geom_r2r(pass, dtype, L);
   if (pass == PASS_ROW_GEN_C2R) return geom_gen1d(dtype, L);
   if (is_row_pass(pass)) return dtype == 0 ? geom_row_f32(pass, L) : geom_row_f64(pass, L);
@@ -803,6 +886,7 @@ hipError_t launch_fused(int dtype, int L, int M, const Args& aA, const Args& aB,
 }
 
 hipError_t launch_pass(int pass, int dtype, int L, const Args& a, long long nblocks, hipStream_t s) {
+  if (pass == PASS_SPEC_FILTER) return launch_spec_filter(dtype, a, nblocks, s);
   if (is_r2r_pass(pass)) return launch_r2r(pass, dtype, L, a, nblocks, s);
   if (pass == PASS_ROW_GEN_C2R) return launch_gen1d(dtype, L, a, nblocks, nullptr, s);
   if (is_row_pass(pass))
@@ -856,8 +940,6 @@ grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out) {
     return fail(GRF_EUNSUPPORTED, "the recursive draw order is that of the periodic one-FFT algorithm");
   if (reflect && d.alg != GRF_ALG_ONE_FFT)
     return fail(GRF_EUNSUPPORTED, "reflecting boundaries use the one-transform method (GRF_ALG_ONE_FFT)");
-  if (d.alg == GRF_ALG_TWO_FFT && d.ndim != 2)
-    return fail(GRF_EUNSUPPORTED, "two-FFT algorithm implemented for d = 2");
   const int last = d.ndim - 1;
   if ((d.ndim >= 2 && !grf::col_length_supported((int)d.dims[0])) ||
       (d.ndim == 3 && !grf::col_length_supported((int)d.dims[1])) || d.dims[last] > (1ll << 30) ||
@@ -995,7 +1077,7 @@ grf_status grf_covariance(grf_plan p, uint64_t seed, int64_t nsamples, double* c
   if (workspace == nullptr || workspace_bytes < c.total) return fail(GRF_EINVAL, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
   const double scale = 1.0 / (double)nsamples;
-  if (p->d == 1 && !p->reflect) {
+  if (p->d == 1 && !p->reflect && p->desc.alg == GRF_ALG_ONE_FFT) {
     double* partial = (double*)workspace;
     Args a = base_args(p, nsamples);
     a.recs = p->rec_dev;
@@ -1117,7 +1199,7 @@ grf_status grf_backward(grf_plan p, uint64_t seed, const void* noise, int64_t ba
     if (p->reflect)
       st = adj_chunk_reflect(p, c, g, nb, s);
     else if (p->desc.alg == GRF_ALG_TWO_FFT)
-      st = adj_chunk_two_fft(p, c, g, ws + w.spec2, nb, s);
+      st = adj_chunk_two_fft(p, c, g, ws + w.spec2, at, nb, s);
     else
       st = adj_chunk_one_fft(p, c, g, at, grad_noise ? ws + w.plane : nullptr, nb, s);
     if (st != GRF_OK) return st;

@@ -40,6 +40,7 @@ enum PassKind {
   PASS_R2R_ROW_LOAD = GRF_PASS_R2R_ROW_LOAD,   // reflecting: cosine transform, last axis
   PASS_R2R_ROW_GEN = GRF_PASS_R2R_ROW_GEN,     // reflecting, d = 1: coefficients + cosine transform
   PASS_COL_SEQ_INV = GRF_PASS_COL_SEQ_INV,     // as PASS_COL_GEN_INV, normals in the recursive draw order
+  PASS_SPEC_FILTER = GRF_PASS_SPEC_FILTER,     // two-FFT, d = 1 and 3: filter on the transformed packed spectrum
   PASS_COL_GRAD3 = 100,                        // PASS_COL_GRAD for d = 3 (internal: adjoint only)
   PASS_COL_GRAD1 = 101,                        // PASS_COL_GRAD for the two-FFT algorithm (internal)
   // adjoint of the reflecting-boundary sampler (internal): cosine transforms
@@ -141,6 +142,11 @@ hipError_t launch_reduce_partials(const double* partial, int batch, int nper, do
 // and the d = 3 noise gradient of the planes k_d = 0, N_d/2 from a.plane.
 hipError_t launch_grad1d(int dtype, const Args& a, long long nblocks, hipStream_t s);
 hipError_t launch_grad_plane(int dtype, const Args& a, hipStream_t s);
+// Two-FFT algorithm, d = 1 and 3: the filter on the packed spectrum (one
+// thread per slot, a.rows = rows of the chunk) and the adjoint's reduction
+// over the packed spectra of g and z (a.ntile workgroups per field).
+hipError_t launch_spec_filter(int dtype, const Args& a, long long nblocks, hipStream_t s);
+hipError_t launch_grad_spec(int dtype, const Args& a, long long nblocks, hipStream_t s);
 hipError_t launch_philox_raw(unsigned long long seed, const uint32_t* ctr, long long n, uint32_t* out, hipStream_t s);
 hipError_t launch_noise(int dtype, unsigned long long seed, int tag, int rows, int nd, int batch, void* out,
                         hipStream_t s);

@@ -314,6 +314,139 @@ __global__ void k_grad_plane(Args a) {
   }
 }
 
+// Two-FFT algorithm for d = 1 and 3 (Section 3, the first algorithm): the
+// filter on the packed spectrum once every axis is forward transformed,
+// A_k = h_k F[z]_k / sqrt(P) (the 1/sqrt(P) is in the filter's scale, or in
+// the table).  One thread per slot (row, m) of a field, rows = the N_1 ... N_{d-1}
+// leading indices.  Interior slots 0 < m < N_d/2 are scaled by h.  Slot 0 of
+// row k holds Z = X(k, 0) + i X(k, N_d/2); both planes are Hermitian in k, so
+// with W = Z(-k): X(k, 0) = (Z + conj W)/2 and X(k, N_d/2) = (Z - conj W)/(2i).
+// The thread of the smaller of the rows k, -k filters both planes and writes
+// both slots (A(-k) = conj A(k), since h is even).
+template <typename T>
+__global__ void __launch_bounds__(256) k_spec_filter(Args a) {
+  using V = C<T>;
+  const long long R = (long long)a.n1 * a.no;
+  const int M = a.M;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.rows * M) return;
+  const int m = (int)(i % M);
+  const long long grow = i / M;
+  const long long b = grow / R;
+  const int row = (int)(grow - b * R);
+  const int k1 = row / a.no, o = row - (row / a.no) * a.no;
+  const Filt<T> f = load_filt<T>(a.recs[b * a.rec_stride], a.scale);
+  const int q1 = wrapk(k1, a.n1), qo = wrapk(o, a.no);
+  const T p2b = (T)(q1 * q1) * (T)a.il2[0] + (T)(qo * qo) * (T)a.il2[1];
+  const T il2d = (T)a.il2[2];
+  const T* hr = a.htab ? (const T*)a.htab + (long long)row * (M + 2) : nullptr;
+  auto hv = [&](int mm) -> T { return hr ? hr[mm] : filt_h(f, p2b + (T)(mm * mm) * il2d); };
+  V* base = (V*)a.data + b * R * M;
+  if (m > 0) {
+    V& x = base[(long long)row * M + m];
+    const T h = hv(m);
+    x = mk<T>(h * x.x, h * x.y);
+    return;
+  }
+  const int pr = ((a.n1 - k1) % a.n1) * a.no + (a.no - o) % a.no;
+  if (pr < row) return;
+  const V z = base[(long long)row * M], w = base[(long long)pr * M];
+  const V x0 = mk<T>((T)0.5 * (z.x + w.x), (T)0.5 * (z.y - w.y));
+  const V xm = mk<T>((T)0.5 * (z.y + w.y), (T)-0.5 * (z.x - w.x));
+  const T h0 = hv(0), hm = hv(M);
+  const V a0 = mk<T>(h0 * x0.x, h0 * x0.y), am = mk<T>(hm * xm.x, hm * xm.y);
+  base[(long long)row * M] = mk<T>(a0.x - am.y, a0.y + am.x);                      // A0 + i AM
+  if (pr != row) base[(long long)pr * M] = mk<T>(a0.x + am.y, am.x - a0.y);      // conj A0 + i conj AM
+}
+
+// Adjoint of the two-FFT algorithm for d = 1 and 3: with G = F[g] (data) and
+// xi = scale F[z] (src2), both packed and transformed along every axis, each
+// half-spectrum entry adds w (h/2) dlogS/dtheta Re(xi conj G) (w = 2 for
+// 0 < m < N_d/2, which stands for k and -k; in the planes m = 0, N_d/2 each
+// k once).  Slot 0 is unpacked as in k_spec_filter; the thread of the pair
+// (k, -k) counts both (w = 2), a self-mirrored row once.  Workgroup `tile`
+// of field b takes slots tile * 256 ... of that field.
+template <typename T>
+__global__ void __launch_bounds__(256) k_grad_spec(Args a) {
+  using V = C<T>;
+  const int tile = blockIdx.x % a.ntile;
+  const long long b = blockIdx.x / a.ntile;
+  const long long R = (long long)a.n1 * a.no;
+  const int M = a.M;
+  const long long e = (long long)tile * 256 + threadIdx.x;
+  double acc0 = 0, acc1 = 0, acc2 = 0;
+  if (e < R * M) {
+    const int m = (int)(e % M);
+    const int row = (int)(e / M);
+    const int k1 = row / a.no, o = row - (row / a.no) * a.no;
+    const FieldRec& rec = a.recs[b * a.rec_stride];
+    const Filt<T> f = load_filt<T>(rec, 1.0);
+    AdjAcc<T> ad(rec);
+    const int q1 = wrapk(k1, a.n1), qo = wrapk(o, a.no);
+    const double p2b = (double)(q1 * q1) * a.il2[0] + (double)(qo * qo) * a.il2[1];
+    const double il2d = a.il2[2];
+    const T* hr = a.htab ? (const T*)a.htab + (long long)row * (M + 2) : nullptr;
+    auto hv = [&](int mm) -> T { return hr ? hr[mm] : filt_h(f, (T)(p2b + (double)mm * mm * il2d)); };
+    const V* G = (const V*)a.data + b * R * M;
+    const V* X = (const V*)a.src2 + b * R * M;
+    const T sc = (T)a.scale;
+    if (m > 0) {
+      const V x = X[(long long)row * M + m];
+      ad.add(2.0, (double)hv(m), p2b + (double)m * m * il2d, mk<T>(sc * x.x, sc * x.y), G[(long long)row * M + m]);
+    } else {
+      const int pr = ((a.n1 - k1) % a.n1) * a.no + (a.no - o) % a.no;
+      if (pr >= row) {
+        const double w = pr == row ? 1.0 : 2.0;
+        const V zx = X[(long long)row * M], wx = X[(long long)pr * M];
+        const V zg = G[(long long)row * M], wg = G[(long long)pr * M];
+        const V x0 = mk<T>((T)0.5 * sc * (zx.x + wx.x), (T)0.5 * sc * (zx.y - wx.y));
+        const V xm = mk<T>((T)0.5 * sc * (zx.y + wx.y), (T)-0.5 * sc * (zx.x - wx.x));
+        const V g0 = mk<T>((T)0.5 * (zg.x + wg.x), (T)0.5 * (zg.y - wg.y));
+        const V gm = mk<T>((T)0.5 * (zg.y + wg.y), (T)-0.5 * (zg.x - wg.x));
+        ad.add(w, (double)hv(0), p2b, x0, g0);
+        ad.add(w, (double)hv(M), p2b + (double)M * M * il2d, xm, gm);
+      }
+    }
+    acc0 = ad.acc0 * rec.gs;
+    acc1 = ad.acc1;
+    acc2 = ad.acc2;
+  }
+  __shared__ double red[3][4];
+  for (int off = 32; off > 0; off >>= 1) {
+    acc0 += __shfl_xor(acc0, off);
+    acc1 += __shfl_xor(acc1, off);
+    acc2 += __shfl_xor(acc2, off);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wv] = acc0;
+    red[1][wv] = acc1;
+    red[2][wv] = acc2;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double sacc = 0;
+    for (int v = 0; v < 4; ++v) sacc += red[threadIdx.x][v];
+    a.partial[(b * a.ntile + tile) * 3 + threadIdx.x] = sacc;
+  }
+}
+
+hipError_t launch_spec_filter(int dtype, const Args& a, long long nblocks, hipStream_t s) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_spec_filter<float>, dim3((unsigned)nblocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_spec_filter<double>, dim3((unsigned)nblocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_spec(int dtype, const Args& a, long long nblocks, hipStream_t s) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_grad_spec<float>, dim3((unsigned)nblocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_grad_spec<double>, dim3((unsigned)nblocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_grad1d(int dtype, const Args& a, long long nblocks, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
   if (dtype == 0)

@@ -71,10 +71,8 @@ def _desc(**kw):
     (dict(ndim=0), -1),
     (dict(dims=(2048, 64)), -4),          # length not in the list
     (dict(dims=(64, 8192)), -4),
-    (dict(ndim=3, alg=1, dims=(16, 16, 16)), -4),
     (dict(ndim=1, dims=(14,)), -1),
     (dict(ndim=1, dims=(8192,)), -4),
-    (dict(ndim=1, alg=1, dims=(64,)), -4),  # two-FFT algorithm: d = 2 only
     (dict(cov_kind=3, m=0.0, k=1, l=1, n=1), -1),   # the family of Section 4 needs m > 0
     (dict(cov_kind=3, m=1.0, k=0, l=1, n=1), -1),   # and k, l, n >= 1
     (dict(cov_kind=3, m=1.0, k=1, l=1, n=65), -1),
