@@ -727,9 +727,6 @@ grf_status adj_chunk_one_fft(const grf_plan_s* p, Args c, const void* g, const A
   return GRF_OK;
 }
 
-// Two-FFT algorithm (d = 2): xi = F[z] / sqrt(P), the white noise through the
-// same transforms into spec2 (the table of a density-defined family already
-// holds the 1/sqrt(P)); dL/dz is left to the caller (the sampler applied to g).
 // Forward transforms along the leading axes of a packed spectrum (d = 3:
 // middle axis, then axis 1), in place.
 grf_status fwd_leading(const grf_plan_s* p, void* data, long long nb, hipStream_t s) {
@@ -750,6 +747,9 @@ grf_status fwd_leading(const grf_plan_s* p, void* data, long long nb, hipStream_
   return run_pass(p, grf::PASS_COL_LOAD_FWD, p->n1, c, 0, nb, s);
 }
 
+// Two-FFT algorithm: xi = F[z] / sqrt(P), the white noise through the same
+// transforms into spec2 (the table of a density-defined family already holds
+// the 1/sqrt(P)); dL/dz is left to the caller (the sampler applied to g).
 grf_status adj_chunk_two_fft(const grf_plan_s* p, Args c, const void* g, void* spec2, const AdjTiles& at,
                              long long nb, hipStream_t s) {
   grf_status st = adj_row_r2c(p, c, g, nb, s);
