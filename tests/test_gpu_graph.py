@@ -39,6 +39,8 @@ CASES = [
     dict(dims=(16, 24, 32), batch=3, kw=dict(cov="matern", boundary="neumann")),
     dict(dims=(128, 256), batch=9, kw=dict(cov="matern", draw_order="recursive")),
     dict(dims=(256, 256), batch=6, kw=dict(cov="paper", m=5.0, k=3, l=1, n=1, lengths=(4.0, 4.0))),
+    dict(dims=(16, 24, 32), batch=4, kw=dict(cov="matern", alg=1)),             # two-FFT, seven passes
+    dict(dims=(360,), batch=8, kw=dict(cov="gaussian", length_scale=0.05, alg=1)),
 ]
 
 
