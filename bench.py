@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--profile-adjoint", action="store_true",
                     help="profiling mode: the adjoint of the 1024^2 x 64 training step (dL/dphi = 2 w phi), "
                          "--steps times")
+    ap.add_argument("--profile-uneven", action="store_true",
+                    help="profiling mode: sample the 4096 uneven fields (graph replay), --steps times")
     ap.add_argument("--copy-calib", action="store_true",
                     help="profiling mode: device copy of 1 GiB, --steps times (counter calibration)")
     return ap.parse_args()
@@ -103,6 +105,16 @@ def profile_mode(args):
             plan.backward(g, seed=0)
         torch.cuda.synchronize()
         print(f"profiled the adjoint of 1024^2 x 64, {args.steps} times", flush=True)
+        return
+    if args.profile_uneven:
+        from synth import uneven_fields
+        bt = grf.Batch(uneven_fields(4096, seed=0))
+        ob = bt.empty()
+        bt.tune(out=ob)
+        for _ in range(args.warmup + args.steps):
+            bt.sample(out=ob)
+        torch.cuda.synchronize()
+        print(f"profiled the 4096 uneven fields, {args.steps} times", flush=True)
         return
     if args.copy_calib:
         a = torch.empty(2 ** 28, dtype=torch.float32, device="cuda")
@@ -217,7 +229,7 @@ def kind_rows(agg):
 
 def main():
     args = parse()
-    if args.profile_stage is not None or args.copy_calib or args.profile_adjoint:
+    if args.profile_stage is not None or args.copy_calib or args.profile_adjoint or args.profile_uneven:
         if args.gpus != 1:
             sys.exit(2)
         profile_mode(args)
