@@ -311,6 +311,21 @@ grf_status grf_batch_destroy(grf_batch b);
  * n x 4 uint32) under key = seed.  For bit-exact checks of the generator. */
 grf_status grf_debug_philox(uint64_t seed, const uint32_t* counters, int64_t n, uint32_t* out, void* stream);
 
+/* The half-spectrum A_k = h_k xi_k that the one-FFT sampler hands to its
+ * inverse transforms (Section 3, the second algorithm: the Hermitian
+ * arrangement of the noise of fields seed .. seed+batch-1 times the filter
+ * h_k = sqrt(S(p_k)/|D|) at the plan's parameters), computed by the
+ * generating pass's own device code.  spec_out: device, batch * (P / N_d) *
+ * (N_d / 2) complex values of the plan's dtype (interleaved re, im), laid out
+ * [field][N_1 ... N_{d-1} row][m], m = 0 .. N_d/2 - 1, where slot m = 0 holds
+ * A(k, 0) + i A(k, N_d/2) (both planes are Hermitian, so each is determined
+ * by its real and imaginary parts over the rows k).  The entries with
+ * 0 < m < N_d/2 are A(k, m) as they are.  For inspection and tests; the
+ * sampler never stores this array.  Errors: GRF_EINVAL, GRF_EUNSUPPORTED (the
+ * two-FFT algorithm, reflecting boundaries or the recursive draw order),
+ * GRF_EDEVICE. */
+grf_status grf_debug_spectrum(grf_plan plan, uint64_t seed, int64_t batch, void* spec_out, void* stream);
+
 /* Human-readable message of the last error on the calling thread. */
 const char* grf_last_error(void);
 

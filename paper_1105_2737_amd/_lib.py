@@ -26,6 +26,7 @@ STATUS_NAMES = {0: "GRF_OK", -1: "GRF_EINVAL", -2: "GRF_ENOMEM", -3: "GRF_EDEVIC
 # every symbol include/grf.h declares
 EXPORTS = ["grf_plan_create", "grf_plan_destroy", "grf_workspace_size", "grf_sample",
            "grf_sample_stage_count", "grf_sample_stage", "grf_sample_stage_info", "grf_sample_from_noise", "grf_noise", "grf_backward", "grf_debug_philox",
+           "grf_debug_spectrum",
            "grf_covariance", "grf_batch_create", "grf_batch_offsets", "grf_batch_sample", "grf_batch_sample_plain",
            "grf_batch_tune", "grf_batch_destroy", "grf_last_error", "grf_version"]
 
@@ -70,6 +71,7 @@ def _load():
         "grf_noise": (ctypes.c_int, [vp, u64, c64, vp, vp]),
         "grf_backward": (ctypes.c_int, [vp, u64, vp, c64, vp, vp, vp, vp, vp, sz, vp]),
         "grf_debug_philox": (ctypes.c_int, [u64, vp, c64, vp, vp]),
+        "grf_debug_spectrum": (ctypes.c_int, [vp, u64, c64, vp, vp]),
         "grf_covariance": (ctypes.c_int, [vp, u64, c64, vp, vp, sz, vp]),
         "grf_batch_create": (ctypes.c_int, [ctypes.POINTER(grf_field_desc), c64, ctypes.POINTER(vp)]),
         "grf_batch_offsets": (ctypes.c_int, [vp, ctypes.POINTER(c64)]),
@@ -155,6 +157,10 @@ def grf_covariance(plan, seed, nsamples, cov, workspace, workspace_bytes, stream
 
 def grf_debug_philox(seed, counters, n, out, stream):
     return check(lib.grf_debug_philox(seed, counters, n, out, stream))
+
+
+def grf_debug_spectrum(plan, seed, batch, out, stream):
+    return check(lib.grf_debug_spectrum(plan, seed, batch, out, stream))
 
 
 def grf_batch_create(fields):

@@ -145,6 +145,14 @@ class Plan:
         L.grf_noise(self.handle, int(seed) & (2 ** 64 - 1), batch, _ptr(out), _stream())
         return out
 
+    def spectrum(self, seed=0, batch=1):
+        """The half-spectrum A = h xi the one-FFT sampler transforms, complex
+        [batch, N_1, ..., N_{d-1}, N_d / 2]; slot 0 holds A(k, 0) + i A(k, N_d/2)."""
+        M = self.dims[-1] // 2
+        out = torch.empty((batch,) + tuple(self.dims[:-1]) + (M, 2), dtype=self.dtype, device=self.device)
+        L.grf_debug_spectrum(self.handle, int(seed) & (2 ** 64 - 1), batch, _ptr(out), _stream())
+        return torch.view_as_complex(out)
+
     def backward(self, grad_out, seed=0, theta=None, noise=None, need_noise_grad=False):
         """(dL/dtheta [batch, 3] float64, dL/dz or None) for either algorithm."""
         grad_out = grad_out.to(device=self.device, dtype=self.dtype).contiguous()

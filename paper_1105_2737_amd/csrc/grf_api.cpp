@@ -1217,6 +1217,30 @@ grf_status grf_backward(grf_plan p, uint64_t seed, const void* noise, int64_t ba
   return GRF_OK;
 }
 
+grf_status grf_debug_spectrum(grf_plan p, uint64_t seed, int64_t batch, void* spec_out, void* stream) {
+  if (p == nullptr || (spec_out == nullptr && batch > 0)) return fail(GRF_EINVAL, "null argument");
+  if (batch < 0) return fail(GRF_EINVAL, "negative batch");
+  if (p->desc.alg != GRF_ALG_ONE_FFT || p->reflect || p->desc.draw_order != GRF_DRAW_COUNTER)
+    return fail(GRF_EUNSUPPORTED, "spectrum defined for the one-FFT algorithm, periodic axes, counter draw order");
+  if (batch == 0) return GRF_OK;
+  grf_status st = check_stream_device(p);
+  if (st != GRF_OK) return st;
+  Args a = base_args(p, batch);
+  a.data = spec_out;
+  a.recs = p->rec_dev;
+  a.rec_stride = 0;
+  a.seed = seed;
+  a.tag = 1;
+  a.htab = p->htab;
+  const long long slots = (long long)(p->P / p->nd) * ((p->M + 1) / 2);
+  a.ntile = (int)((slots + 255) / 256);
+  const long long nblocks = batch * a.ntile;
+  if (nblocks > 0x7fffffffLL) return fail(GRF_EINVAL, "batch too large for one launch");
+  hipError_t e = grf::launch_debug_spectrum(p->dtype, a, nblocks, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "spectrum kernel");
+  return GRF_OK;
+}
+
 grf_status grf_debug_philox(uint64_t seed, const uint32_t* counters, int64_t n, uint32_t* out, void* stream) {
   if (n < 0) return fail(GRF_EINVAL, "negative count");
   if (n == 0) return GRF_OK;

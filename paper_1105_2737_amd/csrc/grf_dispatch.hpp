@@ -147,6 +147,9 @@ hipError_t launch_grad_plane(int dtype, const Args& a, hipStream_t s);
 // over the packed spectra of g and z (a.ntile workgroups per field).
 hipError_t launch_spec_filter(int dtype, const Args& a, long long nblocks, hipStream_t s);
 hipError_t launch_grad_spec(int dtype, const Args& a, long long nblocks, hipStream_t s);
+// The one-FFT sampler's half-spectrum A = h xi before the inverse transforms
+// (a.ntile workgroups per field).
+hipError_t launch_debug_spectrum(int dtype, const Args& a, long long nblocks, hipStream_t s);
 hipError_t launch_philox_raw(unsigned long long seed, const uint32_t* ctr, long long n, uint32_t* out, hipStream_t s);
 hipError_t launch_noise(int dtype, unsigned long long seed, int tag, int rows, int nd, int batch, void* out,
                         hipStream_t s);

@@ -431,6 +431,38 @@ __global__ void __launch_bounds__(256) k_grad_spec(Args a) {
   }
 }
 
+// The half-spectrum A = h xi that the one-FFT sampler transforms (noise,
+// Hermitian arrangement and filter of Section 3's second algorithm), by the
+// generating pass's own gen_pair, packed like the sampler's intermediate:
+// [field][row][N_d/2], slot 0 = A(k, 0) + i A(k, N_d/2).  a.ntile workgroups
+// per field, one slot pair (one Philox block) per thread; a workgroup never
+// spans two fields, so the key is uniform over it, as gen_pair assumes.
+template <typename T>
+__global__ void __launch_bounds__(256) k_debug_spectrum(Args a) {
+  const int b = blockIdx.x / a.ntile;
+  const long long e = (long long)(blockIdx.x % a.ntile) * 256 + threadIdx.x;
+  const int NQ = (a.M + 1) / 2;
+  const long long R = (long long)a.n1 * a.no;
+  if (e >= R * NQ) return;
+  const int row = (int)(e / NQ), q = (int)(e % NQ);
+  const int kk1 = row / a.no, o = row - kk1 * a.no;
+  const Filt<T> f = load_filt<T>(a.recs[0], a.scale);
+  const unsigned long long key = a.seed + (unsigned long long)b;
+  C<T> A0, A1;
+  gen_pair<T>(a, f, nullptr, b, (uint32_t)key, (uint32_t)(key >> 32), kk1, o, 2 * q, A0, A1);
+  C<T>* out = (C<T>*)a.data + ((long long)b * R + row) * a.M + 2 * q;
+  out[0] = A0;
+  if (2 * q + 1 < a.M) out[1] = A1;
+}
+
+hipError_t launch_debug_spectrum(int dtype, const Args& a, long long nblocks, hipStream_t s) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_debug_spectrum<float>, dim3((unsigned)nblocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_debug_spectrum<double>, dim3((unsigned)nblocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_spec_filter(int dtype, const Args& a, long long nblocks, hipStream_t s) {
   if (dtype == 0)
     hipLaunchKernelGGL(k_spec_filter<float>, dim3((unsigned)nblocks), dim3(256), 0, s, a);
