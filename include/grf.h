@@ -189,8 +189,8 @@ grf_status grf_sample_from_noise(grf_plan plan, const void* noise, int64_t batch
  * column generation + inverse transform, then last-axis complex-to-real;
  * d = 3 adds the middle-axis inverse transform; two-FFT, d = 2: last-axis
  * noise + real-to-complex, column forward/filter/inverse, last-axis
- * complex-to-real; two-FFT, d = 1: last-axis noise + real-to-complex, filter
- * (GRF_PASS_SPEC_FILTER), complex-to-real; two-FFT, d = 3: last-axis noise +
+ * complex-to-real; d = 1 (both algorithms): one launch over whole fields
+ * (GRF_PASS_ROW_GEN_C2R); two-FFT, d = 3: last-axis noise +
  * real-to-complex, forward transforms along the middle axis and axis 1, the
  * filter, inverse transforms along axis 1 and the middle axis, last-axis
  * complex-to-real.
@@ -215,13 +215,13 @@ enum {
   GRF_PASS_ROW_C2R = 5,       /* last-axis complex-to-real inverse transform */
   GRF_PASS_ROW_R2C_GEN = 6,   /* last-axis white noise + real-to-complex forward transform (two-FFT) */
   GRF_PASS_ROW_R2C_LOAD = 7,  /* last-axis real-to-complex forward transform of stored rows */
-  GRF_PASS_ROW_GEN_C2R = 8,   /* d = 1: noise + filter + complex-to-real transform of whole fields */
+  GRF_PASS_ROW_GEN_C2R = 8,   /* d = 1: noise (+ forward transform, two-FFT) + filter + complex-to-real, whole fields */
   GRF_PASS_R2R_COL_GEN = 9,   /* reflecting boundaries: coefficients + cosine transform along axis 1 */
   GRF_PASS_R2R_COL_LOAD = 10, /* reflecting boundaries: cosine transform along the middle axis (d = 3) */
   GRF_PASS_R2R_ROW_LOAD = 11, /* reflecting boundaries: cosine transform along the last axis */
   GRF_PASS_R2R_ROW_GEN = 12,  /* reflecting boundaries, d = 1: coefficients + cosine transform of whole fields */
   GRF_PASS_COL_SEQ_INV = 13,  /* as GRF_PASS_COL_GEN_INV, normals in the recursive algorithm's draw order */
-  GRF_PASS_SPEC_FILTER = 14   /* two-FFT, d = 1 and 3: filter on the packed spectrum after the forward transforms */
+  GRF_PASS_SPEC_FILTER = 14   /* two-FFT, d = 3: filter on the packed spectrum after the forward transforms */
 };
 grf_status grf_sample_stage_count(grf_plan plan, int64_t batch, int32_t* count);
 grf_status grf_sample_stage(grf_plan plan, int32_t stage, uint64_t seed, int64_t batch, const double* theta,

@@ -388,10 +388,13 @@ void chunk_passes(const grf_plan_s* p, uint64_t seed, const void* zsrc, long lon
     return;
   }
   const bool seq = p->desc.draw_order == GRF_DRAW_RECURSIVE;
-  if (p->d == 1 && p->desc.alg == GRF_ALG_ONE_FFT) {
-    // one launch: noise, filter and complex-to-real transform of whole fields
-    a.tag = seq ? 3 : 1;
+  if (p->d == 1) {
+    // one launch of whole fields: noise, filter and complex-to-real transform
+    // (the two-FFT algorithm: white noise and its forward transform first)
+    const bool two = p->desc.alg == GRF_ALG_TWO_FFT;
+    a.tag = two ? 0 : seq ? 3 : 1;
     a.seq = seq;
+    if (two) a.scale = 1.0 / std::sqrt((double)p->P);   // the table, where there is one, carries it
     a.tw2 = p->tw_row;
     a.rows = nb;
     push(grf::PASS_ROW_GEN_C2R, p->M, a);

@@ -136,6 +136,89 @@ struct Gen1D {
     EN::template run<+1>(x, t, act, lds, tw, out);
   }
 
+  // The two-FFT algorithm on whole fields (Section 3, the first algorithm):
+  // the white noise (tag 0, or given rows) as y_n = x_{2n} + i x_{2n+1} into
+  // LDS, the forward length-M transform, then per pair (k, M - k) the
+  // real-to-complex post-twiddle X_k = E_k + w^{-k} D_k and the filter
+  // h_k / sqrt(P) in place (slot 0: A_0 + i A_M, both real), and the same
+  // complex-to-real transform as the one-FFT path.
+  __device__ __forceinline__ static void run_two_fft(const Args& a, int bid, char* smem) {
+    E* sm = reinterpret_cast<E*>(smem);
+    V* tws = reinterpret_cast<V*>(smem + ROWS_BYTES);
+    const V* tw = TW_GLOBAL ? (const V*)a.tw2 : tws;
+    const int tid = threadIdx.x;
+    const int r = tid / NT, t = tid % NT;
+    const long long f0 = (long long)bid * RB;
+    const long long left = a.rows - f0;
+    const int nrows = left < RB ? (int)left : RB;
+    if constexpr (!TW_GLOBAL)
+      for (int i = tid; i < 2 * M; i += blockDim.x) tws[i] = ((const V*)a.tw2)[i];
+    constexpr int NQ = M / 2;   // Philox blocks per field
+    for (int i = tid; i < nrows * NQ; i += blockDim.x) {
+      const int rr = i / NQ, q = i % NQ;
+      const long long b = f0 + rr;
+      T z[4];
+      if (a.src != nullptr) {
+        const T* p = (const T*)a.src + b * (2 * M) + 4 * q;
+        z[0] = p[0];
+        z[1] = p[1];
+        z[2] = p[2];
+        z[3] = p[3];
+      } else {
+        const unsigned long long key = a.seed + (unsigned long long)b;
+        normals4<T, false>((uint32_t)q, 0u, (uint32_t)a.tag, (uint32_t)key, (uint32_t)(key >> 32), z);
+      }
+      E* row = sm + rr * RL::STRIDE;
+      row[RL::idx(2 * q)].v[0] = mk<T>(z[0], z[1]);
+      row[RL::idx(2 * q + 1)].v[0] = mk<T>(z[2], z[3]);
+    }
+    __syncthreads();
+    const bool act = r < nrows;
+    auto lds = [&](int i) -> E& { return sm[r * RL::STRIDE + RL::idx(i)]; };
+    V x[1][EN::REG];
+    if (act) {
+#pragma unroll
+      for (int m = 0; m < R0; ++m) x[0][m] = lds(t + m * NT).v[0];
+    }
+    stage_sync<WAVE>();   // from here on a row's LDS area is used by its own threads only
+    EN::template run<-1>(x, t, act, lds, tw, [&](int i, const E& e) { lds(i) = e; });
+    stage_sync<WAVE>();
+    if (act) {
+      const long long b = f0 + r;
+      const Filt<T> f = load_filt<T>(a.recs[b * a.rec_stride], a.scale);
+      const T* ht = (const T*)a.htab;
+      const T il2 = (T)a.il2[2];
+      auto hk = [&](int k) -> T { return ht ? ht[k] : filt_h(f, (T)(k * k) * il2); };
+      for (int k = t; 2 * k <= M; k += NT) {
+        if (k == 0) {
+          const V y0 = lds(0).v[0];
+          lds(0).v[0] = mk<T>(hk(0) * (y0.x + y0.y), hk(M) * (y0.x - y0.y));   // A_0 + i A_M
+          continue;
+        }
+        const int km = M - k;
+        const V yk = lds(k).v[0], ym = lds(km).v[0];
+        const V ek = cscale(cadd(yk, cconj(ym)), (T)0.5);
+        const V dk = cscale(csub(yk, cconj(ym)), (T)0.5);
+        const V xk = cadd(ek, cmul(mk<T>(dk.y, -dk.x), cconj(tw[k])));
+        const T hkk = hk(k);
+        lds(k).v[0] = mk<T>(hkk * xk.x, hkk * xk.y);
+        if (km != k) {
+          const V em = cscale(cadd(ym, cconj(yk)), (T)0.5);
+          const V dm = cscale(csub(ym, cconj(yk)), (T)0.5);
+          const V xm = cadd(em, cmul(mk<T>(dm.y, -dm.x), cconj(tw[km])));
+          const T hm = hk(km);
+          lds(km).v[0] = mk<T>(hm * xm.x, hm * xm.y);
+        }
+      }
+    }
+    stage_sync<WAVE>();
+    if (act) prepare(sm + r * RL::STRIDE, tw, t, x);
+    stage_sync<WAVE>();
+    V* o = (V*)a.data + (f0 + r) * M;
+    auto out = [&](int i, const E& e) { o[i] = e.v[0]; };
+    EN::template run<+1>(x, t, act, lds, tw, out);
+  }
+
   // Covariance estimator: workgroup w takes the field blocks w, w + G, ...
   // (G = gridDim.x) of the a.rows fields, accumulates phi(0) phi(x) in
   // float64, adds its rows in order and writes M complex (= 2M real) partial
@@ -220,6 +303,13 @@ __global__ void __launch_bounds__((Gen1D<T, M, Rad, RB>::THREADS)) k_gen1d(Args 
   using PS = Gen1D<T, M, Rad, RB>;
   __shared__ __align__(16) char smem[PS::LDS_BYTES];
   PS::run(a, blockIdx.x, smem);
+}
+
+template <typename T, int M, class Rad, int RB>
+__global__ void __launch_bounds__((Gen1D<T, M, Rad, RB>::THREADS)) k_gen1d_two(Args a) {
+  using PS = Gen1D<T, M, Rad, RB>;
+  __shared__ __align__(16) char smem[PS::LDS_BYTES];
+  PS::run_two_fft(a, blockIdx.x, smem);
 }
 
 template <typename T, int M, class Rad, int RB>
