@@ -186,3 +186,21 @@ def test_per_field_parameters(grf, dims):
         assert np.abs(phi[b] - ref).max() <= 1e-12 * np.abs(ref).max()
         gref = oadj.grad_theta_alg1(z, g[b], lengths, spectra.MATERN, *th[b])
         assert np.abs(gt[b] - gref).max() <= 1e-10 * np.abs(gref).max()
+
+
+@pytest.mark.parametrize("dims,alg", [((64,), 1), ((8, 12, 16), 1), ((64, 96), 1), ((64, 96), 2), ((4096,), 2)],
+                         ids=str)
+def test_empty_batch_everywhere(grf, dims, alg):
+    """batch = 0 is a no-op for every entry point, whatever the output holds."""
+    plan = grf.Plan(dims, alg=alg)
+    out = torch.full((1,) + dims, 7.0, device="cuda")
+    plan.sample(seed=0, batch=0, out=out)
+    z = plan.noise(seed=0, batch=0)
+    assert z.shape == (0,) + dims
+    plan.sample_from_noise(z, out=out[:0])
+    gt, gz = plan.backward(torch.zeros((0,) + dims), seed=0, need_noise_grad=True)
+    assert gt.shape == (0, 3) and gz.shape == (0,) + dims
+    if alg == 2:
+        assert plan.spectrum(seed=0, batch=0).shape[0] == 0
+    torch.cuda.synchronize()
+    assert torch.all(out == 7.0)
