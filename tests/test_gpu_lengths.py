@@ -1,7 +1,8 @@
 """Every supported transform length against the float64 oracle: the column
 lengths (generation pass along axis 1, the middle-axis pass of d = 3, the
-adjoint's column kernel) and the row half-lengths (last-axis pass, the 1D
-kernel, the adjoint's last-axis pass), for periodic and reflecting plans, in
+adjoint's column kernel, the two-FFT algorithm's column passes) and the row
+half-lengths (last-axis pass, the 1D kernels, the adjoint's last-axis pass,
+the two-FFT algorithm's noise pass), for periodic and reflecting plans, in
 float32 and float64."""
 import numpy as np
 import pytest
@@ -49,6 +50,15 @@ def periodic(grf, dims, dtype):
     assert np.abs(gt[0].cpu().numpy() - rg).max() <= 10 * TOL[dtype] * np.abs(rg).max(), (dims, dtype)
 
 
+def two_fft(grf, dims, dtype):
+    lengths = tuple(1.0 + 0.25 * i for i in range(len(dims)))
+    plan = grf.Plan(dims, lengths=lengths, alg=1, dtype=dtype, cov="matern", sigma=PARAMS[0],
+                    length_scale=PARAMS[1], nu=PARAMS[2])
+    got = plan.sample(seed=3, batch=1)[0].double().cpu().numpy()
+    ref = ogrf.sample(dims, lengths, spectra.MATERN, *PARAMS, seed=3, batch=1, alg=1)[0]
+    assert relerr(got, ref) <= TOL[dtype], (dims, dtype, relerr(got, ref))
+
+
 def reflecting(grf, dims, dtype):
     lengths = tuple(1.0 + 0.25 * i for i in range(len(dims)))
     sine = tuple(i % 2 == 0 for i in range(len(dims)))
@@ -65,6 +75,8 @@ def reflecting(grf, dims, dtype):
 def test_column_length(grf, dtype, L):
     periodic(grf, (L, 16), dtype)
     periodic(grf, (4, L, 8), dtype)
+    two_fft(grf, (L, 16), dtype)
+    two_fft(grf, (4, L, 8), dtype)
     reflecting(grf, (L, 16), dtype)
     reflecting(grf, (4, L, 8), dtype)
 
@@ -74,5 +86,7 @@ def test_column_length(grf, dtype, L):
 def test_row_length(grf, dtype, M):
     periodic(grf, (8, 2 * M), dtype)
     periodic(grf, (2 * M,), dtype)
+    two_fft(grf, (8, 2 * M), dtype)
+    two_fft(grf, (2 * M,), dtype)
     reflecting(grf, (8, 2 * M), dtype)
     reflecting(grf, (2 * M,), dtype)
