@@ -171,7 +171,8 @@ PASS_NAMES = {0: "column noise+inverse FFT (axis 1)", 1: "inverse FFT (axis 2)",
               6: "last-axis noise+R2C", 7: "last-axis R2C", -1: "fused column gen | last-axis C2R",
               9: "reflecting: column coefficients+DCT (axis 1)", 10: "reflecting: DCT (axis 2)",
               11: "reflecting: last-axis DCT", 12: "reflecting: 1D coefficients+DCT",
-              13: "column noise (recursive order)+inverse FFT (axis 1)", 14: "filter on the packed spectrum"}
+              13: "column noise (recursive order)+inverse FFT (axis 1)", 14: "filter on the packed spectrum",
+              109: "column fwd FFT x h x inv FFT (d = 3)", 110: "filter on the packed plane slots"}
 
 
 def pass_bytes(kind, field_bytes):

@@ -191,9 +191,12 @@ grf_status grf_sample_from_noise(grf_plan plan, const void* noise, int64_t batch
  * noise + real-to-complex, column forward/filter/inverse, last-axis
  * complex-to-real; d = 1 (both algorithms): one launch over whole fields
  * (GRF_PASS_ROW_GEN_C2R); two-FFT, d = 3: last-axis noise +
- * real-to-complex, forward transforms along the middle axis and axis 1, the
- * filter, inverse transforms along axis 1 and the middle axis, last-axis
- * complex-to-real.
+ * real-to-complex, forward transform along the middle axis, the column pass
+ * of axis 1 (forward, filter, inverse) for every slot but the packed plane
+ * slot, then for that slot alone forward along axis 1, its filter and the
+ * inverse (three small launches), the middle-axis inverse transform and the
+ * last-axis complex-to-real; the axis-1 column pass and the plane-slot filter
+ * report the internal kinds 109 and 110.
  * With GRF_FUSE=1 a one-FFT d = 2 batch of two or more fields on a supported
  * grid pairs, in each launch, the column pass of one chunk with the last-axis
  * pass of the previous chunk (GRF_PASS_FUSED).
@@ -221,7 +224,7 @@ enum {
   GRF_PASS_R2R_ROW_LOAD = 11, /* reflecting boundaries: cosine transform along the last axis */
   GRF_PASS_R2R_ROW_GEN = 12,  /* reflecting boundaries, d = 1: coefficients + cosine transform of whole fields */
   GRF_PASS_COL_SEQ_INV = 13,  /* as GRF_PASS_COL_GEN_INV, normals in the recursive algorithm's draw order */
-  GRF_PASS_SPEC_FILTER = 14   /* two-FFT, d = 3: filter on the packed spectrum after the forward transforms */
+  GRF_PASS_SPEC_FILTER = 14   /* two-FFT: filter on the packed spectrum after the forward transforms (not in the sampler's sequences) */
 };
 grf_status grf_sample_stage_count(grf_plan plan, int64_t batch, int32_t* count);
 grf_status grf_sample_stage(grf_plan plan, int32_t stage, uint64_t seed, int64_t batch, const double* theta,

@@ -261,6 +261,8 @@ grf_status run_pass(const grf_plan_s* p, int pass, int L, Args a, long long nfix
   long long nblocks;
   if (pass == grf::PASS_SPEC_FILTER) {
     nblocks = (a.rows * a.M + g.threads - 1) / g.threads;
+  } else if (pass == grf::PASS_SPEC_FILTER0) {
+    nblocks = (a.rows + g.threads - 1) / g.threads;
   } else if (grf::is_row_pass(pass)) {
     nblocks = (a.rows + g.per_wg - 1) / g.per_wg;
   } else {
@@ -424,8 +426,8 @@ void chunk_passes(const grf_plan_s* p, uint64_t seed, const void* zsrc, long lon
       push(grf::PASS_COL_LOAD_INV, p->no, m);
     }
   } else if (p->d != 2) {
-    // two-FFT, d = 1 and 3: last-axis R2C, forward transforms along the
-    // leading axes, the filter on the packed spectrum, inverse transforms
+    // two-FFT, d = 3 (d = 1 is one launch, above): last-axis R2C, then the
+    // leading axes
     Args r = a;
     r.tag = 0;
     r.tw2 = p->tw_row;
@@ -441,20 +443,26 @@ void chunk_passes(const grf_plan_s* p, uint64_t seed, const void* zsrc, long lon
     c.stride_ax = (long long)p->no * p->M;
     c.stride_fixed = p->M;
     c.nfixed = p->no;
-    if (p->d == 3) {
-      push(grf::PASS_COL_LOAD_FWD, p->no, m);
-      push(grf::PASS_COL_LOAD_FWD, p->n1, c);
-    }
     Args f = a;
     f.src = nullptr;
     f.rows = nb * (p->P / p->nd);
     f.scale = 1.0 / std::sqrt((double)p->P);   // the table, where there is one, carries it
     f.htab = p->table_only ? p->htab : nullptr;
-    push(grf::PASS_SPEC_FILTER, 0, f);
-    if (p->d == 3) {
-      push(grf::PASS_COL_LOAD_INV, p->n1, c);
-      push(grf::PASS_COL_LOAD_INV, p->no, m);
-    }
+    // d = 3: the middle axis forward; axis 1 forward, filter, inverse for
+    // every slot but the packed plane slot, in one column pass; that slot's
+    // column (M = 1 restricts a column pass to it) forward, its filter with
+    // the mirrored rows, inverse; the middle axis inverse
+    push(grf::PASS_COL_LOAD_FWD, p->no, m);
+    Args cf = c;
+    cf.scale = f.scale;
+    cf.htab = f.htab;
+    push(grf::PASS_COL_FILTER3, p->n1, cf);
+    Args c0 = c;
+    c0.M = 1;
+    push(grf::PASS_COL_LOAD_FWD, p->n1, c0);
+    push(grf::PASS_SPEC_FILTER0, 0, f);
+    push(grf::PASS_COL_LOAD_INV, p->n1, c0);
+    push(grf::PASS_COL_LOAD_INV, p->no, m);
   } else {
     Args r = a;
     r.tag = 0;
@@ -875,7 +883,7 @@ bool row_length_supported(int M) {
 }
 
 Geom pass_geom(int pass, int dtype, int L) {
-  if (pass == PASS_SPEC_FILTER) return Geom{256, 0};
+  if (pass == PASS_SPEC_FILTER || pass == PASS_SPEC_FILTER0) return Geom{256, 0};
   if (is_r2r_pass(pass)) return geom_r2r(pass, dtype, L);
   if (pass == PASS_ROW_GEN_C2R) return geom_gen1d(dtype, L);
   if (is_row_pass(pass)) return dtype == 0 ? geom_row_f32(pass, L) : geom_row_f64(pass, L);
@@ -889,7 +897,8 @@ hipError_t launch_fused(int dtype, int L, int M, const Args& aA, const Args& aB,
 }
 
 hipError_t launch_pass(int pass, int dtype, int L, const Args& a, long long nblocks, hipStream_t s) {
-  if (pass == PASS_SPEC_FILTER) return launch_spec_filter(dtype, a, nblocks, s);
+  if (pass == PASS_SPEC_FILTER || pass == PASS_SPEC_FILTER0)
+    return launch_spec_filter(dtype, a, nblocks, pass == PASS_SPEC_FILTER0, s);
   if (is_r2r_pass(pass)) return launch_r2r(pass, dtype, L, a, nblocks, s);
   if (pass == PASS_ROW_GEN_C2R) return launch_gen1d(dtype, L, a, nblocks, nullptr, s);
   if (is_row_pass(pass))

@@ -52,6 +52,8 @@ enum PassKind {
   PASS_R2R_COL_FWD_RED = 105,
   PASS_COL_GRAD_SEQ = 106,                     // PASS_COL_GRAD / _GRAD3 in the recursive draw order
   PASS_COL_GRAD3_SEQ = 107,
+  PASS_COL_FILTER3 = 109,                      // two-FFT, d = 3: PASS_COL_FILTER without the packed plane slot
+  PASS_SPEC_FILTER0 = 110,                     // two-FFT, d = 3: the filter on the packed plane slots only
 };
 
 inline bool is_r2r_pass(int p) {
@@ -145,7 +147,7 @@ hipError_t launch_grad_plane(int dtype, const Args& a, hipStream_t s);
 // Two-FFT algorithm, d = 1 and 3: the filter on the packed spectrum (one
 // thread per slot, a.rows = rows of the chunk) and the adjoint's reduction
 // over the packed spectra of g and z (a.ntile workgroups per field).
-hipError_t launch_spec_filter(int dtype, const Args& a, long long nblocks, hipStream_t s);
+hipError_t launch_spec_filter(int dtype, const Args& a, long long nblocks, bool slot0, hipStream_t s);
 hipError_t launch_grad_spec(int dtype, const Args& a, long long nblocks, hipStream_t s);
 // The one-FFT sampler's half-spectrum A = h xi before the inverse transforms
 // (a.ntile workgroups per field).

@@ -564,7 +564,11 @@ k_col(Args a) {
 // ---------------------------------------------------------------------------
 // Two-FFT algorithm, column stage: forward transform along axis 1, multiply by
 // h / sqrt(P) (separating the packed planes first), inverse transform.
-template <typename T, int L, class Rad, int CP, int PAD>
+// D3 (d = 3, after the forward transform along the middle axis): the tiles
+// also run over the middle index fx; the packed plane slot (m = 0) needs the
+// column of -fx for its separation, so it is left to the slot-0 passes and
+// this kernel neither filters nor stores it.
+template <typename T, int L, class Rad, int CP, int PAD, bool D3 = false>
 __global__ void __launch_bounds__(((L / Rad::get(0)) * CP + 63) / 64 * 64)
 k_colf(Args a) {
   using V = C<T>;
@@ -580,13 +584,14 @@ k_colf(Args a) {
   const int t = tid / CP;
   int bid = col_block(a.order);
   const int tile = bid % a.ntile;
-  const int b = bid / a.ntile;
+  const int fx = D3 ? (bid / a.ntile) % a.nfixed : 0;
+  const int b = D3 ? bid / a.ntile / a.nfixed : bid / a.ntile;
   for (int i = tid; i < L; i += blockDim.x) tw[i] = ((const V*)a.tw)[i];
   const int m0 = (tile * CP + cp) * 2;
   const bool act = (t < NT) && (m0 < a.M);
   const bool two = (m0 + 1) < a.M;
   const bool al = (a.M & 1) == 0;
-  V* base = (V*)a.data + (long long)b * a.field_stride + m0;
+  V* base = (V*)a.data + (long long)b * a.field_stride + (D3 ? (long long)fx * a.stride_fixed : 0LL) + m0;
   V x[2][EN::REG];
   // filter values of this thread's entries, fetched before the forward
   // transform so that their latency is hidden behind it
@@ -599,7 +604,7 @@ k_colf(Args a) {
     if (ht) {
 #pragma unroll
       for (int m = 0; m < R0; ++m) {
-        const T* hrow = ht + (long long)(t + m * NT) * (a.M + 2);
+        const T* hrow = ht + (long long)((t + m * NT) * (D3 ? a.no : 1) + fx) * (a.M + 2);
         hp[m][0] = hrow[m0];
         hp[m][1] = hrow[m0 + 1];
         hp[m][2] = m0 == 0 ? hrow[a.M] : (T)0;
@@ -617,13 +622,16 @@ k_colf(Args a) {
     for (int m = 0; m < R0; ++m) {
       const int k1 = t + m * NT;
       const int q1 = wrapk(k1, L);
-      const T p2b = (T)(q1 * q1) * (T)a.il2[0];
+      const int qo = D3 ? wrapk(fx, a.no) : 0;
+      const T p2b = (T)(q1 * q1) * (T)a.il2[0] + (T)(qo * qo) * (T)a.il2[1];
       const E e = sm[k1 * RS + cp];
       const T h1 = ht ? hp[m][1] : filt_h(f, p2b + (T)((m0 + 1) * (m0 + 1)) * il2d);
       x[1][m] = cscale(e.v[1], h1);
       if (m0 > 0) {
         const T h0 = ht ? hp[m][0] : filt_h(f, p2b + (T)(m0 * m0) * il2d);
         x[0][m] = cscale(e.v[0], h0);
+      } else if (D3) {
+        x[0][m] = e.v[0];   // not stored
       } else {
         const V w = e.v[0];
         const V wm = sm[((L - k1) % L) * RS + cp].v[0];
@@ -638,7 +646,13 @@ k_colf(Args a) {
     }
   }
   __syncthreads();
-  auto out = [&](int i, const E& e) { st_pair<T>(base + (long long)i * a.stride_ax, two, al, e); };
+  auto out = [&](int i, const E& e) {
+    if (D3 && m0 == 0) {
+      if (two) base[(long long)i * a.stride_ax + 1] = e.v[1];
+    } else {
+      st_pair<T>(base + (long long)i * a.stride_ax, two, al, e);
+    }
+  };
   EN::template run<+1>(x, t, act, lds, tw, out);
 }
 

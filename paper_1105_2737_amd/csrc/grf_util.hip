@@ -323,15 +323,17 @@ __global__ void k_grad_plane(Args a) {
 // with W = Z(-k): X(k, 0) = (Z + conj W)/2 and X(k, N_d/2) = (Z - conj W)/(2i).
 // The thread of the smaller of the rows k, -k filters both planes and writes
 // both slots (A(-k) = conj A(k), since h is even).
-template <typename T>
+// SLOT0: only the packed plane slots (one thread per row), the other slots
+// having been filtered by the column pass.
+template <typename T, bool SLOT0 = false>
 __global__ void __launch_bounds__(256) k_spec_filter(Args a) {
   using V = C<T>;
   const long long R = (long long)a.n1 * a.no;
   const int M = a.M;
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (i >= a.rows * M) return;
-  const int m = (int)(i % M);
-  const long long grow = i / M;
+  if (i >= a.rows * (SLOT0 ? 1 : M)) return;
+  const int m = SLOT0 ? 0 : (int)(i % M);
+  const long long grow = SLOT0 ? i : i / M;
   const long long b = grow / R;
   const int row = (int)(grow - b * R);
   const int k1 = row / a.no, o = row - (row / a.no) * a.no;
@@ -463,11 +465,15 @@ hipError_t launch_debug_spectrum(int dtype, const Args& a, long long nblocks, hi
   return hipGetLastError();
 }
 
-hipError_t launch_spec_filter(int dtype, const Args& a, long long nblocks, hipStream_t s) {
-  if (dtype == 0)
-    hipLaunchKernelGGL(k_spec_filter<float>, dim3((unsigned)nblocks), dim3(256), 0, s, a);
+hipError_t launch_spec_filter(int dtype, const Args& a, long long nblocks, bool slot0, hipStream_t s) {
+  if (dtype == 0 && slot0)
+    hipLaunchKernelGGL((k_spec_filter<float, true>), dim3((unsigned)nblocks), dim3(256), 0, s, a);
+  else if (dtype == 0)
+    hipLaunchKernelGGL((k_spec_filter<float, false>), dim3((unsigned)nblocks), dim3(256), 0, s, a);
+  else if (slot0)
+    hipLaunchKernelGGL((k_spec_filter<double, true>), dim3((unsigned)nblocks), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL(k_spec_filter<double>, dim3((unsigned)nblocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_spec_filter<double, false>), dim3((unsigned)nblocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -82,9 +82,9 @@ def test_routes_and_chunking_bitwise(grf, dims):
 def test_launch_sequence(grf):
     from paper_1105_2737_amd import _lib as L
     for dims, kinds in [((64,), [L.GRF_PASS_ROW_GEN_C2R]),
-                        ((8, 12, 16), [L.GRF_PASS_ROW_R2C_GEN, L.GRF_PASS_COL_LOAD_FWD, L.GRF_PASS_COL_LOAD_FWD,
-                                       L.GRF_PASS_SPEC_FILTER, L.GRF_PASS_COL_LOAD_INV, L.GRF_PASS_COL_LOAD_INV,
-                                       L.GRF_PASS_ROW_C2R])]:
+                        ((8, 12, 16), [L.GRF_PASS_ROW_R2C_GEN, L.GRF_PASS_COL_LOAD_FWD, 109,
+                                       L.GRF_PASS_COL_LOAD_FWD, 110, L.GRF_PASS_COL_LOAD_INV,
+                                       L.GRF_PASS_COL_LOAD_INV, L.GRF_PASS_ROW_C2R])]:
         plan = grf.Plan(dims, alg=1)
         assert [L.grf_sample_stage_info(plan.handle, 2, s)[0] for s in range(L.grf_sample_stage_count(plan.handle, 2))] \
             == kinds
