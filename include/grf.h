@@ -197,19 +197,14 @@ grf_status grf_sample_from_noise(grf_plan plan, const void* noise, int64_t batch
  * inverse (three small launches), the middle-axis inverse transform and the
  * last-axis complex-to-real; the axis-1 column pass and the plane-slot filter
  * report the internal kinds 109 and 110.
- * With GRF_FUSE=1 a one-FFT d = 2 batch of two or more fields on a supported
- * grid pairs, in each launch, the column pass of one chunk with the last-axis
- * pass of the previous chunk (GRF_PASS_FUSED).
  * grf_sample_stage_count returns the number of launches for a batch of
  * `batch` fields (host pointer); grf_sample_stage runs only launch `stage`
  * (0-based) with the arguments of grf_sample, so that each kernel can be
  * timed on its own.  Run alone, a later stage transforms whatever `out`
  * holds.  grf_sample_stage_info reports, for launch `stage` of a batch of
  * `batch` fields, the pass it runs (*kind, one of GRF_PASS_*) and the fields
- * first .. first + count - 1 it covers (for a fused launch, those of its
- * column pass); host pointers, any may be NULL. */
+ * first .. first + count - 1 it covers; host pointers, any may be NULL. */
 enum {
-  GRF_PASS_FUSED = -1,
   GRF_PASS_COL_GEN_INV = 0,   /* noise + filter + inverse transform along axis 1 (one-FFT) */
   GRF_PASS_COL_LOAD_INV = 1,  /* inverse transform along the middle axis (d = 3) */
   GRF_PASS_COL_LOAD_FWD = 2,  /* forward transform along the middle axis */

@@ -17,7 +17,7 @@ from ._lib import (GRFError, grf_plan_create, grf_plan_destroy, grf_workspace_si
                    grf_sample, grf_sample_stage_count, grf_sample_stage, grf_sample_stage_info,
                    grf_sample_from_noise, grf_noise, grf_backward, grf_debug_philox, grf_debug_spectrum,
                    grf_covariance,
-                   grf_last_error, grf_version, GRF_PASS_FUSED, GRF_PASS_COL_GEN_INV,
+                   grf_last_error, grf_version, GRF_PASS_COL_GEN_INV,
                    GRF_PASS_COL_LOAD_INV, GRF_PASS_COL_FILTER, GRF_PASS_ROW_C2R, GRF_PASS_ROW_R2C_GEN, GRF_PASS_ROW_GEN_C2R,
                    GRF_PASS_R2R_COL_GEN, GRF_PASS_R2R_COL_LOAD, GRF_PASS_R2R_ROW_LOAD, GRF_PASS_R2R_ROW_GEN,
                    GRF_PASS_COL_SEQ_INV, GRF_PASS_SPEC_FILTER,

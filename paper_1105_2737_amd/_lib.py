@@ -12,7 +12,7 @@ GRF_ALG_TWO_FFT, GRF_ALG_ONE_FFT = 1, 2
 GRF_F32, GRF_F64 = 0, 1
 GRF_COV_GAUSSIAN, GRF_COV_MATERN, GRF_COV_EXPONENTIAL, GRF_COV_PAPER, GRF_COV_TABULATED = 0, 1, 2, 3, 4
 GRF_OP_SAMPLE, GRF_OP_BACKWARD, GRF_OP_COVARIANCE = 0, 1, 2
-GRF_PASS_FUSED, GRF_PASS_COL_GEN_INV, GRF_PASS_COL_LOAD_INV, GRF_PASS_COL_LOAD_FWD = -1, 0, 1, 2
+GRF_PASS_COL_GEN_INV, GRF_PASS_COL_LOAD_INV, GRF_PASS_COL_LOAD_FWD = 0, 1, 2
 GRF_PASS_COL_FILTER, GRF_PASS_COL_GRAD, GRF_PASS_ROW_C2R, GRF_PASS_ROW_R2C_GEN, GRF_PASS_ROW_R2C_LOAD = 3, 4, 5, 6, 7
 GRF_PASS_ROW_GEN_C2R = 8
 GRF_PASS_R2R_COL_GEN, GRF_PASS_R2R_COL_LOAD, GRF_PASS_R2R_ROW_LOAD, GRF_PASS_R2R_ROW_GEN = 9, 10, 11, 12

@@ -277,18 +277,14 @@ grf_status run_pass(const grf_plan_s* p, int pass, int L, Args a, long long nfix
   return GRF_OK;
 }
 
-// One launch of the sampler: a single pass (pass >= 0), or (pass == -1) a
-// fused launch of a column generation pass (args a, length L) and a last-axis
-// complex-to-real pass over another chunk of fields (args b, half-length M2).
+// One launch of the sampler: pass kind, transform length, arguments and the
+// fields first .. first + count - 1 of the call that it covers.
 struct PassLaunch {
   int pass;
   int L;
   Args a;
-  long long first = 0;        // fields first .. first + count - 1 of the call
+  long long first = 0;
   long long count = 0;
-  int M2 = 0;
-  Args b{};
-  bool hasA = true, hasB = true;
 };
 
 // Fields per chunk: the sampler runs all its passes on one chunk of fields
@@ -307,27 +303,8 @@ long long chunk_fields(const grf_plan_s* p, long long batch) {
   return c;
 }
 
-// The fused schedule is opt-in (GRF_FUSE=1): with the tile shapes in use the
-// two passes launched separately are faster on MI355X (0.86 vs 0.94 ms for
-// 1024 fields of 512 x 512).
-bool fuse_enabled() {
-  const char* e = std::getenv("GRF_FUSE");
-  return e && e[0] == '1';
-}
-
 grf_status run_launch(const grf_plan_s* p, const PassLaunch& pl, hipStream_t s) {
-  if (pl.pass >= 0) return run_pass(p, pl.pass, pl.L, pl.a, 0, pl.count, s);
-  const grf::FusedGeom g = grf::fused_geom(p->dtype, pl.L, pl.M2);
-  if (g.threads <= 0) return fail(GRF_EUNSUPPORTED, "no fused kernel for this shape");
-  Args a = pl.a;
-  a.ntile = (a.M + 2 * g.cp - 1) / (2 * g.cp);
-  const long long nA = pl.hasA ? (long long)a.ntile * a.nfixed * a.batch : 0;
-  const long long nB = pl.hasB ? (pl.b.rows + g.rb - 1) / g.rb : 0;
-  if (nA + nB <= 0) return GRF_OK;
-  if (nA + nB > 0x7fffffffLL) return fail(GRF_EINVAL, "batch too large for one launch");
-  hipError_t e = grf::launch_fused(p->dtype, pl.L, pl.M2, a, pl.b, (int)nA, (int)nB, s);
-  if (e != hipSuccess) return hip_fail(e, "fused kernel launch");
-  return GRF_OK;
+  return run_pass(p, pl.pass, pl.L, pl.a, 0, pl.count, s);
 }
 
 // The passes of the sampler over fields c0 .. c0 + nb - 1 (zsrc == nullptr
@@ -494,30 +471,6 @@ std::vector<PassLaunch> sample_passes(const grf_plan_s* p, uint64_t seed, const 
   std::vector<PassLaunch> v;
   const long long C = chunk_fields(p, batch);
   const long long nch = (batch + C - 1) / C;
-  if (!p->reflect && p->desc.draw_order == GRF_DRAW_COUNTER && p->desc.alg == GRF_ALG_ONE_FFT && p->d == 2 &&
-      fuse_enabled() && batch >= 2 &&
-      grf::fused_geom(p->dtype, p->n1, p->M).threads > 0) {
-    // Fused chunk schedule: launch k runs the column generation pass of
-    // chunk k and the last-axis pass of chunk k-1, so that the VALU-heavy and
-    // the memory-heavy passes share the CUs.
-    std::vector<PassLaunch> parts;
-    for (long long k = 0; k < nch; ++k)
-      chunk_passes(p, seed, zsrc, k * C, std::min(C, batch - k * C), recs, rstride, out, parts);
-    for (long long k = 0; k <= nch; ++k) {
-      PassLaunch pl;
-      pl.pass = -1;
-      pl.L = p->n1;
-      pl.M2 = p->M;
-      pl.hasA = k < nch;
-      pl.hasB = k >= 1;
-      pl.a = pl.hasA ? parts[2 * k].a : parts[0].a;
-      pl.b = pl.hasB ? parts[2 * k - 1].a : parts[1].a;
-      pl.first = pl.hasA ? parts[2 * k].first : 0;
-      pl.count = pl.hasA ? parts[2 * k].count : 0;
-      v.push_back(pl);
-    }
-    return v;
-  }
   for (long long k = 0; k < nch; ++k) chunk_passes(p, seed, zsrc, k * C, std::min(C, batch - k * C), recs, rstride, out, v);
   return v;
 }
@@ -890,12 +843,6 @@ Geom pass_geom(int pass, int dtype, int L) {
   return dtype == 0 ? geom_col_f32(pass, L) : geom_col_f64(pass, L);
 }
 
-FusedGeom fused_geom(int dtype, int L, int M) { return dtype == 0 ? fused_geom_f32(L, M) : fused_geom_f64(L, M); }
-
-hipError_t launch_fused(int dtype, int L, int M, const Args& aA, const Args& aB, int nA, int nB, hipStream_t s) {
-  return dtype == 0 ? launch_fused_f32(L, M, aA, aB, nA, nB, s) : launch_fused_f64(L, M, aA, aB, nA, nB, s);
-}
-
 hipError_t launch_pass(int pass, int dtype, int L, const Args& a, long long nblocks, hipStream_t s) {
   if (pass == PASS_SPEC_FILTER || pass == PASS_SPEC_FILTER0)
     return launch_spec_filter(dtype, a, nblocks, pass == PASS_SPEC_FILTER0, s);
@@ -1148,7 +1095,7 @@ grf_status grf_sample_stage_info(grf_plan p, int64_t batch, int32_t stage, int32
   const std::vector<PassLaunch> v = sample_passes(p, 0, nullptr, batch, p->rec_dev, 0, nullptr);
   if (stage < 0 || stage >= (int)v.size()) return fail(GRF_EINVAL, "stage out of range");
   const PassLaunch& pl = v[stage];
-  if (kind) *kind = pl.pass >= 0 ? pl.pass : GRF_PASS_FUSED;
+  if (kind) *kind = pl.pass;
   if (first) *first = pl.first;
   if (count) *count = pl.count;
   return GRF_OK;
@@ -1165,6 +1112,9 @@ grf_status grf_noise(grf_plan p, uint64_t seed, int64_t batch, void* noise_out, 
   if (batch < 0) return fail(GRF_EINVAL, "negative batch");
   if (batch == 0) return GRF_OK;
   if (noise_out == nullptr) return fail(GRF_EINVAL, "null output");
+  if (batch > 0x7fffffff) return fail(GRF_EINVAL, "batch too large");
+  grf_status st = check_stream_device(p);
+  if (st != GRF_OK) return st;
   const int tag = p->reflect ? 2 : p->desc.draw_order == GRF_DRAW_RECURSIVE ? 3 : (p->desc.alg == GRF_ALG_ONE_FFT ? 1 : 0);
   hipError_t e = grf::launch_noise(p->dtype, seed, tag, (int)(p->P / p->nd), p->nd, (int)batch, noise_out,
                                    (hipStream_t)stream);

@@ -20,10 +20,6 @@ struct Args;
 #define GRF_COL_LENGTHS(X) X(4) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(180) X(256) X(360) X(500) X(512) X(1000) X(1024)
 #define GRF_ROW_LENGTHS(X) X(2) X(4) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(180) X(256) X(360) X(500) X(512) X(1024) X(2048)
 
-// Square grids (N_1 = 2 M) whose column generation pass and last-axis pass
-// can share one launch (chunk c's row pass with chunk c+1's column pass).
-#define GRF_FUSED_PAIRS(X) X(64, 32) X(96, 48) X(128, 64) X(256, 128) X(360, 180) X(512, 256) X(1000, 500) X(1024, 512)
-
 // The passes (values as the GRF_PASS_* constants of the C interface).
 enum PassKind {
   PASS_COL_GEN_INV = GRF_PASS_COL_GEN_INV,     // noise generation + inverse transform (one-FFT algorithm, axis 1)
@@ -74,21 +70,6 @@ struct Geom {
 bool col_length_supported(int L);
 bool row_length_supported(int M);
 Geom pass_geom(int pass, int dtype, int L);
-
-// Geometry of the fused column-generation + last-axis launch for (L, M):
-// threads per workgroup, column pairs per column workgroup, rows per row
-// workgroup.  threads == 0: no fused kernel for this pair.
-struct FusedGeom {
-  int threads, cp, rb;
-};
-FusedGeom fused_geom(int dtype, int L, int M);
-// nA column-generation workgroups (args aA) interleaved with nB last-axis
-// complex-to-real workgroups (args aB) in one launch.
-hipError_t launch_fused(int dtype, int L, int M, const Args& aA, const Args& aB, int nA, int nB, hipStream_t s);
-FusedGeom fused_geom_f32(int L, int M);
-FusedGeom fused_geom_f64(int L, int M);
-hipError_t launch_fused_f32(int L, int M, const Args& aA, const Args& aB, int nA, int nB, hipStream_t s);
-hipError_t launch_fused_f64(int L, int M, const Args& aA, const Args& aB, int nA, int nB, hipStream_t s);
 
 // Launch one pass over `nblocks` workgroups.  dtype: 0 = float32, 1 = float64.
 hipError_t launch_pass(int pass, int dtype, int L, const Args& a, long long nblocks, hipStream_t s);

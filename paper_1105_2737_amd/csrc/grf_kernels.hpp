@@ -1210,27 +1210,6 @@ k_row_c2r(Args a) {
 }
 
 // ---------------------------------------------------------------------------
-// One launch that interleaves the workgroups of two independent passes: nA
-// workgroups of PA (arguments aa) and nB of PB (arguments ab), spread evenly
-// over the grid, so that a memory-bound and a VALU-bound pass share the CUs.
-// The workgroups are first mapped XCD-grouped (col_block), so that each XCD
-// takes a contiguous run of column tiles and of rows.
-template <class PA, class PB>
-__global__ void __launch_bounds__(PA::THREADS > PB::THREADS ? PA::THREADS : PB::THREADS)
-k_fused(Args aa, Args ab, int nA, int nB) {
-  constexpr int LDS = PA::LDS_BYTES > PB::LDS_BYTES ? PA::LDS_BYTES : PB::LDS_BYTES;
-  __shared__ __align__(16) char smem[LDS];
-  const long long n = (long long)nA + nB;
-  const long long b = col_block(1);
-  const int ia = (int)(b * nA / n);
-  const int ia1 = (int)((b + 1) * nA / n);
-  if (ia1 > ia)
-    PA::run(aa, ia, smem);
-  else
-    PB::run(ab, (int)(b - ia), smem);
-}
-
-// ---------------------------------------------------------------------------
 // Last-axis pass: real-to-complex forward transform into packed rows.  Real
 // row x (length N_d, from Philox with the two-FFT algorithm's tag, or loaded)
 // is read as y_n = x[2n] + i x[2n+1]; Y = forward length-M transform;
