@@ -9,11 +9,13 @@ second (2^28 points per step / seconds per step).
 
 Printed alongside on the same JSON line:
   roofline      the dominant kernel of the step (the pass with the largest total
-                time): algorithmic bytes per launch / its mean launch duration,
+                time): algorithmic work per launch / its mean launch duration,
                 from HIP events recorded between the launches of the sampler
-                run in sequence on the launch stream, vs 8 TB/s; the per-pass
-                table; the opt-in fused schedule and the unchunked schedule
-  cpu_baseline  the float64 oracle on a bounded sample of the same workload
+                run in sequence on the launch stream; the HBM fraction of that
+                kernel and of the whole step next to it; the per-pass table
+  cpu_baseline  the float64 oracle on a bounded sample of the same workload, on
+                one core and on all cores of the host (one process per core),
+                timed before the GPU is initialised
   extra         two-FFT algorithm on the same workload, the 256^3 x 16
                 exponential workload, 4096 fields of uneven sizes in one
                 batch, forward+adjoint vs forward at 1024^2 x 64, d = 1
@@ -168,7 +170,7 @@ def event_ms(fn, reps, torch):
 
 PASS_NAMES = {0: "column noise+inverse FFT (axis 1)", 1: "inverse FFT (axis 2)", 2: "forward FFT (axis 2)",
               3: "column fwd FFT x h x inv FFT", 4: "column adjoint", 5: "last-axis C2R",
-              6: "last-axis noise+R2C", 7: "last-axis R2C", -1: "fused column gen | last-axis C2R",
+              6: "last-axis noise+R2C", 7: "last-axis R2C",
               9: "reflecting: column coefficients+DCT (axis 1)", 10: "reflecting: DCT (axis 2)",
               11: "reflecting: last-axis DCT", 12: "reflecting: 1D coefficients+DCT",
               13: "column noise (recursive order)+inverse FFT (axis 1)", 14: "filter on the packed spectrum",
@@ -228,6 +230,65 @@ def kind_rows(agg):
             for k, a in agg.items()]
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _oracle_fields(job):
+    """Worker of the all-core leg: oracle fields seeds[0] .. seeds[1]-1."""
+    from oracle import grf as ogrf, spectra
+    lo, hi = job
+    t0 = time.perf_counter()
+    for b in range(lo, hi):
+        ogrf.sample((512, 512), (1.0, 1.0), spectra.MATERN, 1.0, 0.1, 1.5, seed=b, batch=1, alg=2)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(seconds, batch=1024, P=512 * 512):
+    """The float64 oracle on the headline workload, timed on the host before any
+    GPU work: one core (fields in sequence, as many as fit in `seconds`), then
+    all cores of the process's CPU set (capped at 16: one worker process per
+    core, each sampling its own share of a field subset sized from the
+    single-core rate to take about `seconds` / 2)."""
+    import multiprocessing as mp
+    from oracle import grf as ogrf, spectra
+    t0 = time.perf_counter()
+    n1 = 0
+    while time.perf_counter() - t0 < seconds and n1 < batch:
+        ogrf.sample((512, 512), (1.0, 1.0), spectra.MATERN, 1.0, 0.1, 1.5, seed=n1, batch=1, alg=2)
+        n1 += 1
+    t1 = time.perf_counter() - t0
+    one = P * n1 / t1
+    try:
+        ncores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncores = os.cpu_count() or 1
+    ncores = max(1, min(16, ncores))
+    per = max(1, int(round(0.5 * seconds * n1 / t1)))     # fields per worker
+    nall = min(batch, per * ncores)
+    jobs = [(i * nall // ncores, (i + 1) * nall // ncores) for i in range(ncores)]
+    ctx = mp.get_context("fork")                          # no GPU state exists yet in this process
+    t0 = time.perf_counter()
+    with ctx.Pool(ncores) as pool:
+        pool.map(_oracle_fields, jobs, chunksize=1)
+    tall = time.perf_counter() - t0
+    return {"value": round(P * nall / tall, 1), "unit": "points/s", "cores": ncores, "kind": "oracle",
+            "sample": f"{nall} of the 1024 fields (seeds 0..{nall - 1}) split over {ncores} worker processes, "
+                      "512x512 one-FFT float64 oracle (numpy Philox + Box-Muller, Hermitian arrangement, numpy "
+                      "irfftn), wall clock including the pool start",
+            "single_core": {"value": round(one, 1), "cores": 1,
+                            "sample": f"{n1} fields (seeds 0..{n1 - 1}) in sequence"},
+            "cpu_model": cpu_model()}
+
+
 def main():
     args = parse()
     if args.profile_stage is not None or args.copy_calib or args.profile_adjoint or args.profile_uneven:
@@ -245,19 +306,29 @@ def main():
 
     import paper_1105_2737_amd as grf
 
+    cpu = None if args.no_cpu else cpu_baseline(args.cpu_seconds)
+
     torch.cuda.init()
     dev = torch.cuda.current_device()
     dims, batch = (512, 512), 1024
     P = dims[0] * dims[1]
     plan = grf.Plan(dims, alg=2, dtype=torch.float32, cov="matern", sigma=1.0, length_scale=0.1, nu=1.5)
     out = torch.empty((batch,) + dims, dtype=torch.float32, device="cuda")
-    sec = timed(lambda: plan.sample(seed=0, batch=batch, out=out), args.steps, args.warmup, torch)
-    value = P * batch / sec
+
+    # float32 vs the float64 template on fields {0, 1, B/2, B-1} of the headline workload
+    p64 = grf.Plan(dims, alg=2, dtype=torch.float64, cov="matern", sigma=1.0, length_scale=0.1, nu=1.5)
+    plan.sample(seed=0, batch=batch, out=out)
+    err_fields = (0, 1, batch // 2, batch - 1)
+    head_err = 0.0
+    for b in err_fields:
+        f64 = p64.sample(seed=b, batch=1)[0]
+        head_err = max(head_err, float((out[b].double() - f64).abs().max() / f64.abs().max()))
+    del p64, f64
 
     # per-launch times in sequence; roofline of the dominant kernel (the pass with the
     # largest total time per step), per launch: algorithmic work / mean launch duration
     fbytes = P * 4
-    table = launch_table(plan, batch, torch, grf, max(args.steps // 5, 20))
+    table = launch_table(plan, batch, torch, grf, max(args.steps // 5, 100))
     agg = by_kind(table, fbytes)
     dom = max(agg, key=lambda k: agg[k]["ms"])
     d = agg[dom]
@@ -265,10 +336,11 @@ def main():
     kbytes = d["bytes"] / d["launches"]
     kpoints = d["fields"] * P / d["launches"]
     total_bytes = 12 * P * batch                       # packed spectrum write + read, output write
-    # the chunk schedule that pairs the two passes in one launch (opt-in), for reference
-    os.environ["GRF_FUSE"] = "1"
-    fused_step = timed(lambda: plan.sample(seed=0, batch=batch, out=out), args.steps, args.warmup, torch)
-    del os.environ["GRF_FUSE"]
+
+    # the timed region: W warm-up steps, then K steps
+    sec = timed(lambda: plan.sample(seed=0, batch=batch, out=out), args.steps, args.warmup, torch)
+    value = P * batch / sec
+
     # one launch per pass over the whole batch (no cache-sized chunks), for reference
     unchunked_step = None
     if args.unchunked_ref:
@@ -276,6 +348,7 @@ def main():
         unchunked_step = timed(lambda: plan.sample(seed=0, batch=batch, out=out), args.steps, args.warmup, torch)
         del os.environ["GRF_CHUNK_BYTES"]
     traffic = MEASURED_TRAFFIC.get(kname)
+    k_hbm = kbytes / (kms * 1e-3) / 1e9
     if dom == 0:
         # VALU-bound (noise generation in registers): algorithmic lane-ops vs the VALU issue peak
         ops = gen_pass_ops_per_point(dims[0]) * kpoints
@@ -285,16 +358,18 @@ def main():
                     "algorithmic_ops_per_point": gen_pass_ops_per_point(dims[0]),
                     "algorithmic_ops_per_launch": int(ops)}
     else:
-        achieved = kbytes / (kms * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4)}
+        roofline = {"bound": "hbm", "achieved": round(k_hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(k_hbm / HBM_PEAK_GBS, 4)}
     roofline.update({
         "traffic": None if traffic is None else round(traffic / 1e9, 4), "traffic_unit": "GB/launch",
         "kernel": kname, "kernel_ms_per_launch": round(kms, 4), "launches_per_step": len(table),
-        "algorithmic_bytes_per_launch": int(kbytes), "hbm_view_GBps": round(kbytes / (kms * 1e-3) / 1e9, 1),
-        "whole_step_model_GBps": round(total_bytes / sec / 1e9, 1),
-        "whole_step_model_frac": round(total_bytes / sec / 1e9 / HBM_PEAK_GBS, 4),
-        "passes": kind_rows(agg), "fused_schedule_step_ms": round(fused_step * 1e3, 4),
+        "algorithmic_bytes_per_launch": int(kbytes),
+        # the HBM view: the dominant kernel's algorithmic bytes per launch / its launch
+        # duration, and the whole step's 12 B/point model / the timed step, vs 8 TB/s
+        "hbm_GBps": round(k_hbm, 1), "hbm_frac": round(k_hbm / HBM_PEAK_GBS, 4),
+        "whole_step_hbm_GBps": round(total_bytes / sec / 1e9, 1),
+        "whole_step_hbm_frac": round(total_bytes / sec / 1e9 / HBM_PEAK_GBS, 4),
+        "passes": kind_rows(agg), "pass_sum_ms": round(sum(a["ms"] for a in agg.values()), 4),
         "unchunked_step_ms": None if unchunked_step is None else round(unchunked_step * 1e3, 4)})
 
     result = {
@@ -306,6 +381,7 @@ def main():
                                "1024 fields (seeds 0..1023)", "global_batch": batch, "grid": list(dims),
                    "algorithm": "one-FFT (Hermitian)", "parallelism": "single GPU"},
         "fields_per_s": round(batch / sec, 1),
+        "max_rel_err_vs_fp64": head_err, "error_fields": list(err_fields),
         "roofline": roofline,
     }
     del out
@@ -339,7 +415,7 @@ def main():
         d3, b3 = (256, 256, 256), 16
         p3 = grf.Plan(d3, alg=2, dtype=torch.float32, cov="exponential", sigma=1.0, length_scale=0.05)
         o3 = torch.empty((b3,) + d3, dtype=torch.float32, device="cuda")
-        s3 = timed(lambda: p3.sample(seed=0, batch=b3, out=o3), max(args.steps // 2, 5), 2, torch)
+        s3 = timed(lambda: p3.sample(seed=0, batch=b3, out=o3), max(args.steps, 20), max(args.warmup, 10), torch)
         ab3 = 20 * 2 ** 24 * b3
         extra["one_fft_256cubed_x16"] = {
             "points_per_s": round(2 ** 24 * b3 / s3, 1), "ms_per_step": round(s3 * 1e3, 4),
@@ -412,6 +488,7 @@ def main():
             p5.backward(g, seed=0)
         sfb = timed(fwd_bwd, args.steps, args.warmup, torch)
         sb = timed(lambda: p5.backward(g, seed=0), args.steps, args.warmup, torch)
+        sbz = timed(lambda: p5.backward(g, seed=0, need_noise_grad=True), args.steps, args.warmup, torch)
         # float32 forward and adjoint vs the float64 template on fields {0, 1, B/2, B-1}
         p5_64 = grf.Plan(d5, alg=2, dtype=torch.float64, cov="matern", sigma=1.0, length_scale=0.1, nu=1.5)
         p5.sample(seed=0, batch=b5, out=o5)
@@ -423,7 +500,10 @@ def main():
             gt64, _ = p5_64.backward(2 * w[b:b + 1].double() * f64, seed=b)
             eg.append(float((gt32[b] - gt64[0]).abs().max() / gt64[0].abs().max()))
         extra["adjoint_1024_x64"] = {"fwd_ms": round(sf * 1e3, 4), "fwd_plus_adjoint_ms": round(sfb * 1e3, 4),
-                                     "adjoint_ms": round(sb * 1e3, 4), "ratio_fwd_bwd_vs_fwd": round(sfb / sf, 3),
+                                     "adjoint_ms": round(sb * 1e3, 4),
+                                     "adjoint_with_noise_grad_ms": round(sbz * 1e3, 4),
+                                     "ratio_adjoint_vs_fwd": round(sb / sf, 3),
+                                     "ratio_fwd_bwd_vs_fwd": round(sfb / sf, 3),
                                      "fwd_points_per_s": round(2 ** 20 * b5 / sf, 1),
                                      "max_rel_err_vs_fp64_fwd": max(ef), "max_rel_err_vs_fp64_grad_theta": max(eg),
                                      "loss": "L = sum w phi^2, w ~ U[0,1] from numpy.random.default_rng(1)"}
@@ -550,20 +630,8 @@ def main():
             "points_per_s_at_N4096": rows[-1]["points_per_s"]}
     result["extra"] = extra
 
-    if not args.no_cpu:
-        from oracle import grf as ogrf, spectra
-        nthreads = 1
-        t0 = time.perf_counter()
-        n = 0
-        while time.perf_counter() - t0 < args.cpu_seconds and n < batch:
-            ogrf.sample(dims, (1.0, 1.0), spectra.MATERN, 1.0, 0.1, 1.5, seed=n, batch=1, alg=2)
-            n += 1
-        el = time.perf_counter() - t0
-        result["cpu_baseline"] = {"value": round(P * n / el, 1), "unit": "points/s", "cores": nthreads,
-                                  "kind": "oracle",
-                                  "sample": f"{n} of the 1024 fields (seeds 0..{n - 1}), 512x512 one-FFT float64 "
-                                            "oracle (numpy Philox + Box-Muller, Hermitian arrangement, "
-                                            "numpy irfftn), single thread"}
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
     result["device"] = torch.cuda.get_device_name(dev)
     print(json.dumps(result), flush=True)
 

@@ -23,6 +23,22 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _check(name, t, shape, dtype, device):
+    """A tensor handed to the library as a raw pointer must be exactly what the
+    kernels will read or write: shape, dtype, device and a dense layout."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
 class Plan:
     """A sampling plan: grid, domain, algorithm, precision and covariance family.
 
@@ -99,6 +115,24 @@ class Plan:
     def _empty(self, batch):
         return torch.empty((batch,) + self.dims, dtype=self.dtype, device=self.device)
 
+    def _out(self, out, batch):
+        """The output buffer: [n, *dims] with n >= batch (fields 0 .. batch-1 are
+        written), the plan's dtype and device, dense."""
+        if out is None:
+            return self._empty(batch)
+        if isinstance(out, torch.Tensor) and out.dim() == len(self.dims) + 1 and out.shape[0] >= batch:
+            return _check("out", out, (out.shape[0],) + self.dims, self.dtype, self.device)
+        return _check("out", out, (batch,) + self.dims, self.dtype, self.device)
+
+    def _fields(self, name, t):
+        """A [batch, *dims] input (noise, upstream gradient) in the plan's dtype
+        on the plan's device, dense; returns it and the batch size."""
+        t = torch.as_tensor(t).to(device=self.device, dtype=self.dtype).contiguous()
+        if t.dim() != len(self.dims) + 1 or tuple(t.shape[1:]) != self.dims:
+            raise ValueError(f"{name} must have shape [batch, {', '.join(map(str, self.dims))}], "
+                             f"got {tuple(t.shape)}")
+        return t, int(t.shape[0])
+
     def _workspace(self, batch, op):
         n = L.grf_workspace_size(self.handle, batch, op)
         ws = torch.empty(max(n, 1), dtype=torch.uint8, device=self.device)
@@ -117,17 +151,21 @@ class Plan:
     # -- sampling ------------------------------------------------------------
     def sample(self, seed=0, batch=1, theta=None, out=None):
         """Fields seed .. seed+batch-1, shape [batch, *dims]."""
+        batch = int(batch)
+        if batch < 0:
+            raise ValueError("batch must be >= 0")
         th = self._theta(theta, batch)
-        out = self._empty(batch) if out is None else out
+        out = self._out(out, batch)
         ws, n = self._workspace(batch, L.GRF_OP_SAMPLE)
         L.grf_sample(self.handle, int(seed) & (2 ** 64 - 1), batch, _ptr(th), _ptr(out), _ptr(ws), n, _stream())
         return out
 
     def sample_from_noise(self, noise, theta=None, out=None):
-        noise = noise.to(device=self.device, dtype=self.dtype).contiguous()
-        batch = noise.shape[0]
+        noise, batch = self._fields("noise", noise)
         th = self._theta(theta, batch)
-        out = self._empty(batch) if out is None else out
+        out = self._out(out, batch)
+        if out.data_ptr() == noise.data_ptr() and batch > 0:
+            raise ValueError("noise and out must not alias")
         ws, n = self._workspace(batch, L.GRF_OP_SAMPLE)
         L.grf_sample_from_noise(self.handle, _ptr(noise), batch, _ptr(th), _ptr(out), _ptr(ws), n, _stream())
         return out
@@ -155,11 +193,12 @@ class Plan:
 
     def backward(self, grad_out, seed=0, theta=None, noise=None, need_noise_grad=False):
         """(dL/dtheta [batch, 3] float64, dL/dz or None) for either algorithm."""
-        grad_out = grad_out.to(device=self.device, dtype=self.dtype).contiguous()
-        batch = grad_out.shape[0]
+        grad_out, batch = self._fields("grad_out", grad_out)
         th = self._theta(theta, batch)
         if noise is not None:
-            noise = noise.to(device=self.device, dtype=self.dtype).contiguous()
+            noise, nb = self._fields("noise", noise)
+            if nb != batch:
+                raise ValueError(f"noise has {nb} fields, grad_out {batch}")
         gt = torch.empty((batch, 3), dtype=torch.float64, device=self.device)
         gz = self._empty(batch) if need_noise_grad else None
         ws, n = self._workspace(batch, L.GRF_OP_BACKWARD)
@@ -169,26 +208,48 @@ class Plan:
 
 
 class GRFSample(torch.autograd.Function):
-    """phi = sampler(theta, z): differentiable in theta = [batch, 3]
-    (sigma, length_scale, nu; float64) and, when given, in the noise z.
+    """phi = sampler(theta, z): differentiable in theta (sigma, length_scale,
+    nu; [batch, 3] per field, or [3] shared by every field) and, when given,
+    in the noise z ([batch, *dims]).
+
+    apply(theta, plan, seed=0, noise=None, batch=None): the number of fields
+    is noise.shape[0] when noise is given, else theta.shape[0] for a [batch, 3]
+    theta; a shared [3] theta without noise needs `batch`.  Gradients come
+    back on theta's (and the noise's) own device and dtype.
 
     The forward keeps only theta, the seed and the noise (if given); the
     backward recomputes the Fourier transform of the upstream gradient and
     regenerates the noise in the library (no spectrum is stored)."""
 
     @staticmethod
-    def forward(ctx, theta, plan, seed=0, noise=None):
-        batch = theta.shape[0] if noise is None else noise.shape[0]
+    def forward(ctx, theta, plan, seed=0, noise=None, batch=None):
+        if theta.dim() not in (1, 2) or theta.shape[-1] != 3:
+            raise ValueError(f"theta must be [batch, 3] or [3], got {tuple(theta.shape)}")
+        if noise is not None:
+            nb = int(noise.shape[0])
+        elif theta.dim() == 2:
+            nb = int(theta.shape[0])
+        elif batch is None:
+            raise ValueError("a shared theta of shape [3] without noise needs batch=")
+        else:
+            nb = int(batch)
+        if batch is not None and int(batch) != nb:
+            raise ValueError(f"batch={batch} does not match the {nb} fields of theta / noise")
+        if theta.dim() == 2 and theta.shape[0] != nb:
+            raise ValueError(f"theta has {theta.shape[0]} rows for {nb} fields")
         theta_c = theta.detach().to(device=plan.device, dtype=torch.float64)
         if theta_c.dim() == 1:
-            theta_c = theta_c.expand(batch, 3)
+            theta_c = theta_c.expand(nb, 3)
         theta_c = theta_c.contiguous()
         if noise is None:
-            out = plan.sample(seed=seed, batch=batch, theta=theta_c)
+            out = plan.sample(seed=seed, batch=nb, theta=theta_c)
         else:
             out = plan.sample_from_noise(noise.detach(), theta=theta_c)
         ctx.plan, ctx.seed = plan, seed
         ctx.theta_dim = theta.dim()
+        ctx.theta_device, ctx.theta_dtype = theta.device, theta.dtype
+        ctx.noise_device = noise.device if noise is not None else None
+        ctx.noise_dtype = noise.dtype if noise is not None else None
         ctx.save_for_backward(theta_c, noise.detach() if noise is not None else None)
         ctx.has_noise = noise is not None
         return out
@@ -200,7 +261,10 @@ class GRFSample(torch.autograd.Function):
         gt, gz = ctx.plan.backward(g, seed=ctx.seed, theta=theta_c, noise=noise, need_noise_grad=need_z)
         if ctx.theta_dim == 1:
             gt = gt.sum(0)
-        return gt, None, None, gz
+        gt = gt.to(device=ctx.theta_device, dtype=ctx.theta_dtype)
+        if gz is not None:
+            gz = gz.to(device=ctx.noise_device, dtype=ctx.noise_dtype)
+        return gt, None, None, gz, None
 
 
 class Batch:
@@ -245,13 +309,18 @@ class Batch:
 
     def sample(self, out=None, plain=False):
         """Flat float32 output; field f is out[offsets[f]:offsets[f+1]] viewed as dims[f]."""
-        out = self.empty() if out is None else out
+        out = self._out(out)
         f = L.grf_batch_sample_plain if plain else L.grf_batch_sample
         f(self.handle, _ptr(out), _stream())
         return out
 
+    def _out(self, out):
+        if out is None:
+            return self.empty()
+        return _check("out", out, (self.offsets[-1],), torch.float32, self.device)
+
     def tune(self, out=None):
-        out = self.empty() if out is None else out
+        out = self._out(out)
         L.grf_batch_tune(self.handle, _ptr(out), _stream())
 
     def field(self, out, f):

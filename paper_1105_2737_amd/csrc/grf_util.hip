@@ -101,6 +101,7 @@ hipError_t launch_noise(int dtype, unsigned long long seed, int tag, int rows, i
                         hipStream_t s) {
   const long long total = (long long)batch * rows * ((nd + 3) / 4);
   if (total <= 0) return hipSuccess;
+  if ((total + 255) / 256 > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((total + 255) / 256)), block(256);
   if (dtype == 0)
     hipLaunchKernelGGL(k_noise<float>, grid, block, 0, s, seed, tag, rows, nd, batch, (float*)out);
