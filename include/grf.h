@@ -176,6 +176,22 @@ grf_status grf_workspace_size(grf_plan plan, int64_t batch, int32_t op, size_t* 
 grf_status grf_sample(grf_plan plan, uint64_t seed, int64_t batch, const double* theta, void* out,
                       void* workspace, size_t workspace_bytes, void* stream);
 
+/* For callers that cannot allocate device memory during a call (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * grf_sample without a workspace argument.  Per-field parameters (theta,
+ * as in grf_sample) are turned into per-field constants in a library-owned
+ * device array of GRF_NOALLOC_MAX_FIELDS records (6.5 MiB per device, held
+ * from the first call on a device until the process ends); the call itself
+ * allocates nothing.  theta != NULL with batch > GRF_NOALLOC_MAX_FIELDS is
+ * rejected with GRF_EINVAL before any launch; theta == NULL uses no scratch
+ * and has no limit.  Every call on a device shares that device's array and
+ * rewrites the records it uses before reading them: calls that overlap on one
+ * device (concurrent streams or host threads) race; serialise them.  Output
+ * is bitwise that of grf_sample with the same arguments. */
+#define GRF_NOALLOC_MAX_FIELDS 65536
+grf_status grf_sample_noalloc(grf_plan plan, uint64_t seed, int64_t batch, const double* theta, void* out,
+                              void* stream);
+
 /* As grf_sample, but the normals z are read from `noise` (device, same
  * shape and dtype as the output) instead of being generated. */
 grf_status grf_sample_from_noise(grf_plan plan, const void* noise, int64_t batch, const double* theta,

@@ -14,7 +14,7 @@ package marshals torch tensors (device memory and streams) into its C ABI.
 """
 from .api import Plan, Batch, GRFSample, COV_KINDS  # noqa: F401
 from ._lib import (GRFError, grf_plan_create, grf_plan_destroy, grf_workspace_size,  # noqa: F401
-                   grf_sample, grf_sample_stage_count, grf_sample_stage, grf_sample_stage_info,
+                   grf_sample, grf_sample_noalloc, grf_sample_stage_count, grf_sample_stage, grf_sample_stage_info,
                    grf_sample_from_noise, grf_noise, grf_backward, grf_debug_philox, grf_debug_spectrum,
                    grf_covariance,
                    grf_last_error, grf_version, GRF_PASS_COL_GEN_INV,

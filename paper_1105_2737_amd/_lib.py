@@ -20,11 +20,12 @@ GRF_PASS_COL_SEQ_INV = 13
 GRF_PASS_SPEC_FILTER = 14
 GRF_BC_PERIODIC, GRF_BC_NEUMANN, GRF_BC_DIRICHLET = 0, 1, 2
 GRF_DRAW_COUNTER, GRF_DRAW_RECURSIVE = 0, 1
+GRF_NOALLOC_MAX_FIELDS = 65536
 
 STATUS_NAMES = {0: "GRF_OK", -1: "GRF_EINVAL", -2: "GRF_ENOMEM", -3: "GRF_EDEVICE", -4: "GRF_EUNSUPPORTED"}
 
 # every symbol include/grf.h declares
-EXPORTS = ["grf_plan_create", "grf_plan_destroy", "grf_workspace_size", "grf_sample",
+EXPORTS = ["grf_plan_create", "grf_plan_destroy", "grf_workspace_size", "grf_sample", "grf_sample_noalloc",
            "grf_sample_stage_count", "grf_sample_stage", "grf_sample_stage_info", "grf_sample_from_noise", "grf_noise", "grf_backward", "grf_debug_philox",
            "grf_debug_spectrum",
            "grf_covariance", "grf_batch_create", "grf_batch_offsets", "grf_batch_sample", "grf_batch_sample_plain",
@@ -63,6 +64,7 @@ def _load():
         "grf_plan_destroy": (ctypes.c_int, [vp]),
         "grf_workspace_size": (ctypes.c_int, [vp, c64, i32, ctypes.POINTER(sz)]),
         "grf_sample": (ctypes.c_int, [vp, u64, c64, vp, vp, vp, sz, vp]),
+        "grf_sample_noalloc": (ctypes.c_int, [vp, u64, c64, vp, vp, vp]),
         "grf_sample_stage_count": (ctypes.c_int, [vp, c64, ctypes.POINTER(i32)]),
         "grf_sample_stage": (ctypes.c_int, [vp, i32, u64, c64, vp, vp, vp, sz, vp]),
         "grf_sample_stage_info": (ctypes.c_int, [vp, c64, i32, ctypes.POINTER(i32), ctypes.POINTER(c64),
@@ -118,6 +120,10 @@ def grf_workspace_size(plan, batch, op):
 
 def grf_sample(plan, seed, batch, theta, out, workspace, workspace_bytes, stream):
     return check(lib.grf_sample(plan, seed, batch, theta, out, workspace, workspace_bytes, stream))
+
+
+def grf_sample_noalloc(plan, seed, batch, theta, out, stream):
+    return check(lib.grf_sample_noalloc(plan, seed, batch, theta, out, stream))
 
 
 def grf_sample_stage_count(plan, batch):
