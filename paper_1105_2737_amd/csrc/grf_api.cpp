@@ -253,6 +253,28 @@ int xcd_order() {
   return (e && e[0] == '0') ? 0 : 1;
 }
 
+bool is_adjoint_col_pass(int pass) {
+  return pass == grf::PASS_COL_GRAD || pass == grf::PASS_COL_GRAD3 || pass == grf::PASS_COL_GRAD1 ||
+         pass == grf::PASS_COL_GRAD_SEQ || pass == grf::PASS_COL_GRAD3_SEQ;
+}
+
+// Fields per workgroup of the adjoint's column pass (each workgroup runs one
+// column tile of that many consecutive fields, so that it reads its rows of
+// the filter table once from HBM per run).  Measured on MI355X (adjoint of
+// 1024^2 x 64 / 512^2 x 256 / 256^3 x 16, fields per workgroup 1, 2, 4, 8):
+// 0.273 / 0.246 / 0.255 / 0.273 ms, 0.242 / 0.246 / 0.265 / 0.313 ms and
+// 1.69 / 1.73 / 1.82 / 1.83 ms: two pay off only where the table (2.1 MB at
+// 1024^2) no longer stays in an XCD's 4 MB L2 while the fields stream
+// through it; a 3D plan has no table.  GRF_ADJ_FPW overrides.
+int adjoint_fields_per_wg(const Args& a, size_t esz) {
+  if (const char* e = std::getenv("GRF_ADJ_FPW")) {
+    const int v = std::atoi(e);
+    if (v >= 1) return v;
+  }
+  const long long table = (long long)a.n1 * a.no * (a.M + 2) * (long long)esz;
+  return (a.htab != nullptr && table > (1ll << 20)) ? 2 : 1;
+}
+
 grf_status run_pass(const grf_plan_s* p, int pass, int L, Args a, long long nfixed_blocks_per_field,
                     long long batch, hipStream_t s) {
   (void)nfixed_blocks_per_field;
@@ -267,7 +289,10 @@ grf_status run_pass(const grf_plan_s* p, int pass, int L, Args a, long long nfix
     nblocks = (a.rows + g.per_wg - 1) / g.per_wg;
   } else {
     a.ntile = (a.M + 2 * g.per_wg - 1) / (2 * g.per_wg);
-    nblocks = (long long)a.ntile * a.nfixed * batch;
+    a.fpw = is_adjoint_col_pass(pass) && pass != grf::PASS_COL_GRAD_SEQ && pass != grf::PASS_COL_GRAD3_SEQ
+                ? adjoint_fields_per_wg(a, p->esz)
+                : 1;
+    nblocks = (long long)a.ntile * a.nfixed * ((batch + a.fpw - 1) / a.fpw);
     a.order = xcd_order();
   }
   if (nblocks <= 0) return GRF_OK;

@@ -65,6 +65,7 @@ struct Args {
   int rows_per_field;
   int tag;
   int order;                  // column passes: 1 = XCD-grouped workgroup-to-tile order (col_block)
+  int fpw;                    // adjoint column pass: consecutive fields per workgroup (>= 1)
   // reflecting boundaries (cosine / sine transforms)
   const void* tq;             // (1/2) e^{i pi k / (2N)}, k < N (column) or k <= N/2 (row), of the pass's axis
   int sine;                   // the pass's axis is a sine axis (output sign (-1)^j)
@@ -748,6 +749,11 @@ struct AdjAcc {
 // SEQ: the noise in the recursive algorithm's draw order (seq_entry); dL/dz
 // of an entry goes to the positions of its own draws (a mirrored entry owns
 // none).
+// A workgroup takes one column tile of a.fpw consecutive fields in turn, with
+// the next field's tile loaded while the current one is transformed and
+// reduced; the filter-table rows of the tile are then read once from HBM and
+// a.fpw - 1 times from the cache, and the sums of each field are formed in the
+// same order as with one field per workgroup (the same bits).
 template <typename T, int L, class Rad, int CP, int PAD, bool D3 = false, bool XI = false, bool SEQ = false>
 __global__ void __launch_bounds__(((L / Rad::get(0)) * CP + 63) / 64 * 64)
 k_colg(Args a) {
@@ -761,31 +767,66 @@ k_colg(Args a) {
   __shared__ E sm[L * RS];
   __shared__ V tw[L];
   __shared__ double red[3][NW];
-  const int tid = threadIdx.x;
-  const int cp = tid % CP;
-  const int t = tid / CP;
   int bid = col_block(a.order);
   const int tile = bid % a.ntile;
   const int fx = D3 ? (bid / a.ntile) % a.nfixed : 0;
-  const int b = D3 ? bid / a.ntile / a.nfixed : bid / a.ntile;
-  for (int i = tid; i < L; i += blockDim.x) tw[i] = ((const V*)a.tw)[i];
-  const int m0 = (tile * CP + cp) * 2;
-  const bool act = (t < NT) && (m0 < a.M);
-  const bool two = (m0 + 1) < a.M;
+  // this workgroup's run of fields: b0 .. b0 + nf - 1, the same column tile of each
+  const int b0 = (D3 ? bid / a.ntile / a.nfixed : bid / a.ntile) * a.fpw;
+  // (the recursive draw order keeps one field per workgroup: its reduction has
+  // no registers to spare for the loop)
+  const int nf = SEQ ? 1 : min(a.fpw, a.batch - b0);
+  for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = ((const V*)a.tw)[i];
   const bool al = (a.M & 1) == 0;
-  V* base = (V*)a.data + (long long)b * a.field_stride + (D3 ? (long long)fx * a.stride_fixed : 0LL) + m0;
+  const long long off0 = D3 ? (long long)fx * a.stride_fixed : 0LL;
   // noise / table row of axis-1 index k, and the middle axis's share of p^2
   auto rowof = [&](int k) -> int { return D3 ? k * a.no + fx : k; };
   const double p2o = D3 ? (double)(wrapk(fx, a.no) * wrapk(fx, a.no)) * a.il2[1] : 0.0;
-  V x[2][EN::REG];
+  // The tile of the next field is loaded while the current one is transformed
+  // and reduced, so that loads stay in flight across the whole run.
+  constexpr bool PF = !SEQ;
+  V xpf[2][R0];
+  auto load_tile = [&](int bb, int tt, int mm0, bool aa, bool tw2, V (&dst)[2][R0]) {
+    if (!aa) return;
+    const V* src = (const V*)a.data + (long long)bb * a.field_stride + off0 + mm0;
+#pragma unroll
+    for (int m = 0; m < R0; ++m)
+      ld_pair<T>(src + (long long)(tt + m * NT) * a.stride_ax, tw2, al, dst[0][m], dst[1][m]);
+  };
+  if constexpr (PF) {
+    const int t = threadIdx.x / CP, m0 = (tile * CP + threadIdx.x % CP) * 2;
+    load_tile(b0, t, m0, (t < NT) && (m0 < a.M), (m0 + 1) < a.M, xpf);
+  }
+  for (int j = 0; j < nf; ++j) {
+  const int b = b0 + j;
+  // Everything derived from the thread index is recomputed per field from an
+  // opaque copy of it: hoisted out of the loop, the per-row constants of all
+  // R0 rows and all FFT stages would stay live across it and spill.
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int cp = tid % CP;
+  const int t = tid / CP;
+  const int m0 = (tile * CP + cp) * 2;
+  const bool act = (t < NT) && (m0 < a.M);
+  const bool two = (m0 + 1) < a.M;
   // Straight-line route for the common case (generated noise, filter table,
   // a column pair away from the packed plane slot): the filter-table loads of
   // all rows are issued together and the R0 Philox blocks are independent.
   const bool straight = !XI && !SEQ && a.src == nullptr && a.htab != nullptr && m0 > 0;
-  if (act) {
+  V x[2][EN::REG];
+  if constexpr (PF) {
 #pragma unroll
-    for (int m = 0; m < R0; ++m)
-      ld_pair<T>(base + (long long)(t + m * NT) * a.stride_ax, two, al, x[0][m], x[1][m]);
+    for (int m = 0; m < R0; ++m) {
+      x[0][m] = xpf[0][m];
+      x[1][m] = xpf[1][m];
+    }
+    if (j + 1 < nf) load_tile(b + 1, t, m0, act, two, xpf);
+  } else {
+    load_tile(b, t, m0, act, two, xpf);
+#pragma unroll
+    for (int m = 0; m < R0; ++m) {
+      x[0][m] = xpf[0][m];
+      x[1][m] = xpf[1][m];
+    }
   }
   auto lds = [&](int i) -> E& { return sm[i * RS + cp]; };
   auto to_lds = [&](int i, const E& e) { sm[i * RS + cp] = e; };
@@ -1031,6 +1072,8 @@ k_colg(Args a) {
     double sacc = 0;
     for (int w = 0; w < NW; ++w) sacc += red[tid][w];
     a.partial[((long long)(D3 ? b * a.nfixed + fx : b) * a.ntile + tile) * 3 + tid] = sacc;
+  }
+  __syncthreads();   // the next field's transform reuses sm and red
   }
 }
 

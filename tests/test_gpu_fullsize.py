@@ -50,18 +50,91 @@ def test_256_cubed_x16(grf):
         assert e <= 1e-5
 
 
-def test_1024_squared_x64_forward_and_adjoint(grf):
-    """The training configuration: L = sum w phi^2, w ~ U[0, 1]."""
+@pytest.fixture(scope="module")
+def training_step(grf):
+    """The training configuration at full size: 1024^2 x 64, Matern
+    (1, 0.1, 1.5), seeds 0..63, L = sum w phi^2 with w ~ U[0, 1] from
+    numpy.random.default_rng(1); forward, then the adjoint with dL/dz."""
+    from synth import loss_weights
     plan = grf.Plan((1024, 1024), alg=2, dtype=torch.float32, cov="matern", sigma=1.0, length_scale=0.1, nu=1.5)
     phi = plan.sample(seed=0, batch=64)
-    w = torch.rand((64, 1024, 1024), device="cuda", generator=torch.Generator(device="cuda").manual_seed(1))
+    w = torch.from_numpy(loss_weights((64, 1024, 1024), seed=1).astype(np.float32)).cuda()
     g = 2 * w * phi
-    gt, _ = plan.backward(g, seed=0)
-    for b in (0, 63):
-        ref = ogrf.sample((1024, 1024), (1.0, 1.0), spectra.MATERN, 1.0, 0.1, 1.5, seed=b, batch=1, alg=2)[0]
-        assert relerr(phi[b].double().cpu().numpy(), ref) <= 1e-5
-        z = onoise.field_noise((1024, 1024), b, onoise.TAG_ALG2)
-        rg = oadj.grad_theta_alg2(z, g[b].double().cpu().numpy(), (1.0, 1.0), spectra.MATERN, 1.0, 0.1, 1.5)
-        e = np.abs(gt[b].cpu().numpy() - rg).max() / np.abs(rg).max()
-        print(f"1024^2 field {b}: grad rel err {e:.3e}", flush=True)
-        assert e <= 2e-5
+    gt, gz = plan.backward(g, seed=0, need_noise_grad=True)
+    gt_only, _ = plan.backward(g, seed=0)
+    torch.cuda.synchronize()
+    return dict(phi=phi, g=g, gt=gt, gz=gz, gt_only=gt_only)
+
+
+@pytest.mark.parametrize("b", [0, 63])
+def test_1024_squared_x64_forward_and_theta_gradient(grf, training_step, b):
+    """Field b of the forward pass against the oracle, and each component of
+    dL/d(sigma, ell, nu) against the oracle's analytic gradient on its own
+    scale (so that an error in the smaller components cannot hide behind
+    the largest one)."""
+    phi, g, gt = training_step["phi"], training_step["g"], training_step["gt"]
+    ref = ogrf.sample((1024, 1024), (1.0, 1.0), spectra.MATERN, 1.0, 0.1, 1.5, seed=b, batch=1, alg=2)[0]
+    assert relerr(phi[b].double().cpu().numpy(), ref) <= 1e-5
+    z = onoise.field_noise((1024, 1024), b, onoise.TAG_ALG2)
+    gb = g[b].double().cpu().numpy()
+    rg = oadj.grad_theta_alg2(z, gb, (1.0, 1.0), spectra.MATERN, 1.0, 0.1, 1.5)
+    # each component is a sum over the half-spectrum of w (h/2) dlogS/dtheta Re(xi conj G);
+    # its own scale is the sum of the absolute terms, the quantity that bounds the
+    # rounding error of a float32 evaluation (dL/dnu cancels to ~1e-3 of it)
+    dims, lengths = (1024, 1024), (1.0, 1.0)
+    core = oadj.half_weights(dims) * np.abs(np.real(ogrf.hermitian_noise(z) * np.conj(np.fft.rfftn(gb))))
+    h = spectra.filter_h(dims, lengths, spectra.MATERN, 1.0, 0.1, 1.5, half=True)
+    dlog = spectra.dlog_spectral_density(spectra.MATERN, spectra.freq2_grid(dims, lengths, half=True), 2, 1.0, 0.1, 1.5)
+    got = gt[b].cpu().numpy()
+    for i, name in enumerate(("sigma", "ell", "nu")):
+        scale = float(np.sum(0.5 * h * np.abs(dlog[i]) * core))
+        e, es = abs(got[i] - rg[i]) / abs(rg[i]), abs(got[i] - rg[i]) / scale
+        print(f"1024^2 field {b}: dL/d{name} {got[i]:.6e} vs {rg[i]:.6e}, rel err {e:.3e}, "
+              f"err / sum|terms| {es:.3e} (sum|terms| / |value| {scale / abs(rg[i]):.1f})", flush=True)
+        assert es <= 2e-6
+        assert e <= 1e-4
+    # the theta gradient does not depend on whether dL/dz is also formed
+    assert torch.equal(training_step["gt_only"][b], gt[b])
+
+
+@pytest.mark.parametrize("b", [0, 63])
+def test_1024_squared_x64_noise_gradient(grf, training_step, b):
+    """dL/dz at full size (every slot, including the two self-mirrored
+    planes) against the oracle's transpose of the Hermitian arrangement."""
+    g, gz = training_step["g"], training_step["gz"]
+    ref = oadj.grad_noise_alg2(g[b].double().cpu().numpy(), (1.0, 1.0), spectra.MATERN, 1.0, 0.1, 1.5)
+    got = gz[b].double().cpu().numpy()
+    e = relerr(got, ref)
+    print(f"1024^2 field {b}: dL/dz rel err {e:.3e}", flush=True)
+    assert e <= 1e-5
+    # the plane slots (k_d = 0 and N_d/2 live in slots 0 and 1 of every row)
+    assert relerr(got[:, :2], ref[:, :2]) <= 1e-5
+
+
+def test_1024_squared_fp64_gradient_against_central_differences(grf):
+    """The library's float64 gradient in (sigma, ell, nu) at 1024^2 (one field,
+    the loss of the training configuration) against float64 central finite
+    differences of the library's own float64 sampler, step 1e-6 relative to
+    each parameter."""
+    from synth import loss_weights
+    dims = (1024, 1024)
+    plan = grf.Plan(dims, alg=2, dtype=torch.float64, cov="matern", sigma=1.0, length_scale=0.1, nu=1.5)
+    w = torch.from_numpy(loss_weights((1,) + dims, seed=1)).cuda()
+    theta0 = torch.tensor([[1.0, 0.1, 1.5]], dtype=torch.float64, device="cuda")
+
+    def loss(th):
+        phi = plan.sample(seed=0, batch=1, theta=th)
+        return float((w * phi * phi).sum())
+
+    phi = plan.sample(seed=0, batch=1, theta=theta0)
+    gt, _ = plan.backward(2 * w * phi, seed=0, theta=theta0)
+    gt = gt[0].cpu().numpy()
+    for i, name in enumerate(("sigma", "ell", "nu")):
+        h = 1e-6 * float(theta0[0, i])
+        tp, tm = theta0.clone(), theta0.clone()
+        tp[0, i] += h
+        tm[0, i] -= h
+        fd = (loss(tp) - loss(tm)) / (2 * h)
+        e = abs(gt[i] - fd) / abs(fd)
+        print(f"fp64 dL/d{name}: adjoint {gt[i]:.12e}, central difference {fd:.12e}, rel {e:.2e}", flush=True)
+        assert e <= 1e-6
