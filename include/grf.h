@@ -73,11 +73,17 @@ enum { GRF_DRAW_COUNTER = 0, GRF_DRAW_RECURSIVE = 1 };
 /*
  * Plan description.
  *   ndim      1, 2 or 3 (the grid's dimension d).
- *   dims      N_1..N_d: each even (Section 2 requires even N_i).  Leading
- *             lengths N_1 (and N_2 for d = 3) from {4, 8, 12, 16, 24, 32, 48,
- *             64, 96, 128, 180, 256, 360, 500, 512, 1000, 1024}; the last
- *             length N_d with N_d/2 from {2, 4, ..., 512, 1024, 2048} (the
- *             same list with 2, 1024 and 2048).
+ *   dims      N_1..N_d: each even and a product of 2, 3 and 5 (Section 2
+ *             requires even N_i; the FFT factorisation needs the rest), leading
+ *             lengths N_1 (and N_2 for d = 3) up to 4096, the last length N_d
+ *             up to 16384 (GRF_EUNSUPPORTED above).  The listed lengths run on
+ *             compile-time kernels tuned per length: leading lengths {4, 8, 12,
+ *             16, 24, 32, 48, 64, 96, 128, 180, 256, 360, 500, 512, 1000, 1024},
+ *             N_d/2 from {2, 4, ..., 512, 1024, 2048} (the same list with 2,
+ *             1024 and 2048); every other length runs on runtime-radix kernels
+ *             (sampling with either algorithm, d = 1, 2, 3).  Reflecting
+ *             boundaries, the recursive draw order and grf_backward take the
+ *             listed lengths only (GRF_EUNSUPPORTED otherwise).
  *   lengths   l_1..l_d > 0 (edge lengths of D; the unit torus is all 1).
  *   alg       GRF_ALG_ONE_FFT or GRF_ALG_TWO_FFT (periodic boundaries, counter draw order).
  *   dtype     GRF_F32 (complex64 arithmetic, twiddles from float64) or GRF_F64.
@@ -152,8 +158,9 @@ typedef struct {
 /* Create a plan: validates the description, builds float64 twiddle tables
  * (rounded once to the working precision) and the default per-field
  * constants.  *out receives a library-owned handle.  Errors: GRF_EINVAL (bad
- * description, null pointer), GRF_EUNSUPPORTED (length not in the lists,
- * two-FFT with reflecting boundaries or the recursive draw order),
+ * description, null pointer), GRF_EUNSUPPORTED (a length above its limit,
+ * reflecting boundaries or the recursive draw order with a length not in the
+ * lists, two-FFT with reflecting boundaries or the recursive draw order),
  * GRF_ENOMEM, GRF_EDEVICE. */
 grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out);
 
@@ -277,7 +284,8 @@ grf_status grf_noise(grf_plan plan, uint64_t seed, int64_t batch, void* noise_ou
  * draws); ndim = 1, 2 or 3.
  * For the two-FFT algorithm xi = F[z] / sqrt(P) enters in place of the
  * Hermitian noise, and dL/dz = F*[h F[grad_out]] / sqrt(P), the sampler
- * applied to grad_out. */
+ * applied to grad_out.  Plans with a grid length outside the compiled lists
+ * get GRF_EUNSUPPORTED. */
 grf_status grf_backward(grf_plan plan, uint64_t seed, const void* noise, int64_t batch, const double* theta,
                         const void* grad_out, double* grad_theta, void* grad_noise, void* workspace,
                         size_t workspace_bytes, void* stream);

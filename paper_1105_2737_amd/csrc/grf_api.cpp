@@ -55,6 +55,7 @@ struct grf_plan_s {
   void* tq_col2 = nullptr;
   void* tq_row = nullptr;
   int device = 0;
+  bool listed = true;       // every axis has compile-time kernels (else the runtime-radix passes)
 };
 
 namespace grf {
@@ -175,6 +176,7 @@ AdjTiles adj_tiles(const grf_plan_s* p) {
     return AdjTiles{nt, nt};
   }
   const grf::Geom g = grf::pass_geom(p->d == 3 ? grf::PASS_COL_GRAD3 : grf::PASS_COL_GRAD, p->dtype, p->n1);
+  if (g.per_wg <= 0) return AdjTiles{1, 1};   // no adjoint kernel for this length (grf_backward refuses it)
   const int nt = (p->M + 2 * g.per_wg - 1) / (2 * g.per_wg);
   return AdjTiles{nt, nt * p->no};
 }
@@ -275,9 +277,44 @@ int adjoint_fields_per_wg(const Args& a, size_t esz) {
   return (a.htab != nullptr && table > (1ll << 20)) ? 2 : 1;
 }
 
+// A pass whose transform length has no compile-time kernel runs on the
+// runtime-radix kernels (column passes, the last-axis passes, the d = 1
+// one-launch sampler of the one-FFT algorithm).
+bool fixed_length(int pass, int L) {
+  if (pass == grf::PASS_SPEC_FILTER || pass == grf::PASS_SPEC_FILTER0) return true;
+  if (grf::is_r2r_pass(pass)) return true;   // the reflecting passes exist for the listed lengths only
+  if (grf::is_row_pass(pass)) return grf::row_length_supported(L);
+  return grf::col_length_supported(L);
+}
+
+grf_status run_generic(const grf_plan_s* p, int pass, int L, Args a, long long batch, hipStream_t s) {
+  const grf::GGeom g = grf::generic_geom(pass, p->dtype, L);
+  if (g.threads <= 0) return fail(GRF_EUNSUPPORTED, "no kernel for this transform length and pass");
+  a.gl = L;
+  a.gcp = g.per_wg;
+  a.gnt = g.nt;
+  a.grs = g.rs;
+  a.gs = grf::radix_plan(L, a.grad);
+  if (a.gs < 0) return fail(GRF_EINVAL, "transform length is not 2/3/5-smooth");
+  long long nblocks;
+  if (grf::is_row_pass(pass)) {
+    nblocks = (a.rows + g.per_wg - 1) / g.per_wg;
+  } else {
+    a.ntile = (a.M + 2 * g.per_wg - 1) / (2 * g.per_wg);
+    nblocks = (long long)a.ntile * a.nfixed * batch;
+    a.order = xcd_order();
+  }
+  if (nblocks <= 0) return GRF_OK;
+  if (nblocks > 0x7fffffffLL) return fail(GRF_EINVAL, "batch too large for one launch");
+  hipError_t e = grf::launch_generic(pass, p->dtype, a, nblocks, s);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return GRF_OK;
+}
+
 grf_status run_pass(const grf_plan_s* p, int pass, int L, Args a, long long nfixed_blocks_per_field,
                     long long batch, hipStream_t s) {
   (void)nfixed_blocks_per_field;
+  if (!fixed_length(pass, L)) return run_generic(p, pass, L, a, batch, s);
   const grf::Geom g = grf::pass_geom(pass, p->dtype, L);
   if (g.threads <= 0) return fail(GRF_EUNSUPPORTED, "no kernel for this length");
   long long nblocks;
@@ -401,6 +438,18 @@ void chunk_passes(const grf_plan_s* p, uint64_t seed, const void* zsrc, long lon
     if (two) a.scale = 1.0 / std::sqrt((double)p->P);   // the table, where there is one, carries it
     a.tw2 = p->tw_row;
     a.rows = nb;
+    if (two && !grf::row_length_supported(p->M)) {
+      // no one-launch kernel for this length: white noise + real-to-complex,
+      // the filter on the spectrum, complex-to-real
+      Args f = a;
+      f.htab = p->table_only ? p->htab : nullptr;
+      push(zsrc ? grf::PASS_ROW_R2C_LOAD : grf::PASS_ROW_R2C_GEN, p->M, a);
+      push(grf::PASS_SPEC_FILTER, 0, f);
+      Args c = a;
+      c.src = nullptr;
+      push(grf::PASS_ROW_C2R, p->M, c);
+      return;
+    }
     push(grf::PASS_ROW_GEN_C2R, p->M, a);
     return;
   }
@@ -455,15 +504,23 @@ void chunk_passes(const grf_plan_s* p, uint64_t seed, const void* zsrc, long lon
     // column (M = 1 restricts a column pass to it) forward, its filter with
     // the mirrored rows, inverse; the middle axis inverse
     push(grf::PASS_COL_LOAD_FWD, p->no, m);
-    Args cf = c;
-    cf.scale = f.scale;
-    cf.htab = f.htab;
-    push(grf::PASS_COL_FILTER3, p->n1, cf);
-    Args c0 = c;
-    c0.M = 1;
-    push(grf::PASS_COL_LOAD_FWD, p->n1, c0);
-    push(grf::PASS_SPEC_FILTER0, 0, f);
-    push(grf::PASS_COL_LOAD_INV, p->n1, c0);
+    if (grf::col_length_supported(p->n1)) {
+      Args cf = c;
+      cf.scale = f.scale;
+      cf.htab = f.htab;
+      push(grf::PASS_COL_FILTER3, p->n1, cf);
+      Args c0 = c;
+      c0.M = 1;
+      push(grf::PASS_COL_LOAD_FWD, p->n1, c0);
+      push(grf::PASS_SPEC_FILTER0, 0, f);
+      push(grf::PASS_COL_LOAD_INV, p->n1, c0);
+    } else {
+      // axis 1 on the runtime-radix kernels: forward, the filter on the whole
+      // packed spectrum, inverse
+      push(grf::PASS_COL_LOAD_FWD, p->n1, c);
+      push(grf::PASS_SPEC_FILTER, 0, f);
+      push(grf::PASS_COL_LOAD_INV, p->n1, c);
+    }
     push(grf::PASS_COL_LOAD_INV, p->no, m);
   } else {
     Args r = a;
@@ -481,7 +538,17 @@ void chunk_passes(const grf_plan_s* p, uint64_t seed, const void* zsrc, long lon
     // this pass has VALU to spare: h on the fly beats a table load, except for the
     // families whose filter exists only as a table (built with the 1/sqrt(P) factor)
     c.htab = p->table_only ? p->htab : nullptr;
-    push(grf::PASS_COL_FILTER, p->n1, c);
+    if (grf::col_length_supported(p->n1)) {
+      push(grf::PASS_COL_FILTER, p->n1, c);
+    } else {
+      // axis 1 on the runtime-radix kernels: forward, the filter on the packed
+      // spectrum, inverse
+      Args f = c;
+      f.rows = nb * (long long)p->n1;
+      push(grf::PASS_COL_LOAD_FWD, p->n1, c);
+      push(grf::PASS_SPEC_FILTER, 0, f);
+      push(grf::PASS_COL_LOAD_INV, p->n1, c);
+    }
   }
   Args b = a;
   b.src = nullptr;
@@ -620,9 +687,15 @@ struct CovLayout {
   size_t acc, buf, total;
 };
 
+// The d = 1 one-FFT estimator is an epilogue of the one-launch sampler
+// (listed lengths); every other plan estimates over sampled chunks.
+bool cov_fused(const grf_plan_s* p) {
+  return p->d == 1 && !p->reflect && p->desc.alg == GRF_ALG_ONE_FFT && p->listed;
+}
+
 CovLayout cov_layout(const grf_plan_s* p, long long n) {
   CovLayout c{};
-  if (p->d == 1 && !p->reflect && p->desc.alg == GRF_ALG_ONE_FFT) {
+  if (cov_fused(p)) {
     const grf::Geom g = grf::geom_gen1d(p->dtype, p->M);
     const long long rb = g.per_wg > 0 ? g.per_wg : 1;
     c.groups = std::min<long long>((n + rb - 1) / rb, COV_GROUPS);
@@ -925,10 +998,18 @@ grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out) {
   if (reflect && d.alg != GRF_ALG_ONE_FFT)
     return fail(GRF_EUNSUPPORTED, "reflecting boundaries use the one-transform method (GRF_ALG_ONE_FFT)");
   const int last = d.ndim - 1;
-  if ((d.ndim >= 2 && !grf::col_length_supported((int)d.dims[0])) ||
-      (d.ndim == 3 && !grf::col_length_supported((int)d.dims[1])) || d.dims[last] > (1ll << 30) ||
-      !grf::row_length_supported((int)(d.dims[last] / 2)))
-    return fail(GRF_EUNSUPPORTED, "grid length not in the supported list");
+  // every even 2/3/5-smooth length: the listed ones (grf_configs.hpp) on the
+  // compile-time kernels, the others on the runtime-radix kernels up to their
+  // limits
+  bool listed = d.dims[last] / 2 <= GRF_GENERIC_MAX_ROW && grf::row_length_supported((int)(d.dims[last] / 2));
+  if (d.dims[last] / 2 > GRF_GENERIC_MAX_ROW)
+    return fail(GRF_EUNSUPPORTED, "last-axis length above 2 * GRF_GENERIC_MAX_ROW");
+  for (int i = 0; i < last; ++i) {
+    if (d.dims[i] > GRF_GENERIC_MAX_COL) return fail(GRF_EUNSUPPORTED, "leading-axis length above GRF_GENERIC_MAX_COL");
+    listed = listed && grf::col_length_supported((int)d.dims[i]);
+  }
+  if (!listed && (reflect || d.draw_order == GRF_DRAW_RECURSIVE))
+    return fail(GRF_EUNSUPPORTED, "reflecting boundaries and the recursive draw order take the listed grid lengths only");
 
   grf_plan_s* p = new (std::nothrow) grf_plan_s();
   if (p == nullptr) return fail(GRF_ENOMEM, "host allocation failed");
@@ -947,6 +1028,7 @@ grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out) {
   p->dtype = d.dtype;
   p->esz = d.dtype == GRF_F32 ? 4 : 8;
   p->reflect = reflect;
+  p->listed = listed;
   if (reflect) {
     for (int i = 0; i < d.ndim; ++i) {
       // semantic axis of descriptor axis i: 0 = axis 1, 1 = middle, 2 = last
@@ -1061,7 +1143,7 @@ grf_status grf_covariance(grf_plan p, uint64_t seed, int64_t nsamples, double* c
   if (workspace == nullptr || workspace_bytes < c.total) return fail(GRF_EINVAL, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
   const double scale = 1.0 / (double)nsamples;
-  if (p->d == 1 && !p->reflect && p->desc.alg == GRF_ALG_ONE_FFT) {
+  if (cov_fused(p)) {
     double* partial = (double*)workspace;
     Args a = base_args(p, nsamples);
     a.recs = p->rec_dev;
@@ -1155,6 +1237,7 @@ grf_status grf_backward(grf_plan p, uint64_t seed, const void* noise, int64_t ba
   if (batch == 0) return GRF_OK;
   if (grad_out == nullptr || grad_theta == nullptr) return fail(GRF_EINVAL, "null gradient pointer");
   if (batch > 0x7fffffff) return fail(GRF_EINVAL, "batch too large");
+  if (!p->listed) return fail(GRF_EUNSUPPORTED, "the adjoint takes the listed grid lengths only");
   const WsLayout w = ws_layout(p, batch, GRF_OP_BACKWARD);
   if (workspace == nullptr || workspace_bytes < w.total) return fail(GRF_EINVAL, "workspace too small");
   grf_status st = check_stream_device(p);

@@ -71,6 +71,27 @@ bool col_length_supported(int L);
 bool row_length_supported(int M);
 Geom pass_geom(int pass, int dtype, int L);
 
+// Runtime-radix passes (grf_generic.hpp) for lengths that have no
+// compile-time kernel: column passes (PASS_COL_GEN_INV, PASS_COL_LOAD_INV,
+// PASS_COL_LOAD_FWD) of length L <= GRF_GENERIC_MAX_COL, row passes
+// (PASS_ROW_C2R, PASS_ROW_R2C_GEN, PASS_ROW_R2C_LOAD and, for d = 1 with the
+// one-FFT algorithm, PASS_ROW_GEN_C2R) of half-length M <= GRF_GENERIC_MAX_ROW.
+#define GRF_GENERIC_MAX_COL 4096
+#define GRF_GENERIC_MAX_ROW 8192
+struct GGeom {
+  int threads;    // threads per workgroup (0: unsupported)
+  int per_wg;     // column pairs (column passes) or rows (row passes) per workgroup
+  int nt;         // threads per transform
+  int rs;         // LDS stride (column passes: pairs per row; row passes: elements per row)
+  size_t lds;     // dynamic LDS bytes
+};
+GGeom generic_geom(int pass, int dtype, int L);
+// Radix list of L (8s first, then 4 or 2, then 5s and 3s) into rad; returns
+// the number of stages, -1 if L is not 2/3/5-smooth.
+int radix_plan(int L, int* rad);
+// a.gl .. a.grad must be set (transform length, geometry, radix list).
+hipError_t launch_generic(int pass, int dtype, const Args& a, long long nblocks, hipStream_t s);
+
 // Launch one pass over `nblocks` workgroups.  dtype: 0 = float32, 1 = float64.
 hipError_t launch_pass(int pass, int dtype, int L, const Args& a, long long nblocks, hipStream_t s);
 

@@ -66,6 +66,10 @@ struct Args {
   int tag;
   int order;                  // column passes: 1 = XCD-grouped workgroup-to-tile order (col_block)
   int fpw;                    // adjoint column pass: consecutive fields per workgroup (>= 1)
+  // runtime-radix passes (grf_generic.hpp): transform length, column pairs or
+  // rows per workgroup, threads per transform, LDS stride, the radix list
+  int gl, gcp, gnt, grs, gs;
+  int grad[16];
   // reflecting boundaries (cosine / sine transforms)
   const void* tq;             // (1/2) e^{i pi k / (2N)}, k < N (column) or k <= N/2 (row), of the pass's axis
   int sine;                   // the pass's axis is a sine axis (output sign (-1)^j)
@@ -204,12 +208,12 @@ struct Eng {
 // middle index o).  See the layout note at the top: m0 = 0 yields the packed
 // plane slot.  z comes from Philox (zsrc == nullptr) or from a noise array
 // laid out like the field.
-template <typename T>
+// UK: the key is uniform over the wave (one field per workgroup).
+template <typename T, bool UK = true>
 __device__ __forceinline__ void load_z4(const Args& a, const T* zsrc, int b, int row, int m0, uint32_t k0,
                                         uint32_t k1, T* z) {
   if (zsrc == nullptr) {
-    // one field per workgroup in every caller: the key is wave-uniform
-    normals4<T, true>((uint32_t)(m0 >> 1), (uint32_t)row, (uint32_t)a.tag, k0, k1, z);
+    normals4<T, UK>((uint32_t)(m0 >> 1), (uint32_t)row, (uint32_t)a.tag, k0, k1, z);
   } else {
     const T* p = zsrc + (long long)b * a.field_stride * 2 + (long long)row * a.nd + 2 * m0;
     z[0] = p[0];
@@ -293,7 +297,9 @@ __device__ __forceinline__ C<T> seq_entry(const Args& a, const T* zsrc, int b, u
 
 // SEQ: the normals in the draw order of the recursive algorithm (its own
 // kernel instantiation, so that the default route keeps its registers).
-template <typename T, bool SEQ = false>
+// UK: the key is uniform over the wave (false where a workgroup's rows belong
+// to different fields).
+template <typename T, bool SEQ = false, bool UK = true>
 __device__ __forceinline__ void gen_pair(const Args& a, const Filt<T>& f, const T* zsrc, int b, uint32_t k0,
                                          uint32_t k1, int kk1, int o, int m0, C<T>& A0, C<T>& A1) {
   const int row = kk1 * a.no + o;
@@ -317,7 +323,7 @@ __device__ __forceinline__ void gen_pair(const Args& a, const Filt<T>& f, const 
     return;
   }
   T z[4];
-  load_z4<T>(a, zsrc, b, row, m0, k0, k1, z);
+  load_z4<T, UK>(a, zsrc, b, row, m0, k0, k1, z);
   const T s = (T)0.70710678118654752440;
   const T* ht = (const T*)a.htab;
   const T* hrow = ht ? ht + (long long)row * (a.M + 2) : nullptr;
@@ -352,7 +358,7 @@ __device__ __forceinline__ void gen_pair(const Args& a, const Filt<T>& f, const 
       xn = mk<T>(z[1], (T)0);
     } else {
       T zz[4];
-      load_z4<T>(a, zsrc, b, nrow, 0, k0, k1, zz);
+      load_z4<T, UK>(a, zsrc, b, nrow, 0, k0, k1, zz);
       if (row < nrow) {
         x0 = mk<T>(s * z[0], s * z[1]);
         xn = mk<T>(s * zz[0], s * zz[1]);

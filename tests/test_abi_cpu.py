@@ -69,10 +69,12 @@ def _desc(**kw):
     (dict(cov_kind=9), -1),
     (dict(ndim=4), -1),
     (dict(ndim=0), -1),
-    (dict(dims=(2048, 64)), -4),          # length not in the list
-    (dict(dims=(64, 8192)), -4),
+    (dict(dims=(8192, 64)), -4),          # leading axis above the runtime-radix limit (4096)
+    (dict(dims=(64, 32768)), -4),         # last axis above its limit (16384)
     (dict(ndim=1, dims=(14,)), -1),
-    (dict(ndim=1, dims=(8192,)), -4),
+    (dict(ndim=1, dims=(32768,)), -4),
+    (dict(dims=(80, 64), bc=(1, 1)), -4),            # reflecting boundaries: listed lengths only
+    (dict(dims=(64, 90), draw_order=1), -4),         # recursive draw order: listed lengths only
     (dict(cov_kind=3, m=0.0, k=1, l=1, n=1), -1),   # the family of Section 4 needs m > 0
     (dict(cov_kind=3, m=1.0, k=0, l=1, n=1), -1),   # and k, l, n >= 1
     (dict(cov_kind=3, m=1.0, k=1, l=1, n=65), -1),

@@ -1,0 +1,130 @@
+"""Grid lengths without a compile-time kernel (any even 2/3/5-smooth N up to
+4096 on a leading axis and 16384 on the last axis, Section 3's Input list asks
+only for even N_i): the runtime-radix passes against the float64 oracle, for
+both algorithms, d = 1, 2, 3, float32 and float64, as the leading axis, the
+middle axis and the last axis; large fields; chunked batches give the same
+bits; the features that take the listed lengths only refuse the others."""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import grf as ogrf  # noqa: E402
+from oracle import spectra  # noqa: E402
+
+# leading-axis lengths and last-axis half-lengths that are not in the compiled lists
+GEN_COL = [6, 10, 18, 20, 40, 80, 90, 150, 240, 384, 640, 768, 810, 1200, 1536, 2048, 2700, 4096]
+GEN_HALF = [3, 5, 10, 18, 40, 75, 125, 240, 384, 768, 1500, 4096, 6000, 8192]
+TOL = {torch.float32: 1e-5, torch.float64: 1e-12}
+PARAMS = (1.0, 0.15, 1.5)
+
+
+@pytest.fixture(scope="module")
+def grf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1105_2737_amd as m
+    return m
+
+
+def relerr(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def check(grf, dims, dtype, alg, seed=1, batch=1):
+    lengths = tuple(1.0 + 0.25 * i for i in range(len(dims)))
+    print(f"generic length: dims {dims} alg {alg} {dtype} batch {batch}", flush=True)
+    plan = grf.Plan(dims, lengths=lengths, alg=alg, dtype=dtype, cov="matern", sigma=PARAMS[0],
+                    length_scale=PARAMS[1], nu=PARAMS[2])
+    out = plan.sample(seed=seed, batch=batch)
+    for b in sorted({0, batch - 1}):
+        got = out[b].double().cpu().numpy()
+        ref = ogrf.sample(dims, lengths, spectra.MATERN, *PARAMS, seed=seed + b, batch=1, alg=alg)[0]
+        e = relerr(got, ref)
+        assert e <= TOL[dtype], (dims, alg, dtype, b, e)
+    return plan, out
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["f32", "f64"])
+@pytest.mark.parametrize("L", GEN_COL)
+def test_generic_leading_axis(grf, dtype, L):
+    for alg in (2, 1):
+        check(grf, (L, 16), dtype, alg)           # axis 1 of d = 2
+        check(grf, (4, L, 8), dtype, alg)         # the middle axis of d = 3
+        check(grf, (L, 6, 8), dtype, alg)         # axis 1 of d = 3
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["f32", "f64"])
+@pytest.mark.parametrize("M", GEN_HALF)
+def test_generic_last_axis(grf, dtype, M):
+    for alg in (2, 1):
+        check(grf, (2 * M,), dtype, alg, batch=3)  # d = 1
+        check(grf, (8, 2 * M), dtype, alg)
+        if M <= 1500:
+            check(grf, (4, 6, 2 * M), dtype, alg)
+
+
+@pytest.mark.parametrize("dims", [(90, 250), (768, 80), (40, 30, 18), (4096, 4096), (2048, 6000)])
+def test_generic_mixed_and_large(grf, dims):
+    """Every axis off the lists, and large fields (16.8M and 12.3M points)."""
+    dtype = torch.float32
+    check(grf, dims, dtype, 2, seed=7, batch=1)
+    if np.prod(dims) <= 1 << 22:
+        check(grf, dims, dtype, 1, seed=7, batch=1)
+
+
+def test_generic_chunks_same_bits(grf):
+    """Cache-sized chunks with a ragged tail give the same bits as one chunk."""
+    dims = (384, 90)
+    for alg in (2, 1):
+        plan = grf.Plan(dims, alg=alg, dtype=torch.float32)
+        ref = plan.sample(seed=11, batch=7)
+        old = os.environ.get("GRF_CHUNK_BYTES")
+        os.environ["GRF_CHUNK_BYTES"] = str(3 * dims[0] * dims[1] * 4)
+        try:
+            got = plan.sample(seed=11, batch=7)
+        finally:
+            if old is None:
+                del os.environ["GRF_CHUNK_BYTES"]
+            else:
+                os.environ["GRF_CHUNK_BYTES"] = old
+        assert torch.equal(got, ref)
+        # field b of a batch is field seed + b on its own
+        assert torch.equal(plan.sample(seed=16, batch=1)[0], ref[5])
+
+
+def test_generic_theta_and_noise_routes(grf):
+    """Per-field parameters and a given noise array on a runtime-radix plan."""
+    dims = (80, 150)
+    plan = grf.Plan(dims, alg=2, dtype=torch.float64)
+    theta = torch.tensor([[1.0, 0.15, 1.5], [2.0, 0.1, 0.5]], dtype=torch.float64, device="cuda")
+    out = plan.sample(seed=3, batch=2, theta=theta)
+    for b in range(2):
+        s, ell, nu = theta[b].tolist()
+        ref = ogrf.sample(dims, (1.0, 1.0), spectra.MATERN, s, ell, nu, seed=3 + b, batch=1, alg=2)[0]
+        assert relerr(out[b].cpu().numpy(), ref) <= 1e-12
+    z = plan.noise(seed=3, batch=2)
+    assert torch.equal(plan.sample_from_noise(z, theta=theta), out)
+
+
+def test_generic_refusals(grf):
+    from paper_1105_2737_amd import _lib as L
+    plan = grf.Plan((80, 16), alg=2, dtype=torch.float32)
+    phi = plan.sample(seed=0, batch=1)
+    with pytest.raises(L.GRFError) as ei:
+        plan.backward(phi, seed=0)
+    assert ei.value.status == L.GRF_EUNSUPPORTED
+    for kw in (dict(boundary="neumann"), dict(draw_order="recursive")):
+        with pytest.raises(L.GRFError) as ei:
+            grf.Plan((80, 16), alg=2, dtype=torch.float32, **kw)
+        assert ei.value.status == L.GRF_EUNSUPPORTED
+    with pytest.raises(L.GRFError) as ei:
+        grf.Plan((8192, 16), alg=2, dtype=torch.float32)          # above the leading-axis limit
+    assert ei.value.status == L.GRF_EUNSUPPORTED
+    with pytest.raises(L.GRFError) as ei:
+        grf.Plan((16, 2 * 3 * 7), alg=2, dtype=torch.float32)     # not 2/3/5-smooth
+    assert ei.value.status == L.GRF_EINVAL
