@@ -167,6 +167,27 @@ grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out);
 /* Release a plan and its device tables (NULL is accepted). */
 grf_status grf_plan_destroy(grf_plan plan);
 
+/* Autotuner of a plan: for every pass of the sampler (the launch sequence
+ * of a batch of `batch` fields), times the candidate kernels on one chunk
+ * of fields in `out` (device, batch fields of the plan's shape; its contents
+ * are overwritten) and keeps the fastest for later calls: the compile-time
+ * kernel of a listed length, and the runtime-radix kernel with every radix
+ * order the tuner generates for the length (the splits of its power of two
+ * into radices 8, 4, 2 with its 3s and 5s, in several orders) at 4 and 8
+ * values per thread.  Appends one line per pass to the file named by
+ * GRF_TUNE_CACHE, if set:
+ *   plan <arch> <f32|f64> <pass> <inv|fwd> <length> fixed | generic <vpt> <r1,r2,...>
+ * and grf_plan_create reads that file: the last line for a key (arch, dtype,
+ * pass, direction, length) that the plan uses and that names a kernel it can
+ * run wins; other lines (other architectures, corrupt ones) are ignored.
+ * Synchronises the stream.  Results stay within the tolerance of the oracle
+ * whatever the choice (a different radix order rounds differently). */
+grf_status grf_plan_tune(grf_plan plan, int64_t batch, void* out, void* stream);
+/* The plan's current choice for pass `pass` (a GRF_PASS_* value) of transform
+ * length `length` ("default", "fixed" or "generic <vpt> <radices>"), into the
+ * host buffer buf of len bytes. */
+grf_status grf_plan_tune_choice(grf_plan plan, int32_t pass, int64_t length, char* buf, size_t len);
+
 /* Bytes of device workspace that grf_sample / grf_sample_from_noise
  * (op = GRF_OP_SAMPLE), grf_backward (op = GRF_OP_BACKWARD) or
  * grf_covariance (op = GRF_OP_COVARIANCE, batch = number of samples) need for

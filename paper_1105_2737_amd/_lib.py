@@ -29,7 +29,8 @@ EXPORTS = ["grf_plan_create", "grf_plan_destroy", "grf_workspace_size", "grf_sam
            "grf_sample_stage_count", "grf_sample_stage", "grf_sample_stage_info", "grf_sample_from_noise", "grf_noise", "grf_backward", "grf_debug_philox",
            "grf_debug_spectrum",
            "grf_covariance", "grf_batch_create", "grf_batch_offsets", "grf_batch_sample", "grf_batch_sample_plain",
-           "grf_batch_tune", "grf_batch_destroy", "grf_last_error", "grf_version"]
+           "grf_batch_tune", "grf_batch_destroy", "grf_last_error", "grf_version", "grf_plan_tune",
+           "grf_plan_tune_choice"]
 
 
 class grf_plan_desc(ctypes.Structure):
@@ -81,6 +82,8 @@ def _load():
         "grf_batch_sample_plain": (ctypes.c_int, [vp, vp, vp]),
         "grf_batch_tune": (ctypes.c_int, [vp, vp, vp]),
         "grf_batch_destroy": (ctypes.c_int, [vp]),
+        "grf_plan_tune": (ctypes.c_int, [vp, c64, vp, vp]),
+        "grf_plan_tune_choice": (ctypes.c_int, [vp, i32, c64, ctypes.c_char_p, sz]),
         "grf_last_error": (ctypes.c_char_p, []),
         "grf_version": (ctypes.c_char_p, []),
     }
@@ -197,6 +200,16 @@ def grf_batch_tune(batch, out, stream):
 
 def grf_batch_destroy(batch):
     return check(lib.grf_batch_destroy(batch))
+
+
+def grf_plan_tune(plan, batch, out, stream):
+    return check(lib.grf_plan_tune(plan, batch, out, stream))
+
+
+def grf_plan_tune_choice(plan, pass_, length):
+    buf = ctypes.create_string_buffer(128)
+    check(lib.grf_plan_tune_choice(plan, pass_, length, buf, 128))
+    return buf.value.decode()
 
 
 def grf_last_error():

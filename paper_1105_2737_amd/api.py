@@ -170,6 +170,17 @@ class Plan:
         L.grf_sample_from_noise(self.handle, _ptr(noise), batch, _ptr(th), _ptr(out), _ptr(ws), n, _stream())
         return out
 
+    def tune(self, batch=1, out=None):
+        """Time the candidate kernels of every pass on a chunk of `batch` fields
+        (written into `out`, or a scratch buffer) and keep the fastest; the
+        choices are appended to the GRF_TUNE_CACHE file when set."""
+        batch = int(batch)
+        out = self._out(out, batch)
+        L.grf_plan_tune(self.handle, batch, _ptr(out), _stream())
+
+    def tune_choice(self, pass_, length):
+        return L.grf_plan_tune_choice(self.handle, int(pass_), int(length))
+
     def covariance(self, seed=0, nsamples=1):
         """Statistical covariance (1/n) sum_b phi_b(x_0) phi_b(x) over fields
         seed .. seed+n-1 (float64 tensor of the field's shape)."""

@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -28,9 +29,20 @@
 #include "grf_dispatch.hpp"
 #include "grf_host.hpp"
 #include "grf_kernels.hpp"
+#include "grf_tune_cache.hpp"
 
 using grf::Args;
 using grf::FieldRec;
+
+// The kernel of one pass of a plan, as chosen by the tuner or the cache: the
+// compile-time kernel of its length, or the runtime-radix kernel with a radix
+// order and a number of values per thread.
+struct TuneChoice {
+  bool generic = false;
+  int vpt = 8;
+  int ns = 0;
+  int rad[16] = {};
+};
 
 struct grf_plan_s {
   grf_plan_desc desc;
@@ -56,6 +68,7 @@ struct grf_plan_s {
   void* tq_row = nullptr;
   int device = 0;
   bool listed = true;       // every axis has compile-time kernels (else the runtime-radix passes)
+  std::map<long long, TuneChoice> tune;   // per (pass, transform length): the tuner's or the cache's choice
 };
 
 namespace grf {
@@ -287,14 +300,31 @@ bool fixed_length(int pass, int L) {
   return grf::col_length_supported(L);
 }
 
-grf_status run_generic(const grf_plan_s* p, int pass, int L, Args a, long long batch, hipStream_t s) {
-  const grf::GGeom g = grf::generic_geom(pass, p->dtype, L);
+long long tune_key(int pass, int L) { return (long long)pass * 1000000 + L; }
+
+const TuneChoice* tune_choice(const grf_plan_s* p, int pass, int L) {
+  const auto it = p->tune.find(tune_key(pass, L));
+  return it == p->tune.end() ? nullptr : &it->second;
+}
+
+grf_status run_generic(const grf_plan_s* p, int pass, int L, Args a, long long batch, hipStream_t s,
+                       const TuneChoice* tc) {
+  // untuned: 4 values per thread (the tuner chose 4 over 8 for every
+  // runtime-radix pass it timed on MI355X)
+  const int vpt = tc ? tc->vpt : 4;
+  const grf::GGeom g = grf::generic_geom(pass, p->dtype, L, vpt);
   if (g.threads <= 0) return fail(GRF_EUNSUPPORTED, "no kernel for this transform length and pass");
   a.gl = L;
   a.gcp = g.per_wg;
   a.gnt = g.nt;
   a.grs = g.rs;
-  a.gs = grf::radix_plan(L, a.grad);
+  a.gvpt = vpt;
+  if (tc) {
+    a.gs = tc->ns;
+    for (int i = 0; i < tc->ns; ++i) a.grad[i] = tc->rad[i];
+  } else {
+    a.gs = grf::radix_plan(L, a.grad);
+  }
   if (a.gs < 0) return fail(GRF_EINVAL, "transform length is not 2/3/5-smooth");
   long long nblocks;
   if (grf::is_row_pass(pass)) {
@@ -314,7 +344,8 @@ grf_status run_generic(const grf_plan_s* p, int pass, int L, Args a, long long b
 grf_status run_pass(const grf_plan_s* p, int pass, int L, Args a, long long nfixed_blocks_per_field,
                     long long batch, hipStream_t s) {
   (void)nfixed_blocks_per_field;
-  if (!fixed_length(pass, L)) return run_generic(p, pass, L, a, batch, s);
+  const TuneChoice* tc = tune_choice(p, pass, L);
+  if (tc ? tc->generic : !fixed_length(pass, L)) return run_generic(p, pass, L, a, batch, s, tc);
   const grf::Geom g = grf::pass_geom(pass, p->dtype, L);
   if (g.threads <= 0) return fail(GRF_EUNSUPPORTED, "no kernel for this length");
   long long nblocks;
@@ -907,6 +938,152 @@ grf_status adj_chunk_reflect(const grf_plan_s* p, Args c, const void* g, long lo
   return run_pass(p, grf::PASS_R2R_COL_FWD_RED, p->n1, c, 0, nb, s);
 }
 
+// ---- the plan autotuner -------------------------------------------------
+
+// Passes whose kernel the tuner chooses, their names in the tuning cache and
+// their direction.
+const char* tune_pass_name(int pass) {
+  switch (pass) {
+    case grf::PASS_COL_GEN_INV: return "col-gen";
+    case grf::PASS_COL_LOAD_INV: return "col-load";
+    case grf::PASS_COL_LOAD_FWD: return "col-load";
+    case grf::PASS_ROW_C2R: return "row-c2r";
+    case grf::PASS_ROW_R2C_GEN: return "row-r2c-gen";
+    case grf::PASS_ROW_R2C_LOAD: return "row-r2c-load";
+    case grf::PASS_ROW_GEN_C2R: return "row-gen-c2r";
+    default: return nullptr;
+  }
+}
+const char* tune_dir(int pass) {
+  return (pass == grf::PASS_COL_LOAD_FWD || pass == grf::PASS_ROW_R2C_GEN || pass == grf::PASS_ROW_R2C_LOAD) ? "fwd"
+                                                                                                            : "inv";
+}
+int tune_pass_of(const std::string& name, const std::string& dir) {
+  if (name == "col-gen" && dir == "inv") return grf::PASS_COL_GEN_INV;
+  if (name == "col-load") return dir == "fwd" ? grf::PASS_COL_LOAD_FWD : grf::PASS_COL_LOAD_INV;
+  if (name == "row-c2r" && dir == "inv") return grf::PASS_ROW_C2R;
+  if (name == "row-r2c-gen" && dir == "fwd") return grf::PASS_ROW_R2C_GEN;
+  if (name == "row-r2c-load" && dir == "fwd") return grf::PASS_ROW_R2C_LOAD;
+  if (name == "row-gen-c2r" && dir == "inv") return grf::PASS_ROW_GEN_C2R;
+  return -1;
+}
+
+// Can the runtime-radix kernel run this launch of this plan?  (The d = 1
+// one-launch pass only for the one-FFT algorithm in the counter order.)
+bool generic_capable(const grf_plan_s* p, int pass) {
+  if (tune_pass_name(pass) == nullptr) return false;
+  if (pass == grf::PASS_ROW_GEN_C2R)
+    return p->desc.alg == GRF_ALG_ONE_FFT && p->desc.draw_order == GRF_DRAW_COUNTER;
+  if (pass == grf::PASS_COL_GEN_INV) return p->desc.draw_order == GRF_DRAW_COUNTER;
+  return true;
+}
+
+// Radix lists the tuner tries for L: every split of the power of two into
+// radices 8, 4 and at most two 2s, with the 3s and 5s, each in up to four
+// orders (large radices first, small first, odd radices first, the
+// generator's order); duplicates removed, at most `cap` lists.
+std::vector<std::vector<int>> radix_candidates(int L, size_t cap) {
+  int n = L, e2 = 0, e3 = 0, e5 = 0;
+  while (n % 2 == 0) { n /= 2; ++e2; }
+  while (n % 3 == 0) { n /= 3; ++e3; }
+  while (n % 5 == 0) { n /= 5; ++e5; }
+  std::vector<std::vector<int>> out;
+  if (n != 1) return out;
+  auto add = [&](std::vector<int> r) {
+    if (r.size() > 16 || out.size() >= cap) return;
+    if (std::find(out.begin(), out.end(), r) == out.end()) out.push_back(r);
+  };
+  {
+    int gen[16];
+    const int ns = grf::radix_plan(L, gen);
+    if (ns > 0) add(std::vector<int>(gen, gen + ns));
+  }
+  for (int a8 = e2 / 3; a8 >= 0; --a8) {
+    for (int b4 = (e2 - 3 * a8) / 2; b4 >= 0; --b4) {
+      const int c2 = e2 - 3 * a8 - 2 * b4;
+      if (c2 > 2) continue;
+      std::vector<int> ms;
+      for (int i = 0; i < a8; ++i) ms.push_back(8);
+      for (int i = 0; i < b4; ++i) ms.push_back(4);
+      for (int i = 0; i < c2; ++i) ms.push_back(2);
+      for (int i = 0; i < e5; ++i) ms.push_back(5);
+      for (int i = 0; i < e3; ++i) ms.push_back(3);
+      if (ms.empty()) continue;
+      std::vector<int> desc = ms, asc = ms, odd;
+      std::sort(desc.begin(), desc.end(), std::greater<int>());
+      std::sort(asc.begin(), asc.end());
+      for (int r : desc) if (r % 2) odd.push_back(r);
+      for (int r : desc) if (r % 2 == 0) odd.push_back(r);
+      add(desc);
+      add(odd);
+      add(asc);
+    }
+  }
+  return out;
+}
+
+std::string choice_text(const TuneChoice& c) {
+  if (!c.generic) return "fixed";
+  std::string t = "generic " + std::to_string(c.vpt) + " ";
+  for (int i = 0; i < c.ns; ++i) t += (i ? "," : "") + std::to_string(c.rad[i]);
+  return t;
+}
+
+// A cache entry's choice, validated against the plan (a compile-time kernel
+// must exist for "fixed"; the radices must be from {2, 3, 4, 5, 8} and
+// multiply to L).
+bool parse_choice(const grf_plan_s* p, int pass, long long L, const std::vector<std::string>& w, TuneChoice* c) {
+  if (w[0] == "fixed") {
+    if (!fixed_length(pass, (int)L)) return false;
+    *c = TuneChoice{};
+    return true;
+  }
+  if (w[0] != "generic" || w.size() != 3 || !generic_capable(p, pass)) return false;
+  TuneChoice t;
+  t.generic = true;
+  t.vpt = std::atoi(w[1].c_str());
+  if (t.vpt != 4 && t.vpt != 8) return false;
+  long long prod = 1;
+  size_t i = 0;
+  const std::string& r = w[2];
+  while (i < r.size()) {
+    size_t j = r.find(',', i);
+    if (j == std::string::npos) j = r.size();
+    const int v = std::atoi(r.substr(i, j - i).c_str());
+    if ((v != 2 && v != 3 && v != 4 && v != 5 && v != 8) || t.ns >= 16) return false;
+    t.rad[t.ns++] = v;
+    prod *= v;
+    i = j + 1;
+  }
+  if (prod != L) return false;
+  *c = t;
+  return true;
+}
+
+// The (pass, length) pairs of the plan's sampler that the tuner can choose for.
+std::vector<std::pair<int, int>> tunable_passes(const grf_plan_s* p, long long batch) {
+  std::vector<std::pair<int, int>> v;
+  for (const PassLaunch& pl : sample_passes(p, 0, nullptr, batch, p->rec_dev, 0, nullptr)) {
+    if (tune_pass_name(pl.pass) == nullptr) continue;
+    const std::pair<int, int> k(pl.pass, pl.L);
+    if (std::find(v.begin(), v.end(), k) == v.end()) v.push_back(k);
+  }
+  return v;
+}
+
+void load_plan_cache(grf_plan_s* p) {
+  const std::vector<std::pair<int, int>> mine = tunable_passes(p, 1);
+  const char* dt = p->dtype == GRF_F32 ? "f32" : "f64";
+  for (const grf::tune::Line& l : grf::tune::read("plan", grf::tune::arch_name(p->device))) {
+    if (l.dtype != dt) continue;
+    const int pass = tune_pass_of(l.pass, l.dir);
+    if (pass < 0) continue;
+    if (std::find(mine.begin(), mine.end(), std::make_pair(pass, (int)l.length)) == mine.end()) continue;
+    TuneChoice c;
+    if (parse_choice(p, pass, l.length, l.choice, &c)) p->tune[tune_key(pass, (int)l.length)] = c;
+  }
+}
+
 }  // namespace
 
 namespace grf {
@@ -1107,6 +1284,7 @@ grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out) {
     grf_plan_destroy(p);
     return st;
   }
+  load_plan_cache(p);
   *out = p;
   return GRF_OK;
 }
@@ -1284,6 +1462,92 @@ grf_status grf_backward(grf_plan p, uint64_t seed, const void* noise, int64_t ba
       if (st != GRF_OK) return st;
     }
   }
+  return GRF_OK;
+}
+
+grf_status grf_plan_tune(grf_plan p, int64_t batch, void* out, void* stream) {
+  if (p == nullptr || out == nullptr) return fail(GRF_EINVAL, "null argument");
+  if (batch < 1) return fail(GRF_EINVAL, "batch must be positive");
+  grf_status st = check_stream_device(p);
+  if (st != GRF_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const long long nb = std::min<long long>(batch, chunk_fields(p, batch));
+  const std::vector<PassLaunch> v = sample_passes(p, 0, nullptr, nb, p->rec_dev, 0, out);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(GRF_EDEVICE, "event creation");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(GRF_EDEVICE, "event creation");
+  }
+  const std::string arch = grf::tune::arch_name(p->device);
+  const char* dt = p->dtype == GRF_F32 ? "f32" : "f64";
+  std::string lines;
+  std::vector<long long> done;
+  for (size_t i = 0; i < v.size() && st == GRF_OK; ++i) {
+    const int pass = v[i].pass, L = v[i].L;
+    const long long key = tune_key(pass, L);
+    if (tune_pass_name(pass) == nullptr || std::find(done.begin(), done.end(), key) != done.end()) continue;
+    done.push_back(key);
+    std::vector<TuneChoice> cand;
+    if (fixed_length(pass, L)) cand.push_back(TuneChoice{});
+    if (generic_capable(p, pass)) {
+      for (int vpt : {8, 4}) {
+        for (const std::vector<int>& r : radix_candidates(L, 6)) {
+          TuneChoice c;
+          c.generic = true;
+          c.vpt = vpt;
+          c.ns = (int)r.size();
+          for (int k = 0; k < c.ns; ++k) c.rad[k] = r[k];
+          cand.push_back(c);
+        }
+      }
+    }
+    float best = 1e30f;
+    TuneChoice bestc;
+    bool any = false;
+    for (const TuneChoice& c : cand) {
+      p->tune[key] = c;
+      if (run_launch(p, v[i], s) != GRF_OK) continue;   // a shape this kernel cannot take
+      float tmin = 1e30f;
+      for (int rep = 0; rep < 3 && st == GRF_OK; ++rep) {
+        hipError_t e = hipEventRecord(e0, s);
+        if (e == hipSuccess) st = run_launch(p, v[i], s);
+        if (st != GRF_OK) break;
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (e != hipSuccess) st = hip_fail(e, "tuning run");
+        tmin = std::min(tmin, t);
+      }
+      if (st != GRF_OK) break;
+      if (tmin < best) {
+        best = tmin;
+        bestc = c;
+        any = true;
+      }
+    }
+    if (st != GRF_OK) break;
+    if (!any) {
+      p->tune.erase(key);
+      continue;
+    }
+    p->tune[key] = bestc;
+    lines += std::string("plan ") + arch + " " + dt + " " + tune_pass_name(pass) + " " + tune_dir(pass) + " " +
+             std::to_string(L) + " " + choice_text(bestc) + "\n";
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != GRF_OK) return st;
+  grf::tune::append(lines);
+  return GRF_OK;
+}
+
+grf_status grf_plan_tune_choice(grf_plan p, int32_t pass, int64_t length, char* buf, size_t len) {
+  if (p == nullptr || buf == nullptr || len == 0) return fail(GRF_EINVAL, "null argument");
+  const TuneChoice* c = tune_choice(p, pass, (int)length);
+  const std::string t = c ? choice_text(*c) : std::string("default");
+  std::snprintf(buf, len, "%s", t.c_str());
   return GRF_OK;
 }
 

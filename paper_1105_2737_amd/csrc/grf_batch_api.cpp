@@ -18,6 +18,7 @@
 #include "grf_dispatch.hpp"
 #include "grf_host.hpp"
 #include "grf_kernels.hpp"
+#include "grf_tune_cache.hpp"
 
 using grf::BatchField;
 using grf::BatchItem;
@@ -140,34 +141,18 @@ grf_status enqueue(grf_batch_s* b, void* out, hipStream_t s) {
   return GRF_OK;
 }
 
-// Tune cache: text lines "<arch> col|row <length> <variant>".
-std::string cache_path() {
-  const char* e = std::getenv("GRF_TUNE_CACHE");
-  return e ? std::string(e) : std::string();
-}
-
-std::string arch_name(int dev) {
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
-  std::string a = prop.gcnArchName;
-  const size_t c = a.find(':');
-  return c == std::string::npos ? a : a.substr(0, c);
-}
-
+// Tile-shape choices from the tuning cache (lines "batch <arch> f32 col|row
+// inv <length> <variant>"); foreign, corrupt or out-of-range entries are
+// ignored.
 void load_cache(grf_batch_s* b) {
-  const std::string path = cache_path();
-  if (path.empty()) return;
-  FILE* f = std::fopen(path.c_str(), "r");
-  if (!f) return;
-  const std::string arch = arch_name(b->device);
-  char a[64], kind[8];
-  int len, var;
-  while (std::fscanf(f, "%63s %7s %d %d", a, kind, &len, &var) == 4) {
-    if (arch != a || var < 0 || var >= grf::BATCH_VARIANTS) continue;   // foreign or corrupt entries are ignored
-    if (!std::strcmp(kind, "col") && b->cvar.count(len)) b->cvar[len] = var;
-    if (!std::strcmp(kind, "row") && b->rvar.count(len)) b->rvar[len] = var;
+  for (const grf::tune::Line& l : grf::tune::read("batch", grf::tune::arch_name(b->device))) {
+    if (l.dtype != "f32" || l.dir != "inv") continue;
+    char* end = nullptr;
+    const long v = std::strtol(l.choice[0].c_str(), &end, 10);
+    if (end == l.choice[0].c_str() || *end != '\0' || v < 0 || v >= grf::BATCH_VARIANTS) continue;
+    if (l.pass == "col" && b->cvar.count((int)l.length)) b->cvar[(int)l.length] = (int)v;
+    if (l.pass == "row" && b->rvar.count((int)l.length)) b->rvar[(int)l.length] = (int)v;
   }
-  std::fclose(f);
 }
 
 }  // namespace
@@ -400,7 +385,7 @@ grf_status grf_batch_tune(grf_batch b, void* out, void* stream) {
   };
   grf_status st = GRF_OK;
   std::string lines;
-  const std::string arch = arch_name(b->device);
+  const std::string arch = grf::tune::arch_name(b->device);
   for (int pass = 0; pass < 2 && st == GRF_OK; ++pass) {
     auto& vm = pass == 0 ? b->cvar : b->rvar;
     for (auto& kv : std::map<int, int>(vm)) {
@@ -411,8 +396,9 @@ grf_status grf_batch_tune(grf_batch b, void* out, void* stream) {
       for (int v = 1; v < grf::BATCH_VARIANTS; ++v)
         if (tv[v] < tv[bv]) bv = v;
       vm[kv.first] = bv;
-      char buf[96];
-      std::snprintf(buf, sizeof(buf), "%s %s %d %d\n", arch.c_str(), pass == 0 ? "col" : "row", kv.first, bv);
+      char buf[128];
+      std::snprintf(buf, sizeof(buf), "batch %s f32 %s inv %d %d\n", arch.c_str(), pass == 0 ? "col" : "row",
+                    kv.first, bv);
       lines += buf;
     }
   }
@@ -421,14 +407,7 @@ grf_status grf_batch_tune(grf_batch b, void* out, void* stream) {
   if (st != GRF_OK) return st;
   st = build_queues(b);
   if (st != GRF_OK) return st;
-  const std::string path = cache_path();
-  if (!path.empty()) {
-    FILE* f = std::fopen(path.c_str(), "a");
-    if (f) {
-      std::fputs(lines.c_str(), f);
-      std::fclose(f);
-    }
-  }
+  grf::tune::append(lines);
   return GRF_OK;
 }
 

@@ -85,11 +85,13 @@ struct GGeom {
   int rs;         // LDS stride (column passes: pairs per row; row passes: elements per row)
   size_t lds;     // dynamic LDS bytes
 };
-GGeom generic_geom(int pass, int dtype, int L);
+// vpt: values per thread of a transform (4 or 8; NT = ceil(L / vpt)).
+GGeom generic_geom(int pass, int dtype, int L, int vpt);
 // Radix list of L (8s first, then 4 or 2, then 5s and 3s) into rad; returns
 // the number of stages, -1 if L is not 2/3/5-smooth.
 int radix_plan(int L, int* rad);
-// a.gl .. a.grad must be set (transform length, geometry, radix list).
+// a.gl .. a.grad must be set (transform length, geometry, values per thread,
+// radix list).
 hipError_t launch_generic(int pass, int dtype, const Args& a, long long nblocks, hipStream_t s);
 
 // Launch one pass over `nblocks` workgroups.  dtype: 0 = float32, 1 = float64.

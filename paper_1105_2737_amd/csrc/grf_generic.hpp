@@ -6,10 +6,12 @@
 // Args::grad, produced on the host by a generator: radices 8 first, then
 // 4 or 2, then 5 and 3).  Every stage goes LDS -> registers -> LDS: each
 // thread loads the inputs of its butterflies, the workgroup synchronises, the
-// thread writes the outputs, the workgroup synchronises.  NT = ceil(L / 8)
-// threads per transform, so a thread holds at most 8 + R values of a stage
-// (NB(R) = ceil(8 / R) butterflies); the radix is dispatched per stage to a
-// body compiled for it, so that these values stay in registers.  Twiddles
+// thread writes the outputs, the workgroup synchronises.  NT = ceil(L / VPT)
+// threads per transform (VPT = 4 or 8 values per thread, a tuning choice; 4
+// untuned), so
+// a thread holds at most VPT + R values of a stage (NB(R) = ceil(VPT / R)
+// butterflies); the radix is dispatched per stage to a body compiled for it,
+// so that these values stay in registers.  Twiddles
 // W_L are read from the plan's table in global memory (cached).  Transform
 // data live in dynamic LDS: column passes take CP column pairs per workgroup
 // (one Vec<T, 2> per row), row passes RB rows (one complex per element).
@@ -20,11 +22,11 @@ namespace grf {
 
 // One stage of radix R (Ns = product of the radices before it) over the
 // transform whose element i is acc(i); act: this thread holds a transform.
-template <typename T, int NC, int R, int DIR, class Acc>
+template <typename T, int NC, int R, int DIR, int VPT, class Acc>
 __device__ __forceinline__ void gstage(Acc acc, int t, int NT, int L, int Ns, const C<T>* tw, int tws, bool act) {
   using V = C<T>;
   using E = Vec<T, NC>;
-  constexpr int NB = (8 + R - 1) / R;
+  constexpr int NB = (VPT + R - 1) / R;
   const int LR = L / R;
   const int tstep = L / (Ns * R);
   V v[NB][NC][R];
@@ -75,17 +77,17 @@ __device__ __forceinline__ void gstage(Acc acc, int t, int NT, int L, int Ns, co
 
 // The whole transform of length L = prod a.grad[0 .. a.gs-1], in place in
 // LDS (natural order in and out).
-template <typename T, int NC, int DIR, class Acc>
+template <typename T, int NC, int DIR, int VPT, class Acc>
 __device__ __forceinline__ void grun(const Args& a, Acc acc, int t, int NT, int L, const C<T>* tw, int tws, bool act) {
   int Ns = 1;
   for (int s = 0; s < a.gs; ++s) {
     const int R = a.grad[s];
     switch (R) {
-      case 2: gstage<T, NC, 2, DIR>(acc, t, NT, L, Ns, tw, tws, act); break;
-      case 3: gstage<T, NC, 3, DIR>(acc, t, NT, L, Ns, tw, tws, act); break;
-      case 4: gstage<T, NC, 4, DIR>(acc, t, NT, L, Ns, tw, tws, act); break;
-      case 5: gstage<T, NC, 5, DIR>(acc, t, NT, L, Ns, tw, tws, act); break;
-      default: gstage<T, NC, 8, DIR>(acc, t, NT, L, Ns, tw, tws, act); break;
+      case 2: gstage<T, NC, 2, DIR, VPT>(acc, t, NT, L, Ns, tw, tws, act); break;
+      case 3: gstage<T, NC, 3, DIR, VPT>(acc, t, NT, L, Ns, tw, tws, act); break;
+      case 4: gstage<T, NC, 4, DIR, VPT>(acc, t, NT, L, Ns, tw, tws, act); break;
+      case 5: gstage<T, NC, 5, DIR, VPT>(acc, t, NT, L, Ns, tw, tws, act); break;
+      default: gstage<T, NC, 8, DIR, VPT>(acc, t, NT, L, Ns, tw, tws, act); break;
     }
     Ns *= R;
   }
@@ -97,7 +99,7 @@ __device__ __forceinline__ void grun(const Args& a, Acc acc, int t, int NT, int 
 // algorithm's noise generation (Hermitian arrangement + filter, gen_pair) or a
 // global load; direction DIR.  Tiles, fields and the XCD-grouped order as in
 // ColPass.
-template <typename T, int SRC, int DIR>
+template <typename T, int SRC, int DIR, int VPT>
 __global__ void __launch_bounds__(1024) k_gcol(Args a) {
   using V = C<T>;
   using E = Vec<T, 2>;
@@ -137,7 +139,7 @@ __global__ void __launch_bounds__(1024) k_gcol(Args a) {
     }
   }
   __syncthreads();
-  grun<T, 2, DIR>(a, acc, t, NT, L, (const V*)a.tw, 1, act);
+  grun<T, 2, DIR, VPT>(a, acc, t, NT, L, (const V*)a.tw, 1, act);
   if (act) {
     for (int k = t; k < L; k += NT) st_pair<T>(base + (long long)k * a.stride_ax, two, al, acc(k));
   }
@@ -151,7 +153,7 @@ __global__ void __launch_bounds__(1024) k_gcol(Args a) {
 // (x[2n], x[2n+1]).  SRC_GEN (d = 1, the rows are whole fields): the row's
 // half-spectrum is generated first (the one-FFT arrangement with the filter),
 // then transformed the same way.
-template <typename T, int SRC>
+template <typename T, int SRC, int VPT>
 __global__ void __launch_bounds__(1024) k_grow_c2r(Args a) {
   using V = C<T>;
   using E = Vec<T, 1>;
@@ -210,7 +212,7 @@ __global__ void __launch_bounds__(1024) k_grow_c2r(Args a) {
     }
   }
   __syncthreads();
-  grun<T, 1, +1>(a, acc, t, NT, M, tw2, 2, act);
+  grun<T, 1, +1, VPT>(a, acc, t, NT, M, tw2, 2, act);
   if (act) {
     for (int n = t; n < M; n += NT) o[n] = acc(n).v[0];
   }
@@ -222,7 +224,7 @@ __global__ void __launch_bounds__(1024) k_grow_c2r(Args a) {
 // forward transform, then X_k = E_k + w^{-k} D_k as in RowR2C, slot 0 =
 // (X_0, X_M).  The generated noise: Philox block (q, row, tag, 0) of field b
 // gives slots 4q .. 4q + 3 of the row.
-template <typename T, int SRC>
+template <typename T, int SRC, int VPT>
 __global__ void __launch_bounds__(1024) k_grow_r2c(Args a) {
   using V = C<T>;
   using E = Vec<T, 1>;
@@ -253,7 +255,7 @@ __global__ void __launch_bounds__(1024) k_grow_r2c(Args a) {
     }
   }
   __syncthreads();
-  grun<T, 1, -1>(a, acc, t, NT, M, tw2, 2, act);
+  grun<T, 1, -1, VPT>(a, acc, t, NT, M, tw2, 2, act);
   if (act) {
     V* o = (V*)a.data + row * M;
     for (int k = t; 2 * k <= M; k += NT) {

@@ -34,18 +34,18 @@ bool is_row(int pass) {
   return pass == PASS_ROW_C2R || pass == PASS_ROW_R2C_GEN || pass == PASS_ROW_R2C_LOAD || pass == PASS_ROW_GEN_C2R;
 }
 
-template <typename T>
+template <typename T, int VPT>
 hipError_t glaunch(int pass, const Args& a, long long nblocks, const GGeom& g, hipStream_t s) {
   const dim3 grid((unsigned)nblocks), block((unsigned)g.threads);
   const void* fn = nullptr;
   switch (pass) {
-    case PASS_COL_GEN_INV: fn = reinterpret_cast<const void*>(&k_gcol<T, SRC_GEN, +1>); break;
-    case PASS_COL_LOAD_INV: fn = reinterpret_cast<const void*>(&k_gcol<T, SRC_LOAD, +1>); break;
-    case PASS_COL_LOAD_FWD: fn = reinterpret_cast<const void*>(&k_gcol<T, SRC_LOAD, -1>); break;
-    case PASS_ROW_C2R: fn = reinterpret_cast<const void*>(&k_grow_c2r<T, SRC_LOAD>); break;
-    case PASS_ROW_GEN_C2R: fn = reinterpret_cast<const void*>(&k_grow_c2r<T, SRC_GEN>); break;
-    case PASS_ROW_R2C_GEN: fn = reinterpret_cast<const void*>(&k_grow_r2c<T, SRC_GEN>); break;
-    case PASS_ROW_R2C_LOAD: fn = reinterpret_cast<const void*>(&k_grow_r2c<T, SRC_LOAD>); break;
+    case PASS_COL_GEN_INV: fn = reinterpret_cast<const void*>(&k_gcol<T, SRC_GEN, +1, VPT>); break;
+    case PASS_COL_LOAD_INV: fn = reinterpret_cast<const void*>(&k_gcol<T, SRC_LOAD, +1, VPT>); break;
+    case PASS_COL_LOAD_FWD: fn = reinterpret_cast<const void*>(&k_gcol<T, SRC_LOAD, -1, VPT>); break;
+    case PASS_ROW_C2R: fn = reinterpret_cast<const void*>(&k_grow_c2r<T, SRC_LOAD, VPT>); break;
+    case PASS_ROW_GEN_C2R: fn = reinterpret_cast<const void*>(&k_grow_c2r<T, SRC_GEN, VPT>); break;
+    case PASS_ROW_R2C_GEN: fn = reinterpret_cast<const void*>(&k_grow_r2c<T, SRC_GEN, VPT>); break;
+    case PASS_ROW_R2C_LOAD: fn = reinterpret_cast<const void*>(&k_grow_r2c<T, SRC_LOAD, VPT>); break;
     default: return hipErrorInvalidValue;
   }
   if (g.lds > 64 * 1024) {
@@ -53,32 +53,33 @@ hipError_t glaunch(int pass, const Args& a, long long nblocks, const GGeom& g, h
     if (e != hipSuccess) return e;
   }
   switch (pass) {
-    case PASS_COL_GEN_INV: hipLaunchKernelGGL((k_gcol<T, SRC_GEN, +1>), grid, block, g.lds, s, a); break;
-    case PASS_COL_LOAD_INV: hipLaunchKernelGGL((k_gcol<T, SRC_LOAD, +1>), grid, block, g.lds, s, a); break;
-    case PASS_COL_LOAD_FWD: hipLaunchKernelGGL((k_gcol<T, SRC_LOAD, -1>), grid, block, g.lds, s, a); break;
-    case PASS_ROW_C2R: hipLaunchKernelGGL((k_grow_c2r<T, SRC_LOAD>), grid, block, g.lds, s, a); break;
-    case PASS_ROW_GEN_C2R: hipLaunchKernelGGL((k_grow_c2r<T, SRC_GEN>), grid, block, g.lds, s, a); break;
-    case PASS_ROW_R2C_GEN: hipLaunchKernelGGL((k_grow_r2c<T, SRC_GEN>), grid, block, g.lds, s, a); break;
-    default: hipLaunchKernelGGL((k_grow_r2c<T, SRC_LOAD>), grid, block, g.lds, s, a); break;
+    case PASS_COL_GEN_INV: hipLaunchKernelGGL((k_gcol<T, SRC_GEN, +1, VPT>), grid, block, g.lds, s, a); break;
+    case PASS_COL_LOAD_INV: hipLaunchKernelGGL((k_gcol<T, SRC_LOAD, +1, VPT>), grid, block, g.lds, s, a); break;
+    case PASS_COL_LOAD_FWD: hipLaunchKernelGGL((k_gcol<T, SRC_LOAD, -1, VPT>), grid, block, g.lds, s, a); break;
+    case PASS_ROW_C2R: hipLaunchKernelGGL((k_grow_c2r<T, SRC_LOAD, VPT>), grid, block, g.lds, s, a); break;
+    case PASS_ROW_GEN_C2R: hipLaunchKernelGGL((k_grow_c2r<T, SRC_GEN, VPT>), grid, block, g.lds, s, a); break;
+    case PASS_ROW_R2C_GEN: hipLaunchKernelGGL((k_grow_r2c<T, SRC_GEN, VPT>), grid, block, g.lds, s, a); break;
+    default: hipLaunchKernelGGL((k_grow_r2c<T, SRC_LOAD, VPT>), grid, block, g.lds, s, a); break;
   }
   return hipGetLastError();
 }
 
 }  // namespace
 
-// Column passes: NT = ceil(L / 8) threads per column, CP column pairs per
+// Column passes: NT = ceil(L / vpt) threads per column, CP column pairs per
 // workgroup sized so that the tile stays within 64 KB of LDS (at least one
 // pair; a longer column takes one workgroup per CU), NT * CP <= 1024, and one
-// padding slot per row when it fits.  Row passes: NT = ceil(M / 8) threads per
+// padding slot per row when it fits.  Row passes: NT = ceil(M / vpt) threads per
 // row, RB rows within 32 KB of LDS and 1024 threads, one padding element per
 // row.  Limits: columns up to GRF_GENERIC_MAX_COL, half-rows up to
 // GRF_GENERIC_MAX_ROW (the longest row takes one workgroup, 1024 threads).
-GGeom generic_geom(int pass, int dtype, int L) {
+GGeom generic_geom(int pass, int dtype, int L, int vpt) {
   GGeom g{};
+  if (vpt != 4 && vpt != 8) return g;
   const size_t cplx = dtype == 0 ? 8 : 16;
   if (is_col(pass)) {
     if (L < 2 || L > GRF_GENERIC_MAX_COL) return g;
-    g.nt = (L + 7) / 8;
+    g.nt = (L + vpt - 1) / vpt;
     const size_t pair = 2 * cplx;
     int cp = (int)std::max<size_t>(1, kLdsBudget / ((size_t)L * pair));
     cp = std::min(cp, 8);
@@ -90,7 +91,7 @@ GGeom generic_geom(int pass, int dtype, int L) {
   } else if (is_row(pass)) {
     const int M = L;
     if (M < 1 || M > GRF_GENERIC_MAX_ROW) return g;
-    g.nt = (M + 7) / 8;
+    g.nt = (M + vpt - 1) / vpt;
     g.rs = M + 1;
     int rb = (int)std::max<size_t>(1, (32 * 1024) / ((size_t)g.rs * cplx));
     rb = std::min(rb, 16);
@@ -106,9 +107,10 @@ GGeom generic_geom(int pass, int dtype, int L) {
 }
 
 hipError_t launch_generic(int pass, int dtype, const Args& a, long long nblocks, hipStream_t s) {
-  const GGeom g = generic_geom(pass, dtype, a.gl);
+  const GGeom g = generic_geom(pass, dtype, a.gl, a.gvpt);
   if (g.threads <= 0) return hipErrorInvalidValue;
-  return dtype == 0 ? glaunch<float>(pass, a, nblocks, g, s) : glaunch<double>(pass, a, nblocks, g, s);
+  if (a.gvpt == 4) return dtype == 0 ? glaunch<float, 4>(pass, a, nblocks, g, s) : glaunch<double, 4>(pass, a, nblocks, g, s);
+  return dtype == 0 ? glaunch<float, 8>(pass, a, nblocks, g, s) : glaunch<double, 8>(pass, a, nblocks, g, s);
 }
 
 }  // namespace grf

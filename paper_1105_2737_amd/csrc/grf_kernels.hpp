@@ -68,7 +68,7 @@ struct Args {
   int fpw;                    // adjoint column pass: consecutive fields per workgroup (>= 1)
   // runtime-radix passes (grf_generic.hpp): transform length, column pairs or
   // rows per workgroup, threads per transform, LDS stride, the radix list
-  int gl, gcp, gnt, grs, gs;
+  int gl, gcp, gnt, grs, gs, gvpt;
   int grad[16];
   // reflecting boundaries (cosine / sine transforms)
   const void* tq;             // (1/2) e^{i pi k / (2N)}, k < N (column) or k <= N/2 (row), of the pass's axis

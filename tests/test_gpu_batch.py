@@ -81,6 +81,6 @@ def test_tuning_keeps_results(grf, tmp_path, monkeypatch):
     assert any(" col " in l for l in lines) and any(" row " in l for l in lines)
     # a new batch reads the cache; a corrupt line is ignored
     with open(tmp_path / "tune.txt", "a") as fh:
-        fh.write("gfx950 col 512 7\ngarbage\n")
+        fh.write("gfx950 col 512 7\ngarbage\nbatch gfx942 f32 col inv 512 1\nbatch gfx950 f32 col inv 512 9\n")
     b2 = grf.Batch(fields)
     assert torch.equal(b2.sample(), ref)
