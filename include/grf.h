@@ -343,11 +343,22 @@ grf_status grf_batch_sample(grf_batch b, void* out, void* stream);
 /* The same fields, one plan-style launch pair per field (the baseline the
  * persistent launch is compared with). */
 grf_status grf_batch_sample_plain(grf_batch b, void* out, void* stream);
-/* Autotuner: times both tile shapes of each length present in the batch on
- * the batch's own work items (writing into out, which must hold the batch),
- * keeps the faster, and appends the choice to the GRF_TUNE_CACHE file if set.
- * Synchronises the stream. */
+/* Autotuner: for each column length and each row half-length present in the
+ * batch, both tile shapes, and (one-launch mode) the pipeline group size of
+ * the XCD queues, each timed on the whole batch (writing into out, which must
+ * hold the batch), keeping the fastest; appends the choices to the
+ * GRF_TUNE_CACHE file if set (lines "batch <arch> f32 col|row inv <length>
+ * <variant>" and "batch <arch> f32 group inv 1 <bytes>"; see grf_plan_tune
+ * for the cache rules).  Synchronises the stream. */
 grf_status grf_batch_tune(grf_batch b, void* out, void* stream);
+/* How the batch runs: *launches = 1 (one persistent launch: per-XCD queues of
+ * column and row items, each row item waiting for its field's column items
+ * by a readiness counter; chosen at creation when a launch reaches all 8
+ * XCDs) or 2 (a column and a row launch; GRF_BATCH_LAUNCHES=2 forces it);
+ * *wait_errors = the number of row items of the last sample whose wait gave
+ * up (0 unless the device misbehaves; their fields are then incomplete).
+ * Synchronous; either pointer may be NULL. */
+grf_status grf_batch_info(grf_batch b, int32_t* launches, int32_t* wait_errors);
 grf_status grf_batch_destroy(grf_batch b);
 
 /* Raw Philox-4x32-10 blocks: counters (device, n x 4 uint32) -> out (device,

@@ -30,7 +30,7 @@ EXPORTS = ["grf_plan_create", "grf_plan_destroy", "grf_workspace_size", "grf_sam
            "grf_debug_spectrum",
            "grf_covariance", "grf_batch_create", "grf_batch_offsets", "grf_batch_sample", "grf_batch_sample_plain",
            "grf_batch_tune", "grf_batch_destroy", "grf_last_error", "grf_version", "grf_plan_tune",
-           "grf_plan_tune_choice"]
+           "grf_plan_tune_choice", "grf_batch_info"]
 
 
 class grf_plan_desc(ctypes.Structure):
@@ -82,6 +82,7 @@ def _load():
         "grf_batch_sample_plain": (ctypes.c_int, [vp, vp, vp]),
         "grf_batch_tune": (ctypes.c_int, [vp, vp, vp]),
         "grf_batch_destroy": (ctypes.c_int, [vp]),
+        "grf_batch_info": (ctypes.c_int, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "grf_plan_tune": (ctypes.c_int, [vp, c64, vp, vp]),
         "grf_plan_tune_choice": (ctypes.c_int, [vp, i32, c64, ctypes.c_char_p, sz]),
         "grf_last_error": (ctypes.c_char_p, []),
@@ -196,6 +197,12 @@ def grf_batch_sample_plain(batch, out, stream):
 
 def grf_batch_tune(batch, out, stream):
     return check(lib.grf_batch_tune(batch, out, stream))
+
+
+def grf_batch_info(batch):
+    n, e = ctypes.c_int32(), ctypes.c_int32()
+    check(lib.grf_batch_info(batch, ctypes.byref(n), ctypes.byref(e)))
+    return n.value, e.value
 
 
 def grf_batch_destroy(batch):

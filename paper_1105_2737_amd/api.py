@@ -334,5 +334,9 @@ class Batch:
         out = self._out(out)
         L.grf_batch_tune(self.handle, _ptr(out), _stream())
 
+    def info(self):
+        """(launches per sample: 1 or 2, row items whose wait gave up in the last sample)."""
+        return L.grf_batch_info(self.handle)
+
     def field(self, out, f):
         return out[self.offsets[f]:self.offsets[f + 1]].view(self.dims[f])

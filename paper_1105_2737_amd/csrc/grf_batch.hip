@@ -92,13 +92,15 @@ __device__ __forceinline__ Args batch_args(const BatchField& f, const BatchField
 // One body per (length, tile shape), compiled as a separate function so that
 // each gets its own register allocation (inlined into one switch, the
 // allocator handles all bodies together and spills).
-template <int L, int CP>
+// TAG separates the bodies of the two kernels, so that each is compiled under
+// its own kernel's register limit.
+template <int L, int CP, int TAG = 0>
 __device__ __attribute__((noinline)) void bcol_body(const BatchField* F, int field, int sub, float* out,
                                                     const float2* tw, char* smem) {
   const Args a = batch_args(F[field], F, field, out, tw);
   BColPass<L, CP>::run(a, sub, smem);
 }
-template <int M, int RB>
+template <int M, int RB, int TAG = 0>
 __device__ __attribute__((noinline)) void brow_body(const BatchField* F, int field, int sub, float* out,
                                                     const float2* tw, char* smem) {
   const Args a = batch_args(F[field], F, field, out, tw);
@@ -167,6 +169,95 @@ k_batch_row(const BatchField* __restrict__ F, const BatchItem* __restrict__ item
   }
 }
 
+// ---------------------------------------------------------------------------
+// One persistent launch for both passes.  (length, column pairs variant 0,
+// variant 1) of the column bodies at up to 512 threads; the row bodies are
+// those of k_batch_row.
+#define GRF_BATCH_ONE_COL(X) X(64, 64, 32) X(96, 42, 21) X(128, 32, 16) X(180, 14, 7) X(256, 16, 8) \
+  X(360, 11, 5) X(500, 8, 4) X(512, 8, 4) X(1000, 4, 2) X(1024, 4, 2)
+
+#define GRF_ONE_LDS(L_, A_, B_) (BColPass<L_, A_>::LDS_BYTES > BColPass<L_, B_>::LDS_BYTES ? BColPass<L_, A_>::LDS_BYTES : BColPass<L_, B_>::LDS_BYTES),
+constexpr int one_lds_list[] = {GRF_BATCH_ONE_COL(GRF_ONE_LDS) 0};
+#undef GRF_ONE_LDS
+constexpr int ONE_COL_LDS = max_of(one_lds_list, sizeof(one_lds_list) / sizeof(int));
+constexpr int ONE_LDS = ONE_COL_LDS > ROW_LDS ? ONE_COL_LDS : ROW_LDS;
+static_assert(ONE_LDS <= 80 * 1024, "two one-launch workgroups per CU");
+#define GRF_CHECK_THREADS(L_, A_, B_) static_assert(BColPass<L_, A_>::THREADS <= BATCH_ONE_THREADS, "too many threads");
+GRF_BATCH_ONE_COL(GRF_CHECK_THREADS)
+#undef GRF_CHECK_THREADS
+
+// The XCD this workgroup runs on (hardware register XCC_ID, bits 3:0).
+__device__ __forceinline__ int xcc_id() {
+  return (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (XCD_QUEUES - 1));
+}
+
+// A workgroup takes the items of its own XCD's queue only, so that the
+// column items that write a field's spectrum and the row items that read it
+// run under one L2: a column item's stores are complete at the L2 once each
+// thread has waited for its memory counter, before the readiness count is
+// raised; a row item's first loads of that spectrum follow the wait (no CU
+// holds those lines in its L1 before, since nothing reads them earlier in the
+// launch).  Queue order (host): column items of a group of fields before the
+// row items of that group, so every column item a row item waits for has
+// been taken by a running workgroup.
+__global__ void __launch_bounds__(BATCH_ONE_THREADS, 4)
+k_batch_one(const BatchField* __restrict__ F, const BatchItem* __restrict__ items, const int* __restrict__ qoff,
+            const float2* tw, float* out, int* counters, int* done, int* err) {
+  __shared__ __align__(16) char smem[ONE_LDS];
+  __shared__ int s_item, s_skip;
+  const int q = xcc_id();
+  const int base = qoff[q], n = qoff[q + 1] - base;
+  int* counter = counters + q;
+  for (int i = next_item(counter, n, &s_item); i >= 0; i = next_item(counter, n, &s_item)) {
+    const BatchItem w = items[base + i];
+    const BatchField& f = F[w.field];
+    if (w.sub >= 0) {
+      switch (f.n1 * 4 + f.cvar) {
+#define GRF_CASE(L_, A_, B_)                                                  \
+  case L_ * 4 + 0: bcol_body<L_, A_, 1>(F, w.field, w.sub, out, tw, smem); break; \
+  case L_ * 4 + 1: bcol_body<L_, B_, 1>(F, w.field, w.sub, out, tw, smem); break;
+        GRF_BATCH_ONE_COL(GRF_CASE)
+#undef GRF_CASE
+        default: break;
+      }
+      __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this thread's stores have reached the L2
+      __syncthreads();
+      if (threadIdx.x == 0) __hip_atomic_fetch_add(done + w.field, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      if (threadIdx.x == 0) {
+        int skip = 0;
+        for (int it = 0; __hip_atomic_load(done + w.field, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < f.ntile;
+             ++it) {
+          if (it >= BATCH_ONE_SPIN_LIMIT) {
+            atomicOr(err, 1);
+            skip = 1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+        s_skip = skip;
+      }
+      __syncthreads();
+      if (!s_skip) {
+        switch (f.M * 4 + f.rvar) {
+#define GRF_CASE(M_, A_, B_)                                                         \
+  case M_ * 4 + 0: brow_body<M_, A_, 1>(F, w.field, -w.sub - 1, out, tw, smem); break; \
+  case M_ * 4 + 1: brow_body<M_, B_, 1>(F, w.field, -w.sub - 1, out, tw, smem); break;
+          GRF_BATCH_ROW(GRF_CASE)
+#undef GRF_CASE
+          default: break;
+        }
+      }
+    }
+    __syncthreads();   // the next item reuses the LDS
+  }
+}
+
+// mask |= 1 << XCD of each workgroup (the mask is cleared by a launch before).
+__global__ void k_xcc_seen(int* mask) {
+  if (threadIdx.x == 0) atomicOr(mask, 1 << xcc_id());
+}
+
 __global__ void k_reset_counters(int* c, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0;
 }
@@ -189,6 +280,15 @@ int batch_row_rb(int M, int var) {
     default: return 0;
   }
 }
+int batch_one_cp(int L, int var) {
+  switch (L) {
+#define GRF_X(L_, A_, B_) \
+  case L_: return var == 0 ? A_ : B_;
+    GRF_BATCH_ONE_COL(GRF_X)
+#undef GRF_X
+    default: return 0;
+  }
+}
 bool batch_col_supported(int L) { return batch_col_cp(L, 0) > 0; }
 bool batch_row_supported(int M) { return batch_row_rb(M, 0) > 0; }
 
@@ -204,11 +304,27 @@ hipError_t launch_batch_row(const BatchField* fields, const BatchItem* items, in
                      (const float2*)twpool, out, counter);
   return hipGetLastError();
 }
+hipError_t launch_batch_one(const BatchField* fields, const BatchItem* items, const int* qoff, const void* twpool,
+                            float* out, int* counters, int* done, int* err, int nwg, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_one, dim3(nwg), dim3(BATCH_ONE_THREADS), 0, s, fields, items, qoff,
+                     (const float2*)twpool, out, counters, done, err);
+  return hipGetLastError();
+}
+const void* k_batch_one_ptr() { return reinterpret_cast<const void*>(&k_batch_one); }
+hipError_t launch_xcc_seen(int* mask, int nwg, hipStream_t s) {
+  hipError_t e = launch_reset_counters(mask, 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_xcc_seen, dim3(nwg), dim3(64), 0, s, mask);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e;
+}
 const void* k_batch_col_ptr() { return reinterpret_cast<const void*>(&k_batch_col); }
 const void* k_batch_row_ptr() { return reinterpret_cast<const void*>(&k_batch_row); }
 
 hipError_t launch_reset_counters(int* counters, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, counters, n);
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(1024), 0, s, counters, n);
   return hipGetLastError();
 }
 

@@ -44,6 +44,14 @@ struct grf_batch_s {
   hipGraphExec_t exec = nullptr;
   void* graph_out = nullptr;           // output pointer baked into the graph
   int device = 0;
+  // one-launch mode (the default where every XCD was seen at creation):
+  // per-XCD queues of column and row items, per-field readiness counters
+  bool one = false;
+  long long group_bytes = 24ll << 20;  // fields per pipeline group of an XCD queue, in output bytes
+  BatchItem* d_one_items = nullptr;
+  int* d_one_qoff = nullptr;           // XCD_QUEUES + 1
+  int* d_one_state = nullptr;          // [queue counters XCD_QUEUES][err][pad to 16][done, one per field]
+  int nwg_one = 0;
 };
 
 namespace {
@@ -85,9 +93,105 @@ void col_queues(std::vector<std::array<long long, 3>> fl, std::vector<BatchItem>
   }
 }
 
+constexpr int ONE_STATE_DONE = 16;     // offset of the readiness counters in d_one_state
+
+// One-launch queues: fields go to the XCD queues largest first, each to the
+// least-loaded queue; an XCD's fields are cut into groups of up to
+// group_bytes of output, and its queue holds the column items of group 0,
+// then for g = 1, 2, ... the column items of group g merged with the row items
+// of group g - 1, and at the end the row items of the last group: a field's
+// row items come one group after its column items, so they rarely wait and
+// read a spectrum that is still in the caches, and every row item comes after
+// all column items of its field (each of which a running workgroup took
+// before), so every wait ends.
+grf_status build_one_queues(grf_batch_s* b) {
+  const int n = (int)b->desc.size();
+  std::vector<int> order(n);
+  for (int f = 0; f < n; ++f) order[f] = f;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return (long long)b->fields[x].n1 * b->fields[x].nd > (long long)b->fields[y].n1 * b->fields[y].nd;
+  });
+  std::vector<std::vector<int>> xf(grf::XCD_QUEUES);
+  std::vector<long long> load(grf::XCD_QUEUES, 0);
+  for (int f : order) {
+    const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    xf[x].push_back(f);
+    load[x] += (long long)b->fields[f].n1 * b->fields[f].nd;
+  }
+  std::vector<BatchItem> items;
+  std::vector<int> qoff(grf::XCD_QUEUES + 1, 0);
+  auto cols = [&](const std::vector<int>& g) {
+    std::vector<BatchItem> v;
+    for (int f : g)
+      for (int t = 0; t < b->fields[f].ntile; ++t) v.push_back({f, t});
+    return v;
+  };
+  auto rows = [&](const std::vector<int>& g) {
+    std::vector<BatchItem> v;
+    for (int f : g) {
+      const int rb = grf::batch_row_rb(b->fields[f].M, b->fields[f].rvar);
+      const int nrb = (b->fields[f].n1 + rb - 1) / rb;
+      for (int k = 0; k < nrb; ++k) v.push_back({f, -k - 1});
+    }
+    return v;
+  };
+  // the column items of one group and the row items of the group before,
+  // merged in proportion to their counts (each list keeps its order), so that
+  // at any time some workgroups generate (VALU) while others transform rows
+  // (memory)
+  auto merge = [&](const std::vector<BatchItem>& c, const std::vector<BatchItem>& r) {
+    const size_t nc = c.size(), nr = r.size();
+    size_t i = 0, j = 0;
+    while (i < nc || j < nr) {
+      if (j >= nr || (i < nc && i * nr <= j * nc)) items.push_back(c[i++]);
+      else items.push_back(r[j++]);
+    }
+  };
+  for (int x = 0; x < grf::XCD_QUEUES; ++x) {
+    std::vector<std::vector<int>> groups;
+    long long acc = 0;
+    for (int f : xf[x]) {
+      const long long bytes = (long long)b->fields[f].n1 * b->fields[f].nd * 4;
+      if (groups.empty() || (acc + bytes > b->group_bytes && acc > 0)) {
+        groups.emplace_back();
+        acc = 0;
+      }
+      groups.back().push_back(f);
+      acc += bytes;
+    }
+    for (size_t g = 0; g < groups.size(); ++g) merge(cols(groups[g]), g >= 1 ? rows(groups[g - 1]) : std::vector<BatchItem>());
+    if (!groups.empty()) merge(std::vector<BatchItem>(), rows(groups.back()));
+    qoff[x + 1] = (int)items.size();
+  }
+  if (b->d_one_items) (void)hipFree(b->d_one_items);
+  b->d_one_items = nullptr;
+  hipError_t e = hipMalloc((void**)&b->d_one_items, std::max<size_t>(1, items.size()) * sizeof(BatchItem));
+  if (e != hipSuccess) return fail(GRF_ENOMEM, "hipMalloc of work queues failed");
+  e = hipMemcpy(b->d_one_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_one_qoff, qoff.data(), qoff.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "batch upload");
+  return GRF_OK;
+}
+
 // (Re)build field records and work queues for the current variants; upload.
 grf_status build_queues(grf_batch_s* b) {
   const int n = (int)b->desc.size();
+  if (b->one) {
+    for (int f = 0; f < n; ++f) {
+      BatchField& r = b->fields[f];
+      r.cvar = b->cvar[r.n1];
+      r.rvar = b->rvar[r.M];
+      const int cp = grf::batch_one_cp(r.n1, r.cvar);
+      r.ntile = (r.M + 2 * cp - 1) / (2 * cp);
+    }
+    grf_status st = build_one_queues(b);
+    if (st != GRF_OK) return st;
+    hipError_t e =
+        hipMemcpy(b->d_fields, b->fields.data(), b->fields.size() * sizeof(BatchField), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "batch upload");
+    free_graph(b);
+    return GRF_OK;
+  }
   std::vector<WItem> row;
   std::vector<std::array<long long, 3>> cf;
   for (int f = 0; f < n; ++f) {
@@ -131,6 +235,14 @@ grf_status build_queues(grf_batch_s* b) {
 }
 
 grf_status enqueue(grf_batch_s* b, void* out, hipStream_t s) {
+  if (b->one) {
+    hipError_t e = grf::launch_reset_counters(b->d_one_state, ONE_STATE_DONE + (int)b->fields.size(), s);
+    if (e == hipSuccess)
+      e = grf::launch_batch_one(b->d_fields, b->d_one_items, b->d_one_qoff, b->d_tw, (float*)out, b->d_one_state,
+                                b->d_one_state + ONE_STATE_DONE, b->d_one_state + grf::XCD_QUEUES, b->nwg_one, s);
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
+    return GRF_OK;
+  }
   hipError_t e = grf::launch_reset_counters(b->d_counters, grf::BATCH_COUNTERS, s);
   if (e == hipSuccess)
     e = grf::launch_batch_col(b->d_fields, b->d_col, b->d_qoff, b->d_tw, (float*)out, b->d_counters, b->nwg_col, s);
@@ -152,6 +264,12 @@ void load_cache(grf_batch_s* b) {
     if (end == l.choice[0].c_str() || *end != '\0' || v < 0 || v >= grf::BATCH_VARIANTS) continue;
     if (l.pass == "col" && b->cvar.count((int)l.length)) b->cvar[(int)l.length] = (int)v;
     if (l.pass == "row" && b->rvar.count((int)l.length)) b->rvar[(int)l.length] = (int)v;
+  }
+  for (const grf::tune::Line& l : grf::tune::read("batch", grf::tune::arch_name(b->device))) {
+    if (l.dtype != "f32" || l.pass != "group" || l.dir != "inv" || l.length != 1) continue;
+    char* end = nullptr;
+    const long long v = std::strtoll(l.choice[0].c_str(), &end, 10);
+    if (end != l.choice[0].c_str() && *end == '\0' && v >= (1 << 20)) b->group_bytes = v;
   }
 }
 
@@ -231,12 +349,13 @@ grf_status grf_batch_create(const grf_field_desc* fields, int64_t nfields, grf_b
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_fields, b->fields.size() * sizeof(BatchField));
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_counters, grf::BATCH_COUNTERS * sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_qoff, (grf::XCD_QUEUES + 1) * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_one_qoff, (grf::XCD_QUEUES + 1) * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_one_state, (ONE_STATE_DONE + nfields) * sizeof(int));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
   if (e != hipSuccess) st = hip_fail(e, "batch allocation");
-  if (st == GRF_OK) st = build_queues(b);
   if (st == GRF_OK) {
     // persistent grids: every workgroup slot of the device once
-    int ncu = 0, occ_c = 0, occ_r = 0;
+    int ncu = 0, occ_c = 0, occ_r = 0, occ_o = 0;
     e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device);
     if (e == hipSuccess)
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_c, grf::k_batch_col_ptr(),
@@ -244,10 +363,26 @@ grf_status grf_batch_create(const grf_field_desc* fields, int64_t nfields, grf_b
     if (e == hipSuccess)
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_r, grf::k_batch_row_ptr(),
                                                        grf::BATCH_ROW_THREADS, 0);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_o, grf::k_batch_one_ptr(),
+                                                       grf::BATCH_ONE_THREADS, 0);
     if (e != hipSuccess) st = hip_fail(e, "occupancy query");
     b->nwg_col = std::max(1, ncu * std::max(1, occ_c));
     b->nwg_row = std::max(1, ncu * std::max(1, occ_r));
+    b->nwg_one = std::max(1, ncu * std::max(1, occ_o));
+    // The one-launch kernel takes each workgroup's queue from its XCD: use it
+    // only when a launch of that grid meets all XCD_QUEUES XCDs (else, or with
+    // GRF_BATCH_LAUNCHES=2, the column and row passes run as two launches).
+    const char* lm = std::getenv("GRF_BATCH_LAUNCHES");
+    if (st == GRF_OK && !(lm && lm[0] == '2')) {
+      int mask = 0;
+      e = grf::launch_xcc_seen(b->d_one_state, b->nwg_one, nullptr);
+      if (e == hipSuccess) e = hipMemcpy(&mask, b->d_one_state, sizeof(int), hipMemcpyDeviceToHost);
+      if (e != hipSuccess) st = hip_fail(e, "XCD probe");
+      b->one = mask == (1 << grf::XCD_QUEUES) - 1;
+    }
   }
+  if (st == GRF_OK) st = build_queues(b);
   if (st != GRF_OK) {
     grf_batch_destroy(b);
     return st;
@@ -327,12 +462,91 @@ grf_status grf_batch_sample_plain(grf_batch b, void* out, void* stream) {
   return GRF_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Tuner of the one-launch mode: coordinate descent over the tile shape of
+// each column length and of each row length and over the pipeline group size,
+// each setting timed on the whole batch (best of three after a warm-up).
+grf_status tune_one(grf_batch_s* b, void* out, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  auto time_all = [&](float* ms) -> grf_status {
+    grf_status st = build_queues(b);
+    if (st != GRF_OK) return st;
+    float best = 1e30f;
+    for (int rep = 0; rep < 4; ++rep) {
+      hipError_t e = hipEventRecord(e0, s);
+      if (e != hipSuccess) return hip_fail(e, "tuning run");
+      st = enqueue(b, out, s);
+      if (st != GRF_OK) return st;
+      e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float t = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+      if (e != hipSuccess) return hip_fail(e, "tuning run");
+      if (rep > 0) best = std::min(best, t);
+    }
+    *ms = best;
+    return GRF_OK;
+  };
+  const std::string arch = grf::tune::arch_name(b->device);
+  std::string lines;
+  for (int pass = 0; pass < 2; ++pass) {
+    auto& vm = pass == 0 ? b->cvar : b->rvar;
+    for (auto& kv : std::map<int, int>(vm)) {
+      float tv[grf::BATCH_VARIANTS];
+      for (int v = 0; v < grf::BATCH_VARIANTS; ++v) {
+        vm[kv.first] = v;
+        grf_status st = time_all(&tv[v]);
+        if (st != GRF_OK) return st;
+      }
+      int bv = 0;
+      for (int v = 1; v < grf::BATCH_VARIANTS; ++v)
+        if (tv[v] < tv[bv]) bv = v;
+      vm[kv.first] = bv;
+      char buf[128];
+      std::snprintf(buf, sizeof(buf), "batch %s f32 %s inv %d %d\n", arch.c_str(), pass == 0 ? "col" : "row",
+                    kv.first, bv);
+      lines += buf;
+    }
+  }
+  const long long groups[] = {8ll << 20, 16ll << 20, 24ll << 20, 48ll << 20, 1ll << 40};
+  float bt = 1e30f;
+  long long bg = b->group_bytes;
+  for (long long g : groups) {
+    b->group_bytes = g;
+    float t = 0.0f;
+    grf_status st = time_all(&t);
+    if (st != GRF_OK) return st;
+    if (t < bt) {
+      bt = t;
+      bg = g;
+    }
+  }
+  b->group_bytes = bg;
+  lines += "batch " + arch + " f32 group inv 1 " + std::to_string(bg) + "\n";
+  grf_status st = build_queues(b);
+  if (st != GRF_OK) return st;
+  grf::tune::append(lines);
+  return GRF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 grf_status grf_batch_tune(grf_batch b, void* out, void* stream) {
   if (b == nullptr || out == nullptr) return fail(GRF_EINVAL, "null argument");
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(GRF_EDEVICE, "event creation");
+  if (b->one) {
+    const grf_status st = tune_one(b, out, s, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+  }
   // time one pass of the batch restricted to the fields of one length, per variant
   auto time_pass = [&](bool colpass, int len, int var, float* ms) -> grf_status {
     auto& vm = colpass ? b->cvar : b->rvar;
@@ -411,6 +625,20 @@ grf_status grf_batch_tune(grf_batch b, void* out, void* stream) {
   return GRF_OK;
 }
 
+grf_status grf_batch_info(grf_batch b, int32_t* launches, int32_t* wait_errors) {
+  if (b == nullptr) return fail(GRF_EINVAL, "null argument");
+  if (launches) *launches = b->one ? 1 : 2;
+  if (wait_errors) {
+    int v = 0;
+    if (b->one) {
+      hipError_t e = hipMemcpy(&v, b->d_one_state + grf::XCD_QUEUES, sizeof(int), hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return hip_fail(e, "batch state read");
+    }
+    *wait_errors = v;
+  }
+  return GRF_OK;
+}
+
 grf_status grf_batch_destroy(grf_batch b) {
   if (b == nullptr) return GRF_OK;
   free_graph(b);
@@ -421,6 +649,9 @@ grf_status grf_batch_destroy(grf_batch b) {
   if (b->d_qoff) (void)hipFree(b->d_qoff);
   if (b->d_tw) (void)hipFree(b->d_tw);
   if (b->d_counters) (void)hipFree(b->d_counters);
+  if (b->d_one_items) (void)hipFree(b->d_one_items);
+  if (b->d_one_qoff) (void)hipFree(b->d_one_qoff);
+  if (b->d_one_state) (void)hipFree(b->d_one_state);
   delete b;
   return GRF_OK;
 }

@@ -84,3 +84,64 @@ def test_tuning_keeps_results(grf, tmp_path, monkeypatch):
         fh.write("gfx950 col 512 7\ngarbage\nbatch gfx942 f32 col inv 512 1\nbatch gfx950 f32 col inv 512 9\n")
     b2 = grf.Batch(fields)
     assert torch.equal(b2.sample(), ref)
+
+
+def test_one_launch_agrees_with_two_launches(grf, monkeypatch):
+    """The one persistent launch (per-XCD queues, readiness counters) gives the
+    same bits as the column and row passes launched one after the other, and
+    no row item's wait gave up."""
+    fields = small_batch(40, seed=9)
+    b1 = grf.Batch(fields)
+    launches, _ = b1.info()
+    print(f"launches per sample: {launches}", flush=True)
+    assert launches == 1
+    out1 = b1.sample()
+    torch.cuda.synchronize()
+    assert b1.info() == (1, 0)
+    monkeypatch.setenv("GRF_BATCH_LAUNCHES", "2")
+    b2 = grf.Batch(fields)
+    assert b2.info()[0] == 2
+    out2 = b2.sample()
+    torch.cuda.synchronize()
+    assert torch.equal(out1, out2)
+
+
+def test_one_launch_pipeline_groups_same_bits(grf, tmp_path, monkeypatch):
+    """Pipeline groups of one field each (the row items of a field queued right
+    after the next field's column items) give the same bits."""
+    fields = small_batch(24, seed=4)
+    ref = grf.Batch(fields).sample()
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"batch {arch} f32 group inv 1 1048576\n")
+    monkeypatch.setenv("GRF_TUNE_CACHE", str(cache))
+    b = grf.Batch(fields)
+    for _ in range(3):
+        out = b.sample()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+        assert b.info()[1] == 0
+
+
+def test_config4_full_batch(grf, monkeypatch):
+    """The 4096 uneven fields of the batched workload at full size: the one
+    launch equals the two-launch route bitwise, and sampled fields match the
+    float64 oracle."""
+    fields = uneven_fields(4096, seed=0)
+    b = grf.Batch(fields)
+    out = b.sample()
+    torch.cuda.synchronize()
+    assert b.info() == (1, 0)
+    rng = np.random.default_rng(5)
+    for f in sorted(int(x) for x in rng.choice(len(fields), 6, replace=False)) + [0, 4095]:
+        d = fields[f]
+        o = ogrf.sample(d["dims"], d["lengths"], spectra.MATERN, d["sigma"], d["length_scale"], d["nu"],
+                        seed=d["seed"], batch=1, alg=2)[0]
+        e = np.abs(b.field(out, f).double().cpu().numpy() - o).max() / np.abs(o).max()
+        print(f"uneven field {f} {d['dims']}: {e:.3e}", flush=True)
+        assert e <= 1e-5
+    monkeypatch.setenv("GRF_BATCH_LAUNCHES", "2")
+    b2 = grf.Batch(fields)
+    out2 = b2.sample()
+    torch.cuda.synchronize()
+    assert torch.equal(out, out2)
