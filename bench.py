@@ -212,6 +212,29 @@ def launch_table(plan, batch, torch, grf, reps):
     return [(k, c, t / reps) for (k, f, c), t in zip(info, tot)]
 
 
+def stage_ms(plan, batch, stage, torch, grf, reps):
+    """Mean duration of launch `stage` of plan.sample run `reps` times back to back
+    between two HIP events on the launch stream (after one whole sample, so
+    that it transforms the data it transforms in the sampler): the kernel's own
+    duration, as a kernel trace reports it."""
+    import ctypes
+    out = torch.empty((batch,) + plan.dims, dtype=plan.dtype, device="cuda")
+    s = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(s.cuda_stream)
+    op = ctypes.c_void_p(out.data_ptr())
+    n = grf.grf_sample_stage_count(plan.handle, batch)
+    for st in range(n):
+        grf.grf_sample_stage(plan.handle, st, 0, batch, None, op, None, 0, sp)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        grf.grf_sample_stage(plan.handle, stage, 0, batch, None, op, None, 0, sp)
+    e1.record(s)
+    torch.cuda.synchronize()
+    del out
+    return e0.elapsed_time(e1) / reps
+
+
 def by_kind(table, field_bytes):
     """Aggregate a launch table per pass kind: launches, total ms, algorithmic bytes."""
     agg = {}
@@ -332,9 +355,12 @@ def main():
     agg = by_kind(table, fbytes)
     dom = max(agg, key=lambda k: agg[k]["ms"])
     d = agg[dom]
-    kname, kms = PASS_NAMES[dom], d["ms"] / d["launches"]
+    kname, kms_seq = PASS_NAMES[dom], d["ms"] / d["launches"]
     kbytes = d["bytes"] / d["launches"]
     kpoints = d["fields"] * P / d["launches"]
+    # the dominant kernel's own duration: its first launch of the step repeated back to back
+    kstage = next(i for i, (k, c, t) in enumerate(table) if k == dom)
+    kms = stage_ms(plan, batch, kstage, torch, grf, max(args.steps, 50))
     total_bytes = 12 * P * batch                       # packed spectrum write + read, output write
 
     # the timed region: W warm-up steps, then K steps
@@ -362,7 +388,8 @@ def main():
                     "frac": round(k_hbm / HBM_PEAK_GBS, 4)}
     roofline.update({
         "traffic": None if traffic is None else round(traffic / 1e9, 4), "traffic_unit": "GB/launch",
-        "kernel": kname, "kernel_ms_per_launch": round(kms, 4), "launches_per_step": len(table),
+        "kernel": kname, "kernel_ms_per_launch": round(kms, 4),
+        "kernel_ms_per_launch_in_sequence": round(kms_seq, 4), "launches_per_step": len(table),
         "algorithmic_bytes_per_launch": int(kbytes),
         # the HBM view: the dominant kernel's algorithmic bytes per launch / its launch
         # duration, and the whole step's 12 B/point model / the timed step, vs 8 TB/s
@@ -461,7 +488,18 @@ def main():
                            length_scale=d["length_scale"], nu=d["nu"])
             f64 = p64.sample(seed=d["seed"], batch=1)[0]
             errs.append(float((bt.field(ob, f).double() - f64).abs().max() / f64.abs().max()))
+        launches, wait_errors = bt.info()
+        # the same batch as a column launch and a row launch (the route before the one-launch kernel)
+        os.environ["GRF_BATCH_LAUNCHES"] = "2"
+        bt2 = grf.Batch(fields)
+        del os.environ["GRF_BATCH_LAUNCHES"]
+        bt2.tune(out=ob)
+        sb_two = timed(lambda: bt2.sample(out=ob), args.steps, args.warmup, torch)
+        del bt2
+        bt.sample(out=ob)
         extra["batched_uneven_4096"] = {
+            "launches_per_sample": launches, "wait_errors": wait_errors,
+            "two_launch_ms": round(sb_two * 1e3, 4),
             "points": int(npts), "ms_per_step": round(sb_graph * 1e3, 4),
             "points_per_s": round(npts / sb_graph, 1), "fields_per_s": round(4096 / sb_graph, 1),
             "plain_one_field_per_launch_ms": round(sb_plain * 1e3, 4),
