@@ -713,6 +713,37 @@ struct AdjAcc {
       acc2 += c * dn;
     }
   }
+  // float32, two entries at squared frequencies pf1 and pf0 (float32, as the
+  // filter table forms them) with r = Re(xi conj G) / sqrt 2 given: h = filt_h
+  // evaluated here (its logarithm shared with d/dnu), c = h r, the sums as
+  // add2f; returns h of the first entry, h of the second in h0.
+  __device__ __forceinline__ float add2f_h(const Filt<float>& f, float pf1, float pf0, float r1, float r0,
+                                           float& h0) {
+    float dl1, dl0, dn1 = 0.0f, dn0 = 0.0f, h1;
+    if (gauss) {
+      h1 = f.c0 * __builtin_amdgcn_exp2f(f.e * pf1);
+      h0 = f.c0 * __builtin_amdgcn_exp2f(f.e * pf0);
+      dl1 = fmaf(gl1f, pf1, gl0f);
+      dl0 = fmaf(gl1f, pf0, gl0f);
+    } else {
+      const float u1 = fmaf(f.b, pf1, f.a), u0 = fmaf(f.b, pf0, f.a);
+      const float lg1 = __builtin_amdgcn_logf(u1), lg0 = __builtin_amdgcn_logf(u0);
+      h1 = f.c0 * __builtin_amdgcn_exp2f(f.e * lg1);
+      h0 = f.c0 * __builtin_amdgcn_exp2f(f.e * lg0);
+      const float iu1 = __builtin_amdgcn_rcpf(u1), iu0 = __builtin_amdgcn_rcpf(u0);
+      dl1 = fmaf(gl1f, iu1, gl0f);
+      dl0 = fmaf(gl1f, iu0, gl0f);
+      if (has_nu) {
+        dn1 = gn0f - lg1 * 0.693147180559945309f - gn1f * iu1;
+        dn0 = gn0f - lg0 * 0.693147180559945309f - gn1f * iu0;
+      }
+    }
+    const float c1 = h1 * r1, c0 = h0 * r0;
+    acc0 += (double)(c1 + c0);
+    acc1 += (double)fmaf(c1, dl1, c0 * dl0);
+    acc2 += (double)fmaf(c1, dn1, c0 * dn0);
+    return h1;
+  }
   // float32: two entries with their c = w (h/2) Re(xi conj G) already formed,
   // at squared frequencies pf1 and pf0, one float64 add per sum
   __device__ __forceinline__ void add2f(float pf1, float pf0, float c1, float c0) {
@@ -853,11 +884,16 @@ k_colg(Args a) {
     AdjAcc<T> ad(rec);
     auto add = [&](double w, double h, double p2, V xi, V G) { ad.add(w, h, p2, xi, G); };
     const T s = (T)0.70710678118654752440;
+    // float32 plans of a parametric family compute h here from the logarithm
+    // the d/dnu term needs anyway, by the float expressions the filter table is
+    // built with (the same values), instead of reading the table once per field
+    const bool fly = sizeof(T) == 4 && !__builtin_isnan((float)rec.c0);
     if (straight) {
       struct alignas(2 * sizeof(T)) P2 { T x, y; };
 #pragma unroll 2
       for (int m = 0; m < R0; ++m) {
-        const P2 hq = *reinterpret_cast<const P2*>((const T*)a.htab + (long long)rowof(t + m * NT) * (a.M + 2) + m0);
+        P2 hq;
+        if (!fly) hq = *reinterpret_cast<const P2*>((const T*)a.htab + (long long)rowof(t + m * NT) * (a.M + 2) + m0);
         T zq[4];
         normals4<T, true>((uint32_t)(m0 >> 1), (uint32_t)rowof(t + m * NT), (uint32_t)a.tag, k0, k1, zq);
         const int kk1 = t + m * NT;
@@ -867,10 +903,19 @@ k_colg(Args a) {
         const double p21 = p2b + (double)((m0 + 1) * (m0 + 1)) * il2d;
         const double p20 = p2b + (double)(m0 * m0) * il2d;
         if constexpr (sizeof(T) == 4) {
-          // both entries of the row in float32, one float64 add per row
-          const float c1 = hq.y * s * fmaf(zq[2], e.v[1].x, zq[3] * e.v[1].y);
-          const float c0 = hq.x * s * fmaf(zq[0], e.v[0].x, zq[1] * e.v[0].y);
-          ad.add2f((float)p21, (float)p20, c1, c0);
+          if (fly) {
+            const float p2bf = (float)(q1 * q1) * (float)a.il2[0] + 0.0f * (float)a.il2[1];
+            const float il2df = (float)a.il2[2];
+            const float p21f = p2bf + (float)((m0 + 1) * (m0 + 1)) * il2df;
+            const float p20f = p2bf + (float)(m0 * m0) * il2df;
+            hq.y = ad.add2f_h(f, p21f, p20f, s * fmaf(zq[2], e.v[1].x, zq[3] * e.v[1].y),
+                              s * fmaf(zq[0], e.v[0].x, zq[1] * e.v[0].y), hq.x);
+          } else {
+            // both entries of the row in float32, one float64 add per row
+            const float c1 = hq.y * s * fmaf(zq[2], e.v[1].x, zq[3] * e.v[1].y);
+            const float c0 = hq.x * s * fmaf(zq[0], e.v[0].x, zq[1] * e.v[0].y);
+            ad.add2f((float)p21, (float)p20, c1, c0);
+          }
         } else {
           add(2.0, (double)hq.y, p21, mk<T>(s * zq[2], s * zq[3]), e.v[1]);
           add(2.0, (double)hq.x, p20, mk<T>(s * zq[0], s * zq[1]), e.v[0]);
