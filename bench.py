@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--profile-batch", type=int, default=1024)
     ap.add_argument("--profile-boundary", type=str, default="periodic",
                     help="boundary for --profile-stage: periodic | neumann | dirichlet")
+    ap.add_argument("--profile-draw-order", type=str, default="counter",
+                    help="draw order for --profile-stage: counter | recursive")
     ap.add_argument("--profile-adjoint", action="store_true",
                     help="profiling mode: the adjoint of the 1024^2 x 64 training step (dL/dphi = 2 w phi), "
                          "--steps times")
@@ -129,7 +131,8 @@ def profile_mode(args):
     dims = tuple(int(x) for x in args.profile_dims.split(","))
     cov = "exponential" if len(dims) == 3 else "matern"
     plan = grf.Plan(dims, alg=args.profile_alg, dtype=torch.float32, cov=cov, sigma=1.0,
-                    length_scale=0.05 if len(dims) == 3 else 0.1, nu=1.5, boundary=args.profile_boundary)
+                    length_scale=0.05 if len(dims) == 3 else 0.1, nu=1.5, boundary=args.profile_boundary,
+                    draw_order=args.profile_draw_order)
     batch = args.profile_batch
     out = torch.empty((batch,) + dims, dtype=torch.float32, device="cuda")
     stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -141,7 +144,7 @@ def profile_mode(args):
                                  None, 0, stream)
     torch.cuda.synchronize()
     print(f"profiled stage {args.profile_stage} of alg {args.profile_alg} on {dims} x {batch}, "
-          f"{args.profile_boundary} boundary", flush=True)
+          f"{args.profile_boundary} boundary, {args.profile_draw_order} draw order", flush=True)
 
 
 def timed(fn, steps, warmup, torch):

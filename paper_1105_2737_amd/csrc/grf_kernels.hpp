@@ -295,6 +295,21 @@ __device__ __forceinline__ C<T> seq_entry(const Args& a, const T* zsrc, int b, u
   return mk<T>(g * x, d.kind == 1 ? -(g * y) : g * y);
 }
 
+// The value of another lane of the same 16-lane DPP row: row_shr:1 (0x111)
+// reads lane i - 1, row_shl:k (0x100 + k) lane i + k; a source outside the
+// row gives 0.  Every lane of the row must be active.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const long long w = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)w, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(w >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // SEQ: the normals in the draw order of the recursive algorithm (its own
 // kernel instantiation, so that the default route keeps its registers).
 // UK: the key is uniform over the wave (false where a workgroup's rows belong
@@ -502,6 +517,107 @@ struct ColPass {
     }
   }
 
+  // The recursive algorithm's draw order for generated noise and M even,
+  // bulk entries 1 <= m < M.  Entry m of row R (= k_1 O + o) takes draw pair
+  // p = R (M - 1) + m - 1 of the field's sequence: half (p mod M) & 1 of the
+  // Philox block ((p mod M) >> 1, p / M) (seq_pair).  A lane holds the
+  // entries m0, m0 + 1, pairs p_b - 1 and p_b = R (M - 1) + m0, and
+  // evaluates the block of p_b.  With M even, p_b odd means both pairs lie in
+  // that block (lower, upper half); p_b even means p_b is its lower half and
+  // p_b - 1 the upper half of the block before, which is the block of the
+  // lane to the left (same row, entries m0 - 2, m0 - 1), read across lanes;
+  // for the row's first lane the CP lanes of the row evaluate those blocks in
+  // turn.  A lane so evaluates R0 + ceil(R0 / CP) blocks instead of 2 R0.
+  // The values and float operations are those of seq_entry.  Lanes of the
+  // first tile's m0 = 0 take the general route afterwards (packed plane slot).
+  __device__ __forceinline__ static void gen_seq_fast(const Args& a, int fx, int b, int t, int cp, int m0, bool act,
+                                                      V (&x)[2][EN::REG]) {
+    static_assert(16 % CP == 0, "the CP lanes of a row must lie in one DPP row");
+    const unsigned long long key = a.seed + (unsigned long long)b;
+    const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
+    const uint32_t M = (uint32_t)a.M, tag = (uint32_t)a.tag;
+    const T s = (T)0.70710678118654752440;
+    const T* ht = (const T*)a.htab;
+    // the table loads of all rows first
+    struct alignas(2 * sizeof(T)) P2 { T x, y; };
+    P2 hp[R0] = {};
+    if (ht && act) {
+#pragma unroll
+      for (int m = 0; m < R0; ++m)
+        hp[m] = *reinterpret_cast<const P2*>(ht + (long long)((t + m * NT) * a.no + fx) * (a.M + 2) + m0);
+    }
+    // p_b of row m = p_b of row 0 + m D, D = NT O (M - 1)
+    const uint32_t pb_0 = (uint32_t)(t * a.no + fx) * (M - 1) + (uint32_t)m0;
+    const uint32_t D = (uint32_t)(NT * a.no) * (M - 1);
+    // the row's first lane: upper halves of the blocks of its pairs p_b - 1
+    // (straight-line code throughout: the Philox blocks of all rows are
+    // independent and interleave only within one basic block)
+    constexpr int NX = (R0 + CP - 1) / CP;
+    T ex[NX][2];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+      const int m = k * CP + cp < R0 ? k * CP + cp : R0 - 1;
+      const uint32_t p = pb_0 + (uint32_t)m * D - (uint32_t)(2 * cp) - 1u;   // unused where it wraps (plane lanes)
+      const uint32_t q = p / M, r = p - q * M;
+      const uint4 w = philox4x32_10<true>(make_uint4(r >> 1, q, tag, 0u), k0, k1);
+      box_muller(w.z, w.w, ex[k][0], ex[k][1]);
+    }
+    uint32_t q = pb_0 / M, r = pb_0 - q * M;
+    const uint32_t dq = D / M, dr = D - dq * M;
+    const Filt<T> f = load_filt<T>(a.recs[b * a.rec_stride], a.scale);
+    const int qo = wrapk(fx, a.no);
+    const T p2o = (T)(qo * qo) * (T)a.il2[1], il2d = (T)a.il2[2];
+    auto rows = [&](auto table) {
+      constexpr bool TABLE = decltype(table)::value;
+      static_for<R0>([&](auto mc) {
+        constexpr int m = decltype(mc)::value;
+        if constexpr (m > 0) {
+          r += dr;
+          q += dq;
+          const bool c = r >= M;
+          r = c ? r - M : r;
+          q += c ? 1u : 0u;
+        }
+        const uint4 w = philox4x32_10<true>(make_uint4(r >> 1, q, tag, 0u), k0, k1);
+        T z[4];
+        box_muller(w.x, w.y, z[0], z[1]);
+        box_muller(w.z, w.w, z[2], z[3]);
+        const T u0 = dpp_mov<0x111>(z[2]), u1 = dpp_mov<0x111>(z[3]);   // left lane's upper half
+        T f0, f1;                                                         // lane m % CP's extra block
+        if constexpr (m % CP == 0) {
+          f0 = ex[m / CP][0];
+          f1 = ex[m / CP][1];
+        } else {
+          f0 = dpp_mov<0x100 + m % CP>(ex[m / CP][0]);
+          f1 = dpp_mov<0x100 + m % CP>(ex[m / CP][1]);
+        }
+        // normals of entries m0 and m0 + 1 (p_b and r have one parity, M being even)
+        const bool al = (r & 1) != 0;
+        const T a0 = al ? z[0] : (cp == 0 ? f0 : u0);
+        const T a1 = al ? z[1] : (cp == 0 ? f1 : u1);
+        const T b0 = al ? z[2] : z[0];
+        const T b1 = al ? z[3] : z[1];
+        T h0, h1;
+        if constexpr (TABLE) {
+          h0 = hp[m].x;
+          h1 = hp[m].y;
+        } else {
+          const int q1 = wrapk(t + m * NT, a.n1);
+          const T p2b = (T)(q1 * q1) * (T)a.il2[0] + p2o;
+          h0 = filt_h(f, p2b + (T)(m0 * m0) * il2d);
+          h1 = filt_h(f, p2b + (T)((m0 + 1) * (m0 + 1)) * il2d);
+        }
+        const T g0 = h0 * s, g1 = h1 * s;
+        x[0][m] = mk<T>(g0 * a0, g0 * a1);
+        x[1][m] = mk<T>(g1 * b0, g1 * b1);
+      });
+    };
+    if (ht)
+      rows(std::true_type{});
+    else
+      rows(std::false_type{});
+  }
+
   // Workgroup `bid` of the pass; smem holds LDS_BYTES (16-byte aligned).
   __device__ __forceinline__ static void run(const Args& a, int bid, char* smem) {
     E* sm = reinterpret_cast<E*>(smem);
@@ -532,6 +648,24 @@ struct ColPass {
       }
     }
     for (int i = tid; i < L; i += blockDim.x) tw[i] = ((const V*)a.tw)[i];
+    if constexpr (SRC == SRC_SEQ) {
+      if (a.src == nullptr && (a.M & 1) == 0) {
+        gen_seq_fast(a, fx, b, t, cp, m0, act, x);
+        if (act && tile == 0 && m0 == 0) {
+          const Filt<T> f = load_filt<T>(a.recs[b * a.rec_stride], a.scale);
+          const unsigned long long key = a.seed + (unsigned long long)b;
+          static_for<R0>([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            gen_pair<T, true>(a, f, nullptr, b, (uint32_t)key, (uint32_t)(key >> 32), t + m * NT, fx, 0, x[0][m],
+                              x[1][m]);
+          });
+        }
+        auto lds = [&](int i) -> E& { return sm[i * RS + cp]; };
+        auto out = [&](int i, const E& e) { st_pair<T>(base + (long long)i * a.stride_ax, two, al, e); };
+        EN::template run<DIR>(x, t, act, lds, tw, out);
+        return;
+      }
+    }
     if (act) {
       if constexpr (SRC == SRC_GEN || SRC == SRC_SEQ) {
         const FieldRec& rec = a.recs[b * a.rec_stride];

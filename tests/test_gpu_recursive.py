@@ -44,6 +44,20 @@ def test_against_literal_recursion(grf, dtype, dims, lengths):
         assert relerr(phi[b], ref[b]) <= TOL[dtype], (dims, dtype, b, relerr(phi[b], ref[b]))
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["f32", "f64"])
+@pytest.mark.parametrize("dims", [(96, 128), (64, 1000), (16, 24, 32)], ids=str)
+def test_per_field_theta(grf, dtype, dims):
+    """Per-field (sigma, ell, nu): the generating pass evaluates h per entry
+    instead of reading the plan's table; field b uses key seed + b."""
+    lengths = (1.0,) * len(dims)
+    plan = grf.Plan(dims, lengths=lengths, dtype=dtype, cov="matern", draw_order="recursive")
+    theta = np.array([[1.3, 0.15, 0.7], [0.8, 0.08, 2.2], [1.0, 0.3, 1.5]])
+    phi = plan.sample(seed=7, batch=3, theta=torch.tensor(theta, device="cuda")).double().cpu().numpy()
+    for b, (sg, ell, nu) in enumerate(theta):
+        ref = recursive.sample(dims, lengths, spectra.MATERN, sg, ell, nu, seed=7 + b, batch=1)[0]
+        assert relerr(phi[b], ref) <= TOL[dtype], (dims, dtype, b, relerr(phi[b], ref))
+
+
 @pytest.mark.parametrize("dims", [(512, 512), (64, 64, 64)], ids=str)
 def test_full_size(grf, dims):
     plan = grf.Plan(dims, cov="exponential", sigma=1.0, length_scale=0.05, draw_order="recursive")
