@@ -13,6 +13,8 @@
 #include "grf_configs.hpp"
 #include "grf_kernels.hpp"
 
+#include <type_traits>
+
 namespace grf {
 
 // (length, column pairs variant 0, variant 1)
@@ -22,10 +24,51 @@ namespace grf {
 #define GRF_BATCH_ROW(X) X(32, 128, 64) X(48, 64, 32) X(64, 64, 32) X(96, 42, 21) X(128, 64, 32) \
   X(180, 14, 7) X(256, 16, 8) X(360, 11, 5) X(500, 10, 5) X(512, 8, 4)
 
-template <int L, int CP>
-using BColPass = ColPass<float, L, typename ColCfg<L>::Rad, CP, ColCfg<L>::PAD, SRC_GEN, +1>;
-template <int M, int RB>
-using BRowPass = RowC2RStaged<float, M, typename RowCfg<M>::Rad, RB, 0>;
+// Another radix order, i.e. another number of threads per transform (L / R_0),
+// per length: variants 2 and 3 of the one-launch kernel's bodies (tile shapes
+// CPA / RBA and CPB / RBB), variants 0 and 1 being the plan path's radix
+// order with two tile shapes.  A field's bits depend on its radix order, not
+// on its tile shape.
+template <int L> struct BatchAltCol;
+#define GRF_ALTCOL(L_, CPA_, CPB_, ...)                   \
+  template <> struct BatchAltCol<L_> {                    \
+    using Rad = Radices<__VA_ARGS__>;                     \
+    static constexpr int CPA = CPA_, CPB = CPB_;          \
+  };
+GRF_ALTCOL(64, 32, 16, 4, 4, 4)
+GRF_ALTCOL(96, 21, 10, 4, 8, 3)
+GRF_ALTCOL(128, 16, 8, 4, 8, 4)
+GRF_ALTCOL(180, 16, 8, 6, 6, 5)
+GRF_ALTCOL(256, 8, 4, 4, 8, 8)
+GRF_ALTCOL(360, 8, 4, 6, 6, 10)
+GRF_ALTCOL(500, 4, 2, 5, 10, 10)
+GRF_ALTCOL(512, 4, 2, 4, 8, 4, 4)
+GRF_ALTCOL(1000, 4, 2, 8, 5, 5, 5)
+GRF_ALTCOL(1024, 2, 1, 4, 4, 8, 8)
+#undef GRF_ALTCOL
+template <int M> struct BatchAltRow;
+#define GRF_ALTROW(M_, RBA_, RBB_, ...)                   \
+  template <> struct BatchAltRow<M_> {                    \
+    using Rad = Radices<__VA_ARGS__>;                     \
+    static constexpr int RBA = RBA_, RBB = RBB_;          \
+  };
+GRF_ALTROW(32, 64, 32, 4, 8)
+GRF_ALTROW(48, 64, 32, 8, 6)
+GRF_ALTROW(64, 32, 16, 4, 4, 4)
+GRF_ALTROW(96, 21, 10, 4, 4, 6)
+GRF_ALTROW(128, 32, 16, 8, 4, 4)
+GRF_ALTROW(180, 16, 8, 6, 6, 5)
+GRF_ALTROW(256, 32, 16, 16, 16)
+GRF_ALTROW(360, 12, 6, 9, 5, 8)
+GRF_ALTROW(500, 5, 2, 5, 10, 10)
+GRF_ALTROW(512, 16, 8, 16, 8, 4)
+#undef GRF_ALTROW
+
+template <int L, int CP, bool ALT = false>
+using BColPass = ColPass<float, L, typename std::conditional<ALT, BatchAltCol<L>, ColCfg<L>>::type::Rad, CP,
+                         ColCfg<L>::PAD, SRC_GEN, +1>;
+template <int M, int RB, bool ALT = false>
+using BRowPass = RowC2RStaged<float, M, typename std::conditional<ALT, BatchAltRow<M>, RowCfg<M>>::type::Rad, RB, 0>;
 
 // LDS of the largest body
 #define GRF_COL_LDS(L_, A_, B_) (BColPass<L_, A_>::LDS_BYTES > BColPass<L_, B_>::LDS_BYTES ? BColPass<L_, A_>::LDS_BYTES : BColPass<L_, B_>::LDS_BYTES),
@@ -94,17 +137,17 @@ __device__ __forceinline__ Args batch_args(const BatchField& f, const BatchField
 // allocator handles all bodies together and spills).
 // TAG separates the bodies of the two kernels, so that each is compiled under
 // its own kernel's register limit.
-template <int L, int CP, int TAG = 0>
+template <int L, int CP, int TAG = 0, bool ALT = false>
 __device__ __attribute__((noinline)) void bcol_body(const BatchField* F, int field, int sub, float* out,
                                                     const float2* tw, char* smem) {
   const Args a = batch_args(F[field], F, field, out, tw);
-  BColPass<L, CP>::run(a, sub, smem);
+  BColPass<L, CP, ALT>::run(a, sub, smem);
 }
-template <int M, int RB, int TAG = 0>
+template <int M, int RB, int TAG = 0, bool ALT = false>
 __device__ __attribute__((noinline)) void brow_body(const BatchField* F, int field, int sub, float* out,
                                                     const float2* tw, char* smem) {
   const Args a = batch_args(F[field], F, field, out, tw);
-  BRowPass<M, RB>::run(a, sub, smem);
+  BRowPass<M, RB, ALT>::run(a, sub, smem);
 }
 
 // Next work item of the workgroup (uniform); -1 when the queue is drained.
@@ -176,14 +219,31 @@ k_batch_row(const BatchField* __restrict__ F, const BatchItem* __restrict__ item
 #define GRF_BATCH_ONE_COL(X) X(64, 64, 32) X(96, 42, 21) X(128, 32, 16) X(180, 14, 7) X(256, 16, 8) \
   X(360, 11, 5) X(500, 8, 4) X(512, 8, 4) X(1000, 4, 2) X(1024, 4, 2)
 
-#define GRF_ONE_LDS(L_, A_, B_) (BColPass<L_, A_>::LDS_BYTES > BColPass<L_, B_>::LDS_BYTES ? BColPass<L_, A_>::LDS_BYTES : BColPass<L_, B_>::LDS_BYTES),
+#define GRF_ONE_LDS(L_, A_, B_)                                                                          \
+  max_of((const int[]){BColPass<L_, A_>::LDS_BYTES, BColPass<L_, B_>::LDS_BYTES,                          \
+                       BColPass<L_, BatchAltCol<L_>::CPA, true>::LDS_BYTES,                               \
+                       BColPass<L_, BatchAltCol<L_>::CPB, true>::LDS_BYTES}, 4),
 constexpr int one_lds_list[] = {GRF_BATCH_ONE_COL(GRF_ONE_LDS) 0};
 #undef GRF_ONE_LDS
+#define GRF_ALT_ROW_LDS(M_, A_, B_)                                                                      \
+  max_of((const int[]){BRowPass<M_, BatchAltRow<M_>::RBA, true>::LDS_BYTES,                               \
+                       BRowPass<M_, BatchAltRow<M_>::RBB, true>::LDS_BYTES}, 2),
+constexpr int alt_row_lds_list[] = {GRF_BATCH_ROW(GRF_ALT_ROW_LDS) 0};
+#undef GRF_ALT_ROW_LDS
 constexpr int ONE_COL_LDS = max_of(one_lds_list, sizeof(one_lds_list) / sizeof(int));
-constexpr int ONE_LDS = ONE_COL_LDS > ROW_LDS ? ONE_COL_LDS : ROW_LDS;
+constexpr int ONE_ROW_LDS = max_of(alt_row_lds_list, sizeof(alt_row_lds_list) / sizeof(int)) > ROW_LDS
+                                ? max_of(alt_row_lds_list, sizeof(alt_row_lds_list) / sizeof(int))
+                                : ROW_LDS;
+constexpr int ONE_LDS = ONE_COL_LDS > ONE_ROW_LDS ? ONE_COL_LDS : ONE_ROW_LDS;
 static_assert(ONE_LDS <= 80 * 1024, "two one-launch workgroups per CU");
-#define GRF_CHECK_THREADS(L_, A_, B_) static_assert(BColPass<L_, A_>::THREADS <= BATCH_ONE_THREADS, "too many threads");
+#define GRF_CHECK_THREADS(L_, A_, B_)                                                                   \
+  static_assert(BColPass<L_, A_>::THREADS <= BATCH_ONE_THREADS, "too many threads");                    \
+  static_assert(BColPass<L_, BatchAltCol<L_>::CPA, true>::THREADS <= BATCH_ONE_THREADS, "too many threads");
 GRF_BATCH_ONE_COL(GRF_CHECK_THREADS)
+#undef GRF_CHECK_THREADS
+#define GRF_CHECK_THREADS(M_, A_, B_) \
+  static_assert(BRowPass<M_, BatchAltRow<M_>::RBA, true>::THREADS <= BATCH_ONE_THREADS, "too many threads");
+GRF_BATCH_ROW(GRF_CHECK_THREADS)
 #undef GRF_CHECK_THREADS
 
 // The XCD this workgroup runs on (hardware register XCC_ID, bits 3:0).
@@ -213,9 +273,11 @@ k_batch_one(const BatchField* __restrict__ F, const BatchItem* __restrict__ item
     const BatchField& f = F[w.field];
     if (w.sub >= 0) {
       switch (f.n1 * 4 + f.cvar) {
-#define GRF_CASE(L_, A_, B_)                                                  \
-  case L_ * 4 + 0: bcol_body<L_, A_, 1>(F, w.field, w.sub, out, tw, smem); break; \
-  case L_ * 4 + 1: bcol_body<L_, B_, 1>(F, w.field, w.sub, out, tw, smem); break;
+#define GRF_CASE(L_, A_, B_)                                                                                 \
+  case L_ * 4 + 0: bcol_body<L_, A_, 1>(F, w.field, w.sub, out, tw, smem); break;                              \
+  case L_ * 4 + 1: bcol_body<L_, B_, 1>(F, w.field, w.sub, out, tw, smem); break;                              \
+  case L_ * 4 + 2: bcol_body<L_, BatchAltCol<L_>::CPA, 1, true>(F, w.field, w.sub, out, tw, smem); break;       \
+  case L_ * 4 + 3: bcol_body<L_, BatchAltCol<L_>::CPB, 1, true>(F, w.field, w.sub, out, tw, smem); break;
         GRF_BATCH_ONE_COL(GRF_CASE)
 #undef GRF_CASE
         default: break;
@@ -240,9 +302,11 @@ k_batch_one(const BatchField* __restrict__ F, const BatchItem* __restrict__ item
       __syncthreads();
       if (!s_skip) {
         switch (f.M * 4 + f.rvar) {
-#define GRF_CASE(M_, A_, B_)                                                         \
-  case M_ * 4 + 0: brow_body<M_, A_, 1>(F, w.field, -w.sub - 1, out, tw, smem); break; \
-  case M_ * 4 + 1: brow_body<M_, B_, 1>(F, w.field, -w.sub - 1, out, tw, smem); break;
+#define GRF_CASE(M_, A_, B_)                                                                                   \
+  case M_ * 4 + 0: brow_body<M_, A_, 1>(F, w.field, -w.sub - 1, out, tw, smem); break;                           \
+  case M_ * 4 + 1: brow_body<M_, B_, 1>(F, w.field, -w.sub - 1, out, tw, smem); break;                           \
+  case M_ * 4 + 2: brow_body<M_, BatchAltRow<M_>::RBA, 1, true>(F, w.field, -w.sub - 1, out, tw, smem); break;    \
+  case M_ * 4 + 3: brow_body<M_, BatchAltRow<M_>::RBB, 1, true>(F, w.field, -w.sub - 1, out, tw, smem); break;
           GRF_BATCH_ROW(GRF_CASE)
 #undef GRF_CASE
           default: break;
@@ -274,7 +338,7 @@ int batch_col_cp(int L, int var) {
 int batch_row_rb(int M, int var) {
   switch (M) {
 #define GRF_X(M_, A_, B_) \
-  case M_: return var == 0 ? A_ : B_;
+  case M_: return var == 0 ? A_ : var == 1 ? B_ : var == 2 ? BatchAltRow<M_>::RBA : BatchAltRow<M_>::RBB;
     GRF_BATCH_ROW(GRF_X)
 #undef GRF_X
     default: return 0;
@@ -283,7 +347,7 @@ int batch_row_rb(int M, int var) {
 int batch_one_cp(int L, int var) {
   switch (L) {
 #define GRF_X(L_, A_, B_) \
-  case L_: return var == 0 ? A_ : B_;
+  case L_: return var == 0 ? A_ : var == 1 ? B_ : var == 2 ? BatchAltCol<L_>::CPA : BatchAltCol<L_>::CPB;
     GRF_BATCH_ONE_COL(GRF_X)
 #undef GRF_X
     default: return 0;

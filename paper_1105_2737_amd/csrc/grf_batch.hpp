@@ -31,7 +31,10 @@ struct BatchItem {
 
 constexpr int BATCH_COL_THREADS = 256;
 constexpr int BATCH_ROW_THREADS = 512;
-constexpr int BATCH_VARIANTS = 2;
+constexpr int BATCH_VARIANTS = 2;       // tile shapes of the two-launch kernels' bodies
+// the one-launch kernel's bodies: variants 0, 1 as BATCH_VARIANTS; 2, 3 another
+// radix order (threads per transform) with two tile shapes
+constexpr int BATCH_ONE_VARIANTS = 4;
 constexpr int XCD_QUEUES = 8;         // column work queues, one per XCD
 constexpr int BATCH_COUNTERS = XCD_QUEUES + 1;   // column queues, then the row queue
 
@@ -43,7 +46,9 @@ constexpr int BATCH_COUNTERS = XCD_QUEUES + 1;   // column queues, then the row 
 constexpr int BATCH_ONE_THREADS = 512;
 constexpr int BATCH_ONE_SPIN_LIMIT = 1 << 22;
 
-// Geometry of a variant: column pairs per column workgroup / rows per row workgroup.
+// Geometry of a variant: column pairs per column workgroup / rows per row
+// workgroup (var < BATCH_VARIANTS; batch_row_rb and batch_one_cp also take
+// the one-launch kernel's variants < BATCH_ONE_VARIANTS).
 int batch_col_cp(int L, int var);
 int batch_one_cp(int L, int var);   // column pairs per workgroup in the one-launch kernel
 int batch_row_rb(int M, int var);

@@ -196,8 +196,10 @@ grf_status build_queues(grf_batch_s* b) {
   std::vector<std::array<long long, 3>> cf;
   for (int f = 0; f < n; ++f) {
     BatchField& r = b->fields[f];
-    r.cvar = b->cvar[r.n1];
-    r.rvar = b->rvar[r.M];
+    // the two kernels have the plan path's radix order only: the tile shape of
+    // a one-launch variant
+    r.cvar = b->cvar[r.n1] % grf::BATCH_VARIANTS;
+    r.rvar = b->rvar[r.M] % grf::BATCH_VARIANTS;
     const int cp = grf::batch_col_cp(r.n1, r.cvar);
     const int rb = grf::batch_row_rb(r.M, r.rvar);
     r.ntile = (r.M + 2 * cp - 1) / (2 * cp);
@@ -261,7 +263,7 @@ void load_cache(grf_batch_s* b) {
     if (l.dtype != "f32" || l.dir != "inv") continue;
     char* end = nullptr;
     const long v = std::strtol(l.choice[0].c_str(), &end, 10);
-    if (end == l.choice[0].c_str() || *end != '\0' || v < 0 || v >= grf::BATCH_VARIANTS) continue;
+    if (end == l.choice[0].c_str() || *end != '\0' || v < 0 || v >= grf::BATCH_ONE_VARIANTS) continue;
     if (l.pass == "col" && b->cvar.count((int)l.length)) b->cvar[(int)l.length] = (int)v;
     if (l.pass == "row" && b->rvar.count((int)l.length)) b->rvar[(int)l.length] = (int)v;
   }
@@ -466,9 +468,10 @@ grf_status grf_batch_sample_plain(grf_batch b, void* out, void* stream) {
 
 namespace {
 
-// Tuner of the one-launch mode: coordinate descent over the tile shape of
-// each column length and of each row length and over the pipeline group size,
-// each setting timed on the whole batch (best of three after a warm-up).
+// Tuner of the one-launch mode: coordinate descent over the variant (radix
+// order, i.e. threads per transform, and tile shape) of each column length
+// and of each row length and over the pipeline group size, each setting timed
+// on the whole batch (best of three after a warm-up).
 grf_status tune_one(grf_batch_s* b, void* out, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   auto time_all = [&](float* ms) -> grf_status {
     grf_status st = build_queues(b);
@@ -494,14 +497,14 @@ grf_status tune_one(grf_batch_s* b, void* out, hipStream_t s, hipEvent_t e0, hip
   for (int pass = 0; pass < 2; ++pass) {
     auto& vm = pass == 0 ? b->cvar : b->rvar;
     for (auto& kv : std::map<int, int>(vm)) {
-      float tv[grf::BATCH_VARIANTS];
-      for (int v = 0; v < grf::BATCH_VARIANTS; ++v) {
+      float tv[grf::BATCH_ONE_VARIANTS];
+      for (int v = 0; v < grf::BATCH_ONE_VARIANTS; ++v) {
         vm[kv.first] = v;
         grf_status st = time_all(&tv[v]);
         if (st != GRF_OK) return st;
       }
       int bv = 0;
-      for (int v = 1; v < grf::BATCH_VARIANTS; ++v)
+      for (int v = 1; v < grf::BATCH_ONE_VARIANTS; ++v)
         if (tv[v] < tv[bv]) bv = v;
       vm[kv.first] = bv;
       char buf[128];

@@ -1,7 +1,8 @@
 """GPU tests of the batched uneven-size launch: each field equals the same
 field sampled by its own plan (bitwise), the float64 oracle (float32
 tolerance), the one-field-per-launch baseline (bitwise); graph replays agree
-with each other; the autotuner keeps results unchanged."""
+with each other; tile shapes keep the bits, other radix orders keep the
+oracle tolerance."""
 import numpy as np
 import pytest
 
@@ -68,7 +69,25 @@ def test_graph_replays_agree(grf):
         assert torch.equal(out, first), k
 
 
-def test_tuning_keeps_results(grf, tmp_path, monkeypatch):
+def chosen_variants(path):
+    """(column variant per N_1, row variant per N_2 / 2) from a tuner cache."""
+    col, row = {}, {}
+    for line in path.read_text().split("\n"):
+        w = line.split()
+        if len(w) == 7 and w[0] == "batch" and w[3] in ("col", "row"):
+            (col if w[3] == "col" else row)[int(w[5])] = int(w[6])
+    return col, row
+
+
+def relerr(a, b):
+    return float((a.double() - b.double()).abs().max() / b.double().abs().max())
+
+
+def test_tuning(grf, tmp_path, monkeypatch):
+    """The tuner's choices: a field whose lengths keep the plan path's radix
+    order (variants 0, 1: tile shapes only) keeps its bits; another radix
+    order (variants 2, 3) changes the rounding only (float32 tolerance).  A new
+    batch reads the cache; corrupt and foreign lines are ignored."""
     monkeypatch.setenv("GRF_TUNE_CACHE", str(tmp_path / "tune.txt"))
     fields = small_batch(12, seed=7)
     b = grf.Batch(fields)
@@ -76,14 +95,47 @@ def test_tuning_keeps_results(grf, tmp_path, monkeypatch):
     b.tune()
     got = b.sample()
     torch.cuda.synchronize()
-    assert torch.equal(got, ref)
-    lines = (tmp_path / "tune.txt").read_text().split("\n")
-    assert any(" col " in l for l in lines) and any(" row " in l for l in lines)
-    # a new batch reads the cache; a corrupt line is ignored
+    col, row = chosen_variants(tmp_path / "tune.txt")
+    print("tuned variants:", col, row, flush=True)
+    assert col and row
+    for f, d in enumerate(fields):
+        n1, m = d["dims"][0], d["dims"][1] // 2
+        if col[n1] < 2 and row[m] < 2:
+            assert torch.equal(b.field(got, f), b.field(ref, f)), f
+        else:
+            assert relerr(b.field(got, f), b.field(ref, f)) <= 1e-5, f
     with open(tmp_path / "tune.txt", "a") as fh:
         fh.write("gfx950 col 512 7\ngarbage\nbatch gfx942 f32 col inv 512 1\nbatch gfx950 f32 col inv 512 9\n")
     b2 = grf.Batch(fields)
-    assert torch.equal(b2.sample(), ref)
+    assert torch.equal(b2.sample(), got)
+
+
+@pytest.mark.parametrize("var", [1, 2, 3])
+def test_variants_against_oracle(grf, tmp_path, monkeypatch, var):
+    """Every column and row length on variant `var` (2, 3: the other radix
+    order, another number of threads per transform): the fields match the
+    float64 oracle; tile shapes alone (1) keep the bits of variant 0."""
+    fields = small_batch(24, seed=11)
+    ref = grf.Batch(fields).sample()
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    cols = sorted({d["dims"][0] for d in fields})
+    rows = sorted({d["dims"][1] // 2 for d in fields})
+    cache = tmp_path / "tune.txt"
+    cache.write_text("".join(f"batch {arch} f32 col inv {n} {var}\n" for n in cols) +
+                     "".join(f"batch {arch} f32 row inv {m} {var}\n" for m in rows))
+    monkeypatch.setenv("GRF_TUNE_CACHE", str(cache))
+    b = grf.Batch(fields)
+    out = b.sample()
+    torch.cuda.synchronize()
+    assert b.info() == (1, 0)
+    if var == 1:
+        assert torch.equal(out, ref)
+    kinds = {"matern": spectra.MATERN, "gaussian": spectra.GAUSSIAN, "exponential": spectra.EXPONENTIAL}
+    for f, d in enumerate(fields):
+        o = ogrf.sample(d["dims"], d["lengths"], kinds[d["cov"]], d["sigma"], d["length_scale"], d["nu"],
+                        seed=d["seed"], batch=1, alg=2)[0]
+        got = b.field(out, f).double().cpu().numpy()
+        assert np.abs(got - o).max() / np.abs(o).max() <= 1e-5, (f, d["dims"], var)
 
 
 def test_one_launch_agrees_with_two_launches(grf, monkeypatch):
