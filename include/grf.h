@@ -344,12 +344,16 @@ grf_status grf_batch_sample(grf_batch b, void* out, void* stream);
  * persistent launch is compared with). */
 grf_status grf_batch_sample_plain(grf_batch b, void* out, void* stream);
 /* Autotuner: for each column length and each row half-length present in the
- * batch, both tile shapes, and (one-launch mode) the pipeline group size of
- * the XCD queues, each timed on the whole batch (writing into out, which must
- * hold the batch), keeping the fastest; appends the choices to the
- * GRF_TUNE_CACHE file if set (lines "batch <arch> f32 col|row inv <length>
- * <variant>" and "batch <arch> f32 group inv 1 <bytes>"; see grf_plan_tune
- * for the cache rules).  Synchronises the stream. */
+ * batch, its variants (one-launch mode: two radix orders, i.e. two numbers of
+ * threads per transform, times two tile shapes, variants 0-3; two-launch
+ * mode: the two tile shapes of the plan path's radix order, variants 0-1),
+ * and (one-launch mode) the pipeline group size of the XCD queues, each timed
+ * on the whole batch (writing into out, which must hold the batch), keeping
+ * the fastest; appends the choices to the GRF_TUNE_CACHE file if set (lines
+ * "batch <arch> f32 col|row inv <length> <variant>" and "batch <arch> f32
+ * group inv 1 <bytes>"; see grf_plan_tune for the cache rules).  A tile shape
+ * leaves a field's bits unchanged; the other radix order changes them within
+ * the oracle's float32 tolerance.  Synchronises the stream. */
 grf_status grf_batch_tune(grf_batch b, void* out, void* stream);
 /* How the batch runs: *launches = 1 (one persistent launch: per-XCD queues of
  * column and row items, each row item waiting for its field's column items
