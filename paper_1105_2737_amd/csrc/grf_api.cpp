@@ -310,9 +310,14 @@ const TuneChoice* tune_choice(const grf_plan_s* p, int pass, int L) {
 grf_status run_generic(const grf_plan_s* p, int pass, int L, Args a, long long batch, hipStream_t s,
                        const TuneChoice* tc) {
   // untuned: 4 values per thread (the tuner chose 4 over 8 for every
-  // runtime-radix pass it timed on MI355X)
-  const int vpt = tc ? tc->vpt : 4;
-  const grf::GGeom g = grf::generic_geom(pass, p->dtype, L, vpt);
+  // runtime-radix pass it timed on MI355X), 8 where a transform would need
+  // more than 1024 threads with 4 (lengths above 4096)
+  int vpt = tc ? tc->vpt : 4;
+  grf::GGeom g = grf::generic_geom(pass, p->dtype, L, vpt);
+  if (g.threads <= 0 && !tc) {
+    vpt = 8;
+    g = grf::generic_geom(pass, p->dtype, L, vpt);
+  }
   if (g.threads <= 0) return fail(GRF_EUNSUPPORTED, "no kernel for this transform length and pass");
   a.gl = L;
   a.gcp = g.per_wg;
@@ -1043,6 +1048,7 @@ bool parse_choice(const grf_plan_s* p, int pass, long long L, const std::vector<
   t.generic = true;
   t.vpt = std::atoi(w[1].c_str());
   if (t.vpt != 4 && t.vpt != 8) return false;
+  if (grf::generic_geom(pass, p->dtype, (int)L, t.vpt).threads <= 0) return false;   // no such kernel shape
   long long prod = 1;
   size_t i = 0;
   const std::string& r = w[2];
