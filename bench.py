@@ -147,10 +147,24 @@ def profile_mode(args):
           f"{args.profile_boundary} boundary, {args.profile_draw_order} draw order", flush=True)
 
 
-def timed(fn, steps, warmup, torch):
+# Secondary workloads follow host-side work (plan creation, float64 checks) that
+# leaves the GPU idle; its clock then takes some 25 ms of load to ramp up again
+# (the headline step reads 0.73 ms for its first 20 steps after 2 s idle, 0.633 ms
+# from the 40th on).  Their timed regions therefore follow at least this much
+# warm-up of the same work; the headline's follows its per-launch measurements.
+EXTRA_WARM_S = 0.1
+
+
+def timed(fn, steps, warmup, torch, warm_s=0.0):
+    """Seconds per call of fn over `steps` calls, after `warmup` calls and, if
+    warm_s > 0, more calls until warm_s seconds have passed."""
+    tw = time.perf_counter()
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    while time.perf_counter() - tw < warm_s:
+        fn()
+        torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         fn()
@@ -423,7 +437,7 @@ def main():
         # two-FFT algorithm on the same workload
         p1 = grf.Plan(dims, alg=1, dtype=torch.float32, cov="matern", sigma=1.0, length_scale=0.1, nu=1.5)
         o1 = torch.empty((batch,) + dims, dtype=torch.float32, device="cuda")
-        s1 = timed(lambda: p1.sample(seed=0, batch=batch, out=o1), args.steps, args.warmup, torch)
+        s1 = timed(lambda: p1.sample(seed=0, batch=batch, out=o1), args.steps, args.warmup, torch, EXTRA_WARM_S)
         extra["two_fft_512"] = {"points_per_s": round(P * batch / s1, 1), "ms_per_step": round(s1 * 1e3, 4),
                                 "model_frac": round(20 * P * batch / s1 / 1e9 / HBM_PEAK_GBS, 4),
                                 "time_ratio_vs_one_fft": round(s1 / sec, 3),
@@ -447,7 +461,7 @@ def main():
         gth = torch.Generator().manual_seed(3)
         th = torch.stack([0.5 + 1.5 * torch.rand(batch, generator=gth), 0.05 + 0.15 * torch.rand(batch, generator=gth),
                           0.5 + 2.0 * torch.rand(batch, generator=gth)], 1).double().cuda()
-        st = timed(lambda: plan.sample(seed=0, batch=batch, theta=th, out=out2), args.steps, args.warmup, torch)
+        st = timed(lambda: plan.sample(seed=0, batch=batch, theta=th, out=out2), args.steps, args.warmup, torch, EXTRA_WARM_S)
         p64t = grf.Plan(dims, alg=2, dtype=torch.float64, cov="matern")
         et = []
         for b in (0, batch - 1):
@@ -466,7 +480,7 @@ def main():
         d3, b3 = (256, 256, 256), 16
         p3 = grf.Plan(d3, alg=2, dtype=torch.float32, cov="exponential", sigma=1.0, length_scale=0.05)
         o3 = torch.empty((b3,) + d3, dtype=torch.float32, device="cuda")
-        s3 = timed(lambda: p3.sample(seed=0, batch=b3, out=o3), max(args.steps, 20), max(args.warmup, 10), torch)
+        s3 = timed(lambda: p3.sample(seed=0, batch=b3, out=o3), max(args.steps, 20), max(args.warmup, 10), torch, EXTRA_WARM_S)
         ab3 = 20 * 2 ** 24 * b3
         extra["one_fft_256cubed_x16"] = {
             "points_per_s": round(2 ** 24 * b3 / s3, 1), "ms_per_step": round(s3 * 1e3, 4),
@@ -481,7 +495,7 @@ def main():
         extra["one_fft_256cubed_x16"]["error_fields"] = [0, 1, b3 // 2, b3 - 1]
         # the two-FFT algorithm on the same workload: five passes over the spectrum, 36 B/point
         p3a = grf.Plan(d3, alg=1, dtype=torch.float32, cov="exponential", sigma=1.0, length_scale=0.05)
-        s3a = timed(lambda: p3a.sample(seed=0, batch=b3, out=o3), max(args.steps // 5, 3), 1, torch)
+        s3a = timed(lambda: p3a.sample(seed=0, batch=b3, out=o3), max(args.steps // 5, 3), 1, torch, EXTRA_WARM_S)
         f64 = grf.Plan(d3, alg=1, dtype=torch.float64, cov="exponential", sigma=1.0,
                        length_scale=0.05).sample(seed=0, batch=1)[0]
         extra["two_fft_256cubed_x16"] = {
@@ -500,8 +514,8 @@ def main():
         t0 = time.perf_counter()
         bt.tune(out=ob)
         t_tune = time.perf_counter() - t0
-        sb_graph = timed(lambda: bt.sample(out=ob), args.steps, args.warmup, torch)
-        sb_plain = timed(lambda: bt.sample(out=ob, plain=True), 3, 1, torch)
+        sb_graph = timed(lambda: bt.sample(out=ob), args.steps, args.warmup, torch, EXTRA_WARM_S)
+        sb_plain = timed(lambda: bt.sample(out=ob, plain=True), 3, 1, torch, EXTRA_WARM_S)
         npts = bt.offsets[-1]
         bt.sample(out=ob)
         errs = []
@@ -518,7 +532,7 @@ def main():
         bt2 = grf.Batch(fields)
         del os.environ["GRF_BATCH_LAUNCHES"]
         bt2.tune(out=ob)
-        sb_two = timed(lambda: bt2.sample(out=ob), args.steps, args.warmup, torch)
+        sb_two = timed(lambda: bt2.sample(out=ob), args.steps, args.warmup, torch, EXTRA_WARM_S)
         del bt2
         bt.sample(out=ob)
         extra["batched_uneven_4096"] = {
@@ -540,7 +554,7 @@ def main():
         from synth import loss_weights
         w = torch.from_numpy(loss_weights((b5,) + d5, seed=1).astype(np.float32)).cuda()
         o5 = torch.empty((b5,) + d5, dtype=torch.float32, device="cuda")
-        sf = timed(lambda: p5.sample(seed=0, batch=b5, out=o5), args.steps, args.warmup, torch)
+        sf = timed(lambda: p5.sample(seed=0, batch=b5, out=o5), args.steps, args.warmup, torch, EXTRA_WARM_S)
         g = 2 * w * o5
         w2 = 2 * w                     # dL/dphi = 2 w phi in one elementwise pass
 
@@ -548,9 +562,9 @@ def main():
             p5.sample(seed=0, batch=b5, out=o5)
             torch.mul(o5, w2, out=g)
             p5.backward(g, seed=0)
-        sfb = timed(fwd_bwd, args.steps, args.warmup, torch)
-        sb = timed(lambda: p5.backward(g, seed=0), args.steps, args.warmup, torch)
-        sbz = timed(lambda: p5.backward(g, seed=0, need_noise_grad=True), args.steps, args.warmup, torch)
+        sfb = timed(fwd_bwd, args.steps, args.warmup, torch, EXTRA_WARM_S)
+        sb = timed(lambda: p5.backward(g, seed=0), args.steps, args.warmup, torch, EXTRA_WARM_S)
+        sbz = timed(lambda: p5.backward(g, seed=0, need_noise_grad=True), args.steps, args.warmup, torch, EXTRA_WARM_S)
         # float32 forward and adjoint vs the float64 template on fields {0, 1, B/2, B-1}
         p5_64 = grf.Plan(d5, alg=2, dtype=torch.float64, cov="matern", sigma=1.0, length_scale=0.1, nu=1.5)
         p5.sample(seed=0, batch=b5, out=o5)
@@ -575,19 +589,19 @@ def main():
         # the adjoint in 3D (256^3 x 16, exponential l = 0.05), with and without dL/dz
         p3a = grf.Plan((256, 256, 256), alg=2, dtype=torch.float32, cov="exponential", sigma=1.0, length_scale=0.05)
         o3a = torch.empty((16, 256, 256, 256), dtype=torch.float32, device="cuda")
-        s3f = timed(lambda: p3a.sample(seed=0, batch=16, out=o3a), max(args.steps // 10, 5), 2, torch)
+        s3f = timed(lambda: p3a.sample(seed=0, batch=16, out=o3a), max(args.steps // 10, 5), 2, torch, EXTRA_WARM_S)
         g3 = o3a.clone()
-        s3b = timed(lambda: p3a.backward(g3, seed=0), max(args.steps // 10, 5), 2, torch)
-        s3z = timed(lambda: p3a.backward(g3, seed=0, need_noise_grad=True), max(args.steps // 10, 5), 2, torch)
+        s3b = timed(lambda: p3a.backward(g3, seed=0), max(args.steps // 10, 5), 2, torch, EXTRA_WARM_S)
+        s3z = timed(lambda: p3a.backward(g3, seed=0, need_noise_grad=True), max(args.steps // 10, 5), 2, torch, EXTRA_WARM_S)
         # the adjoint of the other samplers on the headline grid (512^2 x 256 fields)
         av = {}
         oav = torch.empty((256, 512, 512), dtype=torch.float32, device="cuda")
         for nm, kw in (("two_fft", dict(alg=1)), ("neumann", dict(boundary="neumann")),
                        ("dirichlet", dict(boundary="dirichlet")), ("recursive_order", dict(draw_order="recursive"))):
             pv = grf.Plan((512, 512), dtype=torch.float32, cov="matern", sigma=1.0, length_scale=0.1, nu=1.5, **kw)
-            sfv = timed(lambda: pv.sample(seed=0, batch=256, out=oav), max(args.steps // 10, 5), 2, torch)
+            sfv = timed(lambda: pv.sample(seed=0, batch=256, out=oav), max(args.steps // 10, 5), 2, torch, EXTRA_WARM_S)
             gv = oav.clone()
-            sbv = timed(lambda: pv.backward(gv, seed=0), max(args.steps // 10, 5), 2, torch)
+            sbv = timed(lambda: pv.backward(gv, seed=0), max(args.steps // 10, 5), 2, torch, EXTRA_WARM_S)
             av[nm] = {"fwd_ms": round(sfv * 1e3, 4), "adjoint_ms": round(sbv * 1e3, 4),
                       "ratio_adjoint_vs_fwd": round(sbv / sfv, 3)}
             del pv, gv
@@ -605,7 +619,7 @@ def main():
         # (m = 5, k = 3, l = n = 1) on the headline grid and batch (filter from the plan's table)
         pp = grf.Plan(dims, lengths=(4.0, 4.0), alg=2, dtype=torch.float32, cov="paper", m=5.0, k=3, l=1, n=1)
         op = torch.empty((batch,) + dims, dtype=torch.float32, device="cuda")
-        sp = timed(lambda: pp.sample(seed=0, batch=batch, out=op), args.steps // 5, args.warmup // 5, torch)
+        sp = timed(lambda: pp.sample(seed=0, batch=batch, out=op), args.steps // 5, args.warmup // 5, torch, EXTRA_WARM_S)
         pp64 = grf.Plan(dims, lengths=(4.0, 4.0), alg=2, dtype=torch.float64, cov="paper", m=5.0, k=3, l=1, n=1)
         ep = []
         for b in (0, 1, batch // 2, batch - 1):
@@ -625,7 +639,7 @@ def main():
             npts = orf.numel()
             for bc in ("neumann", "dirichlet"):
                 pr = grf.Plan(rdims, alg=2, dtype=torch.float32, boundary=bc, **rfam)
-                sr = timed(lambda: pr.sample(seed=0, batch=rb, out=orf), max(args.steps // 5, 5), max(args.warmup // 5, 2), torch)
+                sr = timed(lambda: pr.sample(seed=0, batch=rb, out=orf), max(args.steps // 5, 5), max(args.warmup // 5, 2), torch, EXTRA_WARM_S)
                 pr64 = grf.Plan(rdims, alg=2, dtype=torch.float64, boundary=bc, **rfam)
                 er = []
                 for b in (0, rb - 1):
@@ -648,7 +662,7 @@ def main():
             orc = torch.empty((rb,) + rdims, dtype=torch.float32, device="cuda")
             npts = orc.numel()
             pq = grf.Plan(rdims, alg=2, dtype=torch.float32, draw_order="recursive", **rfam)
-            sq = timed(lambda: pq.sample(seed=0, batch=rb, out=orc), max(args.steps // 5, 5), max(args.warmup // 5, 2), torch)
+            sq = timed(lambda: pq.sample(seed=0, batch=rb, out=orc), max(args.steps // 5, 5), max(args.warmup // 5, 2), torch, EXTRA_WARM_S)
             pq64 = grf.Plan(rdims, alg=2, dtype=torch.float64, draw_order="recursive", **rfam)
             eq = []
             for b in (0, rb - 1):
@@ -668,7 +682,7 @@ def main():
         p1d = grf.Plan((4096,), lengths=(2 * 3.141592653589793,), alg=2, dtype=torch.float32, cov="matern",
                        sigma=1.0, length_scale=0.07 ** 0.5, nu=3.5)
         o1d = torch.empty((65536, 4096), dtype=torch.float32, device="cuda")
-        s1d = timed(lambda: p1d.sample(seed=0, batch=65536, out=o1d), args.steps // 5, args.warmup // 5, torch)
+        s1d = timed(lambda: p1d.sample(seed=0, batch=65536, out=o1d), args.steps // 5, args.warmup // 5, torch, EXTRA_WARM_S)
         f64 = grf.Plan((4096,), lengths=(2 * 3.141592653589793,), alg=2, dtype=torch.float64, cov="matern",
                        sigma=1.0, length_scale=0.07 ** 0.5, nu=3.5).sample(seed=0, batch=1)[0]
         extra["one_fft_1d_4096_x65536"] = {
@@ -677,7 +691,7 @@ def main():
             "max_rel_err_vs_fp64_field0": float((o1d[0].double() - f64).abs().max() / f64.abs().max())}
         p1a = grf.Plan((4096,), lengths=(2 * 3.141592653589793,), alg=1, dtype=torch.float32, cov="matern",
                        sigma=1.0, length_scale=0.07 ** 0.5, nu=3.5)
-        s1a = timed(lambda: p1a.sample(seed=0, batch=65536, out=o1d), max(args.steps // 10, 3), 1, torch)
+        s1a = timed(lambda: p1a.sample(seed=0, batch=65536, out=o1d), max(args.steps // 10, 3), 1, torch, EXTRA_WARM_S)
         extra["two_fft_1d_4096_x65536"] = {"points_per_s": round(2 ** 28 / s1a, 1), "ms_per_step": round(s1a * 1e3, 4),
                                           "time_ratio_vs_one_fft": round(s1a / s1d, 3)}
         del o1d

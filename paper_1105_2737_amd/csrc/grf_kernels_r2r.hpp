@@ -343,14 +343,24 @@ struct R2RRow {
     }
     __syncthreads();
     if (act) {
+      // c_u = v_{2u} + i v_{2u+1}: output pairs 2u and 2u + 1 are
+      // (v_{2u}, +-v_{N-1-2u}) = (c_u.x, +-c_{M-1-u}.y) and
+      // (v_{2u+1}, +-v_{N-2-2u}) = (c_u.y, +-c_{M-1-u}.x), one vector store
       const E* rowp = sm + r * RL::STRIDE;
-      auto v = [&](int i) -> T {
-        const V c = rowp[RL::idx(i >> 1)].v[0];
-        return (i & 1) ? c.y : c.x;
-      };
       const T sg = a.sine ? (T)-1 : (T)1;
-      V* o = g + (long long)r * M;
-      for (int n = t; n < M; n += NT) o[n] = mk<T>(v(n), sg * v(N - 1 - n));
+      struct alignas(4 * sizeof(T)) P4 { T v[4]; };
+      P4* o = reinterpret_cast<P4*>(g + (long long)r * M);
+#pragma unroll
+      for (int u = t; u < M / 2; u += NT) {
+        const V c0 = rowp[RL::idx(u)].v[0];
+        const V c1 = rowp[RL::idx(M - 1 - u)].v[0];
+        P4 w;
+        w.v[0] = c0.x;
+        w.v[1] = sg * c1.y;
+        w.v[2] = c0.y;
+        w.v[3] = sg * c1.x;
+        o[u] = w;
+      }
     }
   }
 };
