@@ -65,7 +65,7 @@ struct grf_plan_s {
   int sinemask = 0;         // sine axes: bit 0 axis 1, bit 1 middle axis, bit 2 last axis
   void* tq_col1 = nullptr;  // (1/2) e^{i pi k / (2N)} of each axis
   void* tq_col2 = nullptr;
-  void* tq_row = nullptr;
+  void* tq_row = nullptr;   // last axis: q_k, k <= M, then the forward pass's alpha_k, beta_k (make_row_rtable)
   int device = 0;
   bool listed = true;       // every axis has compile-time kernels (else the runtime-radix passes)
   std::map<long long, TuneChoice> tune;   // per (pass, transform length): the tuner's or the cache's choice
@@ -143,6 +143,49 @@ grf_status make_qtable(int N, int count, int dtype, void** out) {
   return GRF_OK;
 }
 
+// The last axis's table: q_k = (1/2) e^{i pi k / (2N)}, k = 0..M (N = 2M), then
+// the forward pass's combined factors alpha_k = q_k (1 + i W_N^k) and
+// beta_k = conj(q_{M-k}) (1 - i W_N^k), k = 0..M-1 (see R2RRow::prep), all in
+// float64, rounded once.
+grf_status make_row_rtable(int N, int dtype, void** out) {
+  const int M = N / 2;
+  std::vector<double> w(2 * (size_t)(3 * M + 1));
+  auto q = [&](int k, double& re, double& im) {
+    const double ang = M_PI * (double)k / (2.0 * (double)N);
+    re = 0.5 * std::cos(ang);
+    im = 0.5 * std::sin(ang);
+  };
+  for (int k = 0; k <= M; ++k) q(k, w[2 * k], w[2 * k + 1]);
+  for (int k = 0; k < M; ++k) {
+    long long kk = k;
+    if (2 * kk > N) kk -= N;
+    const double ang = 2.0 * M_PI * (double)kk / (double)N;
+    const double wr = std::cos(ang), wi = std::sin(ang);
+    double qr, qi, mr, mi;
+    q(k, qr, qi);
+    q(M - k, mr, mi);
+    // 1 + i w = (1 - wi) + i wr;  1 - i w = (1 + wi) - i wr
+    const double ar = 1.0 - wi, ai = wr, br = 1.0 + wi, bi = -wr;
+    double* al = &w[2 * (size_t)(M + 1 + k)];
+    double* be = &w[2 * (size_t)(2 * M + 1 + k)];
+    al[0] = qr * ar - qi * ai;
+    al[1] = qr * ai + qi * ar;
+    be[0] = mr * br + mi * bi;   // conj(q_{M-k}) = mr - i mi
+    be[1] = mr * bi - mi * br;
+  }
+  const size_t bytes = w.size() * (dtype == GRF_F32 ? 4 : 8);
+  hipError_t e = hipMalloc(out, bytes);
+  if (e != hipSuccess) return fail(GRF_ENOMEM, "hipMalloc of twiddle table failed");
+  if (dtype == GRF_F32) {
+    std::vector<float> f(w.begin(), w.end());
+    e = hipMemcpy(*out, f.data(), bytes, hipMemcpyHostToDevice);
+  } else {
+    e = hipMemcpy(*out, w.data(), bytes, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return hip_fail(e, "twiddle upload");
+  return GRF_OK;
+}
+
 }  // namespace host
 }  // namespace grf
 
@@ -152,6 +195,7 @@ using grf::host::fail;
 using grf::host::g_err;
 using grf::host::hip_fail;
 using grf::host::make_qtable;
+using grf::host::make_row_rtable;
 using grf::host::make_table;
 using grf::host::smooth235;
 
@@ -1248,7 +1292,7 @@ grf_status grf_plan_create(const grf_plan_desc* desc, grf_plan* out) {
   if (st == GRF_OK && reflect) {
     if (d.ndim >= 2) st = make_qtable(p->n1, p->n1, p->dtype, &p->tq_col1);
     if (st == GRF_OK && d.ndim == 3) st = make_qtable(p->no, p->no, p->dtype, &p->tq_col2);
-    if (st == GRF_OK) st = make_qtable(p->nd, p->M + 1, p->dtype, &p->tq_row);
+    if (st == GRF_OK) st = make_row_rtable(p->nd, p->dtype, &p->tq_row);
   }
   if (st == GRF_OK) {
     e = hipMalloc((void**)&p->rec_dev, sizeof(FieldRec));

@@ -242,29 +242,37 @@ struct R2RRow {
   // points: 0.838 -> 0.747 ms per 65536 fields); the load pass keeps the LDS
   // copy (2.5% slower without it at 128 x 4096).
   static constexpr bool TW_GLOBAL = SRC == SRC_GEN && M >= 1024;
-  static constexpr int LDS_BYTES = ROWS_BYTES + (TW_GLOBAL ? 0 : N * (int)sizeof(V));
+  // alpha_k, beta_k (2M values) after W_N in LDS for short rows: read from
+  // global memory right before their use, the loads went out one at a time
+  // (M = 128: the pass 33% slower); long rows keep them in the caches (their
+  // LDS would cost occupancy)
+  static constexpr bool AB_LDS = !TW_GLOBAL && M <= 512;
+  static constexpr int LDS_BYTES =
+      ROWS_BYTES + (TW_GLOBAL ? 0 : N * (int)sizeof(V)) + (AB_LDS ? 2 * M * (int)sizeof(V) : 0);
   using EN = Eng<T, M, Rad, NT, 1, 2, WAVE>;
   static_assert(M % 2 == 0, "a Philox block fills two complex slots");
 
   // Z_k of the complex-to-real transform from X_k, X_{N-k}, X_{M-k}, X_{M+k}
-  // (k = 0: X_0 and X_M in x0, x1).
-  __device__ __forceinline__ static V prep(int k, T x0, T x1, T x2, T x3, const V* tw, const V* tq) {
+  // (k = 0: X_0 and X_M in x0, x1).  With Y_k = q_k (X_k - i X_{N-k}),
+  // q_k = (1/2) e^{i pi k / (2N)}, the half-length transform's input is
+  //   Z_k = Y_k + conj Y_{M-k} + i W_N^k (Y_k - conj Y_{M-k})
+  //       = (X_k - i X_{N-k}) alpha_k + (X_{M-k} + i X_{M+k}) beta_k
+  // with alpha_k = q_k (1 + i W_N^k), beta_k = conj(q_{M-k}) (1 - i W_N^k),
+  // tabulated after the q_k (ab = tq + M + 1: alpha_k at k, beta_k at M + k).
+  __device__ __forceinline__ static V prep(int k, T x0, T x1, T x2, T x3, const V* ab) {
     if (k == 0) {
       const T y0 = x0, ym = x1 * (T)0.70710678118654752440;
       return mk<T>(y0 + ym, y0 - ym);
     }
-    const V yk = cmul(mk<T>(x0, -x1), tq[k]);
-    const V ym = cconj(cmul(mk<T>(x2, -x3), tq[M - k]));
-    const V ek = cadd(yk, ym);
-    const V ok = cmul(csub(yk, ym), tw[k]);
-    return mk<T>(ek.x - ok.y, ek.y + ok.x);
+    return cadd(cmul(mk<T>(x0, -x1), ab[k]), cmul(mk<T>(x2, x3), ab[M + k]));
   }
 
   __device__ __forceinline__ static void run(const Args& a, int bid, char* smem) {
     E* sm = reinterpret_cast<E*>(smem);
     V* tws = reinterpret_cast<V*>(smem + ROWS_BYTES);
     const V* tw = TW_GLOBAL ? (const V*)a.tw2 : tws;
-    const V* tq = (const V*)a.tq;
+    const V* abg = (const V*)a.tq + (M + 1);
+    const V* ab = AB_LDS ? tws + N : abg;
     const int tid = threadIdx.x;
     const int r = tid / NT, t = tid % NT;
     const long long row0 = (long long)bid * RB;
@@ -273,7 +281,9 @@ struct R2RRow {
     const bool act = r < nrows;
     V* g = (V*)a.data + row0 * M;
     TwFill<V, TW_GLOBAL ? 1 : N, THREADS> twf;
+    TwFill<V, AB_LDS ? 2 * M : 1, THREADS> abf;
     if (!TW_GLOBAL && tid < THREADS) twf.load((const V*)a.tw2, tid);
+    if (AB_LDS && tid < THREADS) abf.load(abg, tid);
     V x[1][EN::REG];
     if constexpr (SRC == SRC_GEN) {
       constexpr int NQ = M / 2;   // Philox blocks per row
@@ -289,6 +299,7 @@ struct R2RRow {
         rowp[RL::idx(2 * q + 1)].v[0] = mk<T>(v[2], v[3]);
       }
       if (!TW_GLOBAL && tid < THREADS) twf.store(tws, tid);
+      if (AB_LDS && tid < THREADS) abf.store(tws + N, tid);
       __syncthreads();
       const E* rowp = sm + r * RL::STRIDE;
       auto X = [&](int i) -> T {
@@ -299,7 +310,7 @@ struct R2RRow {
 #pragma unroll
         for (int m = 0; m < R0; ++m) {
           const int k = t + m * NT;
-          x[0][m] = k == 0 ? prep(0, X(0), X(M), (T)0, (T)0, tw, tq) : prep(k, X(k), X(N - k), X(M - k), X(M + k), tw, tq);
+          x[0][m] = k == 0 ? prep(0, X(0), X(M), (T)0, (T)0, ab) : prep(k, X(k), X(N - k), X(M - k), X(M + k), ab);
         }
       }
       __syncthreads();   // the rows area is reused by the transform
@@ -317,10 +328,11 @@ struct R2RRow {
         }
       }
       if (!TW_GLOBAL && tid < THREADS) twf.store(tws, tid);
+      if (AB_LDS && tid < THREADS) abf.store(tws + N, tid);
       __syncthreads();
       if (act) {
 #pragma unroll
-        for (int m = 0; m < R0; ++m) x[0][m] = prep(t + m * NT, xa[m], xb[m], xc[m], xd[m], tw, tq);
+        for (int m = 0; m < R0; ++m) x[0][m] = prep(t + m * NT, xa[m], xb[m], xc[m], xd[m], ab);
       }
     }
     auto lds = [&](int i) -> E& { return sm[r * RL::STRIDE + RL::idx(i)]; };
