@@ -219,15 +219,17 @@ k_batch_row(const BatchField* __restrict__ F, const BatchItem* __restrict__ item
 #define GRF_BATCH_ONE_COL(X) X(64, 64, 32) X(96, 42, 21) X(128, 32, 16) X(180, 14, 7) X(256, 16, 8) \
   X(360, 11, 5) X(500, 8, 4) X(512, 8, 4) X(1000, 4, 2) X(1024, 4, 2)
 
+constexpr int max4(int a, int b, int c, int d) {
+  const int x = a > b ? a : b, y = c > d ? c : d;
+  return x > y ? x : y;
+}
 #define GRF_ONE_LDS(L_, A_, B_)                                                                          \
-  max_of((const int[]){BColPass<L_, A_>::LDS_BYTES, BColPass<L_, B_>::LDS_BYTES,                          \
-                       BColPass<L_, BatchAltCol<L_>::CPA, true>::LDS_BYTES,                               \
-                       BColPass<L_, BatchAltCol<L_>::CPB, true>::LDS_BYTES}, 4),
+  max4(BColPass<L_, A_>::LDS_BYTES, BColPass<L_, B_>::LDS_BYTES,                                        \
+       BColPass<L_, BatchAltCol<L_>::CPA, true>::LDS_BYTES, BColPass<L_, BatchAltCol<L_>::CPB, true>::LDS_BYTES),
 constexpr int one_lds_list[] = {GRF_BATCH_ONE_COL(GRF_ONE_LDS) 0};
 #undef GRF_ONE_LDS
 #define GRF_ALT_ROW_LDS(M_, A_, B_)                                                                      \
-  max_of((const int[]){BRowPass<M_, BatchAltRow<M_>::RBA, true>::LDS_BYTES,                               \
-                       BRowPass<M_, BatchAltRow<M_>::RBB, true>::LDS_BYTES}, 2),
+  max4(BRowPass<M_, BatchAltRow<M_>::RBA, true>::LDS_BYTES, BRowPass<M_, BatchAltRow<M_>::RBB, true>::LDS_BYTES, 0, 0),
 constexpr int alt_row_lds_list[] = {GRF_BATCH_ROW(GRF_ALT_ROW_LDS) 0};
 #undef GRF_ALT_ROW_LDS
 constexpr int ONE_COL_LDS = max_of(one_lds_list, sizeof(one_lds_list) / sizeof(int));
