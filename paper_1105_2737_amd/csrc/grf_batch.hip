@@ -3,12 +3,15 @@
 //
 // Both passes reuse the kernel bodies of the single-plan sampler (ColPass,
 // and RowC2RStaged, the LDS-staged form of RowC2R with the same arithmetic),
-// so a field sampled in a batch has the same bits as the same field sampled
-// by a plan.  Column workgroups have 256 threads and at most
-// ~48 KB of LDS (three per CU at the column bodies' register use); row
-// workgroups 512 threads and at most ~70 KB (two per CU).  Each length has two
-// tile shapes (the second with half the columns / rows per workgroup) between
-// which the autotuner chooses.
+// so a field sampled in a batch with the plan path's radix order has the same
+// bits as the same field sampled by a plan.  In the two-launch route column
+// workgroups have 256 threads and at most ~48 KB of LDS (three per CU at the
+// column bodies' register use), row workgroups 512 threads and at most ~70 KB
+// (two per CU), and each length has two tile shapes (the second with half the
+// columns / rows per workgroup).  The one-launch kernel (512 threads, two
+// workgroups per CU) has four bodies per length: those two tile shapes and two
+// of another radix order (another number of threads per transform).  The
+// autotuner chooses among them.
 #include "grf_batch.hpp"
 #include "grf_configs.hpp"
 #include "grf_kernels.hpp"
