@@ -38,17 +38,19 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
-def gen_pass_ops_per_point(n1):
+def gen_pass_ops_per_point(n1, stages=None):
     """Algorithmic VALU lane-ops per output point of the column generation pass (one-FFT,
     d = 2, radix-8 column transform of length n1 = 8^s): Philox-4x32-10 (10 rounds x
     (2 32x32->64 products + 2 three-input xors) per 4 normals) = 10; Box-Muller per
     pair (2 conversions, 2 scalings, log, sqrt, sin, cos at two slots each, 3 products)
     = 15 -> 7.5; filter (h/sqrt2 and two products per complex entry) = 1.5; radix-8
     Stockham stages: 7 ops per complex per stage + 3.5 for the twiddles of every stage
-    but the first, per real point half of that."""
+    but the first, per real point half of that.  `stages`: the radix-8 stages the pass
+    runs (all s by default; s - 1 when the last-axis pass completes the transform)."""
     import math
     s = round(math.log(n1, 8))
-    return 10 + 7.5 + 1.5 + (7 * s + 3.5 * (s - 1)) / 2
+    k = s if stages is None else stages
+    return 10 + 7.5 + 1.5 + (7 * k + 3.5 * (k - 1)) / 2
 
 # HBM bytes per launch of the headline step's kernels (one launch = one cache-sized
 # chunk of 256 fields), from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch,
@@ -58,6 +60,8 @@ def gen_pass_ops_per_point(n1):
 MEASURED_TRAFFIC = {
     "column noise+inverse FFT (axis 1)": (2408 * 2 + 275738) * 1024,
     "last-axis C2R": (131139 * 2 + 262144) * 1024,
+    "column noise+inverse FFT (axis 1) but its last stage": (2375 * 2 + 277610) * 1024,
+    "last stage of axis 1 + last-axis C2R": (131143 * 2 + 262144) * 1024,
 }
 
 
@@ -191,12 +195,14 @@ PASS_NAMES = {0: "column noise+inverse FFT (axis 1)", 1: "inverse FFT (axis 2)",
               9: "reflecting: column coefficients+DCT (axis 1)", 10: "reflecting: DCT (axis 2)",
               11: "reflecting: last-axis DCT", 12: "reflecting: 1D coefficients+DCT",
               13: "column noise (recursive order)+inverse FFT (axis 1)", 14: "filter on the packed spectrum",
-              109: "column fwd FFT x h x inv FFT (d = 3)", 110: "filter on the packed plane slots"}
+              109: "column fwd FFT x h x inv FFT (d = 3)", 110: "filter on the packed plane slots",
+              111: "column noise+inverse FFT (axis 1) but its last stage",
+              112: "last stage of axis 1 + last-axis C2R"}
 
 
 def pass_bytes(kind, field_bytes):
     """Algorithmic HBM bytes of one field through pass `kind` (output-sized packed spectrum)."""
-    return field_bytes * (1 if kind in (0, 6, 9, 12, 13) else 2)
+    return field_bytes * (1 if kind in (0, 6, 9, 12, 13, 111) else 2)
 
 
 def launch_table(plan, batch, torch, grf, reps):
@@ -392,13 +398,15 @@ def main():
         del os.environ["GRF_CHUNK_BYTES"]
     traffic = MEASURED_TRAFFIC.get(kname)
     k_hbm = kbytes / (kms * 1e-3) / 1e9
-    if dom == 0:
+    if dom in (0, 111):
         # VALU-bound (noise generation in registers): algorithmic lane-ops vs the VALU issue peak
-        ops = gen_pass_ops_per_point(dims[0]) * kpoints
+        import math
+        nst = round(math.log(dims[0], 8)) - (1 if dom == 111 else 0)
+        ops = gen_pass_ops_per_point(dims[0], nst) * kpoints
         achieved = ops / (kms * 1e-3) / 1e12
         roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(VALU_PEAK_TOPS, 2),
                     "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                    "algorithmic_ops_per_point": gen_pass_ops_per_point(dims[0]),
+                    "algorithmic_ops_per_point": gen_pass_ops_per_point(dims[0], nst),
                     "algorithmic_ops_per_launch": int(ops)}
     else:
         roofline = {"bound": "hbm", "achieved": round(k_hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

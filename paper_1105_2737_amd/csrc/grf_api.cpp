@@ -393,6 +393,15 @@ grf_status run_generic(const grf_plan_s* p, int pass, int L, Args a, long long b
 grf_status run_pass(const grf_plan_s* p, int pass, int L, Args a, long long nfixed_blocks_per_field,
                     long long batch, hipStream_t s) {
   (void)nfixed_blocks_per_field;
+  if (pass == grf::PASS_ROW_XC2R) {
+    const grf::XGeom g = grf::xc2r_geom(p->dtype, p->n1, p->M);
+    if (g.threads <= 0) return fail(GRF_EUNSUPPORTED, "no kernel for this transform length and pass");
+    const long long nblocks = a.rows / g.rows;
+    if (nblocks <= 0) return GRF_OK;
+    hipError_t e = grf::launch_xc2r(p->dtype, p->n1, p->M, a, nblocks, s);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return GRF_OK;
+  }
   const TuneChoice* tc = tune_choice(p, pass, L);
   if (tc ? tc->generic : !fixed_length(pass, L)) return run_generic(p, pass, L, a, batch, s, tc);
   const grf::Geom g = grf::pass_geom(pass, p->dtype, L);
@@ -447,6 +456,20 @@ long long chunk_fields(const grf_plan_s* p, long long batch) {
 
 grf_status run_launch(const grf_plan_s* p, const PassLaunch& pl, hipStream_t s) {
   return run_pass(p, pl.pass, pl.L, pl.a, 0, pl.count, s);
+}
+
+// d = 2 one-FFT in the counter order on a pair of lengths that has the
+// split kernels (the column transform's last stage in the last-axis pass),
+// with both passes on their compile-time kernels.  GRF_SPLIT=0 keeps the
+// unsplit passes.
+bool split_route(const grf_plan_s* p, bool seq) {
+  if (p->d != 2 || seq || p->reflect || p->desc.alg != GRF_ALG_ONE_FFT || !p->listed) return false;
+  if (grf::xc2r_geom(p->dtype, p->n1, p->M).threads <= 0) return false;
+  if (const char* e = std::getenv("GRF_SPLIT"))
+    if (e[0] == '0') return false;
+  const TuneChoice* c = tune_choice(p, grf::PASS_COL_GEN_INV, p->n1);
+  const TuneChoice* r = tune_choice(p, grf::PASS_ROW_C2R, p->M);
+  return !(c && c->generic) && !(r && r->generic);
 }
 
 // The passes of the sampler over fields c0 .. c0 + nb - 1 (zsrc == nullptr
@@ -545,6 +568,17 @@ void chunk_passes(const grf_plan_s* p, uint64_t seed, const void* zsrc, long lon
       a.stride_ax = (long long)p->no * p->M;
       a.stride_fixed = p->M;
       a.nfixed = p->no;
+    }
+    if (split_route(p, seq)) {
+      // the column transform's last stage in the last-axis pass
+      push(grf::PASS_COL_GEN_PART, p->n1, a);
+      Args b = a;
+      b.src = nullptr;
+      b.tw = p->tw_col1;
+      b.tw2 = p->tw_row;
+      b.rows = nb * (long long)p->n1;
+      push(grf::PASS_ROW_XC2R, p->M, b);
+      return;
     }
     push(seq ? grf::PASS_COL_SEQ_INV : grf::PASS_COL_GEN_INV, p->n1, a);
     if (p->d == 3) {

@@ -50,6 +50,8 @@ enum PassKind {
   PASS_COL_GRAD3_SEQ = 107,
   PASS_COL_FILTER3 = 109,                      // two-FFT, d = 3: PASS_COL_FILTER without the packed plane slot
   PASS_SPEC_FILTER0 = 110,                     // two-FFT, d = 3: the filter on the packed plane slots only
+  PASS_COL_GEN_PART = 111,                     // PASS_COL_GEN_INV stopped before the transform's last stage
+  PASS_ROW_XC2R = 112,                         // that last stage + PASS_ROW_C2R (after PASS_COL_GEN_PART)
 };
 
 inline bool is_r2r_pass(int p) {
@@ -93,6 +95,24 @@ int radix_plan(int L, int* rad);
 // a.gl .. a.grad must be set (transform length, geometry, values per thread,
 // radix list).
 hipError_t launch_generic(int pass, int dtype, const Args& a, long long nblocks, hipStream_t s);
+
+// The d = 2 one-FFT sampler with the column transform's last stage moved into
+// the last-axis pass (PASS_COL_GEN_PART + PASS_ROW_XC2R), for the (N_1, M)
+// pairs listed; the two passes give the bits of PASS_COL_GEN_INV +
+// PASS_ROW_C2R.
+#define GRF_XC2R_PAIRS(X) X(512, 256)
+constexpr bool xc2r_col_length(int L) {
+#define GRF_X(L_, M_) L == L_ ||
+  return GRF_XC2R_PAIRS(GRF_X) false;
+#undef GRF_X
+}
+struct XGeom {
+  int threads;   // threads per workgroup (0: no kernel for the pair)
+  int rows;      // rows per workgroup (the column transform's last radix)
+};
+XGeom xc2r_geom(int dtype, int n1, int M);
+// a.rows = fields * N_1, a.tw = W_{N_1}, a.tw2 = W_{N_d}; nblocks = a.rows / rows.
+hipError_t launch_xc2r(int dtype, int n1, int M, const Args& a, long long nblocks, hipStream_t s);
 
 // Launch one pass over `nblocks` workgroups.  dtype: 0 = float32, 1 = float64.
 hipError_t launch_pass(int pass, int dtype, int L, const Args& a, long long nblocks, hipStream_t s);

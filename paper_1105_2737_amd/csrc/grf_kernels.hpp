@@ -130,10 +130,12 @@ struct Eng {
   static_assert(Rad::prod() == L, "radices must multiply to L");
   static_assert(L / Rad::get(0) == NT, "stage 0 must give one butterfly per thread");
 
-  template <int s, int DIR, class Lds, class Out>
+  // SKIP > 0: stop SKIP stages early; the last stage run hands its outputs to
+  // `out` at the indices the next stage would read them from.
+  template <int s, int DIR, int SKIP = 0, class Lds, class Out>
   __device__ __forceinline__ static void stage(V (&x)[NC][REG], int t, bool act, Lds lds, const V* tw, Out out) {
     constexpr int Rs = Rad::get(s), Ns = Rad::ns(s), nb = NB(s), LR = L / Rs;
-    constexpr bool last = (s == S - 1);
+    constexpr bool last = (s == S - 1 - SKIP);
     constexpr int TSTEP = L / (Ns * Rs);
     if (act) {
 #pragma unroll
@@ -160,7 +162,10 @@ struct Eng {
               E e;
 #pragma unroll
               for (int c = 0; c < NC; ++c) e.v[c] = x[c][b * Rs + m];
-              out(j + m * LR, e);
+              if constexpr (SKIP == 0)
+                out(j + m * LR, e);
+              else
+                out((j / Ns) * Ns * Rs + k + m * Ns, e);
             }
           } else {
             const int base = (j / Ns) * Ns * Rs + k;
@@ -193,13 +198,13 @@ struct Eng {
         }
       }
       stage_sync<WAVE>();
-      stage<s + 1, DIR>(x, t, act, lds, tw, out);
+      stage<s + 1, DIR, SKIP>(x, t, act, lds, tw, out);
     }
   }
 
-  template <int DIR, class Lds, class Out>
+  template <int DIR, int SKIP = 0, class Lds, class Out>
   __device__ __forceinline__ static void run(V (&x)[NC][REG], int t, bool act, Lds lds, const V* tw, Out out) {
-    stage<0, DIR>(x, t, act, lds, tw, out);
+    stage<0, DIR, SKIP>(x, t, act, lds, tw, out);
   }
 };
 
@@ -459,7 +464,9 @@ struct TwFill {
 // ---------------------------------------------------------------------------
 // Column pass over a leading axis.
 // SRC_SEQ: generation with the normals in the recursive algorithm's draw order.
-enum { SRC_GEN = 0, SRC_LOAD = 1, SRC_SEQ = 2 };
+// SRC_GEN_PART: generation like SRC_GEN, the transform stopped before its last
+// stage (the last-axis pass RowXC2R completes it).
+enum { SRC_GEN = 0, SRC_LOAD = 1, SRC_SEQ = 2, SRC_GEN_PART = 3 };
 
 template <typename T, int L, class Rad, int CP, int PAD, int SRC, int DIR>
 struct ColPass {
@@ -476,6 +483,7 @@ struct ColPass {
   // 1000 and 1024).
   static constexpr bool GEN_STRAIGHT = L >= 360;
   using EN = Eng<T, L, Rad, NT, 2, 1>;
+  static constexpr int SKIP = SRC == SRC_GEN_PART ? 1 : 0;
 
   // Noise generation of tile `tile` of field b (fixed index fx) straight into
   // x, for the common case of generated noise and a filter table: the table
@@ -635,7 +643,7 @@ struct ColPass {
     const bool al = (a.M & 1) == 0;
     V* base = (V*)a.data + (long long)b * a.field_stride + (long long)fx * a.stride_fixed + m0;
     V x[2][EN::REG];
-    if constexpr (SRC == SRC_GEN && GEN_STRAIGHT) {
+    if constexpr ((SRC == SRC_GEN || SRC == SRC_GEN_PART) && GEN_STRAIGHT) {
       if (a.src == nullptr && a.htab != nullptr) {
         TwFill<V, L, THREADS> twf;
         if (tid < THREADS) twf.load((const V*)a.tw, tid);
@@ -643,7 +651,7 @@ struct ColPass {
         if (tid < THREADS) twf.store(tw, tid);   // first read after the stage-0 barrier
         auto lds = [&](int i) -> E& { return sm[i * RS + cp]; };
         auto out = [&](int i, const E& e) { st_pair<T>(base + (long long)i * a.stride_ax, two, al, e); };
-        EN::template run<DIR>(x, t, act, lds, tw, out);
+        EN::template run<DIR, SKIP>(x, t, act, lds, tw, out);
         return;
       }
     }
@@ -662,12 +670,12 @@ struct ColPass {
         }
         auto lds = [&](int i) -> E& { return sm[i * RS + cp]; };
         auto out = [&](int i, const E& e) { st_pair<T>(base + (long long)i * a.stride_ax, two, al, e); };
-        EN::template run<DIR>(x, t, act, lds, tw, out);
+        EN::template run<DIR, SKIP>(x, t, act, lds, tw, out);
         return;
       }
     }
     if (act) {
-      if constexpr (SRC == SRC_GEN || SRC == SRC_SEQ) {
+      if constexpr (SRC == SRC_GEN || SRC == SRC_GEN_PART || SRC == SRC_SEQ) {
         const FieldRec& rec = a.recs[b * a.rec_stride];
         const Filt<T> f = load_filt<T>(rec, a.scale);
         const unsigned long long key = a.seed + (unsigned long long)b;
@@ -690,7 +698,7 @@ struct ColPass {
     }
     auto lds = [&](int i) -> E& { return sm[i * RS + cp]; };
     auto out = [&](int i, const E& e) { st_pair<T>(base + (long long)i * a.stride_ax, two, al, e); };
-    EN::template run<DIR>(x, t, act, lds, tw, out);
+    EN::template run<DIR, SKIP>(x, t, act, lds, tw, out);
   }
 };
 
@@ -1427,6 +1435,92 @@ struct RowC2RStaged {
     EN::template run<+1>(x, t, act, lds, tw, out);
   }
 };
+
+// The last-axis pass of a d = 2 plan whose column generation pass stopped
+// before its last stage (SRC_GEN_PART; that pass is VALU-bound, this one
+// memory-bound, so the stage moves to where the VALU has room).  Workgroup
+// (field, j) takes the RC rows j + m L / RC (m < RC) of the partial column
+// transform, which are the inputs of the column transform's last radix-RC
+// butterfly j: per column, twiddles W_L^{m j} and DFT_RC give the finished
+// rows j + m L / RC, in LDS; then the complex-to-real pass of RowC2RStaged on
+// them (same arithmetic in both steps as the two passes it replaces, so the
+// same bits), written back in place.  M threads run the column step (one per
+// column), NT * RC the row step.
+template <typename T, int M, class Rad, int L, int RC>
+struct RowXC2R {
+  using V = C<T>;
+  using E = Vec<T, 1>;
+  using RL = RowLds<M>;
+  static constexpr int RB = RC;
+  static constexpr int NT = M / Rad::get(0);
+  static constexpr int R0 = Rad::get(0);
+  static constexpr int LR = L / RC;   // butterflies of the column transform's last stage
+  static constexpr int T_ROW = (NT * RB + 63) / 64 * 64;
+  static constexpr int T_COL = (M + 63) / 64 * 64;
+  static constexpr int THREADS = T_ROW > T_COL ? T_ROW : T_COL;
+  static constexpr int LDS_BYTES = RB * RL::STRIDE * (int)sizeof(E) + 2 * M * (int)sizeof(V);
+  static constexpr bool WAVE = (64 % NT) == 0;
+  using EN = Eng<T, M, Rad, NT, 1, 2, WAVE>;
+
+  // a: the row pass's arguments (a.data = the fields, a.tw2 = W_{N_d}), a.tw =
+  // W_L of the column transform; a.rows = fields * L.
+  __device__ __forceinline__ static void run(const Args& a, int bid, char* smem) {
+    E* sm = reinterpret_cast<E*>(smem);
+    V* tw = reinterpret_cast<V*>(smem + RB * RL::STRIDE * sizeof(E));
+    const int tid = threadIdx.x;
+    const long long field = bid / LR;
+    const int j = bid % LR;
+    V* g = (V*)a.data + field * (long long)L * M;
+    // the column transform's last stage, one column per thread (the column
+    // pass's arithmetic: twiddles W_L^{m j}, DFT_RC), into the rows in LDS
+    if (tid < M) {
+      const V* twc = (const V*)a.tw;
+      V y[RC];
+#pragma unroll
+      for (int m = 0; m < RC; ++m) y[m] = g[(long long)(j + m * LR) * M + tid];
+#pragma unroll
+      for (int m = 1; m < RC; ++m) y[m] = ctw<+1>(y[m], twc[m * j]);
+      Dft<RC, +1, V>::run(y);
+#pragma unroll
+      for (int m = 0; m < RC; ++m) sm[m * RL::STRIDE + RL::idx(tid)].v[0] = y[m];
+    }
+    for (int i = tid; i < 2 * M; i += blockDim.x) tw[i] = ((const V*)a.tw2)[i];
+    __syncthreads();
+    // complex-to-real along the last axis (RowC2RStaged's arithmetic)
+    const int r = tid / NT;
+    const int t = tid % NT;
+    const bool act = (r < RB) && (t < NT);
+    V x[1][EN::REG];
+    if (act) {
+      const E* rowp = sm + r * RL::STRIDE;
+#pragma unroll
+      for (int m = 0; m < R0; ++m) {
+        const int k = t + m * NT;
+        const V xk = rowp[RL::idx(k)].v[0];
+        if (k == 0) {
+          x[0][m] = mk<T>(xk.x + xk.y, xk.x - xk.y);
+        } else {
+          const V xm = cconj(rowp[RL::idx(M - k)].v[0]);
+          const V ek = cadd(xk, xm);
+          const V ok = cmul(csub(xk, xm), tw[k]);
+          x[0][m] = mk<T>(ek.x - ok.y, ek.y + ok.x);
+        }
+      }
+    }
+    __syncthreads();
+    auto lds = [&](int i) -> E& { return sm[r * RL::STRIDE + RL::idx(i)]; };
+    V* o = g + (long long)(j + r * LR) * M;
+    auto out = [&](int i, const E& e) { o[i] = e.v[0]; };
+    EN::template run<+1>(x, t, act, lds, tw, out);
+  }
+};
+
+template <typename T, int M, class Rad, int L, int RC>
+__global__ void __launch_bounds__((RowXC2R<T, M, Rad, L, RC>::THREADS)) k_row_xc2r(Args a) {
+  using PS = RowXC2R<T, M, Rad, L, RC>;
+  __shared__ __align__(16) char smem[PS::LDS_BYTES];
+  PS::run(a, blockIdx.x, smem);
+}
 
 // Kernel wrapper of RowC2R.
 template <typename T, int M, class Rad, int RB, int PADR>

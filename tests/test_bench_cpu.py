@@ -53,6 +53,10 @@ def test_pass_bytes_and_kind_rows():
     # generation passes write the packed spectrum once; transforms read and write it
     assert bench.pass_bytes(0, fb) == fb
     assert bench.pass_bytes(5, fb) == 2 * fb
+    # the column pass without its last stage writes once; the pass that completes it reads and writes
+    assert bench.pass_bytes(111, fb) == fb
+    assert bench.pass_bytes(112, fb) == 2 * fb
+    assert bench.gen_pass_ops_per_point(512, 2) == bench.gen_pass_ops_per_point(512) - (7 + 3.5) / 2
     agg = bench.by_kind([(0, 256, 0.085), (5, 256, 0.080), (0, 256, 0.085), (5, 256, 0.080)], fb)
     assert agg[0]["launches"] == 2 and agg[0]["fields"] == 512
     assert agg[5]["bytes"] == 2 * 2 * fb * 256
