@@ -69,6 +69,7 @@ struct grf_plan_s {
   int device = 0;
   bool listed = true;       // every axis has compile-time kernels (else the runtime-radix passes)
   std::map<long long, TuneChoice> tune;   // per (pass, transform length): the tuner's or the cache's choice
+  mutable bool tuning = false;            // the tuner's view: the unsplit passes (UnsplitScope)
 };
 
 namespace grf {
@@ -458,12 +459,23 @@ grf_status run_launch(const grf_plan_s* p, const PassLaunch& pl, hipStream_t s) 
   return run_pass(p, pl.pass, pl.L, pl.a, 0, pl.count, s);
 }
 
+// The tuner chooses per pass between the compile-time kernel and
+// runtime-radix ones on the unsplit sequence (column generation + plain
+// complex-to-real); the split route runs where both keep the compile-time
+// kernels.  While a scope lives, the plan's sequences are the unsplit ones.
+struct UnsplitScope {
+  const grf_plan_s* p;
+  const bool prev;
+  explicit UnsplitScope(const grf_plan_s* q) : p(q), prev(q->tuning) { p->tuning = true; }
+  ~UnsplitScope() { p->tuning = prev; }
+};
+
 // d = 2 one-FFT in the counter order on a pair of lengths that has the
 // split kernels (the column transform's last stage in the last-axis pass),
 // with both passes on their compile-time kernels.  GRF_SPLIT=0 keeps the
 // unsplit passes.
 bool split_route(const grf_plan_s* p, bool seq) {
-  if (p->d != 2 || seq || p->reflect || p->desc.alg != GRF_ALG_ONE_FFT || !p->listed) return false;
+  if (p->d != 2 || seq || p->reflect || p->desc.alg != GRF_ALG_ONE_FFT || !p->listed || p->tuning) return false;
   if (grf::xc2r_geom(p->dtype, p->n1, p->M).threads <= 0) return false;
   if (const char* e = std::getenv("GRF_SPLIT"))
     if (e[0] == '0') return false;
@@ -1146,6 +1158,7 @@ bool parse_choice(const grf_plan_s* p, int pass, long long L, const std::vector<
 
 // The (pass, length) pairs of the plan's sampler that the tuner can choose for.
 std::vector<std::pair<int, int>> tunable_passes(const grf_plan_s* p, long long batch) {
+  const UnsplitScope unsplit(p);
   std::vector<std::pair<int, int>> v;
   for (const PassLaunch& pl : sample_passes(p, 0, nullptr, batch, p->rec_dev, 0, nullptr)) {
     if (tune_pass_name(pl.pass) == nullptr) continue;
@@ -1556,6 +1569,7 @@ grf_status grf_plan_tune(grf_plan p, int64_t batch, void* out, void* stream) {
   if (st != GRF_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   const long long nb = std::min<long long>(batch, chunk_fields(p, batch));
+  const UnsplitScope unsplit(p);
   const std::vector<PassLaunch> v = sample_passes(p, 0, nullptr, nb, p->rec_dev, 0, out);
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return fail(GRF_EDEVICE, "event creation");

@@ -21,6 +21,7 @@
 //   row  : last-axis complex-to-real (inverse) or real-to-complex (forward,
 //          with noise generation or a global load), one row per NT threads.
 #pragma once
+#include <type_traits>
 #include <utility>
 
 #include "grf_device.hpp"
@@ -109,6 +110,17 @@ __device__ __forceinline__ void stage_sync() {
   }
 }
 
+// An LDS accessor takes an index, or an index and an offset: with the second
+// form the offset (a constant once the loops are unrolled) stays apart from
+// the per-thread index, so that a padded layout adds it as an immediate.
+template <class Lds>
+__device__ __forceinline__ decltype(auto) lds_at(Lds& lds, int i, int off) {
+  if constexpr (std::is_invocable_v<Lds&, int, int>)
+    return lds(i, off);
+  else
+    return lds(i + off);
+}
+
 // ---------------------------------------------------------------------------
 // Block FFT engine: NC interleaved length-L transforms per thread group.
 // x[c][b*R + m] holds the inputs of butterfly b (j = t + b NT) of the current
@@ -174,7 +186,7 @@ struct Eng {
               E e;
 #pragma unroll
               for (int c = 0; c < NC; ++c) e.v[c] = x[c][b * Rs + m];
-              lds(base + m * Ns) = e;
+              lds_at(lds, base, m * Ns) = e;
             }
           }
         }
@@ -190,7 +202,7 @@ struct Eng {
           if (nb2 * NT == LR2 || j < LR2) {
 #pragma unroll
             for (int m = 0; m < R2; ++m) {
-              const E e = lds(j + m * LR2);
+              const E e = lds_at(lds, t, b * NT + m * LR2);
 #pragma unroll
               for (int c = 0; c < NC; ++c) x[c][b * R2 + m] = e.v[c];
             }
@@ -1278,6 +1290,10 @@ template <int M> struct RowLds {
   static constexpr int PADDED = M >= 16;
   static constexpr int STRIDE = M + (PADDED ? M / 16 : 0);
   __device__ __forceinline__ static int idx(int i) { return PADDED ? i + (i >> 4) : i; }
+  // idx(i + off) for off >= 0, with a multiple of 16 added after the shift
+  __device__ __forceinline__ static int idx(int i, int off) {
+    return (PADDED && off % 16 == 0) ? idx(i) + off + off / 16 : idx(i + off);
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -1373,7 +1389,7 @@ struct RowC2R {
         }
       }
     }
-    auto lds = [&](int i) -> E& { return sm[r * RL::STRIDE + RL::idx(i)]; };
+    auto lds = [&](int i, int off = 0) -> E& { return sm[r * RL::STRIDE + RL::idx(i, off)]; };
     auto out = [&](int i, const E& e) { o[i] = e.v[0]; };
     EN::template run<+1>(x, t, act, lds, tw, out);
   }
@@ -1417,11 +1433,12 @@ struct RowC2RStaged {
 #pragma unroll
       for (int m = 0; m < R0; ++m) {
         const int k = t + m * NT;
-        const V xk = rowp[RL::idx(k)].v[0];
+        const V xk = rowp[RL::idx(t, m * NT)].v[0];
         if (k == 0) {
           x[0][m] = mk<T>(xk.x + xk.y, xk.x - xk.y);
         } else {
-          const V xm = cconj(rowp[RL::idx(M - k)].v[0]);
+          // M - k = (M - t - (R0 - 1) NT) + (R0 - 1 - m) NT, both terms >= 0
+          const V xm = cconj(rowp[RL::idx(M - t - (R0 - 1) * NT, (R0 - 1 - m) * NT)].v[0]);
           const V ek = cadd(xk, xm);
           const V ok = cmul(csub(xk, xm), tw[k]);
           x[0][m] = mk<T>(ek.x - ok.y, ek.y + ok.x);
@@ -1429,7 +1446,7 @@ struct RowC2RStaged {
       }
     }
     __syncthreads();
-    auto lds = [&](int i) -> E& { return sm[r * RL::STRIDE + RL::idx(i)]; };
+    auto lds = [&](int i, int off = 0) -> E& { return sm[r * RL::STRIDE + RL::idx(i, off)]; };
     V* o = g + (long long)r * M;
     auto out = [&](int i, const E& e) { o[i] = e.v[0]; };
     EN::template run<+1>(x, t, act, lds, tw, out);
@@ -1496,11 +1513,12 @@ struct RowXC2R {
 #pragma unroll
       for (int m = 0; m < R0; ++m) {
         const int k = t + m * NT;
-        const V xk = rowp[RL::idx(k)].v[0];
+        const V xk = rowp[RL::idx(t, m * NT)].v[0];
         if (k == 0) {
           x[0][m] = mk<T>(xk.x + xk.y, xk.x - xk.y);
         } else {
-          const V xm = cconj(rowp[RL::idx(M - k)].v[0]);
+          // M - k = (M - t - (R0 - 1) NT) + (R0 - 1 - m) NT, both terms >= 0
+          const V xm = cconj(rowp[RL::idx(M - t - (R0 - 1) * NT, (R0 - 1 - m) * NT)].v[0]);
           const V ek = cadd(xk, xm);
           const V ok = cmul(csub(xk, xm), tw[k]);
           x[0][m] = mk<T>(ek.x - ok.y, ek.y + ok.x);
@@ -1508,7 +1526,7 @@ struct RowXC2R {
       }
     }
     __syncthreads();
-    auto lds = [&](int i) -> E& { return sm[r * RL::STRIDE + RL::idx(i)]; };
+    auto lds = [&](int i, int off = 0) -> E& { return sm[r * RL::STRIDE + RL::idx(i, off)]; };
     V* o = g + (long long)(j + r * LR) * M;
     auto out = [&](int i, const E& e) { o[i] = e.v[0]; };
     EN::template run<+1>(x, t, act, lds, tw, out);
@@ -1631,11 +1649,11 @@ struct RowR2C {
     if constexpr (SRC != SRC_LOAD) {
       if (act) {
 #pragma unroll
-        for (int m = 0; m < R0; ++m) x[0][m] = sm[r * RL::STRIDE + RL::idx(t + m * NT)].v[0];
+        for (int m = 0; m < R0; ++m) x[0][m] = sm[r * RL::STRIDE + RL::idx(t, m * NT)].v[0];
       }
       stage_sync<WAVE>();   // the first stage overwrites the row in LDS
     }
-    auto lds = [&](int i) -> E& { return sm[r * RL::STRIDE + RL::idx(i)]; };
+    auto lds = [&](int i, int off = 0) -> E& { return sm[r * RL::STRIDE + RL::idx(i, off)]; };
     EN::template run<-1>(x, t, act, lds, tw, [&](int i, const E& e) { lds(i) = e; });
     stage_sync<WAVE>();
     if (act) {

@@ -131,7 +131,7 @@ struct Gen1D {
     if (act) prepare(sm + r * RL::STRIDE, tw, t, x);
     __syncthreads();
     V* o = (V*)a.data + (f0 + r) * M;
-    auto lds = [&](int i) -> E& { return sm[r * RL::STRIDE + RL::idx(i)]; };
+    auto lds = [&](int i, int off = 0) -> E& { return sm[r * RL::STRIDE + RL::idx(i, off)]; };
     auto out = [&](int i, const E& e) { o[i] = e.v[0]; };
     EN::template run<+1>(x, t, act, lds, tw, out);
   }
@@ -174,7 +174,7 @@ struct Gen1D {
     }
     __syncthreads();
     const bool act = r < nrows;
-    auto lds = [&](int i) -> E& { return sm[r * RL::STRIDE + RL::idx(i)]; };
+    auto lds = [&](int i, int off = 0) -> E& { return sm[r * RL::STRIDE + RL::idx(i, off)]; };
     V x[1][EN::REG];
     if (act) {
 #pragma unroll
@@ -247,7 +247,7 @@ struct Gen1D {
       V x[1][EN::REG];
       if (act) prepare(sm + r * RL::STRIDE, tw, t, x);
       __syncthreads();
-      auto lds = [&](int i) -> E& { return sm[r * RL::STRIDE + RL::idx(i)]; };
+      auto lds = [&](int i, int off = 0) -> E& { return sm[r * RL::STRIDE + RL::idx(i, off)]; };
       auto none = [&](int, const E&) {};
       EN::template run<+1>(x, t, act, lds, tw, none);
       // x now holds the outputs i = t + b NT + m LRL of the last stage at

@@ -335,7 +335,7 @@ struct R2RRow {
         for (int m = 0; m < R0; ++m) x[0][m] = prep(t + m * NT, xa[m], xb[m], xc[m], xd[m], ab);
       }
     }
-    auto lds = [&](int i) -> E& { return sm[r * RL::STRIDE + RL::idx(i)]; };
+    auto lds = [&](int i, int off = 0) -> E& { return sm[r * RL::STRIDE + RL::idx(i, off)]; };
     auto none = [&](int, const E&) {};
     EN::template run<+1>(x, t, act, lds, tw, none);
     // x holds the outputs i = t + b NT + m LRL of the last stage at x[0][b R + m];
@@ -627,7 +627,7 @@ struct R2RRowF {
       }
     }
     __syncthreads();
-    auto lds = [&](int i) -> E& { return rowp[RL::idx(i)]; };
+    auto lds = [&](int i, int off = 0) -> E& { return rowp[RL::idx(i, off)]; };
     auto none = [&](int, const E&) {};
     EN::template run<-1>(x, t, act, lds, tw, none);
     constexpr int LAST = Rad::count - 1;
