@@ -197,12 +197,13 @@ PASS_NAMES = {0: "column noise+inverse FFT (axis 1)", 1: "inverse FFT (axis 2)",
               13: "column noise (recursive order)+inverse FFT (axis 1)", 14: "filter on the packed spectrum",
               109: "column fwd FFT x h x inv FFT (d = 3)", 110: "filter on the packed plane slots",
               111: "column noise+inverse FFT (axis 1) but its last stage",
-              112: "last stage of axis 1 + last-axis C2R"}
+              112: "last stage of axis 1 + last-axis C2R",
+              113: "column noise (recursive order)+inverse FFT (axis 1) but its last stage"}
 
 
 def pass_bytes(kind, field_bytes):
     """Algorithmic HBM bytes of one field through pass `kind` (output-sized packed spectrum)."""
-    return field_bytes * (1 if kind in (0, 6, 9, 12, 13, 111) else 2)
+    return field_bytes * (1 if kind in (0, 6, 9, 12, 13, 111, 113) else 2)
 
 
 def launch_table(plan, batch, torch, grf, reps):

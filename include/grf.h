@@ -240,11 +240,12 @@ grf_status grf_sample_from_noise(grf_plan plan, const void* noise, int64_t batch
  * slot, then for that slot alone forward along axis 1, its filter and the
  * inverse (three small launches), the middle-axis inverse transform and the
  * last-axis complex-to-real; the axis-1 column pass and the plane-slot filter
- * report the internal kinds 109 and 110.  One-FFT, d = 2, counter order, on
- * the 512 x 512 grid: the column pass stops before the last radix stage of
- * its transform (internal kind 111) and the last-axis pass runs that stage
- * before the complex-to-real (112), with the same bits as the two passes
- * above (the environment variable GRF_SPLIT=0 selects those instead).
+ * report the internal kinds 109 and 110.  One-FFT, d = 2, on the 512 x 512
+ * grid: the column pass stops before the last radix stage of
+ * its transform (internal kind 111; 113 in the recursive draw order) and the
+ * last-axis pass runs that stage before the complex-to-real (112), with the
+ * same bits as the two passes above (the environment variable GRF_SPLIT=0
+ * selects those instead).
  * grf_sample_stage_count returns the number of launches for a batch of
  * `batch` fields (host pointer); grf_sample_stage runs only launch `stage`
  * (0-based) with the arguments of grf_sample, so that each kernel can be

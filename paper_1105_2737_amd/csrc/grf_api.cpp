@@ -470,16 +470,17 @@ struct UnsplitScope {
   ~UnsplitScope() { p->tuning = prev; }
 };
 
-// d = 2 one-FFT in the counter order on a pair of lengths that has the
-// split kernels (the column transform's last stage in the last-axis pass),
-// with both passes on their compile-time kernels.  GRF_SPLIT=0 keeps the
-// unsplit passes.
-bool split_route(const grf_plan_s* p, bool seq) {
-  if (p->d != 2 || seq || p->reflect || p->desc.alg != GRF_ALG_ONE_FFT || !p->listed || p->tuning) return false;
+// d = 2 one-FFT (either draw order) on a pair of lengths that has the split
+// kernels (the column transform's last stage in the last-axis pass), with
+// both passes on their compile-time kernels.  GRF_SPLIT=0 keeps the unsplit
+// passes.
+bool split_route(const grf_plan_s* p) {
+  if (p->d != 2 || p->reflect || p->desc.alg != GRF_ALG_ONE_FFT || !p->listed || p->tuning) return false;
   if (grf::xc2r_geom(p->dtype, p->n1, p->M).threads <= 0) return false;
   if (const char* e = std::getenv("GRF_SPLIT"))
     if (e[0] == '0') return false;
-  const TuneChoice* c = tune_choice(p, grf::PASS_COL_GEN_INV, p->n1);
+  const bool seq = p->desc.draw_order == GRF_DRAW_RECURSIVE;
+  const TuneChoice* c = tune_choice(p, seq ? grf::PASS_COL_SEQ_INV : grf::PASS_COL_GEN_INV, p->n1);
   const TuneChoice* r = tune_choice(p, grf::PASS_ROW_C2R, p->M);
   return !(c && c->generic) && !(r && r->generic);
 }
@@ -581,9 +582,9 @@ void chunk_passes(const grf_plan_s* p, uint64_t seed, const void* zsrc, long lon
       a.stride_fixed = p->M;
       a.nfixed = p->no;
     }
-    if (split_route(p, seq)) {
+    if (split_route(p)) {
       // the column transform's last stage in the last-axis pass
-      push(grf::PASS_COL_GEN_PART, p->n1, a);
+      push(seq ? grf::PASS_COL_SEQ_PART : grf::PASS_COL_GEN_PART, p->n1, a);
       Args b = a;
       b.src = nullptr;
       b.tw = p->tw_col1;

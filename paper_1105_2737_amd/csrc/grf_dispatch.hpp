@@ -51,7 +51,8 @@ enum PassKind {
   PASS_COL_FILTER3 = 109,                      // two-FFT, d = 3: PASS_COL_FILTER without the packed plane slot
   PASS_SPEC_FILTER0 = 110,                     // two-FFT, d = 3: the filter on the packed plane slots only
   PASS_COL_GEN_PART = 111,                     // PASS_COL_GEN_INV stopped before the transform's last stage
-  PASS_ROW_XC2R = 112,                         // that last stage + PASS_ROW_C2R (after PASS_COL_GEN_PART)
+  PASS_ROW_XC2R = 112,                         // that last stage + PASS_ROW_C2R (after PASS_COL_GEN_PART or _SEQ_PART)
+  PASS_COL_SEQ_PART = 113,                     // PASS_COL_SEQ_INV stopped before the transform's last stage
 };
 
 inline bool is_r2r_pass(int p) {
@@ -97,9 +98,11 @@ int radix_plan(int L, int* rad);
 hipError_t launch_generic(int pass, int dtype, const Args& a, long long nblocks, hipStream_t s);
 
 // The d = 2 one-FFT sampler with the column transform's last stage moved into
-// the last-axis pass (PASS_COL_GEN_PART + PASS_ROW_XC2R), for the (N_1, M)
-// pairs listed; the two passes give the bits of PASS_COL_GEN_INV +
-// PASS_ROW_C2R.
+// the last-axis pass (PASS_COL_GEN_PART or PASS_COL_SEQ_PART, then
+// PASS_ROW_XC2R), for the (N_1, M) pairs listed; the two passes give the bits
+// of PASS_COL_GEN_INV (PASS_COL_SEQ_INV) + PASS_ROW_C2R.
+// (1024, 512) measured slower: 0.689 -> 0.702 ms per 1024^2 x 256 step, the
+// last-axis pass gaining more than the column pass (last radix 4) loses.
 #define GRF_XC2R_PAIRS(X) X(512, 256)
 constexpr bool xc2r_col_length(int L) {
 #define GRF_X(L_, M_) L == L_ ||

@@ -476,9 +476,9 @@ struct TwFill {
 // ---------------------------------------------------------------------------
 // Column pass over a leading axis.
 // SRC_SEQ: generation with the normals in the recursive algorithm's draw order.
-// SRC_GEN_PART: generation like SRC_GEN, the transform stopped before its last
-// stage (the last-axis pass RowXC2R completes it).
-enum { SRC_GEN = 0, SRC_LOAD = 1, SRC_SEQ = 2, SRC_GEN_PART = 3 };
+// SRC_GEN_PART, SRC_SEQ_PART: generation like SRC_GEN, SRC_SEQ, the transform
+// stopped before its last stage (the last-axis pass RowXC2R completes it).
+enum { SRC_GEN = 0, SRC_LOAD = 1, SRC_SEQ = 2, SRC_GEN_PART = 3, SRC_SEQ_PART = 4 };
 
 template <typename T, int L, class Rad, int CP, int PAD, int SRC, int DIR>
 struct ColPass {
@@ -495,7 +495,8 @@ struct ColPass {
   // 1000 and 1024).
   static constexpr bool GEN_STRAIGHT = L >= 360;
   using EN = Eng<T, L, Rad, NT, 2, 1>;
-  static constexpr int SKIP = SRC == SRC_GEN_PART ? 1 : 0;
+  static constexpr bool SEQ = SRC == SRC_SEQ || SRC == SRC_SEQ_PART;
+  static constexpr int SKIP = (SRC == SRC_GEN_PART || SRC == SRC_SEQ_PART) ? 1 : 0;
 
   // Noise generation of tile `tile` of field b (fixed index fx) straight into
   // x, for the common case of generated noise and a filter table: the table
@@ -668,7 +669,7 @@ struct ColPass {
       }
     }
     for (int i = tid; i < L; i += blockDim.x) tw[i] = ((const V*)a.tw)[i];
-    if constexpr (SRC == SRC_SEQ) {
+    if constexpr (SEQ) {
       if (a.src == nullptr && (a.M & 1) == 0) {
         gen_seq_fast(a, fx, b, t, cp, m0, act, x);
         if (act && tile == 0 && m0 == 0) {
@@ -687,13 +688,13 @@ struct ColPass {
       }
     }
     if (act) {
-      if constexpr (SRC == SRC_GEN || SRC == SRC_GEN_PART || SRC == SRC_SEQ) {
+      if constexpr (SRC == SRC_GEN || SRC == SRC_GEN_PART || SEQ) {
         const FieldRec& rec = a.recs[b * a.rec_stride];
         const Filt<T> f = load_filt<T>(rec, a.scale);
         const unsigned long long key = a.seed + (unsigned long long)b;
         const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
         const T* zsrc = (const T*)a.src;
-        if constexpr (SRC == SRC_SEQ) {
+        if constexpr (SEQ) {
           static_for<R0>([&](auto mc) {
             constexpr int m = decltype(mc)::value;
             gen_pair<T, true>(a, f, zsrc, b, k0, k1, t + m * NT, fx, m0, x[0][m], x[1][m]);
@@ -1472,9 +1473,8 @@ struct RowXC2R {
   static constexpr int NT = M / Rad::get(0);
   static constexpr int R0 = Rad::get(0);
   static constexpr int LR = L / RC;   // butterflies of the column transform's last stage
-  static constexpr int T_ROW = (NT * RB + 63) / 64 * 64;
-  static constexpr int T_COL = (M + 63) / 64 * 64;
-  static constexpr int THREADS = T_ROW > T_COL ? T_ROW : T_COL;
+  static constexpr int THREADS = (NT * RB + 63) / 64 * 64;
+  static constexpr int CPT = (M + THREADS - 1) / THREADS;   // columns per thread in the column stage
   static constexpr int LDS_BYTES = RB * RL::STRIDE * (int)sizeof(E) + 2 * M * (int)sizeof(V);
   static constexpr bool WAVE = (64 % NT) == 0;
   using EN = Eng<T, M, Rad, NT, 1, 2, WAVE>;
@@ -1488,18 +1488,30 @@ struct RowXC2R {
     const long long field = bid / LR;
     const int j = bid % LR;
     V* g = (V*)a.data + field * (long long)L * M;
-    // the column transform's last stage, one column per thread (the column
+    // the column transform's last stage, CPT columns per thread (the column
     // pass's arithmetic: twiddles W_L^{m j}, DFT_RC), into the rows in LDS
-    if (tid < M) {
+    {
       const V* twc = (const V*)a.tw;
-      V y[RC];
+      V y[CPT][RC];
 #pragma unroll
-      for (int m = 0; m < RC; ++m) y[m] = g[(long long)(j + m * LR) * M + tid];
+      for (int q = 0; q < CPT; ++q) {
+        const int c = tid + q * THREADS;
+        if (M % THREADS == 0 || c < M) {
 #pragma unroll
-      for (int m = 1; m < RC; ++m) y[m] = ctw<+1>(y[m], twc[m * j]);
-      Dft<RC, +1, V>::run(y);
+          for (int m = 0; m < RC; ++m) y[q][m] = g[(long long)(j + m * LR) * M + c];
+        }
+      }
 #pragma unroll
-      for (int m = 0; m < RC; ++m) sm[m * RL::STRIDE + RL::idx(tid)].v[0] = y[m];
+      for (int q = 0; q < CPT; ++q) {
+        const int c = tid + q * THREADS;
+        if (M % THREADS == 0 || c < M) {
+#pragma unroll
+          for (int m = 1; m < RC; ++m) y[q][m] = ctw<+1>(y[q][m], twc[m * j]);
+          Dft<RC, +1, V>::run(y[q]);
+#pragma unroll
+          for (int m = 0; m < RC; ++m) sm[m * RL::STRIDE + RL::idx(c)].v[0] = y[q][m];
+        }
+      }
     }
     for (int i = tid; i < 2 * M; i += blockDim.x) tw[i] = ((const V*)a.tw2)[i];
     __syncthreads();

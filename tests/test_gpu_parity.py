@@ -300,15 +300,17 @@ def test_chunked_schedule_matches_unchunked(grf, dims, alg, dtype):
     assert _with_env(big, lambda: grf.grf_sample_stage_count(plan.handle, B)) == nper
 
 
+@pytest.mark.parametrize("order", ["counter", "recursive"])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
-def test_split_last_stage_matches_unsplit(grf, dtype):
+def test_split_last_stage_matches_unsplit(grf, dtype, order):
     """512 x 512, one-FFT: the column pass without its last radix stage plus the
-    last-axis pass that runs it (kinds 111, 112) give the bits of the column
-    pass plus the plain complex-to-real (GRF_SPLIT=0), with seeds, per-field
-    theta and supplied noise, over a ragged chunk schedule."""
+    last-axis pass that runs it (kinds 111 or 113, then 112) give the bits of
+    the column pass plus the plain complex-to-real (GRF_SPLIT=0), with seeds,
+    per-field theta and supplied noise, over a ragged chunk schedule."""
     dims, B = (512, 512), 5
     esz = 4 if dtype == torch.float32 else 8
-    plan = grf.Plan(dims, alg=2, dtype=dtype, cov="matern", sigma=1.0, length_scale=0.1, nu=1.5)
+    plan = grf.Plan(dims, alg=2, dtype=dtype, cov="matern", sigma=1.0, length_scale=0.1, nu=1.5, draw_order=order)
+    gen, part = ((grf.GRF_PASS_COL_GEN_INV, 111) if order == "counter" else (grf.GRF_PASS_COL_SEQ_INV, 113))
     g = torch.Generator().manual_seed(8)
     theta = torch.stack([1 + torch.rand(B, generator=g), 0.05 + 0.1 * torch.rand(B, generator=g),
                          0.5 + 2 * torch.rand(B, generator=g)], 1).double()
@@ -316,18 +318,18 @@ def test_split_last_stage_matches_unsplit(grf, dtype):
     chunk = {"GRF_CHUNK_BYTES": str(2 * dims[0] * dims[1] * esz)}   # 2, 2, 1 fields
     kinds = _with_env(chunk, lambda: [grf.grf_sample_stage_info(plan.handle, B, s)[0]
                                       for s in range(grf.grf_sample_stage_count(plan.handle, B))])
-    assert kinds == [111, 112] * 3
+    assert kinds == [part, 112] * 3
     off = _with_env(dict(chunk, GRF_SPLIT="0"), lambda: [grf.grf_sample_stage_info(plan.handle, B, s)[0]
                                                         for s in range(grf.grf_sample_stage_count(plan.handle, B))])
-    assert off == [grf.GRF_PASS_COL_GEN_INV, grf.GRF_PASS_ROW_C2R] * 3
+    assert off == [gen, grf.GRF_PASS_ROW_C2R] * 3
     for run in (lambda: plan.sample(seed=13, batch=B), lambda: plan.sample(seed=2, batch=B, theta=theta),
                 lambda: plan.sample_from_noise(z)):
         got = _with_env(chunk, run)
         ref = _with_env(dict(chunk, GRF_SPLIT="0"), run)
         torch.cuda.synchronize()
         assert torch.equal(got, ref)
-    # and against the oracle, two fields
-    ref = oracle_fields(dims, (1.0, 1.0), "matern", (1.0, 0.1, 1.5), 13, 2, 2)
-    got = plan.sample(seed=13, batch=2).double().cpu().numpy()
-    for b in range(2):
-        assert relerr(got[b], ref[b]) <= TOL[dtype]
+    if order == "counter":   # and against the oracle, two fields (the recursive order's oracle test is its own)
+        ref = oracle_fields(dims, (1.0, 1.0), "matern", (1.0, 0.1, 1.5), 13, 2, 2)
+        got = plan.sample(seed=13, batch=2).double().cpu().numpy()
+        for b in range(2):
+            assert relerr(got[b], ref[b]) <= TOL[dtype]
