@@ -493,16 +493,22 @@ struct ColPass {
   // occupancy anyway; for short columns its extra registers cost occupancy
   // (measured: 18% slower at L = 96, even at 256, 11% faster at 360, 22% at
   // 1000 and 1024).
+  // Without a filter table (per-field parameters, 3D plans) the same holds:
+  // 512^2 x 1024 with per-field theta 0.643 -> 0.629 ms, 1024^2 x 64 0.181 ->
+  // 0.174 ms, but 256^3 x 16 (L = 256) 1.024 -> 1.059 ms.
   static constexpr bool GEN_STRAIGHT = L >= 360;
   using EN = Eng<T, L, Rad, NT, 2, 1>;
   static constexpr bool SEQ = SRC == SRC_SEQ || SRC == SRC_SEQ_PART;
   static constexpr int SKIP = (SRC == SRC_GEN_PART || SRC == SRC_SEQ_PART) ? 1 : 0;
 
   // Noise generation of tile `tile` of field b (fixed index fx) straight into
-  // x, for the common case of generated noise and a filter table: the table
-  // loads of all rows are issued first and the R0 Philox blocks are
-  // independent, so they interleave.  Only the lanes holding the packed plane
-  // slot (m0 = 0, first tile) take the general route afterwards.
+  // x, for generated noise: the filter-table loads of all rows are issued
+  // first and the R0 Philox blocks are independent, so they interleave.  Only
+  // the lanes holding the packed plane slot (m0 = 0, first tile) take the
+  // general route afterwards.
+  // TABLE = false: no table (per-field parameters, or a 3D plan); h is
+  // evaluated per entry by gen_pair's float expressions, after the noise.
+  template <bool TABLE = true>
   __device__ __forceinline__ static void gen_fast(const Args& a, int tile, int fx, int b, int t, int m0, bool act,
                                                   V (&x)[2][EN::REG]) {
     if (!act) return;
@@ -511,10 +517,12 @@ struct ColPass {
     const T* ht = (const T*)a.htab;
     struct alignas(2 * sizeof(T)) P2 { T x, y; };
     P2 hp[R0];
+    if constexpr (TABLE) {
 #pragma unroll
-    for (int m = 0; m < R0; ++m) {
-      const int row = (t + m * NT) * a.no + fx;
-      hp[m] = *reinterpret_cast<const P2*>(ht + (long long)row * (a.M + 2) + m0);
+      for (int m = 0; m < R0; ++m) {
+        const int row = (t + m * NT) * a.no + fx;
+        hp[m] = *reinterpret_cast<const P2*>(ht + (long long)row * (a.M + 2) + m0);
+      }
     }
     T z[R0][4];
 #pragma unroll
@@ -524,6 +532,19 @@ struct ColPass {
     }
     // all noise first, then the products that wait for the table loads
     __builtin_amdgcn_sched_barrier(0);
+    if constexpr (!TABLE) {
+      const Filt<T> f = load_filt<T>(a.recs[b * a.rec_stride], a.scale);
+      const int qo = wrapk(fx, a.no);
+      const T p2o = (T)(qo * qo) * (T)a.il2[1], il2d = (T)a.il2[2];
+      const T e0 = (T)(m0 * m0) * il2d, e1 = (T)((m0 + 1) * (m0 + 1)) * il2d;
+#pragma unroll
+      for (int m = 0; m < R0; ++m) {
+        const int q1 = wrapk(t + m * NT, a.n1);
+        const T p2b = (T)(q1 * q1) * (T)a.il2[0] + p2o;
+        hp[m].x = filt_h(f, p2b + e0);
+        hp[m].y = filt_h(f, p2b + e1);
+      }
+    }
     const T s = (T)0.70710678118654752440;
 #pragma unroll
     for (int m = 0; m < R0; ++m) {
@@ -532,7 +553,7 @@ struct ColPass {
       x[1][m] = mk<T>(g1 * z[m][2], g1 * z[m][3]);
     }
     if (tile == 0 && m0 == 0) {
-      const Filt<T> f = load_filt<T>(a.recs[0], a.scale);
+      const Filt<T> f = load_filt<T>(a.recs[b * a.rec_stride], a.scale);
 #pragma unroll
       for (int m = 0; m < R0; ++m) gen_pair<T>(a, f, nullptr, b, k0, k1, t + m * NT, fx, 0, x[0][m], x[1][m]);
     }
@@ -657,10 +678,13 @@ struct ColPass {
     V* base = (V*)a.data + (long long)b * a.field_stride + (long long)fx * a.stride_fixed + m0;
     V x[2][EN::REG];
     if constexpr ((SRC == SRC_GEN || SRC == SRC_GEN_PART) && GEN_STRAIGHT) {
-      if (a.src == nullptr && a.htab != nullptr) {
+      if (a.src == nullptr) {
         TwFill<V, L, THREADS> twf;
         if (tid < THREADS) twf.load((const V*)a.tw, tid);
-        gen_fast(a, tile, fx, b, t, m0, act, x);
+        if (a.htab != nullptr)
+          gen_fast<true>(a, tile, fx, b, t, m0, act, x);
+        else
+          gen_fast<false>(a, tile, fx, b, t, m0, act, x);
         if (tid < THREADS) twf.store(tw, tid);   // first read after the stage-0 barrier
         auto lds = [&](int i) -> E& { return sm[i * RS + cp]; };
         auto out = [&](int i, const E& e) { st_pair<T>(base + (long long)i * a.stride_ax, two, al, e); };
