@@ -67,9 +67,11 @@ GRF_ALTROW(500, 5, 2, 5, 10, 10)
 GRF_ALTROW(512, 16, 8, 16, 8, 4)
 #undef GRF_ALTROW
 
+// (FLY = false: the per-field filter is evaluated by the per-row route; the
+// straight-line form's registers would be the whole persistent kernel's)
 template <int L, int CP, bool ALT = false>
 using BColPass = ColPass<float, L, typename std::conditional<ALT, BatchAltCol<L>, ColCfg<L>>::type::Rad, CP,
-                         ColCfg<L>::PAD, SRC_GEN, +1>;
+                         ColCfg<L>::PAD, SRC_GEN, +1, false>;
 template <int M, int RB, bool ALT = false>
 using BRowPass = RowC2RStaged<float, M, typename std::conditional<ALT, BatchAltRow<M>, RowCfg<M>>::type::Rad, RB, 0>;
 

@@ -480,7 +480,8 @@ struct TwFill {
 // stopped before its last stage (the last-axis pass RowXC2R completes it).
 enum { SRC_GEN = 0, SRC_LOAD = 1, SRC_SEQ = 2, SRC_GEN_PART = 3, SRC_SEQ_PART = 4 };
 
-template <typename T, int L, class Rad, int CP, int PAD, int SRC, int DIR>
+// FLY: the straight-line generation also where there is no filter table.
+template <typename T, int L, class Rad, int CP, int PAD, int SRC, int DIR, bool FLY = true>
 struct ColPass {
   using V = C<T>;
   using E = Vec<T, 2>;
@@ -678,13 +679,17 @@ struct ColPass {
     V* base = (V*)a.data + (long long)b * a.field_stride + (long long)fx * a.stride_fixed + m0;
     V x[2][EN::REG];
     if constexpr ((SRC == SRC_GEN || SRC == SRC_GEN_PART) && GEN_STRAIGHT) {
-      if (a.src == nullptr) {
+      if (a.src == nullptr && (FLY || a.htab != nullptr)) {
         TwFill<V, L, THREADS> twf;
         if (tid < THREADS) twf.load((const V*)a.tw, tid);
-        if (a.htab != nullptr)
+        if constexpr (FLY) {
+          if (a.htab != nullptr)
+            gen_fast<true>(a, tile, fx, b, t, m0, act, x);
+          else
+            gen_fast<false>(a, tile, fx, b, t, m0, act, x);
+        } else {
           gen_fast<true>(a, tile, fx, b, t, m0, act, x);
-        else
-          gen_fast<false>(a, tile, fx, b, t, m0, act, x);
+        }
         if (tid < THREADS) twf.store(tw, tid);   // first read after the stage-0 barrier
         auto lds = [&](int i) -> E& { return sm[i * RS + cp]; };
         auto out = [&](int i, const E& e) { st_pair<T>(base + (long long)i * a.stride_ax, two, al, e); };
