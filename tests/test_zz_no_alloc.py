@@ -23,7 +23,7 @@ def _theta(batch, seed):
 
 
 @pytest.mark.parametrize("dims,dtype", [((96, 128), torch.float32), ((64, 48, 48), torch.float32),
-                                        ((96, 128), torch.float64)])
+                                        ((96, 128), torch.float64), ((512, 512), torch.float32)])
 def test_noalloc_matches_sample(dims, dtype):
     import paper_1105_2737_amd as grf
     from paper_1105_2737_amd import _lib as L
