@@ -81,8 +81,8 @@ enum { GRF_DRAW_COUNTER = 0, GRF_DRAW_RECURSIVE = 1 };
  *             16, 24, 32, 48, 64, 96, 128, 180, 256, 360, 500, 512, 1000, 1024},
  *             N_d/2 from {2, 4, ..., 512, 1024, 2048} (the same list with 2,
  *             1024 and 2048); every other length runs on runtime-radix kernels
- *             (sampling with either algorithm, d = 1, 2, 3).  Reflecting
- *             boundaries, the recursive draw order and grf_backward take the
+ *             (sampling and grf_backward with either algorithm, d = 1, 2, 3).
+ *             Reflecting boundaries and the recursive draw order take the
  *             listed lengths only (GRF_EUNSUPPORTED otherwise).
  *   lengths   l_1..l_d > 0 (edge lengths of D; the unit torus is all 1).
  *   alg       GRF_ALG_ONE_FFT or GRF_ALG_TWO_FFT (periodic boundaries, counter draw order).
@@ -310,8 +310,10 @@ grf_status grf_noise(grf_plan plan, uint64_t seed, int64_t batch, void* noise_ou
  * draws); ndim = 1, 2 or 3.
  * For the two-FFT algorithm xi = F[z] / sqrt(P) enters in place of the
  * Hermitian noise, and dL/dz = F*[h F[grad_out]] / sqrt(P), the sampler
- * applied to grad_out.  Plans with a grid length outside the compiled lists
- * get GRF_EUNSUPPORTED. */
+ * applied to grad_out.  At a grid length outside the compiled lists the
+ * one-FFT reduction reads G = F[grad_out], transformed along every axis by the
+ * runtime-radix passes, back from the workspace (one more pass over the
+ * spectrum than the fused column kernel of a listed length). */
 grf_status grf_backward(grf_plan plan, uint64_t seed, const void* noise, int64_t batch, const double* theta,
                         const void* grad_out, double* grad_theta, void* grad_noise, void* workspace,
                         size_t workspace_bytes, void* stream);
@@ -319,10 +321,13 @@ grf_status grf_backward(grf_plan plan, uint64_t seed, const void* noise, int64_t
 /* ---- Batches of fields with different sizes and parameters --------------
  * d = 2, one-FFT algorithm, float32.  Every field has its own grid, edge
  * lengths, covariance parameters and seed.  grf_batch_sample runs the whole
- * batch as two persistent launches (column generation of every field, then
- * the last-axis pass of every field), each workgroup taking work items from an
- * atomic queue in decreasing order of cost; the launches are captured once in
- * a hipGraph and replayed.  Results are bit-identical to sampling each field
+ * batch as one persistent launch (per-XCD queues of column-generation items
+ * and last-axis items, a last-axis item waiting on its field's readiness
+ * counter) or, where one launch cannot reach all 8 XCDs, as two (column
+ * generation of every field, then the last-axis pass of every field), each
+ * workgroup taking work items from an atomic queue in decreasing order of
+ * cost; the launches are captured once in a hipGraph and replayed
+ * (grf_batch_info tells which).  Results are bit-identical to sampling each field
  * with its own plan.  N_1 must be one of {64, 96, 128, 180, 256, 360, 500, 512,
  * 1000, 1024} and N_2/2 one of {32, 48, 64, 96, 128, 180, 256, 360, 500, 512}. */
 typedef struct grf_batch_s* grf_batch;

@@ -280,7 +280,9 @@ class GRFSample(torch.autograd.Function):
 
 class Batch:
     """Fields of different sizes and parameters (d = 2, one-FFT, float32)
-    sampled together by two persistent launches replayed from a hipGraph.
+    sampled together by one persistent launch (per-XCD queues of column and
+    last-axis items, per-field readiness counters; two launches where one
+    cannot reach all 8 XCDs) replayed from a hipGraph.
 
     fields: iterable of dicts with keys dims=(N_1, N_2), seed, and optionally
     lengths, cov ('gaussian' | 'matern' | 'exponential'), sigma, length_scale, nu.

@@ -224,13 +224,18 @@ AdjTiles adj_tiles(const grf_plan_s* p) {
     const int nt = (p->M + 2 * g.per_wg - 1) / (2 * g.per_wg);
     return AdjTiles{nt, nt * p->no};
   }
-  if (p->desc.alg == GRF_ALG_TWO_FFT && p->d != 2) {
+  if (p->desc.alg == GRF_ALG_TWO_FFT && (p->d != 2 || !p->listed)) {
     const long long slots = (long long)p->n1 * p->no * p->M;
     const int nt = (int)((slots + 255) / 256);
     return AdjTiles{nt, nt};
   }
   if (p->d == 1) {
-    const int nt = (p->M / 2 + 255) / 256;
+    const int nt = ((p->M + 1) / 2 + 255) / 256;
+    return AdjTiles{nt, nt};
+  }
+  if (!p->listed) {   // k_grad_gen: one slot pair per thread
+    const long long slots = (long long)p->n1 * p->no * ((p->M + 1) / 2);
+    const int nt = (int)((slots + 255) / 256);
     return AdjTiles{nt, nt};
   }
   const grf::Geom g = grf::pass_geom(p->d == 3 ? grf::PASS_COL_GRAD3 : grf::PASS_COL_GRAD, p->dtype, p->n1);
@@ -875,6 +880,8 @@ grf_status adj_row_r2c(const grf_plan_s* p, const Args& c, const void* g, long l
   return run_pass(p, grf::PASS_ROW_R2C_LOAD, p->M, r, 0, nb, s);
 }
 
+grf_status fwd_all_leading(const grf_plan_s* p, void* data, long long nb, hipStream_t s);
+
 // One-FFT algorithm, periodic: G = F[g] by the last-axis R2C, (d = 3: the
 // middle axis forward,) then axis 1 forward inside the reduction pass; d = 1:
 // the reduction reads the last-axis spectrum.
@@ -888,6 +895,16 @@ grf_status adj_chunk_one_fft(const grf_plan_s* p, Args c, const void* g, const A
   if (p->d == 1) {
     c.ntile = at.ntile;
     hipError_t e = grf::launch_grad1d(p->dtype, c, nb * at.ntile, s);
+    return e == hipSuccess ? GRF_OK : hip_fail(e, "adjoint launch");
+  }
+  if (!p->listed) {
+    // lengths without a compile-time adjoint column kernel: G transformed
+    // along every leading axis in place, then the reduction reads it back
+    st = fwd_all_leading(p, c.data, nb, s);
+    if (st != GRF_OK) return st;
+    c.ntile = at.ntile;
+    if (nb * at.ntile > 0x7fffffffLL) return fail(GRF_EINVAL, "batch too large for one launch");
+    hipError_t e = grf::launch_grad_gen(p->dtype, c, nb * at.ntile, s);
     return e == hipSuccess ? GRF_OK : hip_fail(e, "adjoint launch");
   }
   if (p->d == 3) {
@@ -936,6 +953,19 @@ grf_status fwd_leading(const grf_plan_s* p, void* data, long long nb, hipStream_
   return run_pass(p, grf::PASS_COL_LOAD_FWD, p->n1, c, 0, nb, s);
 }
 
+// Forward transforms along every leading axis of a packed spectrum, d = 2
+// included (axis 1), in place.
+grf_status fwd_all_leading(const grf_plan_s* p, void* data, long long nb, hipStream_t s) {
+  if (p->d != 2) return fwd_leading(p, data, nb, s);
+  Args c = base_args(p, nb);
+  c.data = data;
+  c.tw = p->tw_col1;
+  c.stride_ax = p->M;
+  c.stride_fixed = p->M;
+  c.nfixed = 1;
+  return run_pass(p, grf::PASS_COL_LOAD_FWD, p->n1, c, 0, nb, s);
+}
+
 // Two-FFT algorithm: xi = F[z] / sqrt(P), the white noise through the same
 // transforms into spec2 (the table of a density-defined family already holds
 // the 1/sqrt(P)); dL/dz is left to the caller (the sampler applied to g).
@@ -943,10 +973,11 @@ grf_status adj_chunk_two_fft(const grf_plan_s* p, Args c, const void* g, void* s
                              long long nb, hipStream_t s) {
   grf_status st = adj_row_r2c(p, c, g, nb, s);
   if (st != GRF_OK) return st;
-  if (p->d != 2) {
-    // d = 1, 3: G = F[g] and F[z] transformed along every axis, then one
+  if (p->d != 2 || !p->listed) {
+    // d = 1, 3 (and d = 2 at lengths without a compile-time adjoint column
+    // kernel): G = F[g] and F[z] transformed along every axis, then one
     // reduction pass over the two packed spectra
-    st = fwd_leading(p, c.data, nb, s);
+    st = fwd_all_leading(p, c.data, nb, s);
     if (st != GRF_OK) return st;
     Args rz = base_args(p, nb);
     rz.data = spec2;
@@ -957,7 +988,7 @@ grf_status adj_chunk_two_fft(const grf_plan_s* p, Args c, const void* g, void* s
     rz.rows = nb * (p->P / p->nd);
     st = run_pass(p, c.src ? grf::PASS_ROW_R2C_LOAD : grf::PASS_ROW_R2C_GEN, p->M, rz, 0, nb, s);
     if (st != GRF_OK) return st;
-    st = fwd_leading(p, spec2, nb, s);
+    st = fwd_all_leading(p, spec2, nb, s);
     if (st != GRF_OK) return st;
     c.src2 = spec2;
     c.scale = p->table_only ? 1.0 : 1.0 / std::sqrt((double)p->P);
@@ -1513,7 +1544,6 @@ grf_status grf_backward(grf_plan p, uint64_t seed, const void* noise, int64_t ba
   if (batch == 0) return GRF_OK;
   if (grad_out == nullptr || grad_theta == nullptr) return fail(GRF_EINVAL, "null gradient pointer");
   if (batch > 0x7fffffff) return fail(GRF_EINVAL, "batch too large");
-  if (!p->listed) return fail(GRF_EUNSUPPORTED, "the adjoint takes the listed grid lengths only");
   const WsLayout w = ws_layout(p, batch, GRF_OP_BACKWARD);
   if (workspace == nullptr || workspace_bytes < w.total) return fail(GRF_EINVAL, "workspace too small");
   grf_status st = check_stream_device(p);

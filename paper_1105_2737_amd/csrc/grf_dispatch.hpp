@@ -176,6 +176,10 @@ hipError_t launch_grad_plane(int dtype, const Args& a, hipStream_t s);
 // over the packed spectra of g and z (a.ntile workgroups per field).
 hipError_t launch_spec_filter(int dtype, const Args& a, long long nblocks, bool slot0, hipStream_t s);
 hipError_t launch_grad_spec(int dtype, const Args& a, long long nblocks, hipStream_t s);
+// One-FFT adjoint (d = 2, 3) on a spectrum transformed along every axis (grid
+// lengths without a compile-time adjoint column kernel): a.ntile workgroups of
+// 256 threads per field, one slot pair of a row per thread.
+hipError_t launch_grad_gen(int dtype, const Args& a, long long nblocks, hipStream_t s);
 // The one-FFT sampler's half-spectrum A = h xi before the inverse transforms
 // (a.ntile workgroups per field).
 hipError_t launch_debug_spectrum(int dtype, const Args& a, long long nblocks, hipStream_t s);

@@ -156,7 +156,9 @@ __global__ void __launch_bounds__(256) k_grad1d(Args a) {
   const int tile = blockIdx.x % a.ntile;
   const int b = blockIdx.x / a.ntile;
   const int q = tile * 256 + threadIdx.x;
-  const int NQ = a.M / 2;
+  // counter order: block q holds the entries 2q, 2q + 1 (an odd N/2 leaves the
+  // last block with one entry, its draws 2 and 3 unused)
+  const int NQ = a.seq ? a.M / 2 : (a.M + 1) / 2;
   double acc0 = 0, acc1 = 0, acc2 = 0;
   if (q < NQ) {
     const FieldRec& rec = a.recs[b * a.rec_stride];
@@ -168,7 +170,7 @@ __global__ void __launch_bounds__(256) k_grad1d(Args a) {
       normals4<T, true>((uint32_t)q, 0u, (uint32_t)a.tag, (uint32_t)key, (uint32_t)(key >> 32), z);
     } else {
       const T* p = (const T*)a.src + (long long)b * a.nd + 4 * q;
-      for (int e = 0; e < 4; ++e) z[e] = p[e];
+      for (int e = 0; e < 4; ++e) z[e] = 4 * q + e < a.nd ? p[e] : (T)0;
     }
     const double il2 = a.il2[2];
     const T* ht = (const T*)a.htab;
@@ -210,12 +212,14 @@ __global__ void __launch_bounds__(256) k_grad1d(Args a) {
       acc2 = ad.acc2;
     } else {
     const int ka = 2 * q + 1, kb = 2 * q;
-    const T ha = hk(ka);
-    const V Ga = G[ka];
-    ad.add(2.0, (double)ha, (double)ka * ka * il2, mk<T>(s * z[2], s * z[3]), Ga);
-    if (gz) {
-      gz[2] = s2 * ha * Ga.x;
-      gz[3] = s2 * ha * Ga.y;
+    if (ka < a.M) {
+      const T ha = hk(ka);
+      const V Ga = G[ka];
+      ad.add(2.0, (double)ha, (double)ka * ka * il2, mk<T>(s * z[2], s * z[3]), Ga);
+      if (gz) {
+        gz[2] = s2 * ha * Ga.x;
+        gz[3] = s2 * ha * Ga.y;
+      }
     }
     const V Gb = G[kb];
     if (q > 0) {
@@ -434,6 +438,123 @@ __global__ void __launch_bounds__(256) k_grad_spec(Args a) {
   }
 }
 
+// Adjoint of the one-FFT algorithm (d = 2, 3) at grid lengths without a
+// compile-time adjoint column kernel: G = F[g] transformed along every axis by
+// the runtime-radix passes and read back from memory (packed like the
+// sampler's intermediate, slot 0 = Z(k) = G(k, 0) + i G(k, N_d/2)), instead of
+// being formed inside the column transform.  Each thread takes the entries
+// 2q, 2q + 1 of one row (one Philox block), regenerates their noise and h as
+// gen_pair does, and adds w (h/2) dlogS/dtheta Re(xi conj G) (w = 2 for
+// 0 < m < N_d/2).  Slot 0 is unpacked with the mirrored row:
+// G(k, 0) = (Z(k) + conj Z(-k)) / 2, G(k, N_d/2) = (Z(k) - conj Z(-k)) / 2i;
+// the lower row of a pair (k, -k) counts both (w = 2) and writes dL/dz of the
+// first two normals of both rows, a self-mirrored row counts once.  dL/dz of
+// an interior entry A = h s (z + i z') is 2 h s G.
+template <typename T>
+__global__ void __launch_bounds__(256) k_grad_gen(Args a) {
+  using V = C<T>;
+  const int tile = blockIdx.x % a.ntile;
+  const int b = blockIdx.x / a.ntile;
+  const int NQ = (a.M + 1) / 2;
+  const long long R = (long long)a.n1 * a.no;
+  const long long e = (long long)tile * 256 + threadIdx.x;
+  double acc0 = 0, acc1 = 0, acc2 = 0;
+  if (e < R * NQ) {
+    const int row = (int)(e / NQ), q = (int)(e % NQ), m0 = 2 * q;
+    const int k1 = row / a.no, o = row - k1 * a.no;
+    const FieldRec& rec = a.recs[b * a.rec_stride];
+    const Filt<T> f = load_filt<T>(rec, 1.0);
+    AdjAcc<T> ad(rec);
+    const unsigned long long key = a.seed + (unsigned long long)b;
+    const uint32_t key0 = (uint32_t)key, key1 = (uint32_t)(key >> 32);
+    const T* zsrc = (const T*)a.src;
+    T z[4];
+    load_z4<T>(a, zsrc, b, row, m0, key0, key1, z);
+    const int q1 = wrapk(k1, a.n1), qo = wrapk(o, a.no);
+    const double p2b = (double)(q1 * q1) * a.il2[0] + (double)(qo * qo) * a.il2[1];
+    const double il2d = a.il2[2];
+    // h by gen_pair's float expressions (or its table)
+    const T* hr = a.htab ? (const T*)a.htab + (long long)row * (a.M + 2) : nullptr;
+    const T p2bt = (T)(q1 * q1) * (T)a.il2[0] + (T)(qo * qo) * (T)a.il2[1];
+    const T il2t = (T)a.il2[2];
+    auto hv = [&](int m) -> T { return hr ? hr[m] : filt_h(f, p2bt + (T)(m * m) * il2t); };
+    const V* Gf = (const V*)a.data + (long long)b * R * a.M;
+    const V* G = Gf + (long long)row * a.M;
+    T* gzf = a.aux ? (T*)a.aux + (long long)b * a.field_stride * 2 : nullptr;
+    T* gz = gzf ? gzf + (long long)row * a.nd + 2 * m0 : nullptr;
+    const T s = (T)0.70710678118654752440, s2 = (T)1.4142135623730950488;
+    if (m0 + 1 < a.M) {
+      const int m = m0 + 1;
+      const T h1 = hv(m);
+      const V G1 = G[m];
+      ad.add(2.0, (double)h1, p2b + (double)m * m * il2d, mk<T>(s * z[2], s * z[3]), G1);
+      if (gz) {
+        gz[2] = s2 * h1 * G1.x;
+        gz[3] = s2 * h1 * G1.y;
+      }
+    }
+    if (m0 > 0) {
+      const T h0 = hv(m0);
+      const V G0 = G[m0];
+      ad.add(2.0, (double)h0, p2b + (double)m0 * m0 * il2d, mk<T>(s * z[0], s * z[1]), G0);
+      if (gz) {
+        gz[0] = s2 * h0 * G0.x;
+        gz[1] = s2 * h0 * G0.y;
+      }
+    } else {
+      const int nrow = ((a.n1 - k1) % a.n1) * a.no + (a.no - o) % a.no;
+      if (nrow >= row) {
+        const T h0 = hv(0), hm = hv(a.M);
+        const V zg = G[0], wg = Gf[(long long)nrow * a.M];
+        const V g0 = mk<T>((T)0.5 * (zg.x + wg.x), (T)0.5 * (zg.y - wg.y));
+        const V gm = mk<T>((T)0.5 * (zg.y + wg.y), (T)-0.5 * (zg.x - wg.x));
+        const double pm = p2b + (double)a.M * a.M * il2d;
+        if (nrow == row) {   // A(k, 0) = h z_0 and A(k, N_d/2) = h z_1, both real
+          ad.add(1.0, (double)h0, p2b, mk<T>(z[0], (T)0), g0);
+          ad.add(1.0, (double)hm, pm, mk<T>(z[1], (T)0), gm);
+          if (gz) {
+            gz[0] = h0 * g0.x;
+            gz[1] = hm * gm.x;
+          }
+        } else {   // xi(k, 0) from this row's block, xi(k, N_d/2) from the mirrored row's
+          T zz[4];
+          load_z4<T>(a, zsrc, b, nrow, 0, key0, key1, zz);
+          ad.add(2.0, (double)h0, p2b, mk<T>(s * z[0], s * z[1]), g0);
+          ad.add(2.0, (double)hm, pm, mk<T>(s * zz[0], s * zz[1]), gm);
+          if (gz) {
+            gz[0] = s2 * h0 * g0.x;
+            gz[1] = s2 * h0 * g0.y;
+            T* gn = gzf + (long long)nrow * a.nd;
+            gn[0] = s2 * hm * gm.x;
+            gn[1] = s2 * hm * gm.y;
+          }
+        }
+      }
+    }
+    acc0 = ad.acc0 * rec.gs;
+    acc1 = ad.acc1;
+    acc2 = ad.acc2;
+  }
+  __shared__ double red[3][4];
+  for (int off = 32; off > 0; off >>= 1) {
+    acc0 += __shfl_xor(acc0, off);
+    acc1 += __shfl_xor(acc1, off);
+    acc2 += __shfl_xor(acc2, off);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wv] = acc0;
+    red[1][wv] = acc1;
+    red[2][wv] = acc2;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double sacc = 0;
+    for (int v = 0; v < 4; ++v) sacc += red[threadIdx.x][v];
+    a.partial[((long long)b * a.ntile + tile) * 3 + threadIdx.x] = sacc;
+  }
+}
+
 // The half-spectrum A = h xi that the one-FFT sampler transforms (noise,
 // Hermitian arrangement and filter of Section 3's second algorithm), by the
 // generating pass's own gen_pair, packed like the sampler's intermediate:
@@ -483,6 +604,15 @@ hipError_t launch_grad_spec(int dtype, const Args& a, long long nblocks, hipStre
     hipLaunchKernelGGL(k_grad_spec<float>, dim3((unsigned)nblocks), dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL(k_grad_spec<double>, dim3((unsigned)nblocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_gen(int dtype, const Args& a, long long nblocks, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_grad_gen<float>, dim3((unsigned)nblocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_grad_gen<double>, dim3((unsigned)nblocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

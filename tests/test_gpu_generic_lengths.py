@@ -13,7 +13,9 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
+from oracle import adjoint as oadj  # noqa: E402
 from oracle import grf as ogrf  # noqa: E402
+from oracle import noise as onoise  # noqa: E402
 from oracle import spectra  # noqa: E402
 
 # leading-axis lengths and last-axis half-lengths that are not in the compiled lists
@@ -113,11 +115,6 @@ def test_generic_theta_and_noise_routes(grf):
 
 def test_generic_refusals(grf):
     from paper_1105_2737_amd import _lib as L
-    plan = grf.Plan((80, 16), alg=2, dtype=torch.float32)
-    phi = plan.sample(seed=0, batch=1)
-    with pytest.raises(L.GRFError) as ei:
-        plan.backward(phi, seed=0)
-    assert ei.value.status == L.GRF_EUNSUPPORTED
     for kw in (dict(boundary="neumann"), dict(draw_order="recursive")):
         with pytest.raises(L.GRFError) as ei:
             grf.Plan((80, 16), alg=2, dtype=torch.float32, **kw)
@@ -128,3 +125,67 @@ def test_generic_refusals(grf):
     with pytest.raises(L.GRFError) as ei:
         grf.Plan((16, 2 * 3 * 7), alg=2, dtype=torch.float32)     # not 2/3/5-smooth
     assert ei.value.status == L.GRF_EINVAL
+
+
+# (dims, lengths): every axis off the lists, one axis off, a self-mirrored
+# column length of 6, odd half-lengths, d = 1 and 3
+ADJ_DIMS = [((80, 150), (1.0, 1.5)), ((6, 10), (1.0, 1.0)), ((384, 16), (2.0, 1.0)), ((16, 250), (1.0, 2.0)),
+            ((10, 18, 6), (1.0, 1.25, 1.5)), ((4, 40, 16), (1.0, 1.0, 1.0)), ((150,), (1.0,)), ((2 * 1500,), (2.0,))]
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["f32", "f64"])
+@pytest.mark.parametrize("alg", [2, 1])
+@pytest.mark.parametrize("dims,lengths", ADJ_DIMS, ids=str)
+def test_generic_adjoint(grf, dtype, alg, dims, lengths):
+    """dL/dtheta and dL/dz of runtime-radix plans against the float64 oracle,
+    each theta component against its own scale, for two fields with generated
+    noise, and the same gradients with the noise passed in."""
+    params = (1.2, 0.15, 1.5)
+    print(f"generic adjoint: dims {dims} alg {alg} {dtype}", flush=True)
+    plan = grf.Plan(dims, lengths=lengths, alg=alg, dtype=dtype, cov="matern", sigma=params[0],
+                    length_scale=params[1], nu=params[2])
+    B, seed = 2, 5
+    g = torch.randn((B,) + dims, dtype=torch.float64, generator=torch.Generator().manual_seed(9))
+    gt, gz = plan.backward(g, seed=seed, need_noise_grad=True)
+    gt = gt.cpu().numpy()
+    gz = gz.double().cpu().numpy()
+    tol = 1e-5 if dtype == torch.float32 else 1e-12
+    tag = onoise.TAG_ALG2 if alg == 2 else onoise.TAG_ALG1
+    for b in range(B):
+        z = onoise.field_noise(dims, seed + b, tag)
+        gb = g[b].numpy()
+        if alg == 2:
+            rt = oadj.grad_theta_alg2(z, gb, lengths, spectra.MATERN, *params)
+            rz = oadj.grad_noise_alg2(gb, lengths, spectra.MATERN, *params)
+        else:
+            rt = oadj.grad_theta_alg1(z, gb, lengths, spectra.MATERN, *params)
+            rz = oadj.grad_noise_alg1(gb, lengths, spectra.MATERN, *params)
+        # each component against its own scale: the sum of its absolute terms
+        # w (h/2) |dlogS/dtheta| |Re(xi conj G)|, which bounds the rounding error
+        P = int(np.prod(dims))
+        xi = ogrf.hermitian_noise(z) if alg == 2 else np.fft.rfftn(z) / np.sqrt(P)
+        core = oadj.half_weights(dims) * np.abs(np.real(xi * np.conj(np.fft.rfftn(gb))))
+        h = spectra.filter_h(dims, lengths, spectra.MATERN, *params, half=True)
+        dlog = spectra.dlog_spectral_density(spectra.MATERN, spectra.freq2_grid(dims, lengths, half=True),
+                                             len(dims), *params)
+        for c in range(3):
+            scale = float(np.sum(0.5 * h * np.abs(dlog[c]) * core))
+            assert abs(gt[b, c] - rt[c]) <= tol * scale, (b, c, gt[b], rt, scale)
+        assert relerr(gz[b], rz) <= tol, (b, relerr(gz[b], rz))
+    z = plan.noise(seed=seed, batch=B)
+    gt2, gz2 = plan.backward(g, noise=z, need_noise_grad=True)
+    assert np.allclose(gt2.cpu().numpy(), gt, rtol=tol, atol=0)
+    assert relerr(gz2.double().cpu().numpy(), gz) <= tol
+
+
+def test_generic_adjoint_sigma_identity(grf):
+    """sigma dL/dsigma = 2 L for L = sum w phi^2 (phi is linear in sigma), on a
+    larger runtime-radix grid with per-field parameters."""
+    dims = (768, 240)
+    plan = grf.Plan(dims, dtype=torch.float64, cov="matern")
+    th = torch.tensor([[1.0, 0.1, 1.5], [0.5, 0.2, 0.7]], dtype=torch.float64)
+    phi = plan.sample(seed=2, batch=2, theta=th)
+    w = torch.rand(phi.shape, dtype=torch.float64, generator=torch.Generator().manual_seed(1)).to(phi.device)
+    gt, _ = plan.backward(2 * w * phi, seed=2, theta=th)
+    L = (w * phi ** 2).sum(dim=(1, 2))
+    np.testing.assert_allclose((gt[:, 0].cpu() * th[:, 0]).numpy(), 2 * L.cpu().numpy(), rtol=1e-10)
