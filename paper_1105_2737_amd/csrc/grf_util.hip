@@ -24,13 +24,30 @@ __global__ void k_prep_recs(const double* theta, int batch, int kind, int d, dou
   out[b] = r;
 }
 
-__global__ void k_reduce_partials(const double* partial, int batch, int nper, double* grad) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= batch * 3) return;
-  const int b = i / 3, c = i % 3;
-  double s = 0;
-  for (int k = 0; k < nper; ++k) s += partial[((long long)b * nper + k) * 3 + c];
-  grad[i] = s;
+// grad[b][c] = sum_k partial[b][k][c]: one wave per field, lane l summing
+// k = l, l + 64, ... in increasing order, then a fixed butterfly over the
+// lanes, so the result depends on nper only (not on chunking or timing).
+__global__ void __launch_bounds__(256) k_reduce_partials(const double* partial, int batch, int nper, double* grad) {
+  const int lane = threadIdx.x & 63;
+  const long long b = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (b >= batch) return;   // whole waves leave together
+  double s0 = 0, s1 = 0, s2 = 0;
+  const double* p = partial + b * nper * 3;
+  for (int k = lane; k < nper; k += 64) {
+    s0 += p[3 * k];
+    s1 += p[3 * k + 1];
+    s2 += p[3 * k + 2];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    s0 += __shfl_xor(s0, off);
+    s1 += __shfl_xor(s1, off);
+    s2 += __shfl_xor(s2, off);
+  }
+  if (lane == 0) {
+    grad[3 * b] = s0;
+    grad[3 * b + 1] = s1;
+    grad[3 * b + 2] = s2;
+  }
 }
 
 __global__ void k_philox_raw(unsigned long long seed, const uint32_t* ctr, long long n, uint32_t* out) {
@@ -87,7 +104,8 @@ hipError_t launch_prep_recs(const double* theta, int batch, int kind, int d, dou
 }
 
 hipError_t launch_reduce_partials(const double* partial, int batch, int nper, double* grad, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_partials, dim3((batch * 3 + 255) / 256), dim3(256), 0, s, partial, batch, nper, grad);
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_partials, dim3((batch + 3) / 4), dim3(256), 0, s, partial, batch, nper, grad);
   return hipGetLastError();
 }
 
