@@ -29,13 +29,19 @@ __device__ __forceinline__ void gstage(Acc acc, int t, int NT, int L, int Ns, co
   constexpr int NB = (VPT + R - 1) / R;
   const int LR = L / R;
   const int tstep = L / (Ns * R);
+  // j / Ns by one float product: (j + 1/2) / Ns lies at least 1 / (2 Ns) from
+  // an integer, and for j < L <= 2^20 the product's relative error (below
+  // 2^-22) moves it by less than that, so its integer part is exact (an
+  // integer division by a runtime value costs ~25 VALU instructions)
+  const float ins = 1.0f / (float)Ns;
+  auto quo = [&](int j) -> int { return (int)(((float)j + 0.5f) * ins); };
   V v[NB][NC][R];
   if (act) {
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int j = t + i * NT;
       if (j < LR) {
-        const int k = j % Ns;
+        const int k = j - quo(j) * Ns;
 #pragma unroll
         for (int m = 0; m < R; ++m) {
           const E e = acc(j + m * LR);
@@ -61,7 +67,8 @@ __device__ __forceinline__ void gstage(Acc acc, int t, int NT, int L, int Ns, co
     for (int i = 0; i < NB; ++i) {
       const int j = t + i * NT;
       if (j < LR) {
-        const int base = (j / Ns) * Ns * R + j % Ns;
+        const int q = quo(j);
+        const int base = q * Ns * R + (j - q * Ns);
 #pragma unroll
         for (int m = 0; m < R; ++m) {
           E e;
