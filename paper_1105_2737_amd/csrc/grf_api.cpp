@@ -359,13 +359,15 @@ const TuneChoice* tune_choice(const grf_plan_s* p, int pass, int L) {
 
 grf_status run_generic(const grf_plan_s* p, int pass, int L, Args a, long long batch, hipStream_t s,
                        const TuneChoice* tc) {
-  // untuned: 4 values per thread (the tuner chose 4 over 8 for every
-  // runtime-radix pass it timed on MI355X), 8 where a transform would need
-  // more than 1024 threads with 4 (lengths above 4096)
-  int vpt = tc ? tc->vpt : 4;
+  // untuned: 8 values per thread in float32, 4 in float64 (measured on
+  // MI355X with the generator's radix order over 12 workloads in d = 1, 2, 3:
+  // float32 sampling 1.03-1.37x faster with 8, float64 mostly 3-11% faster
+  // with 4), the other where a transform does not fit the first (more than
+  // 1024 threads, or too much LDS)
+  int vpt = tc ? tc->vpt : (p->dtype == GRF_F32 ? 8 : 4);
   grf::GGeom g = grf::generic_geom(pass, p->dtype, L, vpt);
   if (g.threads <= 0 && !tc) {
-    vpt = 8;
+    vpt = 12 - vpt;
     g = grf::generic_geom(pass, p->dtype, L, vpt);
   }
   if (g.threads <= 0) return fail(GRF_EUNSUPPORTED, "no kernel for this transform length and pass");
