@@ -36,7 +36,10 @@ __device__ __forceinline__ void gstage(Acc acc, int t, int NT, int L, int Ns, co
   const float ins = 1.0f / (float)Ns;
   auto quo = [&](int j) -> int { return (int)(((float)j + 0.5f) * ins); };
   V v[NB][NC][R];
+  V w[NB][R];   // the butterflies' twiddles (w[i][0] unused)
   if (act) {
+    // every LDS value and twiddle of the thread's butterflies requested
+    // before any is used, so that their latencies overlap
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int j = t + i * NT;
@@ -50,10 +53,19 @@ __device__ __forceinline__ void gstage(Acc acc, int t, int NT, int L, int Ns, co
         }
         if (Ns > 1) {
 #pragma unroll
-          for (int m = 1; m < R; ++m) {
-            const V w = tw[(long long)tws * (m * k * tstep)];
+          for (int m = 1; m < R; ++m) w[i][m] = tw[tws * (m * k * tstep)];
+        }
+      }
+    }
 #pragma unroll
-            for (int c = 0; c < NC; ++c) v[i][c][m] = ctw<DIR>(v[i][c][m], w);
+    for (int i = 0; i < NB; ++i) {
+      const int j = t + i * NT;
+      if (j < LR) {
+        if (Ns > 1) {
+#pragma unroll
+          for (int m = 1; m < R; ++m) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) v[i][c][m] = ctw<DIR>(v[i][c][m], w[i][m]);
           }
         }
 #pragma unroll
@@ -138,10 +150,18 @@ __global__ void __launch_bounds__(1024) k_gcol(Args a) {
         acc(k) = e;
       }
     } else {
-      for (int k = t; k < L; k += NT) {
-        E e;
-        ld_pair<T>(base + (long long)k * a.stride_ax, two, al, e.v[0], e.v[1]);
-        acc(k) = e;
+      // NT = ceil(L / VPT): the thread's elements are t + i NT, i < VPT; all
+      // loads issued before the first LDS store
+      E xr[VPT];
+#pragma unroll
+      for (int i = 0; i < VPT; ++i) {
+        const int k = t + i * NT;
+        if (k < L) ld_pair<T>(base + (long long)k * a.stride_ax, two, al, xr[i].v[0], xr[i].v[1]);
+      }
+#pragma unroll
+      for (int i = 0; i < VPT; ++i) {
+        const int k = t + i * NT;
+        if (k < L) acc(k) = xr[i];
       }
     }
   }
@@ -190,13 +210,41 @@ __global__ void __launch_bounds__(1024) k_grow_c2r(Args a) {
         if (2 * q + 1 < M) acc(2 * q + 1).v[0] = A1;
       }
     } else {
-      for (int k = t; k < M; k += NT) acc(k).v[0] = o[k];
+      // NT = ceil(M / VPT): elements t + i NT, i < VPT, all loads issued first
+      V xr[VPT];
+#pragma unroll
+      for (int i = 0; i < VPT; ++i) {
+        const int k = t + i * NT;
+        if (k < M) xr[i] = o[k];
+      }
+#pragma unroll
+      for (int i = 0; i < VPT; ++i) {
+        const int k = t + i * NT;
+        if (k < M) acc(k).v[0] = xr[i];
+      }
+    }
+  }
+  // the pre-twiddle's factors, requested before the barrier: the thread's
+  // pairs are k = t + i NT with 2k <= M, i.e. i <= VPT / 2
+  constexpr int NPT = VPT / 2 + 1;
+  V wk[NPT], wm[NPT];
+  if (act) {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int k = t + i * NT;
+      if (k > 0 && 2 * k <= M) {
+        wk[i] = tw2[k];
+        wm[i] = tw2[M - k];
+      }
     }
   }
   __syncthreads();
   // pre-twiddle, pairs (k, M - k) by one thread (in place)
   if (act) {
-    for (int k = t; 2 * k <= M; k += NT) {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int k = t + i * NT;
+      if (2 * k > M) continue;
       if (k == 0) {
         const V x0 = acc(0).v[0];
         acc(0).v[0] = mk<T>(x0.x + x0.y, x0.x - x0.y);
@@ -207,13 +255,13 @@ __global__ void __launch_bounds__(1024) k_grow_c2r(Args a) {
       {
         const V c = cconj(xm);
         const V ek = cadd(xk, c);
-        const V ok = cmul(csub(xk, c), tw2[k]);
+        const V ok = cmul(csub(xk, c), wk[i]);
         acc(k).v[0] = mk<T>(ek.x - ok.y, ek.y + ok.x);
       }
       if (km != k) {
         const V c = cconj(xk);
         const V ek = cadd(xm, c);
-        const V ok = cmul(csub(xm, c), tw2[km]);
+        const V ok = cmul(csub(xm, c), wm[i]);
         acc(km).v[0] = mk<T>(ek.x - ok.y, ek.y + ok.x);
       }
     }
@@ -248,7 +296,17 @@ __global__ void __launch_bounds__(1024) k_grow_r2c(Args a) {
   if (act) {
     if constexpr (SRC == SRC_LOAD) {
       const V* src = (const V*)a.src + row * M;
-      for (int k = t; k < M; k += NT) acc(k).v[0] = src[k];
+      V xr[VPT];
+#pragma unroll
+      for (int i = 0; i < VPT; ++i) {
+        const int k = t + i * NT;
+        if (k < M) xr[i] = src[k];
+      }
+#pragma unroll
+      for (int i = 0; i < VPT; ++i) {
+        const int k = t + i * NT;
+        if (k < M) acc(k).v[0] = xr[i];
+      }
     } else {
       const long long b = row / a.rows_per_field;
       const int frow = (int)(row - b * a.rows_per_field);
@@ -262,10 +320,25 @@ __global__ void __launch_bounds__(1024) k_grow_r2c(Args a) {
     }
   }
   __syncthreads();
+  constexpr int NPT = VPT / 2 + 1;
+  V wk[NPT], wm[NPT];
+  if (act) {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int k = t + i * NT;
+      if (k > 0 && 2 * k <= M) {
+        wk[i] = tw2[k];
+        wm[i] = tw2[M - k];
+      }
+    }
+  }
   grun<T, 1, -1, VPT>(a, acc, t, NT, M, tw2, 2, act);
   if (act) {
     V* o = (V*)a.data + row * M;
-    for (int k = t; 2 * k <= M; k += NT) {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int k = t + i * NT;
+      if (2 * k > M) continue;
       if (k == 0) {
         const V y0 = acc(0).v[0];
         o[0] = mk<T>(y0.x + y0.y, y0.x - y0.y);
@@ -276,12 +349,12 @@ __global__ void __launch_bounds__(1024) k_grow_r2c(Args a) {
       const V ek = cscale(cadd(yk, cconj(ym)), (T)0.5);
       const V dk = cscale(csub(yk, cconj(ym)), (T)0.5);
       const V dki = mk<T>(dk.y, -dk.x);
-      o[k] = cadd(ek, cmul(dki, cconj(tw2[k])));
+      o[k] = cadd(ek, cmul(dki, cconj(wk[i])));
       if (km != k) {
         const V em = cscale(cadd(ym, cconj(yk)), (T)0.5);
         const V dm = cscale(csub(ym, cconj(yk)), (T)0.5);
         const V dmi = mk<T>(dm.y, -dm.x);
-        o[km] = cadd(em, cmul(dmi, cconj(tw2[km])));
+        o[km] = cadd(em, cmul(dmi, cconj(wm[i])));
       }
     }
   }
