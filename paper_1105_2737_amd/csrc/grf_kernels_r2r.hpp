@@ -408,9 +408,12 @@ __device__ __forceinline__ double r2r_p2(const Args& a, int n1, int no, int nd) 
 // The reduction step of four consecutive slots (row = n1 * no + no index,
 // last-axis slots s .. s + 3) of field b with G = (B^T g) there: regenerate
 // z (or read it from a.src2), add the terms, write dL/dz to a.aux if asked.
-template <typename T, bool UNIFORM_KEY>
+// PRE: the coefficients a_n of the four slots come from cpre (loaded by the
+// caller from the plan's table) instead of a load here.
+template <typename T, bool UNIFORM_KEY, bool PRE = false>
 __device__ __forceinline__ void r2r_adj4(const Args& a, const Filt<T>& f, AdjAcc<T>& ad, int b, uint32_t k0,
-                                         uint32_t k1, int n1, int no, int s, const T* G, int nvalid) {
+                                         uint32_t k1, int n1, int no, int s, const T* G, int nvalid,
+                                         const T* cpre = nullptr) {
   const int row = n1 * a.no + no;
   T z[4];
   if (a.src2 == nullptr) {
@@ -421,12 +424,51 @@ __device__ __forceinline__ void r2r_adj4(const Args& a, const Filt<T>& f, AdjAcc
     for (int e = 0; e < 4; ++e) z[e] = e < nvalid ? p[e] : (T)0;
   }
   T* gz = a.aux ? (T*)a.aux + (long long)b * a.field_stride * 2 + (long long)row * a.nd + s : nullptr;
+  if constexpr (sizeof(T) == 4) {
+    // float32: the four slots' terms c = a_n z G / 2, c dlogS/dl and
+    // c dlogS/dnu formed and summed in float32 (p^2 by the float expression
+    // of r2r_coef, dlogS as in AdjAcc::add2f), one float64 add per sum
+    const int k1 = (a.bcmask & 1) ? a.n1 - n1 : n1;
+    const int ko = (a.bcmask & 2) ? a.no - no : no;
+    const float p2r = (float)(k1 * k1) * (float)a.il2[0] + (float)(ko * ko) * (float)a.il2[1];
+    const float il2d = (float)a.il2[2];
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    if (e < nvalid) {
-      const T c = a.htab ? ((const T*)a.htab)[(long long)row * a.nd + s + e] : r2r_coef<T>(a, f, n1, no, s + e);
-      ad.add(1.0, (double)c, r2r_p2(a, n1, no, s + e), mk<T>(z[e], (T)0), mk<T>(G[e], (T)0));
-      if (gz) gz[e] = c * G[e];
+    for (int e = 0; e < 4; ++e) {
+      if (e < nvalid) {
+        const float c = PRE ? (float)cpre[e]
+                            : a.htab ? ((const float*)a.htab)[(long long)row * a.nd + s + e]
+                                     : r2r_coef<float>(a, f, n1, no, s + e);
+        const int kd = (a.bcmask & 4) ? a.nd - (s + e) : s + e;
+        const float pf = 0.25f * (p2r + (float)(kd * kd) * il2d);
+        float dl, dn = 0.0f;
+        if (ad.gauss) {
+          dl = fmaf(ad.gl1f, pf, ad.gl0f);
+        } else {
+          const float u = fmaf(ad.rbf, pf, ad.raf);
+          const float iu = __builtin_amdgcn_rcpf(u);
+          dl = fmaf(ad.gl1f, iu, ad.gl0f);
+          if (ad.has_nu) dn = ad.gn0f - __builtin_amdgcn_logf(u) * 0.693147180559945309f - ad.gn1f * iu;
+        }
+        const float cc = 0.5f * c * ((float)z[e] * (float)G[e]);
+        s0 += cc;
+        s1 = fmaf(cc, dl, s1);
+        s2 = fmaf(cc, dn, s2);
+        if (gz) gz[e] = c * G[e];
+      }
+    }
+    ad.acc0 += (double)s0;
+    ad.acc1 += (double)s1;
+    ad.acc2 += (double)s2;
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (e < nvalid) {
+        const T c = PRE ? cpre[e]
+                        : a.htab ? ((const T*)a.htab)[(long long)row * a.nd + s + e] : r2r_coef<T>(a, f, n1, no, s + e);
+        ad.add(1.0, (double)c, r2r_p2(a, n1, no, s + e), mk<T>(z[e], (T)0), mk<T>(G[e], (T)0));
+        if (gz) gz[e] = c * G[e];
+      }
     }
   }
 }
@@ -482,6 +524,22 @@ struct R2RColF {
         }
       }
     }
+    // the reduction's coefficients a_n from the plan's table, requested here
+    // so that their latency overlaps the transform
+    T cq[RED ? R0 : 1][4];
+    const bool pre = RED && act && a.htab != nullptr;
+    if constexpr (RED) {
+      if (pre) {
+#pragma unroll
+        for (int m = 0; m < R0; ++m) {
+          const T* cp4 = (const T*)a.htab + (long long)((t + m * NT) * a.no + fx) * a.nd + 2 * m0;
+          cq[m][0] = cp4[0];
+          cq[m][1] = cp4[1];
+          cq[m][2] = two ? cp4[2] : (T)0;
+          cq[m][3] = two ? cp4[3] : (T)0;
+        }
+      }
+    }
     __syncthreads();   // the twiddle tables
     auto lds = [&](int i) -> E& { return sm[i * RS + cp]; };
     auto none = [&](int, const E&) {};
@@ -526,7 +584,11 @@ struct R2RColF {
           X[2 * c + 1] = fmat(q.x, B.x, -(q.y * B.y));
         }
         if constexpr (RED) {
-          r2r_adj4<T, true>(a, f, ad, b, (uint32_t)key, (uint32_t)(key >> 32), k, fx, 2 * m0, X, two ? 4 : 2);
+          if (pre)
+            r2r_adj4<T, true, true>(a, f, ad, b, (uint32_t)key, (uint32_t)(key >> 32), k, fx, 2 * m0, X, two ? 4 : 2,
+                                    cq[m]);
+          else
+            r2r_adj4<T, true>(a, f, ad, b, (uint32_t)key, (uint32_t)(key >> 32), k, fx, 2 * m0, X, two ? 4 : 2);
         } else {
           E o;
           o.v[0] = mk<T>(X[0], X[1]);
