@@ -756,10 +756,33 @@ struct R2RRowF {
         const Filt<T> f = load_filt<T>(rec, 1.0);
         AdjAcc<T> ad(rec);
         const unsigned long long key = a.seed + (unsigned long long)b;
-        for (int q4 = t; q4 < M / 2; q4 += NT) {
-          const V p0 = rowp[RL::idx(2 * q4)].v[0], p1 = rowp[RL::idx(2 * q4 + 1)].v[0];
-          const T G[4] = {p0.x, p0.y, p1.x, p1.y};
-          r2r_adj4<T, false>(a, f, ad, b, (uint32_t)key, (uint32_t)(key >> 32), 0, 0, 4 * q4, G, 4);
+        // the thread's slots 4 q4 .. 4 q4 + 3, q4 = t + i NT < M / 2; their
+        // coefficients from the plan's table all requested before the first
+        // is used
+        constexpr int NQ4 = (R0 + 1) / 2;
+        T cq[NQ4][4];
+        const bool pre = a.htab != nullptr;
+        if (pre) {
+#pragma unroll
+          for (int i = 0; i < NQ4; ++i) {
+            const int q4 = t + i * NT;
+            if (q4 < M / 2) {
+#pragma unroll
+              for (int e = 0; e < 4; ++e) cq[i][e] = ((const T*)a.htab)[4 * q4 + e];
+            }
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < NQ4; ++i) {
+          const int q4 = t + i * NT;
+          if (q4 < M / 2) {
+            const V p0 = rowp[RL::idx(2 * q4)].v[0], p1 = rowp[RL::idx(2 * q4 + 1)].v[0];
+            const T G[4] = {p0.x, p0.y, p1.x, p1.y};
+            if (pre)
+              r2r_adj4<T, false, true>(a, f, ad, b, (uint32_t)key, (uint32_t)(key >> 32), 0, 0, 4 * q4, G, 4, cq[i]);
+            else
+              r2r_adj4<T, false>(a, f, ad, b, (uint32_t)key, (uint32_t)(key >> 32), 0, 0, 4 * q4, G, 4);
+          }
         }
         acc0 = ad.acc0 * rec.gs;
         acc1 = ad.acc1;
