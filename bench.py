@@ -88,6 +88,9 @@ def parse():
     ap.add_argument("--profile-adjoint", action="store_true",
                     help="profiling mode: the adjoint of the 1024^2 x 64 training step (dL/dphi = 2 w phi), "
                          "--steps times")
+    ap.add_argument("--profile-adjoint-reflect", choices=["neumann", "dirichlet"], default=None,
+                    help="profiling mode: forward and adjoint of the reflecting sampler on 512^2 x 256 fields "
+                         "(dL/dphi = phi), --steps times each")
     ap.add_argument("--profile-uneven", action="store_true",
                     help="profiling mode: sample the 4096 uneven fields (graph replay), --steps times")
     ap.add_argument("--copy-calib", action="store_true",
@@ -113,6 +116,19 @@ def profile_mode(args):
             plan.backward(g, seed=0)
         torch.cuda.synchronize()
         print(f"profiled the adjoint of 1024^2 x 64, {args.steps} times", flush=True)
+        return
+    if args.profile_adjoint_reflect is not None:
+        plan = grf.Plan((512, 512), alg=2, dtype=torch.float32, cov="matern", sigma=1.0, length_scale=0.1, nu=1.5,
+                        boundary=args.profile_adjoint_reflect)
+        phi = plan.sample(seed=0, batch=256)
+        for _ in range(args.warmup + args.steps):
+            plan.sample(seed=0, batch=256, out=phi)
+        g = phi.clone()
+        for _ in range(args.warmup + args.steps):
+            plan.backward(g, seed=0)
+        torch.cuda.synchronize()
+        print(f"profiled the {args.profile_adjoint_reflect} sampler and its adjoint on 512^2 x 256, "
+              f"{args.steps} times each", flush=True)
         return
     if args.profile_uneven:
         from synth import uneven_fields
@@ -338,7 +354,8 @@ def cpu_baseline(seconds, batch=1024, P=512 * 512):
 
 def main():
     args = parse()
-    if args.profile_stage is not None or args.copy_calib or args.profile_adjoint or args.profile_uneven:
+    if (args.profile_stage is not None or args.copy_calib or args.profile_adjoint or args.profile_uneven
+            or args.profile_adjoint_reflect is not None):
         if args.gpus != 1:
             sys.exit(2)
         profile_mode(args)
