@@ -78,9 +78,10 @@ enum { GRF_DRAW_COUNTER = 0, GRF_DRAW_RECURSIVE = 1 };
  *             lengths N_1 (and N_2 for d = 3) up to 4096, the last length N_d
  *             up to 16384 (GRF_EUNSUPPORTED above).  The listed lengths run on
  *             compile-time kernels tuned per length: leading lengths {4, 8, 12,
- *             16, 24, 32, 48, 64, 96, 128, 180, 256, 360, 500, 512, 1000, 1024},
- *             N_d/2 from {2, 4, ..., 512, 1024, 2048} (the same list with 2,
- *             1024 and 2048); every other length runs on runtime-radix kernels
+ *             16, 24, 32, 48, 64, 96, 128, 180, 256, 360, 384, 500, 512, 768,
+ *             1000, 1024}, N_d/2 from {2, 4, 8, 12, 16, 24, 32, 48, 64, 96, 128,
+ *             180, 192, 256, 360, 384, 500, 512, 1024, 2048}; every other length
+ *             runs on runtime-radix kernels
  *             (sampling and grf_backward with either algorithm, d = 1, 2, 3).
  *             Reflecting boundaries and the recursive draw order take the
  *             listed lengths only (GRF_EUNSUPPORTED otherwise).

@@ -27,8 +27,10 @@ GRF_COLCFG(128, 16, 8, 1, 8, 4, 4)
 GRF_COLCFG(180, 8, 4, 1, 5, 6, 6)
 GRF_COLCFG(256, 8, 4, 1, 8, 8, 4)
 GRF_COLCFG(360, 8, 4, 1, 8, 5, 9)
+GRF_COLCFG(384, 8, 4, 1, 8, 8, 6)
 GRF_COLCFG(500, 4, 2, 1, 10, 10, 5)
 GRF_COLCFG(512, 4, 2, 0, 8, 8, 8)
+GRF_COLCFG(768, 4, 2, 1, 8, 8, 4, 3)
 GRF_COLCFG(1000, 4, 2, 0, 10, 10, 10)
 GRF_COLCFG(1024, 4, 2, 0, 8, 8, 4, 4)
 #undef GRF_COLCFG
@@ -59,8 +61,10 @@ GRF_ROWCFG(64, 16, 16, 8, 8)
 GRF_ROWCFG(96, 16, 8, 8, 12)
 GRF_ROWCFG(128, 16, 8, 16, 8)
 GRF_ROWCFG(180, 4, 4, 5, 6, 6)
+GRF_ROWCFG(192, 8, 4, 8, 8, 3)
 GRF_ROWCFG(256, 8, 8, 8, 8, 4)
 GRF_ROWCFG(360, 4, 4, 8, 5, 9)
+GRF_ROWCFG(384, 4, 4, 8, 8, 6)
 GRF_ROWCFG(500, 4, 2, 10, 10, 5)
 GRF_ROWCFG(512, 4, 4, 8, 8, 8)
 GRF_ROWCFG(1024, 4, 2, 16, 8, 8)

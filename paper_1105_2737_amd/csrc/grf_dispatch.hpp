@@ -17,8 +17,8 @@ struct Args;
 // Supported transform lengths (2^a 3^b 5^c):
 //   column (leading-axis) lengths: GRF_COL_LENGTHS
 //   row half-lengths M = N_d / 2:  GRF_ROW_LENGTHS
-#define GRF_COL_LENGTHS(X) X(4) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(180) X(256) X(360) X(500) X(512) X(1000) X(1024)
-#define GRF_ROW_LENGTHS(X) X(2) X(4) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(180) X(256) X(360) X(500) X(512) X(1024) X(2048)
+#define GRF_COL_LENGTHS(X) X(4) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(180) X(256) X(360) X(384) X(500) X(512) X(768) X(1000) X(1024)
+#define GRF_ROW_LENGTHS(X) X(2) X(4) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(180) X(192) X(256) X(360) X(384) X(500) X(512) X(1024) X(2048)
 
 // The passes (values as the GRF_PASS_* constants of the C interface).
 enum PassKind {

@@ -19,8 +19,8 @@ from oracle import noise as onoise  # noqa: E402
 from oracle import spectra  # noqa: E402
 
 # leading-axis lengths and last-axis half-lengths that are not in the compiled lists
-GEN_COL = [6, 10, 18, 20, 40, 80, 90, 150, 240, 384, 640, 768, 810, 1200, 1536, 2048, 2700, 4096]
-GEN_HALF = [3, 5, 10, 18, 40, 75, 125, 240, 384, 768, 1500, 4096, 6000, 8192]
+GEN_COL = [6, 10, 18, 20, 40, 80, 90, 150, 240, 640, 720, 810, 1200, 1280, 1536, 2048, 2700, 4096]
+GEN_HALF = [3, 5, 10, 18, 40, 75, 125, 240, 720, 768, 1500, 4096, 6000, 8192]
 TOL = {torch.float32: 1e-5, torch.float64: 1e-12}
 PARAMS = (1.0, 0.15, 1.5)
 
@@ -70,7 +70,7 @@ def test_generic_last_axis(grf, dtype, M):
             check(grf, (4, 6, 2 * M), dtype, alg)
 
 
-@pytest.mark.parametrize("dims", [(90, 250), (768, 80), (40, 30, 18), (4096, 4096), (2048, 6000)])
+@pytest.mark.parametrize("dims", [(90, 250), (720, 80), (40, 30, 18), (4096, 4096), (2048, 6000)])
 def test_generic_mixed_and_large(grf, dims):
     """Every axis off the lists, and large fields (16.8M and 12.3M points)."""
     dtype = torch.float32
@@ -81,7 +81,7 @@ def test_generic_mixed_and_large(grf, dims):
 
 def test_generic_chunks_same_bits(grf):
     """Cache-sized chunks with a ragged tail give the same bits as one chunk."""
-    dims = (384, 90)
+    dims = (720, 90)
     for alg in (2, 1):
         plan = grf.Plan(dims, alg=alg, dtype=torch.float32)
         ref = plan.sample(seed=11, batch=7)
@@ -129,7 +129,7 @@ def test_generic_refusals(grf):
 
 # (dims, lengths): every axis off the lists, one axis off, a self-mirrored
 # column length of 6, odd half-lengths, d = 1 and 3
-ADJ_DIMS = [((80, 150), (1.0, 1.5)), ((6, 10), (1.0, 1.0)), ((384, 16), (2.0, 1.0)), ((16, 250), (1.0, 2.0)),
+ADJ_DIMS = [((80, 150), (1.0, 1.5)), ((6, 10), (1.0, 1.0)), ((720, 16), (2.0, 1.0)), ((16, 250), (1.0, 2.0)),
             ((10, 18, 6), (1.0, 1.25, 1.5)), ((4, 40, 16), (1.0, 1.0, 1.0)), ((150,), (1.0,)), ((2 * 1500,), (2.0,))]
 
 
@@ -181,7 +181,7 @@ def test_generic_adjoint(grf, dtype, alg, dims, lengths):
 def test_generic_adjoint_sigma_identity(grf):
     """sigma dL/dsigma = 2 L for L = sum w phi^2 (phi is linear in sigma), on a
     larger runtime-radix grid with per-field parameters."""
-    dims = (768, 240)
+    dims = (720, 240)
     plan = grf.Plan(dims, dtype=torch.float64, cov="matern")
     th = torch.tensor([[1.0, 0.1, 1.5], [0.5, 0.2, 0.7]], dtype=torch.float64)
     phi = plan.sample(seed=2, batch=2, theta=th)

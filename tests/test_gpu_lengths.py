@@ -17,8 +17,8 @@ from oracle import noise as onoise  # noqa: E402
 from oracle import reflect  # noqa: E402
 from oracle import spectra  # noqa: E402
 
-COL = [4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 180, 256, 360, 500, 512, 1000, 1024]
-ROW_HALF = [2, 4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 180, 256, 360, 500, 512, 1024, 2048]
+COL = [4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 180, 256, 360, 384, 500, 512, 768, 1000, 1024]
+ROW_HALF = [2, 4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 180, 192, 256, 360, 384, 500, 512, 1024, 2048]
 TOL = {torch.float32: 1e-5, torch.float64: 1e-12}
 PARAMS = (1.0, 0.15, 1.5)
 

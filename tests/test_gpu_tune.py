@@ -27,7 +27,7 @@ def relerr(a, b):
     return np.abs(a - b).max() / np.abs(b).max()
 
 
-@pytest.mark.parametrize("dims,alg", [((384, 90), 2), ((384, 90), 1), ((512, 512), 2), ((40, 30, 18), 2),
+@pytest.mark.parametrize("dims,alg", [((720, 90), 2), ((720, 90), 1), ((512, 512), 2), ((40, 30, 18), 2),
                                       ((2700,), 2)])
 def test_tuned_plan_matches_oracle_and_cache_round_trip(grf, tmp_path, monkeypatch, dims, alg):
     from paper_1105_2737_amd import _lib as L
