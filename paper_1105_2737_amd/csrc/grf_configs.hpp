@@ -30,7 +30,7 @@ GRF_COLCFG(360, 8, 4, 1, 8, 5, 9)
 GRF_COLCFG(384, 8, 4, 1, 8, 8, 6)
 GRF_COLCFG(500, 4, 2, 1, 10, 10, 5)
 GRF_COLCFG(512, 4, 2, 0, 8, 8, 8)
-GRF_COLCFG(768, 4, 2, 1, 8, 8, 4, 3)
+GRF_COLCFG(768, 4, 2, 1, 4, 8, 8, 3)
 GRF_COLCFG(1000, 4, 2, 0, 10, 10, 10)
 GRF_COLCFG(1024, 4, 2, 0, 8, 8, 4, 4)
 #undef GRF_COLCFG
