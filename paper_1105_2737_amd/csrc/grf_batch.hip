@@ -22,7 +22,7 @@ namespace grf {
 
 // (length, column pairs variant 0, variant 1)
 #define GRF_BATCH_COL(X) X(64, 32, 16) X(96, 16, 8) X(128, 16, 8) X(180, 7, 4) X(256, 8, 4) \
-  X(360, 5, 3) X(500, 4, 2) X(512, 4, 2) X(1000, 2, 1) X(1024, 2, 1)
+  X(360, 2, 1) X(500, 4, 2) X(512, 4, 2) X(1000, 2, 1) X(1024, 2, 1)
 // (half-length, rows variant 0, variant 1)
 #define GRF_BATCH_ROW(X) X(32, 128, 64) X(48, 64, 32) X(64, 64, 32) X(96, 42, 21) X(128, 64, 32) \
   X(180, 14, 7) X(256, 16, 8) X(360, 11, 5) X(500, 10, 5) X(512, 8, 4)
@@ -222,7 +222,7 @@ k_batch_row(const BatchField* __restrict__ F, const BatchItem* __restrict__ item
 // variant 1) of the column bodies at up to 512 threads; the row bodies are
 // those of k_batch_row.
 #define GRF_BATCH_ONE_COL(X) X(64, 64, 32) X(96, 42, 21) X(128, 32, 16) X(180, 14, 7) X(256, 16, 8) \
-  X(360, 11, 5) X(500, 8, 4) X(512, 8, 4) X(1000, 4, 2) X(1024, 4, 2)
+  X(360, 5, 2) X(500, 8, 4) X(512, 8, 4) X(1000, 4, 2) X(1024, 4, 2)
 
 constexpr int max4(int a, int b, int c, int d) {
   const int x = a > b ? a : b, y = c > d ? c : d;

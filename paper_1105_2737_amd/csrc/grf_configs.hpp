@@ -8,10 +8,11 @@ namespace grf {
 // Column (leading-axis) transforms.  Radices stay <= 10 here: a thread holds
 // a column pair, and a radix-16 butterfly on pairs keeps 32 complex values
 // live, which costs occupancy.  The first radix sets the threads per column
-// (L / R_0): 384 and 768 start with 4 (twice the waves per CU of a first 8 in
-// the same LDS; measured 1.34x / 1.40x faster generating passes).  The lengths
-// the uneven batch also runs (64 ... 1024 in its lists) keep orders whose
-// thread counts fit its persistent kernel, which must reproduce these bits.
+// (L / R_0): 360, 384 and 768 start with 4 (twice the waves per CU of a
+// first 8 in the same LDS; measured 1.19-1.40x faster generating passes).  The
+// lengths the uneven batch also runs (64 ... 1024 in its lists) need orders
+// whose thread counts fit its persistent kernel's tiles, since its plan-order
+// bodies reproduce these bits (its 360 tiles were narrowed for 4-10-9).
 template <int L> struct ColCfg;
 #define GRF_COLCFG(L_, CP32_, CP64_, PAD_, ...)            \
   template <> struct ColCfg<L_> {                          \
@@ -30,7 +31,7 @@ GRF_COLCFG(96, 16, 8, 1, 8, 4, 3)
 GRF_COLCFG(128, 16, 8, 1, 8, 4, 4)
 GRF_COLCFG(180, 8, 4, 1, 5, 6, 6)
 GRF_COLCFG(256, 8, 4, 1, 8, 8, 4)
-GRF_COLCFG(360, 8, 4, 1, 8, 5, 9)
+GRF_COLCFG(360, 8, 4, 1, 4, 10, 9)
 GRF_COLCFG(384, 8, 4, 1, 4, 8, 4, 3)
 GRF_COLCFG(500, 4, 2, 1, 10, 10, 5)
 GRF_COLCFG(512, 4, 2, 0, 8, 8, 8)
